@@ -1,0 +1,201 @@
+"""Seeded synthetic event generator (the input side only).
+
+This module draws detector hits and their truth; it holds none of the track
+finder's arithmetic (no response, no seeds, no fitting), so both the HIP path
+and the FP64 CPU oracle may consume what it produces.
+
+The detector follows the paper's simplified VELO model (Section 3): planes
+perpendicular to the beam axis z, straight tracks, Gaussian smearing of the
+in-plane coordinates and uniformly distributed noise hits.  The concrete
+workloads (plane positions, track counts, slope ranges, inefficiency, noise
+fractions) are the JSON files in ``configs/``; readings where the workload text
+leaves a choice open are listed in the design doc.
+
+Random streams: every event uses its own ``numpy.random.Philox`` keyed by
+``(config key, event index)``, so any event can be regenerated alone and in any
+order.  Coordinates are drawn in FP64 and rounded once to FP32, which is the
+hit precision both sides consume.
+
+Measurement dimension:
+  * ``meas_dim == 2``: a hit is (plane, x, y); a track is (x0, y0, tx, ty) with
+    x(z) = x0 + tx*z and y(z) = y0 + ty*z.
+  * ``meas_dim == 1``: the 2D toy of Section 2 / Fig. 1.  Planes sit at
+    positions z (the paper's x); a hit carries one measured coordinate u (the
+    paper's y) stored in ``x``; a track is (x0, tx) = (beta, alpha) with
+    u(z) = x0 + tx*z.
+"""
+from __future__ import annotations
+
+import dataclasses
+import json
+import os
+from typing import Optional
+
+import numpy as np
+
+_CFG_DIR = os.path.join(os.path.dirname(os.path.abspath(__file__)), "configs")
+
+
+def load_config(name: str) -> dict:
+    """Load a workload description (``c1`` .. ``c5``) from ``configs/``."""
+    path = name if name.endswith(".json") else os.path.join(_CFG_DIR, name + ".json")
+    with open(path) as f:
+        return json.load(f)
+
+
+def plane_z(cfg: dict) -> np.ndarray:
+    """Plane positions along z as FP32 (equally spaced for the VELO-like configs)."""
+    pl = cfg["planes"]
+    if pl["kind"] == "list":
+        z = np.asarray(pl["z"], dtype=np.float64)
+    elif pl["kind"] == "uniform":
+        n = int(pl["n"])
+        z = pl["z_first"] + (pl["z_last"] - pl["z_first"]) * np.arange(n, dtype=np.float64) / (n - 1)
+    else:
+        raise ValueError("unknown plane kind %r" % pl["kind"])
+    return z.astype(np.float32)
+
+
+@dataclasses.dataclass
+class Event:
+    x: np.ndarray          # float32 [n_hits]
+    y: Optional[np.ndarray]  # float32 [n_hits] or None for meas_dim 1
+    plane: np.ndarray      # int32 [n_hits]
+    label: np.ndarray      # int32 [n_hits], index of the generating track, -1 for noise
+    truth: np.ndarray      # float64 [n_tracks, 2*meas_dim]: (x0, tx) or (x0, y0, tx, ty)
+    truth_nhits: np.ndarray  # int32 [n_tracks]
+
+    @property
+    def n_hits(self) -> int:
+        return int(self.x.shape[0])
+
+
+@dataclasses.dataclass
+class Batch:
+    meas_dim: int
+    plane_z: np.ndarray          # float32 [n_planes]
+    event_offsets: np.ndarray    # int64 [n_events+1]
+    x: np.ndarray                # float32 [total_hits]
+    y: Optional[np.ndarray]      # float32 [total_hits] or None
+    plane: np.ndarray            # int32 [total_hits]
+    label: np.ndarray            # int32 [total_hits]
+    truth: list                  # per event float64 arrays
+    truth_nhits: list            # per event int32 arrays
+
+    @property
+    def n_events(self) -> int:
+        return int(self.event_offsets.shape[0] - 1)
+
+    def event(self, e: int) -> Event:
+        a, b = int(self.event_offsets[e]), int(self.event_offsets[e + 1])
+        return Event(self.x[a:b], None if self.y is None else self.y[a:b], self.plane[a:b],
+                     self.label[a:b], self.truth[e], self.truth_nhits[e])
+
+
+def _rng(cfg: dict, idx: int) -> np.random.Generator:
+    key = np.array([int(cfg["key"]), int(idx)], dtype=np.uint64)
+    return np.random.Generator(np.random.Philox(key=key))
+
+
+def _draw_param(rng, spec, n):
+    if spec["kind"] == "uniform":
+        return rng.uniform(spec["lo"], spec["hi"], n)
+    if spec["kind"] == "normal":
+        return rng.normal(0.0, spec["sd"], n)
+    raise ValueError("unknown distribution %r" % spec["kind"])
+
+
+def make_event(cfg: dict, idx: int, zp: Optional[np.ndarray] = None) -> Event:
+    """Generate event ``idx`` of workload ``cfg`` (deterministic in (key, idx))."""
+    rng = _rng(cfg, idx)
+    D = int(cfg["meas_dim"])
+    if zp is None:
+        zp = plane_z(cfg)
+    z64 = zp.astype(np.float64)
+    n_planes = zp.shape[0]
+    tr = cfg["tracks"]
+
+    cnt = tr["count"]
+    if cnt["kind"] == "fixed":
+        n_tracks = int(cnt["n"])
+    elif cnt["kind"] == "poisson":
+        n_tracks = int(np.clip(rng.poisson(cnt["mean"]), cnt["lo"], cnt["hi"]))
+    else:
+        raise ValueError("unknown count kind %r" % cnt["kind"])
+
+    if D == 2:
+        x0 = _draw_param(rng, tr["x0"], n_tracks)
+        y0 = _draw_param(rng, tr["x0"], n_tracks)
+        tx = _draw_param(rng, tr["tx"], n_tracks)
+        ty = _draw_param(rng, tr["tx"], n_tracks)
+        truth = np.stack([x0, y0, tx, ty], axis=1)
+    else:
+        x0 = _draw_param(rng, tr["x0"], n_tracks)
+        tx = _draw_param(rng, tr["tx"], n_tracks)
+        truth = np.stack([x0, tx], axis=1)
+
+    # one candidate hit per (track, plane); inefficiency drops each independently
+    sd = float(tr["smear_sd"])
+    keep = rng.random((n_tracks, n_planes)) >= float(tr["inefficiency"])
+    hx = x0[:, None] + tx[:, None] * z64[None, :] + rng.normal(0.0, sd, (n_tracks, n_planes))
+    if D == 2:
+        hy = y0[:, None] + ty[:, None] * z64[None, :] + rng.normal(0.0, sd, (n_tracks, n_planes))
+    tid = np.broadcast_to(np.arange(n_tracks, dtype=np.int32)[:, None], (n_tracks, n_planes))
+    pid = np.broadcast_to(np.arange(n_planes, dtype=np.int32)[None, :], (n_tracks, n_planes))
+    tx_hits = hx[keep]
+    ty_hits = hy[keep] if D == 2 else None
+    t_lab = tid[keep]
+    t_pl = pid[keep]
+    truth_nhits = keep.sum(axis=1).astype(np.int32)
+    n_true = int(t_lab.shape[0])
+
+    nz = cfg["noise"]
+    if nz["kind"] == "count":
+        n_noise = int(nz["n"])
+    elif nz["kind"] == "fraction":
+        n_noise = int(round(float(nz["f"]) * n_true))
+    elif nz["kind"] == "fraction_uniform":
+        f = rng.uniform(nz["f_lo"], nz["f_hi"])
+        n_noise = int(round(f * n_true))
+    else:
+        raise ValueError("unknown noise kind %r" % nz["kind"])
+    n_pl = rng.integers(0, n_planes, n_noise).astype(np.int32)
+    n_x = rng.uniform(nz["lo"], nz["hi"], n_noise)
+    n_y = rng.uniform(nz["lo"], nz["hi"], n_noise) if D == 2 else None
+
+    x = np.concatenate([tx_hits, n_x])
+    y = np.concatenate([ty_hits, n_y]) if D == 2 else None
+    plane = np.concatenate([t_pl, n_pl]).astype(np.int32)
+    label = np.concatenate([t_lab, np.full(n_noise, -1, np.int32)]).astype(np.int32)
+    perm = rng.permutation(x.shape[0])
+    return Event(
+        x=x[perm].astype(np.float32),
+        y=None if y is None else y[perm].astype(np.float32),
+        plane=plane[perm], label=label[perm], truth=truth, truth_nhits=truth_nhits)
+
+
+def make_batch(cfg: dict, n_events: Optional[int] = None, start: int = 0) -> Batch:
+    """Events ``start .. start+n_events-1`` of ``cfg`` concatenated in CSR form."""
+    if n_events is None:
+        n_events = int(cfg["n_events"]) - start
+    zp = plane_z(cfg)
+    evs = [make_event(cfg, start + i, zp) for i in range(n_events)]
+    return batch_from_events(int(cfg["meas_dim"]), zp, evs)
+
+
+def batch_from_events(meas_dim: int, zp: np.ndarray, evs: list) -> Batch:
+    off = np.zeros(len(evs) + 1, np.int64)
+    off[1:] = np.cumsum([e.n_hits for e in evs])
+    cat = lambda a: np.concatenate(a) if a else np.zeros(0)
+    return Batch(
+        meas_dim=meas_dim, plane_z=np.asarray(zp, np.float32), event_offsets=off,
+        x=cat([e.x for e in evs]).astype(np.float32),
+        y=None if meas_dim == 1 else cat([e.y for e in evs]).astype(np.float32),
+        plane=cat([e.plane for e in evs]).astype(np.int32),
+        label=cat([e.label for e in evs]).astype(np.int32),
+        truth=[e.truth for e in evs], truth_nhits=[e.truth_nhits for e in evs])
+
+
+def reconstructible(ev: Event, n_min: int = 2) -> np.ndarray:
+    """Mask of true tracks with at least ``n_min`` hits (Section 3: N_min = 2)."""
+    return ev.truth_nhits >= n_min
