@@ -1,0 +1,238 @@
+/*
+ * libretina: the optimisation-based Artificial Retina track finder
+ * (Borisyak, Ustyuzhanin, Derkach, Belous, "Numerical optimization for
+ * Artificial Retina Algorithm", arXiv:1709.08610) on AMD Instinct MI355X
+ * (gfx950).
+ *
+ * Problem statement (Section 2, Algorithm 1): hits in, line parameters out.
+ * The response of a line hypothesis theta to an event's hits X is Eq. (1),
+ *     R(theta) = sum_k exp(-s(x_k, theta)^2 / sigma^2),
+ * with s the Euclidean distance between hit k and the line's intersection
+ * with the hit's detector plane (Section 3).  Track finding locates the local
+ * maxima of R by many independent truncated-Newton ascents from seeds
+ * (Algorithm 1), then clusters the converged solutions and keeps, per
+ * cluster, the highest response above a threshold R0.
+ *
+ * Conventions shared by every entry point
+ *   - C ABI, C99 types only.  Every function returns int: RETINA_OK (0) or a
+ *     negative retina_status; no exception or abort crosses the boundary.
+ *     The message of the last failure is retina_last_error(ctx).
+ *   - Geometry: planes perpendicular to z at plane_z[p] (host memory, FP32,
+ *     any order).  meas_dim 2: a hit is (plane, x, y) and a line is
+ *     theta = (x0, y0, tx, ty) with x(z) = x0 + tx z, y(z) = y0 + ty z.
+ *     meas_dim 1 (the 2D toy of Section 2, Fig. 1): a hit is (plane, u) with
+ *     u stored in x (y unused, may be NULL) and theta = (x0, tx), u(z) = x0 +
+ *     tx z.  n_par = 2*meas_dim.
+ *   - Hits: CSR over events: event e owns hits event_offsets[e] ..
+ *     event_offsets[e+1]-1 in any order.  x, y FP32; plane int32.
+ *   - Memory: retina_hits.mem says where the hit arrays, the event offsets,
+ *     explicit seeds and every output array live (RETINA_MEM_HOST: ordinary
+ *     host memory; RETINA_MEM_DEVICE: device memory of the context's device,
+ *     e.g. torch tensors' data_ptr()).  Device-memory calls are ordered on
+ *     the context's stream and return after that stream has finished them.
+ *   - Ownership: the caller owns every input and output buffer; the library
+ *     keeps no caller pointer after a call returns.  The library owns the
+ *     context (device pool, stream, captured graphs) until retina_destroy.
+ *   - Validation happens before any result is written: NaN/Inf hit
+ *     coordinates or plane positions, plane index outside [0, n_planes),
+ *     decreasing offsets, sigma <= 0 or non-finite, meas_dim not 1 or 2, NULL
+ *     required pointers and negative sizes all give RETINA_ERR_INVALID_ARG
+ *     and leave outputs untouched.  An event without hits is valid (R = 0,
+ *     no tracks).
+ *   - Threading: one context per host thread; a context is not thread-safe.
+ */
+#ifndef RETINA_H
+#define RETINA_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct retina_ctx retina_ctx;
+
+typedef enum {
+    RETINA_OK = 0,
+    RETINA_ERR_INVALID_ARG = -1,
+    RETINA_ERR_OUT_OF_MEMORY = -2,
+    RETINA_ERR_DEVICE = -3,     /* no usable gfx950 device, or a HIP runtime failure */
+    RETINA_ERR_CAPACITY = -4,   /* an output array is too small; see retina_find_tracks */
+    RETINA_ERR_INTERNAL = -6
+} retina_status;
+
+enum { RETINA_MEM_HOST = 0, RETINA_MEM_DEVICE = 1 };
+enum { RETINA_WANT_R = 1, RETINA_WANT_GRAD = 2, RETINA_WANT_HESS = 4 };
+enum { RETINA_SEED_LATTICE = 0, RETINA_SEED_EXPLICIT = 1 };
+
+/* per-seed / per-track flag bits */
+enum {
+    RETINA_CONVERGED = 1,  /* -H positive definite at the last FP64 Newton polish and its
+                              scaled step <= conv_tol * sigma_final */
+    RETINA_STALLED = 2,    /* some line search accepted none of its step lengths */
+    RETINA_NOT_PD = 4,     /* -H not positive definite at the last polish */
+    RETINA_NEGCURV = 8     /* some Newton-CG direction met non-positive curvature */
+};
+
+typedef struct {
+    int32_t meas_dim;       /* 1 or 2 */
+    int32_t n_planes;       /* 1 .. RETINA_MAX_PLANES */
+    const float* plane_z;   /* host memory, n_planes finite values */
+} retina_geometry;
+
+#define RETINA_MAX_PLANES 64
+#define RETINA_MAX_SIGMA 16
+
+typedef struct {
+    int32_t mem;                   /* RETINA_MEM_HOST or RETINA_MEM_DEVICE */
+    int64_t n_events;              /* >= 0 */
+    const int64_t* event_offsets;  /* n_events+1, [0] = 0, non-decreasing */
+    const float* x;
+    const float* y;                /* NULL allowed when meas_dim == 1 */
+    const int32_t* plane;
+} retina_hits;
+
+/* Method parameters of Algorithm 1 as this library reads it.  A trajectory
+ * takes n_sigma continuation steps (sigma[0..n_sigma-1], one truncated-Newton
+ * step each; Section 3 changes the bandwidth with every step) and then
+ * n_final_steps steps at sigma_final, followed by n_polish FP64 Newton
+ * iterations at sigma_final.  The number of updates is fixed (Section 2:
+ * no early exit). */
+typedef struct {
+    int32_t n_sigma;            /* 0 .. RETINA_MAX_SIGMA */
+    const float* sigma;         /* host memory */
+    float sigma_final;
+    int32_t n_final_steps;
+    int32_t n_polish;           /* >= 1 */
+    int32_t ls_trials;          /* backtracking step lengths 1, 1/2, .., 2^-(ls_trials-1); >= 1 */
+    float armijo_c1;            /* sufficient-increase constant */
+    float step_cap_sigmas;      /* scaled step capped at step_cap_sigmas * sigma */
+    float small_step_sigmas;    /* Newton steps (no negative curvature) with scaled length
+                                   <= small_step_sigmas * sigma are taken without a search */
+    int32_t n_slope_steps;      /* meas_dim 2: the first n_slope_steps steps move only (tx, ty) */
+    float conv_tol;             /* converged iff last polish step <= conv_tol * sigma_final */
+    float R0;                   /* keep clusters whose best response is >= R0 */
+    float d_merge;              /* cluster radius: largest in-plane separation over the two
+                                   end planes of the detector */
+    int32_t seed_mode;          /* RETINA_SEED_LATTICE or RETINA_SEED_EXPLICIT */
+    int32_t lattice_n[2];       /* lattice: dims (tx, ty) for meas_dim 2 (x0 = y0 = 0),
+                                   (tx, x0) for meas_dim 1; dim 0 is the slow index */
+    float lattice_lo[2];
+    float lattice_hi[2];        /* cell centres: FP32(lo + (j + 1/2)(hi - lo)/n) formed in FP64 */
+    const double* seeds;        /* EXPLICIT: n_par doubles per seed (rounded to FP32 for the
+                                   ascent), in the hits' memory space */
+    const int64_t* seed_offsets;/* EXPLICIT: n_events+1, in the hits' memory space */
+} retina_params;
+
+/* One reconstructed track (48 bytes). */
+typedef struct {
+    double theta[4];    /* (x0, y0, tx, ty); meas_dim 1: (x0, tx, 0, 0) */
+    float R;            /* response at sigma_final from the last polish evaluation */
+    int32_t n_members;  /* converged seeds in the cluster */
+    int32_t seed_index; /* the leader's seed index within its event */
+    int32_t flags;      /* the leader's RETINA_* flag bits */
+} retina_track;
+
+/* Optional per-seed results (diagnostics and parity checks).  Arrays in the
+ * hits' memory space, indexed by global seed number (events in order). */
+typedef struct {
+    double* theta;      /* n_seeds * n_par, or NULL */
+    float* R;           /* n_seeds, or NULL */
+    int32_t* flags;     /* n_seeds, or NULL */
+    int32_t* n_reval;   /* n_seeds: R-only evaluations spent in line searches, or NULL */
+    int64_t capacity;   /* number of seeds the arrays hold */
+} retina_seed_out;
+
+/* Create a context on HIP device `device_ordinal` (must be gfx950).  Creates
+ * a library-owned stream of default priority.  RETINA_ERR_DEVICE when no such
+ * device exists; *out is NULL then. */
+int retina_create(int device_ordinal, retina_ctx** out);
+
+/* Release the context and everything it owns.  NULL-safe. */
+void retina_destroy(retina_ctx* ctx);
+
+/* Message of the last failure on ctx (static text when ctx is NULL).  Valid
+ * until the next call on ctx. */
+const char* retina_last_error(const retina_ctx* ctx);
+
+/* Order the context's device work on `hip_stream` (a hipStream_t of the
+ * context's device, e.g. torch.cuda.current_stream().cuda_stream); NULL
+ * restores the library's own stream. */
+int retina_set_stream(retina_ctx* ctx, void* hip_stream);
+
+/* Upper bound (bytes) on the device pool; 0 = unlimited.  Calls whose
+ * working set would exceed it return RETINA_ERR_OUT_OF_MEMORY. */
+int retina_set_max_device_bytes(retina_ctx* ctx, int64_t max_bytes);
+
+/* Kernel timing with HIP events recorded on the context's stream around each
+ * launch of retina_find_tracks / retina_response while enabled.  Times
+ * accumulate (milliseconds) until retina_profile_reset. */
+typedef struct {
+    int64_t calls;        /* profiled calls since the last reset */
+    double ms_stage;      /* hit validation + per-plane sort */
+    double ms_plan;       /* work list */
+    double ms_hot;        /* ascent (find_tracks) or response kernel */
+    double ms_merge;      /* clustering + selection + output */
+    double ms_total;      /* first kernel start to last kernel end */
+} retina_profile;
+
+int retina_set_profiling(retina_ctx* ctx, int32_t enable);
+int retina_get_profile(const retina_ctx* ctx, retina_profile* out);
+int retina_profile_reset(retina_ctx* ctx);
+
+/* Launch shape of the hot kernels (the autotuner's knobs).
+ *   kernel     0: the ascent kernel of retina_find_tracks; 1: retina_response
+ *   cand       candidate lines per lane: 1 or 2
+ *   tile_hits  hits held in LDS per work-group (events with more hits are
+ *              streamed through it tile by tile): 256 .. 16384 for
+ *              meas_dim 2, 256 .. 32768 for meas_dim 1
+ * Results differ between shapes only by FP32 summation order.  The
+ * persistent grid is sized from the resulting occupancy. */
+int retina_set_tuning(retina_ctx* ctx, int32_t meas_dim, int32_t kernel, int32_t cand,
+                      int32_t tile_hits);
+
+/* Current shape: *cand, *tile_hits and the persistent grid size *grid. */
+int retina_get_tuning(const retina_ctx* ctx, int32_t meas_dim, int32_t kernel, int32_t* cand,
+                      int32_t* tile_hits, int32_t* grid);
+
+/* Eq. (1) and its derivatives at caller-given line parameters.
+ *   theta        n_theta * n_par FP32 values, in the hits' memory space
+ *   n_theta      number of parameter vectors (>= 0)
+ *   theta_offsets n_events+1 offsets into theta (non-decreasing, [0] = 0,
+ *                last = n_theta), hits' memory space; NULL allowed when
+ *                n_events == 1 (all n_theta belong to event 0)
+ *   sigma        bandwidth (> 0)
+ *   want         RETINA_WANT_R is implied; | RETINA_WANT_GRAD | RETINA_WANT_HESS
+ *   R            n_theta floats
+ *   grad         n_theta * n_par floats (NULL unless WANT_GRAD):
+ *                dR/dtheta in theta's component order
+ *   hess         n_theta * n_par(n_par+1)/2 floats (NULL unless WANT_HESS):
+ *                upper triangle row-major (00,01,..,11,12,..)
+ * FP32 arithmetic; residuals formed with one fused multiply-add so that no
+ * large intermediate is rounded. */
+int retina_response(retina_ctx* ctx, const retina_geometry* geom, const retina_hits* hits,
+                    const float* theta, int64_t n_theta, const int64_t* theta_offsets,
+                    float sigma, uint32_t want, float* R, float* grad, float* hess);
+
+/* Algorithm 1 on every event of the batch in one device pass: seeds (lattice
+ * or explicit), truncated-Newton ascents with sigma continuation, FP64 Newton
+ * polish, clustering and selection.
+ *   tracks         capacity retina_track slots; event e's tracks are
+ *                  tracks[track_offsets[e] .. track_offsets[e+1]-1], in the
+ *                  order their clusters were founded (decreasing R)
+ *   track_offsets  n_events+1
+ *   event_flags    n_events (or NULL): bit 1 (RETINA_STALLED) if any seed of
+ *                  the event stalled
+ *   seeds_out      optional per-seed results (NULL to skip)
+ * RETINA_ERR_CAPACITY: the tracks do not fit; then only
+ * track_offsets[n_events] is written, with the required total. */
+int retina_find_tracks(retina_ctx* ctx, const retina_geometry* geom, const retina_hits* hits,
+                       const retina_params* params, retina_track* tracks, int64_t capacity,
+                       int64_t* track_offsets, int32_t* event_flags,
+                       const retina_seed_out* seeds_out);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* RETINA_H */

@@ -1,0 +1,723 @@
+// libretina host side: context, device pool, argument validation, launch
+// sequence and the C-ABI entry points declared in include/retina.h.
+#include <math.h>
+#include <stdarg.h>
+#include <stdio.h>
+#include <string.h>
+
+#include <algorithm>
+#include <string>
+#include <vector>
+
+#include "rt_internal.h"
+
+using namespace rt;
+
+namespace {
+
+struct Buf {
+    void* p = nullptr;
+    size_t cap = 0;
+};
+
+enum BufId {
+    B_HITS, B_POFF, B_NHITS, B_SOFF, B_ORDER, B_ITEMS, B_STH, B_SR, B_SFL, B_SNR, B_MLEAD, B_MMEM,
+    B_MKEYS, B_EVNT, B_EVFL, B_EVTOFF,
+    // staging copies for host-memory calls
+    B_INX, B_INY, B_INPL, B_INOFF, B_INSEEDS, B_INSOFF, B_INTH, B_INTHOFF, B_OUTTR, B_OUTTOFF,
+    B_OUTEVF, B_OUTSTH, B_OUTSR, B_OUTSFL, B_OUTSNR, B_OUTR, B_OUTG, B_OUTH,
+    B_COUNT
+};
+
+}  // namespace
+
+struct retina_ctx {
+    int device = 0;
+    hipStream_t own = nullptr;
+    hipStream_t stream = nullptr;
+    int n_cu = 0;
+    std::string err;
+    int64_t max_bytes = 0;
+    Buf buf[B_COUNT];
+    Desc* d_desc = nullptr;
+    Desc* h_desc = nullptr;       // pinned
+    Counters* d_cnt = nullptr;
+    Counters* h_cnt = nullptr;    // pinned
+    HotConfig ascent_cfg[3];      // by meas_dim
+    HotConfig resp_cfg[3];
+    bool prof = false;
+    hipEvent_t ev[5] = {};
+    retina_profile prof_acc = {};
+};
+
+namespace {
+
+const char* kNoCtx = "retina: NULL context";
+
+int fail(retina_ctx* c, int code, const char* fmt, ...) __attribute__((format(printf, 3, 4)));
+int fail(retina_ctx* c, int code, const char* fmt, ...)
+{
+    char msg[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(msg, sizeof(msg), fmt, ap);
+    va_end(ap);
+    if (c) c->err = msg;
+    return code;
+}
+
+#define HIP_TRY(c, expr)                                                                     \
+    do {                                                                                     \
+        hipError_t _e = (expr);                                                              \
+        if (_e != hipSuccess)                                                                \
+            return fail((c), RETINA_ERR_DEVICE, "HIP error %s at %s:%d", hipGetErrorString(_e), \
+                        __FILE__, __LINE__);                                                 \
+    } while (0)
+
+struct DeviceGuard {
+    int prev = -1;
+    explicit DeviceGuard(int dev)
+    {
+        if (hipGetDevice(&prev) != hipSuccess) prev = -1;
+        if (prev != dev) (void)hipSetDevice(dev);
+    }
+    ~DeviceGuard()
+    {
+        int cur = -1;
+        if (prev >= 0 && hipGetDevice(&cur) == hipSuccess && cur != prev) (void)hipSetDevice(prev);
+    }
+};
+
+size_t pool_bytes(const retina_ctx* c)
+{
+    size_t s = 0;
+    for (int i = 0; i < B_COUNT; ++i) s += c->buf[i].cap;
+    return s;
+}
+
+// grow-only buffer; contents are not preserved
+int ensure(retina_ctx* c, int id, size_t bytes, void** out)
+{
+    Buf& b = c->buf[id];
+    if (bytes == 0) bytes = 16;
+    if (b.cap < bytes) {
+        size_t want = std::max(bytes, b.cap + b.cap / 2);
+        if (c->max_bytes > 0 && pool_bytes(c) - b.cap + want > (size_t)c->max_bytes) {
+            want = bytes;
+            if (pool_bytes(c) - b.cap + want > (size_t)c->max_bytes)
+                return fail(c, RETINA_ERR_OUT_OF_MEMORY,
+                            "device pool limit %lld bytes exceeded (need %zu more)",
+                            (long long)c->max_bytes, want);
+        }
+        if (b.p) (void)hipFree(b.p);
+        b.p = nullptr;
+        b.cap = 0;
+        if (hipMalloc(&b.p, want) != hipSuccess) {
+            (void)hipGetLastError();
+            return fail(c, RETINA_ERR_OUT_OF_MEMORY, "hipMalloc of %zu bytes failed", want);
+        }
+        b.cap = want;
+    }
+    *out = b.p;
+    return RETINA_OK;
+}
+
+template <typename T>
+int ensure_t(retina_ctx* c, int id, size_t count, T** out)
+{
+    void* p;
+    int rc = ensure(c, id, count * sizeof(T), &p);
+    *out = (T*)p;
+    return rc;
+}
+
+int check_geometry(retina_ctx* c, const retina_geometry* g)
+{
+    if (!g) return fail(c, RETINA_ERR_INVALID_ARG, "geometry is NULL");
+    if (g->meas_dim != 1 && g->meas_dim != 2)
+        return fail(c, RETINA_ERR_INVALID_ARG, "meas_dim must be 1 or 2 (got %d)", g->meas_dim);
+    if (g->n_planes < 1 || g->n_planes > kMaxPlanes)
+        return fail(c, RETINA_ERR_INVALID_ARG, "n_planes must be in [1, %d] (got %d)", kMaxPlanes,
+                    g->n_planes);
+    if (!g->plane_z) return fail(c, RETINA_ERR_INVALID_ARG, "plane_z is NULL");
+    for (int p = 0; p < g->n_planes; ++p)
+        if (!isfinite(g->plane_z[p]))
+            return fail(c, RETINA_ERR_INVALID_ARG, "plane_z[%d] is not finite", p);
+    return RETINA_OK;
+}
+
+int check_hits(retina_ctx* c, const retina_geometry* g, const retina_hits* h)
+{
+    if (!h) return fail(c, RETINA_ERR_INVALID_ARG, "hits is NULL");
+    if (h->mem != RETINA_MEM_HOST && h->mem != RETINA_MEM_DEVICE)
+        return fail(c, RETINA_ERR_INVALID_ARG, "hits.mem must be RETINA_MEM_HOST or RETINA_MEM_DEVICE");
+    if (h->n_events < 0) return fail(c, RETINA_ERR_INVALID_ARG, "n_events < 0");
+    if (h->n_events > 0x7FFFFFFF) return fail(c, RETINA_ERR_INVALID_ARG, "n_events too large");
+    if (!h->event_offsets) return fail(c, RETINA_ERR_INVALID_ARG, "event_offsets is NULL");
+    if (h->n_events > 0 && (!h->x || !h->plane))
+        return fail(c, RETINA_ERR_INVALID_ARG, "hit arrays x / plane are NULL");
+    if (h->n_events > 0 && g->meas_dim == 2 && !h->y)
+        return fail(c, RETINA_ERR_INVALID_ARG, "hit array y is NULL with meas_dim 2");
+    return RETINA_OK;
+}
+
+// read one int64 of a caller array in either memory space
+int read_i64(retina_ctx* c, int mem, const int64_t* p, int64_t idx, int64_t* out)
+{
+    if (mem == RETINA_MEM_HOST) {
+        *out = p[idx];
+        return RETINA_OK;
+    }
+    HIP_TRY(c, hipMemcpyAsync(out, p + idx, sizeof(int64_t), hipMemcpyDeviceToHost, c->stream));
+    HIP_TRY(c, hipStreamSynchronize(c->stream));
+    return RETINA_OK;
+}
+
+int host_offsets_ok(const int64_t* off, int64_t n)
+{
+    if (off[0] != 0) return 0;
+    for (int64_t i = 0; i < n; ++i)
+        if (off[i + 1] < off[i]) return 0;
+    return 1;
+}
+
+void fill_geometry(Desc& d, const retina_geometry* g)
+{
+    d.meas_dim = g->meas_dim;
+    d.n_planes = g->n_planes;
+    double s2 = 0.0, zmin = g->plane_z[0], zmax = g->plane_z[0];
+    for (int p = 0; p < kMaxPlanes; ++p) d.plane_z[p] = p < g->n_planes ? g->plane_z[p] : 0.0f;
+    for (int p = 0; p < g->n_planes; ++p) {
+        const double z = g->plane_z[p];
+        s2 += z * z;
+        zmin = std::min(zmin, z);
+        zmax = std::max(zmax, z);
+    }
+    d.z_first = (float)zmin;
+    d.z_last = (float)zmax;
+    d.z_ref = (float)sqrt(s2 / g->n_planes);
+}
+
+// stage caller hits (copying host arrays into the pool when needed)
+int stage_inputs(retina_ctx* c, Desc& d, const retina_geometry* g, const retina_hits* h, int64_t n_hits)
+{
+    d.n_events = h->n_events;
+    d.n_hits = n_hits;
+    const int D = g->meas_dim;
+    if (h->mem == RETINA_MEM_DEVICE) {
+        d.in_off = h->event_offsets;
+        d.in_x = h->x;
+        d.in_y = D == 2 ? h->y : nullptr;
+        d.in_plane = h->plane;
+    } else {
+        int64_t* off;
+        float *x, *y = nullptr;
+        int32_t* pl;
+        int rc;
+        if ((rc = ensure_t(c, B_INOFF, h->n_events + 1, &off))) return rc;
+        if ((rc = ensure_t(c, B_INX, n_hits, &x))) return rc;
+        if (D == 2 && (rc = ensure_t(c, B_INY, n_hits, &y))) return rc;
+        if ((rc = ensure_t(c, B_INPL, n_hits, &pl))) return rc;
+        HIP_TRY(c, hipMemcpyAsync(off, h->event_offsets, sizeof(int64_t) * (h->n_events + 1),
+                                  hipMemcpyHostToDevice, c->stream));
+        if (n_hits) {
+            HIP_TRY(c, hipMemcpyAsync(x, h->x, sizeof(float) * n_hits, hipMemcpyHostToDevice, c->stream));
+            if (D == 2)
+                HIP_TRY(c, hipMemcpyAsync(y, h->y, sizeof(float) * n_hits, hipMemcpyHostToDevice, c->stream));
+            HIP_TRY(c, hipMemcpyAsync(pl, h->plane, sizeof(int32_t) * n_hits, hipMemcpyHostToDevice, c->stream));
+        }
+        d.in_off = off;
+        d.in_x = x;
+        d.in_y = y;
+        d.in_plane = pl;
+    }
+    int rc;
+    const int64_t E = h->n_events;
+    if ((rc = ensure_t(c, B_HITS, (size_t)std::max<int64_t>(n_hits, 1) * D, &d.hits))) return rc;
+    if ((rc = ensure_t(c, B_POFF, (size_t)E * (g->n_planes + 1) + 1, &d.plane_off))) return rc;
+    if ((rc = ensure_t(c, B_NHITS, (size_t)E + 1, &d.ev_nhits))) return rc;
+    if ((rc = ensure_t(c, B_SOFF, (size_t)E + 1, &d.seed_off))) return rc;
+    if ((rc = ensure_t(c, B_ORDER, (size_t)E + 1, &d.order))) return rc;
+    return RETINA_OK;
+}
+
+int device_error(retina_ctx* c, uint32_t err)
+{
+    if (err & kErrOffsets) return fail(c, RETINA_ERR_INVALID_ARG, "event_offsets must start at 0 and be non-decreasing");
+    if (err & kErrCoord) return fail(c, RETINA_ERR_INVALID_ARG, "a hit coordinate is NaN or infinite");
+    if (err & kErrPlane) return fail(c, RETINA_ERR_INVALID_ARG, "a hit plane index is outside [0, n_planes)");
+    if (err & kErrSeedOff) return fail(c, RETINA_ERR_INVALID_ARG, "seed_offsets must start at 0 and be non-decreasing");
+    if (err & kErrSeedVal) return fail(c, RETINA_ERR_INVALID_ARG, "an explicit seed is NaN or infinite");
+    if (err & kErrThetaOff) return fail(c, RETINA_ERR_INVALID_ARG, "theta_offsets must start at 0 and be non-decreasing");
+    return fail(c, RETINA_ERR_INTERNAL, "device error bits 0x%x", err);
+}
+
+HotConfig default_hot(const retina_ctx* c, int D, bool ascent)
+{
+    HotConfig h;
+    h.cand = ascent ? 2 : 1;
+    h.tile_hits = D == 2 ? 6144 : 8192;
+    h.grid = c->n_cu * hot_max_blocks_per_cu(D, h, ascent);
+    return h;
+}
+
+// event i of the profiled launch sequence (no-op unless profiling)
+void prof_mark(retina_ctx* c, int i)
+{
+    if (c->prof) (void)hipEventRecord(c->ev[i], c->stream);
+}
+
+// after the stream has drained: accumulate the kernel times
+void prof_collect(retina_ctx* c)
+{
+    if (!c->prof) return;
+    float t[4];
+    for (int i = 0; i < 4; ++i)
+        if (hipEventElapsedTime(&t[i], c->ev[i], c->ev[i + 1]) != hipSuccess) t[i] = 0.0f;
+    float tot = 0.0f;
+    if (hipEventElapsedTime(&tot, c->ev[0], c->ev[4]) != hipSuccess) tot = 0.0f;
+    c->prof_acc.calls += 1;
+    c->prof_acc.ms_stage += t[0];
+    c->prof_acc.ms_plan += t[1];
+    c->prof_acc.ms_hot += t[2];
+    c->prof_acc.ms_merge += t[3];
+    c->prof_acc.ms_total += tot;
+}
+
+int upload_desc(retina_ctx* c)
+{
+    HIP_TRY(c, hipMemcpyAsync(c->d_desc, c->h_desc, sizeof(Desc), hipMemcpyHostToDevice, c->stream));
+    return RETINA_OK;
+}
+
+int download_counters(retina_ctx* c)
+{
+    HIP_TRY(c, hipMemcpyAsync(c->h_cnt, c->d_cnt, sizeof(Counters), hipMemcpyDeviceToHost, c->stream));
+    HIP_TRY(c, hipStreamSynchronize(c->stream));
+    return RETINA_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int retina_create(int device_ordinal, retina_ctx** out)
+{
+    if (!out) return RETINA_ERR_INVALID_ARG;
+    *out = nullptr;
+    int n = 0;
+    if (hipGetDeviceCount(&n) != hipSuccess || n <= 0) {
+        (void)hipGetLastError();
+        return RETINA_ERR_DEVICE;
+    }
+    if (device_ordinal < 0 || device_ordinal >= n) return RETINA_ERR_DEVICE;
+    hipDeviceProp_t prop;
+    if (hipGetDeviceProperties(&prop, device_ordinal) != hipSuccess) return RETINA_ERR_DEVICE;
+    if (strncmp(prop.gcnArchName, "gfx950", 6) != 0) return RETINA_ERR_DEVICE;
+    DeviceGuard guard(device_ordinal);
+    retina_ctx* c = new retina_ctx();
+    c->device = device_ordinal;
+    c->n_cu = prop.multiProcessorCount;
+    if (hipStreamCreateWithFlags(&c->own, hipStreamNonBlocking) != hipSuccess ||
+        hipMalloc(&c->d_desc, sizeof(Desc)) != hipSuccess ||
+        hipHostMalloc(&c->h_desc, sizeof(Desc), hipHostMallocDefault) != hipSuccess ||
+        hipMalloc(&c->d_cnt, sizeof(Counters)) != hipSuccess ||
+        hipHostMalloc(&c->h_cnt, sizeof(Counters), hipHostMallocDefault) != hipSuccess) {
+        retina_destroy(c);
+        return RETINA_ERR_DEVICE;
+    }
+    c->stream = c->own;
+    for (int D = 1; D <= 2; ++D) {
+        c->ascent_cfg[D] = default_hot(c, D, true);
+        c->resp_cfg[D] = default_hot(c, D, false);
+    }
+    *out = c;
+    return RETINA_OK;
+}
+
+void retina_destroy(retina_ctx* c)
+{
+    if (!c) return;
+    DeviceGuard guard(c->device);
+    if (c->stream) (void)hipStreamSynchronize(c->stream);
+    for (int i = 0; i < B_COUNT; ++i)
+        if (c->buf[i].p) (void)hipFree(c->buf[i].p);
+    if (c->d_desc) (void)hipFree(c->d_desc);
+    if (c->h_desc) (void)hipHostFree(c->h_desc);
+    if (c->d_cnt) (void)hipFree(c->d_cnt);
+    if (c->h_cnt) (void)hipHostFree(c->h_cnt);
+    for (int i = 0; i < 5; ++i)
+        if (c->ev[i]) (void)hipEventDestroy(c->ev[i]);
+    if (c->own) (void)hipStreamDestroy(c->own);
+    delete c;
+}
+
+const char* retina_last_error(const retina_ctx* c)
+{
+    if (!c) return kNoCtx;
+    return c->err.c_str();
+}
+
+int retina_set_stream(retina_ctx* c, void* s)
+{
+    if (!c) return RETINA_ERR_INVALID_ARG;
+    c->stream = s ? (hipStream_t)s : c->own;
+    return RETINA_OK;
+}
+
+int retina_set_max_device_bytes(retina_ctx* c, int64_t max_bytes)
+{
+    if (!c) return RETINA_ERR_INVALID_ARG;
+    if (max_bytes < 0) return fail(c, RETINA_ERR_INVALID_ARG, "max_bytes < 0");
+    c->max_bytes = max_bytes;
+    return RETINA_OK;
+}
+
+int retina_set_profiling(retina_ctx* c, int32_t enable)
+{
+    if (!c) return RETINA_ERR_INVALID_ARG;
+    DeviceGuard guard(c->device);
+    if (enable && !c->ev[0]) {
+        for (int i = 0; i < 5; ++i)
+            HIP_TRY(c, hipEventCreate(&c->ev[i]));
+    }
+    c->prof = enable != 0;
+    return RETINA_OK;
+}
+
+int retina_get_profile(const retina_ctx* c, retina_profile* out)
+{
+    if (!c || !out) return RETINA_ERR_INVALID_ARG;
+    *out = c->prof_acc;
+    return RETINA_OK;
+}
+
+int retina_profile_reset(retina_ctx* c)
+{
+    if (!c) return RETINA_ERR_INVALID_ARG;
+    c->prof_acc = retina_profile{};
+    return RETINA_OK;
+}
+
+int retina_set_tuning(retina_ctx* c, int32_t meas_dim, int32_t kernel, int32_t cand, int32_t tile_hits)
+{
+    if (!c) return RETINA_ERR_INVALID_ARG;
+    c->err.clear();
+    if (meas_dim != 1 && meas_dim != 2) return fail(c, RETINA_ERR_INVALID_ARG, "meas_dim must be 1 or 2");
+    if (kernel != 0 && kernel != 1) return fail(c, RETINA_ERR_INVALID_ARG, "kernel must be 0 or 1");
+    if (cand != 1 && cand != 2) return fail(c, RETINA_ERR_INVALID_ARG, "cand must be 1 or 2");
+    const int max_tile = meas_dim == 2 ? 16384 : 32768;
+    if (tile_hits < 256 || tile_hits > max_tile)
+        return fail(c, RETINA_ERR_INVALID_ARG, "tile_hits must be in [256, %d]", max_tile);
+    DeviceGuard guard(c->device);
+    HotConfig h;
+    h.cand = cand;
+    h.tile_hits = tile_hits;
+    const int per_cu = hot_max_blocks_per_cu(meas_dim, h, kernel == 0);
+    h.grid = c->n_cu * per_cu;
+    (kernel == 0 ? c->ascent_cfg : c->resp_cfg)[meas_dim] = h;
+    return RETINA_OK;
+}
+
+int retina_get_tuning(const retina_ctx* c, int32_t meas_dim, int32_t kernel, int32_t* cand,
+                      int32_t* tile_hits, int32_t* grid)
+{
+    if (!c || (meas_dim != 1 && meas_dim != 2) || (kernel != 0 && kernel != 1)) return RETINA_ERR_INVALID_ARG;
+    const HotConfig& h = (kernel == 0 ? c->ascent_cfg : c->resp_cfg)[meas_dim];
+    if (cand) *cand = h.cand;
+    if (tile_hits) *tile_hits = h.tile_hits;
+    if (grid) *grid = h.grid;
+    return RETINA_OK;
+}
+
+int retina_response(retina_ctx* c, const retina_geometry* g, const retina_hits* h, const float* theta,
+                    int64_t n_theta, const int64_t* theta_offsets, float sigma, uint32_t want, float* R,
+                    float* grad, float* hess)
+{
+    if (!c) return RETINA_ERR_INVALID_ARG;
+    c->err.clear();
+    int rc;
+    if ((rc = check_geometry(c, g)) || (rc = check_hits(c, g, h))) return rc;
+    if (!(sigma > 0.0f) || !isfinite(sigma)) return fail(c, RETINA_ERR_INVALID_ARG, "sigma must be finite and > 0");
+    if (n_theta < 0) return fail(c, RETINA_ERR_INVALID_ARG, "n_theta < 0");
+    if (want & ~(uint32_t)(RETINA_WANT_R | RETINA_WANT_GRAD | RETINA_WANT_HESS))
+        return fail(c, RETINA_ERR_INVALID_ARG, "unknown want bits 0x%x", want);
+    if (!theta_offsets && h->n_events != 1)
+        return fail(c, RETINA_ERR_INVALID_ARG, "theta_offsets may be NULL only with one event");
+    if (n_theta > 0 && (!theta || !R)) return fail(c, RETINA_ERR_INVALID_ARG, "theta / R is NULL");
+    if (n_theta > 0 && (want & RETINA_WANT_GRAD) && !grad) return fail(c, RETINA_ERR_INVALID_ARG, "grad is NULL");
+    if (n_theta > 0 && (want & RETINA_WANT_HESS) && !hess) return fail(c, RETINA_ERR_INVALID_ARG, "hess is NULL");
+    if (h->n_events == 0 || n_theta == 0) return RETINA_OK;
+    DeviceGuard guard(c->device);
+    const int D = g->meas_dim, NP = 2 * D, NH = NP * (NP + 1) / 2;
+    const int64_t E = h->n_events;
+    const bool host = h->mem == RETINA_MEM_HOST;
+    if (host && !host_offsets_ok(h->event_offsets, E))
+        return fail(c, RETINA_ERR_INVALID_ARG, "event_offsets must start at 0 and be non-decreasing");
+    if (host && theta_offsets && !host_offsets_ok(theta_offsets, E))
+        return fail(c, RETINA_ERR_INVALID_ARG, "theta_offsets must start at 0 and be non-decreasing");
+    int64_t n_hits, th_last = n_theta;
+    if ((rc = read_i64(c, h->mem, h->event_offsets, E, &n_hits))) return rc;
+    if (theta_offsets && (rc = read_i64(c, h->mem, theta_offsets, E, &th_last))) return rc;
+    if (th_last != n_theta) return fail(c, RETINA_ERR_INVALID_ARG, "theta_offsets[n_events] != n_theta");
+    if (n_hits < 0 || n_hits > 0x7FFFFFFF) return fail(c, RETINA_ERR_INVALID_ARG, "bad total hit count");
+
+    Desc& d = *c->h_desc;
+    memset(&d, 0, sizeof(Desc));
+    fill_geometry(d, g);
+    d.cnt = c->d_cnt;
+    if ((rc = stage_inputs(c, d, g, h, n_hits))) return rc;
+    const HotConfig hc = c->resp_cfg[D];
+    d.seeds_per_item = hot_seeds_per_item(hc);
+    d.items_cap = n_theta / d.seeds_per_item + E + 1;
+    if ((rc = ensure_t(c, B_ITEMS, (size_t)d.items_cap, &d.items))) return rc;
+    d.want = want | RETINA_WANT_R;
+    d.resp_sigma = sigma;
+    // inputs
+    if (host) {
+        float* th;
+        int64_t* to;
+        if ((rc = ensure_t(c, B_INTH, (size_t)n_theta * NP, &th))) return rc;
+        if ((rc = ensure_t(c, B_INTHOFF, (size_t)E + 1, &to))) return rc;
+        HIP_TRY(c, hipMemcpyAsync(th, theta, sizeof(float) * n_theta * NP, hipMemcpyHostToDevice, c->stream));
+        if (theta_offsets) {
+            HIP_TRY(c, hipMemcpyAsync(to, theta_offsets, sizeof(int64_t) * (E + 1), hipMemcpyHostToDevice, c->stream));
+        } else {
+            const int64_t tmp[2] = {0, n_theta};
+            HIP_TRY(c, hipMemcpyAsync(to, tmp, sizeof(tmp), hipMemcpyHostToDevice, c->stream));
+            HIP_TRY(c, hipStreamSynchronize(c->stream));
+        }
+        d.in_theta = th;
+        d.in_theta_off = to;
+        if ((rc = ensure_t(c, B_OUTR, (size_t)n_theta, &d.out_R))) return rc;
+        if ((want & RETINA_WANT_GRAD) && (rc = ensure_t(c, B_OUTG, (size_t)n_theta * NP, &d.out_grad))) return rc;
+        if ((want & RETINA_WANT_HESS) && (rc = ensure_t(c, B_OUTH, (size_t)n_theta * NH, &d.out_hess))) return rc;
+    } else {
+        d.in_theta = theta;
+        if (theta_offsets) {
+            d.in_theta_off = theta_offsets;
+        } else {
+            int64_t* to;
+            if ((rc = ensure_t(c, B_INTHOFF, 2, &to))) return rc;
+            const int64_t tmp[2] = {0, n_theta};
+            HIP_TRY(c, hipMemcpyAsync(to, tmp, sizeof(tmp), hipMemcpyHostToDevice, c->stream));
+            HIP_TRY(c, hipStreamSynchronize(c->stream));
+            d.in_theta_off = to;
+        }
+        d.out_R = R;
+        d.out_grad = grad;
+        d.out_hess = hess;
+    }
+    if ((rc = upload_desc(c))) return rc;
+    prof_mark(c, 0);
+    launch_reset(c->d_desc, c->stream);
+    launch_stage(c->d_desc, (int)std::min<int64_t>((E + 3) / 4, (int64_t)c->n_cu * 8), c->stream);
+    prof_mark(c, 1);
+    launch_plan_response(c->d_desc, c->stream);
+    prof_mark(c, 2);
+    launch_response(c->d_desc, D, hc, (want & (RETINA_WANT_GRAD | RETINA_WANT_HESS)) != 0, c->stream);
+    prof_mark(c, 3);
+    prof_mark(c, 4);
+    HIP_TRY(c, hipGetLastError());
+    if ((rc = download_counters(c))) return rc;
+    prof_collect(c);
+    if (c->h_cnt->err) return device_error(c, c->h_cnt->err);
+    if (host) {
+        HIP_TRY(c, hipMemcpyAsync(R, d.out_R, sizeof(float) * n_theta, hipMemcpyDeviceToHost, c->stream));
+        if (want & RETINA_WANT_GRAD)
+            HIP_TRY(c, hipMemcpyAsync(grad, d.out_grad, sizeof(float) * n_theta * NP, hipMemcpyDeviceToHost, c->stream));
+        if (want & RETINA_WANT_HESS)
+            HIP_TRY(c, hipMemcpyAsync(hess, d.out_hess, sizeof(float) * n_theta * NH, hipMemcpyDeviceToHost, c->stream));
+        HIP_TRY(c, hipStreamSynchronize(c->stream));
+    }
+    return RETINA_OK;
+}
+
+int retina_find_tracks(retina_ctx* c, const retina_geometry* g, const retina_hits* h,
+                       const retina_params* P, retina_track* tracks, int64_t capacity,
+                       int64_t* track_offsets, int32_t* event_flags, const retina_seed_out* so)
+{
+    if (!c) return RETINA_ERR_INVALID_ARG;
+    c->err.clear();
+    int rc;
+    if ((rc = check_geometry(c, g)) || (rc = check_hits(c, g, h))) return rc;
+    if (!P) return fail(c, RETINA_ERR_INVALID_ARG, "params is NULL");
+    if (P->n_sigma < 0 || P->n_sigma > kMaxSigma)
+        return fail(c, RETINA_ERR_INVALID_ARG, "n_sigma must be in [0, %d]", kMaxSigma);
+    if (P->n_sigma > 0 && !P->sigma) return fail(c, RETINA_ERR_INVALID_ARG, "sigma is NULL");
+    for (int i = 0; i < P->n_sigma; ++i)
+        if (!(P->sigma[i] > 0.0f) || !isfinite(P->sigma[i]))
+            return fail(c, RETINA_ERR_INVALID_ARG, "sigma[%d] must be finite and > 0", i);
+    if (!(P->sigma_final > 0.0f) || !isfinite(P->sigma_final))
+        return fail(c, RETINA_ERR_INVALID_ARG, "sigma_final must be finite and > 0");
+    if (P->n_final_steps < 0 || P->n_polish < 1 || P->ls_trials < 1 || P->n_slope_steps < 0)
+        return fail(c, RETINA_ERR_INVALID_ARG, "step counts: n_final_steps >= 0, n_polish >= 1, ls_trials >= 1");
+    if (P->n_sigma + P->n_final_steps > 64 || P->n_polish > 16 || P->ls_trials > 16)
+        return fail(c, RETINA_ERR_INVALID_ARG, "step counts too large");
+    const float fp[] = {P->armijo_c1, P->step_cap_sigmas, P->small_step_sigmas, P->conv_tol, P->R0, P->d_merge};
+    for (float v : fp)
+        if (!isfinite(v)) return fail(c, RETINA_ERR_INVALID_ARG, "method constants must be finite");
+    if (!(P->step_cap_sigmas > 0.0f) || !(P->d_merge >= 0.0f) || !(P->conv_tol > 0.0f))
+        return fail(c, RETINA_ERR_INVALID_ARG, "step_cap_sigmas, conv_tol must be > 0 and d_merge >= 0");
+    if (P->seed_mode != RETINA_SEED_LATTICE && P->seed_mode != RETINA_SEED_EXPLICIT)
+        return fail(c, RETINA_ERR_INVALID_ARG, "unknown seed_mode %d", P->seed_mode);
+    if (P->seed_mode == RETINA_SEED_LATTICE) {
+        if (P->lattice_n[0] < 1 || P->lattice_n[1] < 1 || (int64_t)P->lattice_n[0] * P->lattice_n[1] > (1 << 24))
+            return fail(c, RETINA_ERR_INVALID_ARG, "lattice_n must be >= 1 with at most 2^24 seeds");
+        for (int i = 0; i < 2; ++i)
+            if (!isfinite(P->lattice_lo[i]) || !isfinite(P->lattice_hi[i]))
+                return fail(c, RETINA_ERR_INVALID_ARG, "lattice box must be finite");
+    } else if (!P->seeds || !P->seed_offsets) {
+        return fail(c, RETINA_ERR_INVALID_ARG, "explicit seeds / seed_offsets are NULL");
+    }
+    if (capacity < 0) return fail(c, RETINA_ERR_INVALID_ARG, "capacity < 0");
+    if (!track_offsets) return fail(c, RETINA_ERR_INVALID_ARG, "track_offsets is NULL");
+    if (capacity > 0 && !tracks) return fail(c, RETINA_ERR_INVALID_ARG, "tracks is NULL");
+    DeviceGuard guard(c->device);
+    const int D = g->meas_dim, NP = 2 * D;
+    const int64_t E = h->n_events;
+    const bool host = h->mem == RETINA_MEM_HOST;
+    if (host && !host_offsets_ok(h->event_offsets, E))
+        return fail(c, RETINA_ERR_INVALID_ARG, "event_offsets must start at 0 and be non-decreasing");
+    if (host && P->seed_mode == RETINA_SEED_EXPLICIT && !host_offsets_ok(P->seed_offsets, E))
+        return fail(c, RETINA_ERR_INVALID_ARG, "seed_offsets must start at 0 and be non-decreasing");
+    if (E == 0) {
+        if (host) track_offsets[0] = 0;
+        else HIP_TRY(c, hipMemsetAsync(track_offsets, 0, sizeof(int64_t), c->stream));
+        HIP_TRY(c, hipStreamSynchronize(c->stream));
+        return RETINA_OK;
+    }
+    int64_t n_hits, n_seeds;
+    if ((rc = read_i64(c, h->mem, h->event_offsets, E, &n_hits))) return rc;
+    if (n_hits < 0 || n_hits > 0x7FFFFFFF) return fail(c, RETINA_ERR_INVALID_ARG, "bad total hit count");
+    if (P->seed_mode == RETINA_SEED_EXPLICIT) {
+        if ((rc = read_i64(c, h->mem, P->seed_offsets, E, &n_seeds))) return rc;
+        if (n_seeds < 0 || n_seeds > 0x7FFFFFFF) return fail(c, RETINA_ERR_INVALID_ARG, "bad total seed count");
+        if (host)
+            for (int64_t i = 0; i < n_seeds * NP; ++i)
+                if (!isfinite(P->seeds[i])) return fail(c, RETINA_ERR_INVALID_ARG, "an explicit seed is NaN or infinite");
+    } else {
+        n_seeds = E * (int64_t)P->lattice_n[0] * P->lattice_n[1];
+        if (n_seeds > 0x7FFFFFFF) return fail(c, RETINA_ERR_INVALID_ARG, "too many seeds in the batch");
+    }
+    if (so && so->capacity < n_seeds)
+        return fail(c, RETINA_ERR_CAPACITY, "seeds_out holds %lld seeds, %lld needed",
+                    (long long)so->capacity, (long long)n_seeds);
+
+    Desc& d = *c->h_desc;
+    memset(&d, 0, sizeof(Desc));
+    fill_geometry(d, g);
+    d.cnt = c->d_cnt;
+    if ((rc = stage_inputs(c, d, g, h, n_hits))) return rc;
+    const HotConfig hc = c->ascent_cfg[D];
+    d.seeds_per_item = hot_seeds_per_item(hc);
+    d.items_cap = n_seeds / d.seeds_per_item + E + 1;
+    if ((rc = ensure_t(c, B_ITEMS, (size_t)d.items_cap, &d.items))) return rc;
+    d.seed_mode = P->seed_mode;
+    d.lattice_n[0] = P->lattice_n[0];
+    d.lattice_n[1] = P->lattice_n[1];
+    for (int i = 0; i < 2; ++i) { d.lattice_lo[i] = P->lattice_lo[i]; d.lattice_hi[i] = P->lattice_hi[i]; }
+    d.n_sigma = P->n_sigma;
+    for (int i = 0; i < P->n_sigma; ++i) d.sigma[i] = P->sigma[i];
+    d.sigma_final = P->sigma_final;
+    d.n_final_steps = P->n_final_steps;
+    d.n_polish = P->n_polish;
+    d.ls_trials = P->ls_trials;
+    d.n_slope_steps = P->n_slope_steps;
+    d.armijo_c1 = P->armijo_c1;
+    d.step_cap = P->step_cap_sigmas;
+    d.small_step = P->small_step_sigmas;
+    d.conv_tol = P->conv_tol;
+    d.R0 = P->R0;
+    d.d_merge = P->d_merge;
+    if (P->seed_mode == RETINA_SEED_EXPLICIT) {
+        if (host) {
+            double* s;
+            int64_t* o;
+            if ((rc = ensure_t(c, B_INSEEDS, (size_t)std::max<int64_t>(n_seeds, 1) * NP, &s))) return rc;
+            if ((rc = ensure_t(c, B_INSOFF, (size_t)E + 1, &o))) return rc;
+            if (n_seeds)
+                HIP_TRY(c, hipMemcpyAsync(s, P->seeds, sizeof(double) * n_seeds * NP, hipMemcpyHostToDevice, c->stream));
+            HIP_TRY(c, hipMemcpyAsync(o, P->seed_offsets, sizeof(int64_t) * (E + 1), hipMemcpyHostToDevice, c->stream));
+            d.in_seeds = s;
+            d.in_seed_off = o;
+        } else {
+            d.in_seeds = P->seeds;
+            d.in_seed_off = P->seed_offsets;
+        }
+    }
+    const size_t ns1 = (size_t)std::max<int64_t>(n_seeds, 1);
+    if ((rc = ensure_t(c, B_STH, ns1 * 4, &d.s_theta)) || (rc = ensure_t(c, B_SR, ns1, &d.s_R)) ||
+        (rc = ensure_t(c, B_SFL, ns1, &d.s_flags)) || (rc = ensure_t(c, B_SNR, ns1, &d.s_nreval)) ||
+        (rc = ensure_t(c, B_MLEAD, ns1, &d.m_leader)) || (rc = ensure_t(c, B_MMEM, ns1, &d.m_members)) ||
+        (rc = ensure_t(c, B_MKEYS, ns1 * 2, &d.m_keys)) || (rc = ensure_t(c, B_EVNT, (size_t)E, &d.ev_ntracks)) ||
+        (rc = ensure_t(c, B_EVFL, (size_t)E, &d.ev_flags)) || (rc = ensure_t(c, B_EVTOFF, (size_t)E + 1, &d.ev_toff)))
+        return rc;
+    // outputs
+    const int64_t host_cap = std::min<int64_t>(capacity, n_seeds);
+    if (host) {
+        if ((rc = ensure_t(c, B_OUTTR, (size_t)std::max<int64_t>(host_cap, 1), &d.out_tracks)) ||
+            (rc = ensure_t(c, B_OUTTOFF, (size_t)E + 1, &d.out_track_off)))
+            return rc;
+        d.out_capacity = host_cap;
+        if (event_flags && (rc = ensure_t(c, B_OUTEVF, (size_t)E, &d.out_ev_flags))) return rc;
+        if (so) {
+            if (so->theta && (rc = ensure_t(c, B_OUTSTH, ns1 * NP, &d.out_s_theta))) return rc;
+            if (so->R && (rc = ensure_t(c, B_OUTSR, ns1, &d.out_s_R))) return rc;
+            if (so->flags && (rc = ensure_t(c, B_OUTSFL, ns1, &d.out_s_flags))) return rc;
+            if (so->n_reval && (rc = ensure_t(c, B_OUTSNR, ns1, &d.out_s_nreval))) return rc;
+        }
+    } else {
+        d.out_tracks = tracks;
+        d.out_capacity = capacity;
+        d.out_track_off = track_offsets;
+        d.out_ev_flags = event_flags;
+        if (so) {
+            d.out_s_theta = so->theta;
+            d.out_s_R = so->R;
+            d.out_s_flags = so->flags;
+            d.out_s_nreval = so->n_reval;
+        }
+    }
+    if ((rc = upload_desc(c))) return rc;
+    prof_mark(c, 0);
+    launch_reset(c->d_desc, c->stream);
+    launch_stage(c->d_desc, (int)std::min<int64_t>((E + 3) / 4, (int64_t)c->n_cu * 8), c->stream);
+    prof_mark(c, 1);
+    launch_plan_tracks(c->d_desc, c->stream);
+    prof_mark(c, 2);
+    launch_ascent(c->d_desc, D, hc, c->stream);
+    prof_mark(c, 3);
+    launch_merge(c->d_desc, D, (int)std::min<int64_t>(E, (int64_t)c->n_cu), c->stream);
+    launch_finalize(c->d_desc, c->stream);
+    launch_emit(c->d_desc, D, (int)std::min<int64_t>(E, (int64_t)c->n_cu * 4), c->stream);
+    prof_mark(c, 4);
+    HIP_TRY(c, hipGetLastError());
+    if ((rc = download_counters(c))) return rc;
+    prof_collect(c);
+    const uint32_t err = c->h_cnt->err;
+    const int64_t total = c->h_cnt->total_tracks;
+    if (err & ~kErrCapacity) return device_error(c, err);
+    if (err & kErrCapacity || total > capacity) {
+        if (host) track_offsets[E] = total;
+        return fail(c, RETINA_ERR_CAPACITY, "%lld tracks found, capacity %lld", (long long)total,
+                    (long long)capacity);
+    }
+    if (host) {
+        if (total)
+            HIP_TRY(c, hipMemcpyAsync(tracks, d.out_tracks, sizeof(retina_track) * total, hipMemcpyDeviceToHost, c->stream));
+        HIP_TRY(c, hipMemcpyAsync(track_offsets, d.out_track_off, sizeof(int64_t) * (E + 1), hipMemcpyDeviceToHost, c->stream));
+        if (event_flags)
+            HIP_TRY(c, hipMemcpyAsync(event_flags, d.out_ev_flags, sizeof(int32_t) * E, hipMemcpyDeviceToHost, c->stream));
+        if (so && n_seeds) {
+            if (so->theta) HIP_TRY(c, hipMemcpyAsync(so->theta, d.out_s_theta, sizeof(double) * n_seeds * NP, hipMemcpyDeviceToHost, c->stream));
+            if (so->R) HIP_TRY(c, hipMemcpyAsync(so->R, d.out_s_R, sizeof(float) * n_seeds, hipMemcpyDeviceToHost, c->stream));
+            if (so->flags) HIP_TRY(c, hipMemcpyAsync(so->flags, d.out_s_flags, sizeof(int32_t) * n_seeds, hipMemcpyDeviceToHost, c->stream));
+            if (so->n_reval) HIP_TRY(c, hipMemcpyAsync(so->n_reval, d.out_s_nreval, sizeof(int32_t) * n_seeds, hipMemcpyDeviceToHost, c->stream));
+        }
+        HIP_TRY(c, hipStreamSynchronize(c->stream));
+    }
+    return RETINA_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,727 @@
+// The hot path: Eq. (1) with its gradient and Hessian, evaluated for many
+// candidate lines against every hit of an event, and the multi-start
+// truncated-Newton ascent built on it (Algorithm 1).
+//
+// Layout and work split (CDNA4, wave64):
+//   * a work-group (4 waves) owns one event's hits in LDS and 4*64*C
+//     candidate lines (C per lane, each wave its own 64*C);
+//   * every lane walks the same hit (an LDS broadcast read), so the hit loop
+//     is wave-uniform and the per-pair work is pure VALU: two fused residuals,
+//     one exp2 and six running sums;
+//   * hits are grouped by plane, where z is constant, so the per-pair sums are
+//     P_e, P_x, P_y, P_xx, P_yy, P_xy and the z-moments are folded once per
+//     plane into 16 accumulators (8 for meas_dim 1);
+//   * events larger than the LDS tile are streamed through it tile by tile;
+//   * the kernels are persistent: work-groups pull (event, seed block) items
+//     from an atomic cursor over a longest-first list.
+//
+// Residuals are formed as fma(-t, z, x) - x0 so the product t*z is never
+// rounded on its own: x reaches ~260 mm where one FP32 ulp is already
+// ~1.5e-5 mm, too coarse next to a 0.03 mm bandwidth.  The FP64 polish
+// evaluates at an FP64 theta split into two floats (hi + lo) so that the
+// gradient it solves with belongs to the FP64 point.
+#include "rt_internal.h"
+
+namespace rt {
+
+constexpr float kLog2e = 1.44269504088896340736f;
+
+template <int D>
+struct Acc;  // number of accumulators
+template <>
+struct Acc<2> { static constexpr int N = 16; };
+template <>
+struct Acc<1> { static constexpr int N = 8; };
+
+// Candidate line parameters held by a lane: offsets o[], slopes t[] per
+// measured coordinate (meas_dim 1 uses index 0 only).
+template <int C>
+struct Cands {
+    float o[C][2];
+    float t[C][2];
+};
+
+// One plane segment [lo, hi) of LDS hits at plane position z.
+template <int D, int C, bool DERIV, bool DF>
+__device__ __forceinline__ void seg_accumulate(const float* __restrict__ s_hits, int lo, int hi,
+                                               float z, const Cands<C>& c, const Cands<C>& cl,
+                                               float nc, float (&acc)[C][Acc<D>::N])
+{
+    float pe[C], px[C], py[C], pxx[C], pyy[C], pxy[C];
+#pragma unroll
+    for (int j = 0; j < C; ++j) { pe[j] = px[j] = py[j] = pxx[j] = pyy[j] = pxy[j] = 0.0f; }
+    if constexpr (D == 2) {
+        const float2* h = reinterpret_cast<const float2*>(s_hits);
+#pragma unroll 2
+        for (int k = lo; k < hi; ++k) {
+            const float2 v = h[k];
+#pragma unroll
+            for (int j = 0; j < C; ++j) {
+                float rx = __builtin_fmaf(-c.t[j][0], z, v.x);
+                float ry = __builtin_fmaf(-c.t[j][1], z, v.y);
+                if (DF) {
+                    rx = __builtin_fmaf(-cl.t[j][0], z, rx);
+                    ry = __builtin_fmaf(-cl.t[j][1], z, ry);
+                }
+                rx -= c.o[j][0];
+                ry -= c.o[j][1];
+                if (DF) {
+                    rx -= cl.o[j][0];
+                    ry -= cl.o[j][1];
+                }
+                const float d2 = __builtin_fmaf(ry, ry, rx * rx);
+                const float e = __builtin_amdgcn_exp2f(d2 * nc);
+                pe[j] += e;
+                if (DERIV) {
+                    const float ex = e * rx;
+                    const float ey = e * ry;
+                    px[j] += ex;
+                    py[j] += ey;
+                    pxx[j] = __builtin_fmaf(ex, rx, pxx[j]);
+                    pyy[j] = __builtin_fmaf(ey, ry, pyy[j]);
+                    pxy[j] = __builtin_fmaf(ex, ry, pxy[j]);
+                }
+            }
+        }
+    } else {
+#pragma unroll 4
+        for (int k = lo; k < hi; ++k) {
+            const float v = s_hits[k];
+#pragma unroll
+            for (int j = 0; j < C; ++j) {
+                float r = __builtin_fmaf(-c.t[j][0], z, v);
+                if (DF) r = __builtin_fmaf(-cl.t[j][0], z, r);
+                r -= c.o[j][0];
+                if (DF) r -= cl.o[j][0];
+                const float e = __builtin_amdgcn_exp2f((r * r) * nc);
+                pe[j] += e;
+                if (DERIV) {
+                    const float er = e * r;
+                    px[j] += er;
+                    pxx[j] = __builtin_fmaf(er, r, pxx[j]);
+                }
+            }
+        }
+    }
+    const float z2 = z * z;
+#pragma unroll
+    for (int j = 0; j < C; ++j) {
+        float* a = acc[j];
+        a[0] += pe[j];
+        if (DERIV) {
+            a[1] = __builtin_fmaf(pe[j], z, a[1]);
+            a[2] = __builtin_fmaf(pe[j], z2, a[2]);
+            if constexpr (D == 2) {
+                a[3] += px[j];
+                a[4] = __builtin_fmaf(px[j], z, a[4]);
+                a[5] += py[j];
+                a[6] = __builtin_fmaf(py[j], z, a[6]);
+                a[7] += pxx[j];
+                a[8] = __builtin_fmaf(pxx[j], z, a[8]);
+                a[9] = __builtin_fmaf(pxx[j], z2, a[9]);
+                a[10] += pyy[j];
+                a[11] = __builtin_fmaf(pyy[j], z, a[11]);
+                a[12] = __builtin_fmaf(pyy[j], z2, a[12]);
+                a[13] += pxy[j];
+                a[14] = __builtin_fmaf(pxy[j], z, a[14]);
+                a[15] = __builtin_fmaf(pxy[j], z2, a[15]);
+            } else {
+                a[3] += px[j];
+                a[4] = __builtin_fmaf(px[j], z, a[4]);
+                a[5] += pxx[j];
+                a[6] = __builtin_fmaf(pxx[j], z, a[6]);
+                a[7] = __builtin_fmaf(pxx[j], z2, a[7]);
+            }
+        }
+    }
+}
+
+// Per-event context held by the work-group.
+struct EventView {
+    const float* g_hits;  // global staged hits of the event (first hit)
+    int n;                // hits
+    int P;
+    bool resident;        // all hits already in LDS
+    int tile_cap;
+};
+
+// One pass over all of the event's hits for the lane's C candidates.
+// Tiled events are streamed through LDS; the work-group must call this
+// uniformly then (it contains barriers).
+template <int D, int C, bool DERIV, bool DF>
+__device__ __forceinline__ void event_pass(const Desc* __restrict__ d, float* s_hits,
+                                           const int* s_poff, const EventView& ev,
+                                           const Cands<C>& c, const Cands<C>& cl, float nc,
+                                           float (&acc)[C][Acc<D>::N])
+{
+#pragma unroll
+    for (int j = 0; j < C; ++j)
+#pragma unroll
+        for (int a = 0; a < Acc<D>::N; ++a) acc[j][a] = 0.0f;
+    for (int t0 = 0; t0 < ev.n; t0 += ev.tile_cap) {
+        const int t1 = min(ev.n, t0 + ev.tile_cap);
+        if (!ev.resident) {
+            __syncthreads();
+            if (D == 2) {
+                const float2* src = reinterpret_cast<const float2*>(ev.g_hits) + t0;
+                float2* dst = reinterpret_cast<float2*>(s_hits);
+                for (int i = threadIdx.x; i < t1 - t0; i += blockDim.x) dst[i] = src[i];
+            } else {
+                for (int i = threadIdx.x; i < t1 - t0; i += blockDim.x) s_hits[i] = ev.g_hits[t0 + i];
+            }
+            __syncthreads();
+        }
+        for (int p = 0; p < ev.P; ++p) {
+            const int lo = max(s_poff[p], t0);
+            const int hi = min(s_poff[p + 1], t1);
+            if (lo >= hi) continue;
+            seg_accumulate<D, C, DERIV, DF>(s_hits, lo - t0, hi - t0, d->plane_z[p], c, cl, nc, acc);
+        }
+    }
+}
+
+// Gradient and Hessian from the accumulators (formulas of Eq. (1)
+// differentiated; theta order (x0, y0, tx, ty) or (x0, tx)).  Full matrix.
+template <int D, typename T>
+__device__ __forceinline__ void grad_hess(const float* a, float sigma, T* g, T (*H)[2 * D])
+{
+    const T s2 = (T)sigma * (T)sigma;
+    const T two = (T)2 / s2;
+    const T four = (T)4 / (s2 * s2);
+    if constexpr (D == 2) {
+        g[0] = two * (T)a[3];
+        g[1] = two * (T)a[5];
+        g[2] = two * (T)a[4];
+        g[3] = two * (T)a[6];
+        H[0][0] = four * (T)a[7] - two * (T)a[0];
+        H[0][1] = four * (T)a[13];
+        H[0][2] = four * (T)a[8] - two * (T)a[1];
+        H[0][3] = four * (T)a[14];
+        H[1][1] = four * (T)a[10] - two * (T)a[0];
+        H[1][2] = four * (T)a[14];
+        H[1][3] = four * (T)a[11] - two * (T)a[1];
+        H[2][2] = four * (T)a[9] - two * (T)a[2];
+        H[2][3] = four * (T)a[15];
+        H[3][3] = four * (T)a[12] - two * (T)a[2];
+    } else {
+        g[0] = two * (T)a[3];
+        g[1] = two * (T)a[4];
+        H[0][0] = four * (T)a[5] - two * (T)a[0];
+        H[0][1] = four * (T)a[6] - two * (T)a[1];
+        H[1][1] = four * (T)a[7] - two * (T)a[2];
+    }
+#pragma unroll
+    for (int i = 0; i < 2 * D; ++i)
+#pragma unroll
+        for (int j = 0; j < i; ++j) H[i][j] = H[j][i];
+}
+
+// Truncated-Newton direction for maximising R in scaled coordinates
+// (scaled = ds * theta): conjugate gradients on (-H~) p~ = g~ from zero, at
+// most N iterations, stopping at a residual below 1e-4 |g~|; a non-positive
+// curvature on the first direction gives a steepest-ascent step of one
+// bandwidth, on a later one the current iterate.  The scaled step is capped
+// at cap*sigma.  Returns the unscaled direction.
+template <int N>
+__device__ __forceinline__ void newton_cg(const float* g, const float (*H)[N], const float* ds,
+                                          float sigma, float cap, float* p, float& pn, bool& neg)
+{
+    float b[N], A[N][N];
+#pragma unroll
+    for (int i = 0; i < N; ++i) b[i] = g[i] / ds[i];
+#pragma unroll
+    for (int i = 0; i < N; ++i)
+#pragma unroll
+        for (int j = 0; j < N; ++j) A[i][j] = -H[i][j] / (ds[i] * ds[j]);
+    float bb = 0.0f;
+#pragma unroll
+    for (int i = 0; i < N; ++i) bb = __builtin_fmaf(b[i], b[i], bb);
+    const float bn = sqrtf(bb);
+    float q[N];
+#pragma unroll
+    for (int i = 0; i < N; ++i) q[i] = 0.0f;
+    neg = false;
+    if (bn > 0.0f) {
+        const float tol = 1e-4f * bn;
+        float x[N], r[N], dv[N];
+#pragma unroll
+        for (int i = 0; i < N; ++i) { x[i] = 0.0f; r[i] = b[i]; dv[i] = b[i]; }
+        bool done = false;
+#pragma unroll
+        for (int k = 0; k < N; ++k) {
+            if (!done) {
+                float Ad[N], dAd = 0.0f, rr = 0.0f;
+#pragma unroll
+                for (int i = 0; i < N; ++i) {
+                    float s = 0.0f;
+#pragma unroll
+                    for (int j = 0; j < N; ++j) s = __builtin_fmaf(A[i][j], dv[j], s);
+                    Ad[i] = s;
+                }
+#pragma unroll
+                for (int i = 0; i < N; ++i) {
+                    dAd = __builtin_fmaf(dv[i], Ad[i], dAd);
+                    rr = __builtin_fmaf(r[i], r[i], rr);
+                }
+                if (!(dAd > 0.0f)) {
+                    neg = true;
+                    if (k == 0) {
+#pragma unroll
+                        for (int i = 0; i < N; ++i) q[i] = sigma * (b[i] / bn);
+                    } else {
+#pragma unroll
+                        for (int i = 0; i < N; ++i) q[i] = x[i];
+                    }
+                    done = true;
+                } else {
+                    const float alpha = rr / dAd;
+                    float rn = 0.0f;
+#pragma unroll
+                    for (int i = 0; i < N; ++i) {
+                        x[i] = __builtin_fmaf(alpha, dv[i], x[i]);
+                        r[i] = __builtin_fmaf(-alpha, Ad[i], r[i]);
+                        rn = __builtin_fmaf(r[i], r[i], rn);
+                    }
+                    if (sqrtf(rn) < tol) {
+#pragma unroll
+                        for (int i = 0; i < N; ++i) q[i] = x[i];
+                        done = true;
+                    } else {
+                        const float beta = rn / rr;
+#pragma unroll
+                        for (int i = 0; i < N; ++i) dv[i] = __builtin_fmaf(beta, dv[i], r[i]);
+                    }
+                }
+            }
+        }
+        if (!done) {
+#pragma unroll
+            for (int i = 0; i < N; ++i) q[i] = x[i];
+        }
+    }
+    float qq = 0.0f;
+#pragma unroll
+    for (int i = 0; i < N; ++i) qq = __builtin_fmaf(q[i], q[i], qq);
+    pn = sqrtf(qq);
+    const float lim = cap * sigma;
+    if (pn > lim) {
+        const float s = lim / pn;
+#pragma unroll
+        for (int i = 0; i < N; ++i) q[i] *= s;
+        pn = lim;
+    }
+#pragma unroll
+    for (int i = 0; i < N; ++i) p[i] = q[i] / ds[i];
+}
+
+// FP64 Cholesky solve of A x = b (N <= 4); false when A is not positive definite.
+template <int N>
+__device__ __forceinline__ bool chol_solve(const double (*A)[N], const double* b, double* x)
+{
+    double L[N][N];
+#pragma unroll
+    for (int i = 0; i < N; ++i)
+#pragma unroll
+        for (int j = 0; j < N; ++j) L[i][j] = 0.0;
+    bool ok = true;
+#pragma unroll
+    for (int i = 0; i < N; ++i) {
+#pragma unroll
+        for (int j = 0; j <= i; ++j) {
+            double s = A[i][j];
+#pragma unroll
+            for (int k = 0; k < j; ++k) s -= L[i][k] * L[j][k];
+            if (i == j) {
+                if (!(s > 0.0)) { ok = false; s = 1.0; }
+                L[i][i] = sqrt(s);
+            } else {
+                L[i][j] = s / L[j][j];
+            }
+        }
+    }
+    double y[N];
+#pragma unroll
+    for (int i = 0; i < N; ++i) {
+        double s = b[i];
+#pragma unroll
+        for (int k = 0; k < i; ++k) s -= L[i][k] * y[k];
+        y[i] = s / L[i][i];
+    }
+#pragma unroll
+    for (int i = N - 1; i >= 0; --i) {
+        double s = y[i];
+#pragma unroll
+        for (int k = i + 1; k < N; ++k) s -= L[k][i] * x[k];
+        x[i] = s / L[i][i];
+    }
+    return ok;
+}
+
+// theta (x0, y0, tx, ty) / (x0, tx) <-> lane candidate slots
+template <int D, int C>
+__device__ __forceinline__ void set_cand(Cands<C>& c, int j, const float* th)
+{
+    if constexpr (D == 2) { c.o[j][0] = th[0]; c.o[j][1] = th[1]; c.t[j][0] = th[2]; c.t[j][1] = th[3]; }
+    else { c.o[j][0] = th[0]; c.t[j][0] = th[1]; c.o[j][1] = 0.0f; c.t[j][1] = 0.0f; }
+}
+
+__device__ __forceinline__ bool wg_or(bool v, bool resident)
+{
+    // resident events have no barriers inside a pass: waves may iterate on their own
+    if (resident) return __any(v) != 0;
+    return __syncthreads_or(v) != 0;
+}
+
+// Load the event's plane offsets (event-relative) and, if it fits, its hits.
+__device__ __forceinline__ EventView begin_event(const Desc* __restrict__ d, int e, float* s_hits,
+                                                 int* s_poff, int tile_cap)
+{
+    const int P = d->n_planes;
+    const int32_t* po = d->plane_off + (int64_t)e * (P + 1);
+    const int base = po[0];
+    EventView ev;
+    ev.P = P;
+    ev.n = d->ev_nhits[e];
+    ev.g_hits = d->hits + (int64_t)base * d->meas_dim;
+    ev.tile_cap = tile_cap;
+    ev.resident = ev.n <= tile_cap;
+    if ((int)threadIdx.x <= P) s_poff[threadIdx.x] = po[threadIdx.x] - base;
+    if (ev.resident) {
+        if (d->meas_dim == 2) {
+            const float2* src = reinterpret_cast<const float2*>(ev.g_hits);
+            float2* dst = reinterpret_cast<float2*>(s_hits);
+            for (int i = threadIdx.x; i < ev.n; i += blockDim.x) dst[i] = src[i];
+        } else {
+            for (int i = threadIdx.x; i < ev.n; i += blockDim.x) s_hits[i] = ev.g_hits[i];
+        }
+    }
+    __syncthreads();
+    return ev;
+}
+
+// ------------------------------------------------------------------ ascent
+template <int D, int C>
+__global__ __launch_bounds__(kBlock) void k_ascent(const Desc* __restrict__ d, int tile_cap)
+{
+    constexpr int NP = 2 * D;
+    constexpr int NA = Acc<D>::N;
+    extern __shared__ float s_hits[];
+    __shared__ int s_poff[kMaxPlanes + 1];
+    __shared__ int s_item;
+    if (d->cnt->err) return;
+    const int wave = threadIdx.x / kWave;
+    const int lane = threadIdx.x & (kWave - 1);
+    const int64_t n_items = d->cnt->n_items;
+    const int n_steps = d->n_sigma + d->n_final_steps;
+    const float zr = d->z_ref;
+    float ds[NP];
+    if constexpr (D == 2) { ds[0] = 1.0f; ds[1] = 1.0f; ds[2] = zr; ds[3] = zr; }
+    else { ds[0] = 1.0f; ds[1] = zr; }
+    const Cands<C> zero_c = {};
+
+    for (;;) {
+        if (threadIdx.x == 0) s_item = (int)atomicAdd(&d->cnt->item, 1u);
+        __syncthreads();
+        const int item = s_item;
+        if (item >= n_items) break;
+        const int2 it = d->items[item];
+        const int e = it.x;
+        const EventView ev = begin_event(d, e, s_hits, s_poff, tile_cap);
+        const int64_t sbase = d->seed_off[e];
+        const int ns = (int)(d->seed_off[e + 1] - sbase);
+
+        // seeds
+        float th[C][NP];
+        bool active[C];
+        int flags[C], nre[C];
+#pragma unroll
+        for (int j = 0; j < C; ++j) {
+            const int sj = it.y + (wave * C + j) * kWave + lane;
+            active[j] = sj < ns;
+            flags[j] = 0;
+            nre[j] = 0;
+            const int sjc = active[j] ? sj : 0;
+            if (d->seed_mode == RETINA_SEED_EXPLICIT) {
+                const double* s = d->in_seeds + (sbase + sjc) * NP;
+#pragma unroll
+                for (int a = 0; a < NP; ++a) th[j][a] = active[j] ? (float)s[a] : 0.0f;
+            } else {
+                const int n1 = d->lattice_n[1];
+                const int i0 = sjc / n1, i1 = sjc % n1;
+                const double lo0 = d->lattice_lo[0], hi0 = d->lattice_hi[0];
+                const double lo1 = d->lattice_lo[1], hi1 = d->lattice_hi[1];
+                const float v0 = (float)(lo0 + ((double)i0 + 0.5) * (hi0 - lo0) / (double)d->lattice_n[0]);
+                const float v1 = (float)(lo1 + ((double)i1 + 0.5) * (hi1 - lo1) / (double)n1);
+                if constexpr (D == 2) { th[j][0] = 0.0f; th[j][1] = 0.0f; th[j][2] = v0; th[j][3] = v1; }
+                else { th[j][0] = v1; th[j][1] = v0; }
+            }
+        }
+
+        for (int s = 0; s < n_steps; ++s) {
+            const float sig = s < d->n_sigma ? d->sigma[s] : d->sigma_final;
+            const float nc = -kLog2e / (sig * sig);
+            Cands<C> c;
+#pragma unroll
+            for (int j = 0; j < C; ++j) set_cand<D, C>(c, j, th[j]);
+            float acc[C][NA];
+            event_pass<D, C, true, false>(d, s_hits, s_poff, ev, c, zero_c, nc, acc);
+            float p[C][NP], Rc[C], gp[C], alpha[C];
+            bool pend[C];
+            int trial[C];
+            const bool slope_only = D == 2 && s < d->n_slope_steps;
+#pragma unroll
+            for (int j = 0; j < C; ++j) {
+                float g[NP], H[NP][NP];
+                grad_hess<D, float>(acc[j], sig, g, H);
+                float pn;
+                bool neg;
+                if constexpr (D == 2) {
+                    if (slope_only) {
+                        const float gs[2] = {g[2], g[3]};
+                        const float Hs[2][2] = {{H[2][2], H[2][3]}, {H[3][2], H[3][3]}};
+                        const float dss[2] = {ds[2], ds[3]};
+                        float ps[2];
+                        newton_cg<2>(gs, Hs, dss, sig, d->step_cap, ps, pn, neg);
+                        p[j][0] = 0.0f; p[j][1] = 0.0f; p[j][2] = ps[0]; p[j][3] = ps[1];
+                    } else {
+                        newton_cg<NP>(g, H, ds, sig, d->step_cap, p[j], pn, neg);
+                    }
+                } else {
+                    newton_cg<NP>(g, H, ds, sig, d->step_cap, p[j], pn, neg);
+                }
+                if (neg) flags[j] |= RETINA_NEGCURV;
+                Rc[j] = acc[j][0];
+                float dot = 0.0f;
+#pragma unroll
+                for (int a = 0; a < NP; ++a) dot = __builtin_fmaf(g[a], p[j][a], dot);
+                gp[j] = dot;
+                alpha[j] = 1.0f;
+                trial[j] = 0;
+                if (!neg && pn <= d->small_step * sig) {
+#pragma unroll
+                    for (int a = 0; a < NP; ++a) th[j][a] += p[j][a];
+                    pend[j] = false;
+                } else {
+                    pend[j] = true;
+                }
+            }
+            // backtracking line search, one R-only pass per round of trials
+            for (;;) {
+                bool any = false;
+#pragma unroll
+                for (int j = 0; j < C; ++j) any |= pend[j];
+                if (!wg_or(any, ev.resident)) break;
+                float tt[C][NP];
+#pragma unroll
+                for (int j = 0; j < C; ++j)
+#pragma unroll
+                    for (int a = 0; a < NP; ++a)
+                        tt[j][a] = pend[j] ? __builtin_fmaf(alpha[j], p[j][a], th[j][a]) : th[j][a];
+#pragma unroll
+                for (int j = 0; j < C; ++j) set_cand<D, C>(c, j, tt[j]);
+                float racc[C][NA];
+                event_pass<D, C, false, false>(d, s_hits, s_poff, ev, c, zero_c, nc, racc);
+#pragma unroll
+                for (int j = 0; j < C; ++j) {
+                    if (!pend[j]) continue;
+                    ++nre[j];
+                    if (racc[j][0] >= Rc[j] + d->armijo_c1 * alpha[j] * gp[j]) {
+#pragma unroll
+                        for (int a = 0; a < NP; ++a) th[j][a] = tt[j][a];
+                        pend[j] = false;
+                    } else if (++trial[j] >= d->ls_trials) {
+                        pend[j] = false;
+                        flags[j] |= RETINA_STALLED;
+                    } else {
+                        alpha[j] *= 0.5f;
+                    }
+                }
+            }
+        }
+
+        // FP64 Newton polish at sigma_final
+        double T[C][NP];
+#pragma unroll
+        for (int j = 0; j < C; ++j)
+#pragma unroll
+            for (int a = 0; a < NP; ++a) T[j][a] = (double)th[j][a];
+        const float sf = d->sigma_final;
+        const float ncf = -kLog2e / (sf * sf);
+        float Rfin[C];
+        double step[C];
+        bool pd[C];
+        for (int it2 = 0; it2 < d->n_polish; ++it2) {
+            Cands<C> ch, cl;
+#pragma unroll
+            for (int j = 0; j < C; ++j) {
+                float hi[NP], lo[NP];
+#pragma unroll
+                for (int a = 0; a < NP; ++a) {
+                    hi[a] = (float)T[j][a];
+                    lo[a] = (float)(T[j][a] - (double)hi[a]);
+                }
+                set_cand<D, C>(ch, j, hi);
+                set_cand<D, C>(cl, j, lo);
+            }
+            float acc[C][NA];
+            event_pass<D, C, true, true>(d, s_hits, s_poff, ev, ch, cl, ncf, acc);
+#pragma unroll
+            for (int j = 0; j < C; ++j) {
+                double g[NP], H[NP][NP], A[NP][NP], dl[NP];
+                grad_hess<D, double>(acc[j], sf, g, H);
+#pragma unroll
+                for (int a = 0; a < NP; ++a)
+#pragma unroll
+                    for (int b = 0; b < NP; ++b) A[a][b] = -H[a][b];
+                pd[j] = chol_solve<NP>(A, g, dl);
+                Rfin[j] = acc[j][0];
+                if (pd[j]) {
+                    double s2 = 0.0;
+#pragma unroll
+                    for (int a = 0; a < NP; ++a) {
+                        T[j][a] += dl[a];
+                        const double sd = (double)ds[a] * dl[a];
+                        s2 += sd * sd;
+                    }
+                    step[j] = sqrt(s2);
+                } else {
+                    step[j] = INFINITY;
+                }
+            }
+        }
+#pragma unroll
+        for (int j = 0; j < C; ++j) {
+            if (!pd[j]) flags[j] |= RETINA_NOT_PD;
+            else if (step[j] <= (double)d->conv_tol * (double)sf) flags[j] |= RETINA_CONVERGED;
+            if (!active[j]) continue;
+            const int sj = it.y + (wave * C + j) * kWave + lane;
+            const int64_t gs = sbase + sj;
+            double* o = d->s_theta + gs * 4;
+#pragma unroll
+            for (int a = 0; a < 4; ++a) o[a] = a < NP ? T[j][a] : 0.0;
+            d->s_R[gs] = Rfin[j];
+            d->s_flags[gs] = flags[j];
+            d->s_nreval[gs] = nre[j];
+        }
+        __syncthreads();
+    }
+}
+
+// ---------------------------------------------------------------- response
+template <int D, int C, bool DERIV>
+__global__ __launch_bounds__(kBlock) void k_response(const Desc* __restrict__ d, int tile_cap)
+{
+    constexpr int NP = 2 * D;
+    constexpr int NA = Acc<D>::N;
+    extern __shared__ float s_hits[];
+    __shared__ int s_poff[kMaxPlanes + 1];
+    __shared__ int s_item;
+    if (d->cnt->err) return;
+    const int wave = threadIdx.x / kWave;
+    const int lane = threadIdx.x & (kWave - 1);
+    const int64_t n_items = d->cnt->n_items;
+    const float sig = d->resp_sigma;
+    const float nc = -kLog2e / (sig * sig);
+    const Cands<C> zero_c = {};
+    for (;;) {
+        if (threadIdx.x == 0) s_item = (int)atomicAdd(&d->cnt->item, 1u);
+        __syncthreads();
+        const int item = s_item;
+        if (item >= n_items) break;
+        const int2 it = d->items[item];
+        const int e = it.x;
+        const EventView ev = begin_event(d, e, s_hits, s_poff, tile_cap);
+        const int64_t sbase = d->seed_off[e];
+        const int ns = (int)(d->seed_off[e + 1] - sbase);
+        Cands<C> c;
+        bool active[C];
+#pragma unroll
+        for (int j = 0; j < C; ++j) {
+            const int sj = it.y + (wave * C + j) * kWave + lane;
+            active[j] = sj < ns;
+            float th[NP];
+            const float* src = d->in_theta + (sbase + (active[j] ? sj : 0)) * NP;
+#pragma unroll
+            for (int a = 0; a < NP; ++a) th[a] = active[j] ? src[a] : 0.0f;
+            set_cand<D, C>(c, j, th);
+        }
+        float acc[C][NA];
+        event_pass<D, C, DERIV, false>(d, s_hits, s_poff, ev, c, zero_c, nc, acc);
+#pragma unroll
+        for (int j = 0; j < C; ++j) {
+            if (!active[j]) continue;
+            const int64_t gj = sbase + it.y + (wave * C + j) * kWave + lane;
+            d->out_R[gj] = acc[j][0];
+            if (DERIV) {
+                float g[NP], H[NP][NP];
+                grad_hess<D, float>(acc[j], sig, g, H);
+                if (d->want & RETINA_WANT_GRAD) {
+#pragma unroll
+                    for (int a = 0; a < NP; ++a) d->out_grad[gj * NP + a] = g[a];
+                }
+                if (d->want & RETINA_WANT_HESS) {
+                    int q = 0;
+#pragma unroll
+                    for (int a = 0; a < NP; ++a)
+#pragma unroll
+                        for (int b = a; b < NP; ++b) d->out_hess[gj * (NP * (NP + 1) / 2) + q++] = H[a][b];
+                }
+            }
+        }
+        __syncthreads();
+    }
+}
+
+// ------------------------------------------------------------------ launch
+int hot_seeds_per_item(const HotConfig& c) { return (kBlock / kWave) * kWave * c.cand; }
+
+size_t hot_lds_bytes(int meas_dim, const HotConfig& c) { return (size_t)c.tile_hits * meas_dim * sizeof(float); }
+
+template <typename K>
+static int occupancy(K kern, size_t lds)
+{
+    int nb = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, kern, kBlock, lds) != hipSuccess) return 1;
+    return nb > 0 ? nb : 1;
+}
+
+int hot_max_blocks_per_cu(int D, const HotConfig& c, bool ascent)
+{
+    const size_t lds = hot_lds_bytes(D, c);
+    if (ascent) {
+        if (D == 2) return c.cand == 2 ? occupancy(k_ascent<2, 2>, lds) : occupancy(k_ascent<2, 1>, lds);
+        return c.cand == 2 ? occupancy(k_ascent<1, 2>, lds) : occupancy(k_ascent<1, 1>, lds);
+    }
+    if (D == 2) return c.cand == 2 ? occupancy(k_response<2, 2, true>, lds) : occupancy(k_response<2, 1, true>, lds);
+    return c.cand == 2 ? occupancy(k_response<1, 2, true>, lds) : occupancy(k_response<1, 1, true>, lds);
+}
+
+void launch_ascent(const Desc* d, int D, const HotConfig& c, hipStream_t st)
+{
+    const size_t lds = hot_lds_bytes(D, c);
+    const dim3 g(c.grid), b(kBlock);
+    if (D == 2) {
+        if (c.cand == 2) hipLaunchKernelGGL((k_ascent<2, 2>), g, b, lds, st, d, c.tile_hits);
+        else hipLaunchKernelGGL((k_ascent<2, 1>), g, b, lds, st, d, c.tile_hits);
+    } else {
+        if (c.cand == 2) hipLaunchKernelGGL((k_ascent<1, 2>), g, b, lds, st, d, c.tile_hits);
+        else hipLaunchKernelGGL((k_ascent<1, 1>), g, b, lds, st, d, c.tile_hits);
+    }
+}
+
+void launch_response(const Desc* d, int D, const HotConfig& c, bool deriv, hipStream_t st)
+{
+    const size_t lds = hot_lds_bytes(D, c);
+    const dim3 g(c.grid), b(kBlock);
+#define RT_LAUNCH_RESP(DD, CC, DV) hipLaunchKernelGGL((k_response<DD, CC, DV>), g, b, lds, st, d, c.tile_hits)
+    if (D == 2) {
+        if (deriv) { if (c.cand == 2) RT_LAUNCH_RESP(2, 2, true); else RT_LAUNCH_RESP(2, 1, true); }
+        else { if (c.cand == 2) RT_LAUNCH_RESP(2, 2, false); else RT_LAUNCH_RESP(2, 1, false); }
+    } else {
+        if (deriv) { if (c.cand == 2) RT_LAUNCH_RESP(1, 2, true); else RT_LAUNCH_RESP(1, 1, true); }
+        else { if (c.cand == 2) RT_LAUNCH_RESP(1, 2, false); else RT_LAUNCH_RESP(1, 1, false); }
+    }
+#undef RT_LAUNCH_RESP
+}
+
+}  // namespace rt

@@ -1,0 +1,252 @@
+// Hit staging and work planning.
+//
+// k_stage  validates each event's hits and counting-sorts them by plane
+//          (stable: a hit keeps its input order within its plane), writing
+//          per-(event, plane) offsets.  The hot kernels fold their sums per
+//          plane, where z is constant, so the plane grouping is what lets the
+//          per-hit work stay at six accumulators.
+// k_plan   counts seeds per event, orders events longest first (hits x seeds)
+//          and materialises the persistent kernels' (event, seed block)
+//          work list.
+#include "rt_internal.h"
+
+namespace rt {
+
+__global__ void k_reset(const Desc* __restrict__ d)
+{
+    if (threadIdx.x == 0) {
+        Counters* c = d->cnt;
+        c->item = 0;
+        c->err = 0;
+        c->n_items = 0;
+        c->total_tracks = 0;
+        c->total_seeds = 0;
+    }
+}
+
+__device__ __forceinline__ uint64_t lanemask_lt()
+{
+    const int lane = threadIdx.x & (kWave - 1);
+    return lane == 0 ? 0ull : (~0ull >> (kWave - lane));
+}
+
+// One wavefront per event.  Pass 1: histogram of planes (LDS atomics) and
+// validation.  Exclusive scan over planes.  Pass 2: stable scatter, ranks
+// from wave ballots per distinct plane in the chunk.
+__global__ __launch_bounds__(kBlock) void k_stage(const Desc* __restrict__ d)
+{
+    __shared__ int s_cnt[kBlock / kWave][kMaxPlanes];
+    const int wave = threadIdx.x / kWave;
+    const int lane = threadIdx.x & (kWave - 1);
+    const int P = d->n_planes;
+    const int D = d->meas_dim;
+    const int64_t E = d->n_events;
+    int* cnt = s_cnt[wave];
+    uint32_t err = 0;
+    for (int64_t e = (int64_t)blockIdx.x * (kBlock / kWave) + wave; e < E;
+         e += (int64_t)gridDim.x * (kBlock / kWave)) {
+        const int64_t a = d->in_off[e];
+        const int64_t b = d->in_off[e + 1];
+        if ((e == 0 && a != 0) || b < a || b > d->n_hits) {
+            err |= kErrOffsets;
+            continue;
+        }
+        if (lane < P) cnt[lane] = 0;
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        bool bad = false;
+        for (int64_t k0 = a; k0 < b; k0 += kWave) {
+            const int64_t k = k0 + lane;
+            if (k < b) {
+                const int p = d->in_plane[k];
+                const float x = d->in_x[k];
+                const float y = D == 2 ? d->in_y[k] : 0.0f;
+                if (p < 0 || p >= P) { err |= kErrPlane; bad = true; }
+                else atomicAdd(&cnt[p], 1);
+                if (!isfinite(x) || !isfinite(y)) { err |= kErrCoord; bad = true; }
+            }
+        }
+        __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        if (__any(bad)) continue;
+        // exclusive scan of the plane counts (lanes 0..P-1)
+        int c = lane < P ? cnt[lane] : 0;
+        int incl = c;
+        for (int off = 1; off < kWave; off <<= 1) {
+            const int v = __shfl_up(incl, off, kWave);
+            if (lane >= off) incl += v;
+        }
+        int cursor = (int)a + incl - c;  // lane p: next free slot of plane p
+        int32_t* po = d->plane_off + e * (P + 1);
+        if (lane < P) po[lane] = cursor;
+        if (lane == 0) { po[P] = (int)b; d->ev_nhits[e] = (int)(b - a); }
+        for (int64_t k0 = a; k0 < b; k0 += kWave) {
+            const int64_t k = k0 + lane;
+            const bool live = k < b;
+            const int p = live ? d->in_plane[k] : -1;
+            bool pending = live;
+            int pos = 0;
+            while (true) {
+                const uint64_t pm = __ballot(pending);
+                if (pm == 0) break;
+                const int leader = __ffsll((unsigned long long)pm) - 1;
+                const int q = __shfl(p, leader, kWave);
+                const uint64_t m = __ballot(pending && p == q);
+                const int base = __shfl(cursor, q, kWave);
+                if (pending && p == q) {
+                    pos = base + __popcll(m & lanemask_lt());
+                    pending = false;
+                }
+                if (lane == q) cursor += __popcll(m);
+            }
+            if (live) {
+                if (D == 2) {
+                    float2 v;
+                    v.x = d->in_x[k];
+                    v.y = d->in_y[k];
+                    reinterpret_cast<float2*>(d->hits)[pos] = v;
+                } else {
+                    d->hits[pos] = d->in_x[k];
+                }
+            }
+        }
+    }
+    if (err) atomicOr(&d->cnt->err, err);
+}
+
+// ---------------------------------------------------------------- planning
+// Work list for the persistent kernels.  seed_mode 0: lattice (same count per
+// event); 1: explicit seeds (in_seed_off); 2: response thetas (in_theta_off).
+__device__ __forceinline__ int64_t block_excl_scan(int64_t v, int64_t* s_tmp, int64_t& total)
+{
+    // blockDim.x == 1024
+    const int t = threadIdx.x;
+    s_tmp[t] = v;
+    __syncthreads();
+    for (int off = 1; off < 1024; off <<= 1) {
+        const int64_t add = t >= off ? s_tmp[t - off] : 0;
+        __syncthreads();
+        s_tmp[t] += add;
+        __syncthreads();
+    }
+    const int64_t incl = s_tmp[t];
+    total = s_tmp[1023];
+    __syncthreads();
+    return incl - v;
+}
+
+__global__ __launch_bounds__(1024) void k_plan(const Desc* __restrict__ d, int mode)
+{
+    __shared__ int64_t s_tmp[1024];
+    __shared__ uint64_t s_key[kPlanSortCap];
+    const int t = threadIdx.x;
+    const int64_t E = d->n_events;
+    if (d->cnt->err) return;
+    if (mode < 0) mode = d->seed_mode;
+    const int64_t* so = mode == 1 ? d->in_seed_off : (mode == 2 ? d->in_theta_off : nullptr);
+    const int64_t lat = (int64_t)d->lattice_n[0] * d->lattice_n[1];
+    uint32_t err = 0;
+    if (so && t == 0 && so[0] != 0) err |= (mode == 1 ? kErrSeedOff : kErrThetaOff);
+    // global seed offsets in event order
+    int64_t carry = 0;
+    for (int64_t e0 = 0; e0 < E; e0 += 1024) {
+        const int64_t e = e0 + t;
+        int64_t n = 0;
+        if (e < E) {
+            n = so ? so[e + 1] - so[e] : lat;
+            if (n < 0) { err |= (mode == 1 ? kErrSeedOff : kErrThetaOff); n = 0; }
+        }
+        int64_t tot;
+        const int64_t ex = block_excl_scan(n, s_tmp, tot);
+        if (e < E) d->seed_off[e] = carry + ex;
+        carry += tot;
+    }
+    if (t == 0) { d->seed_off[E] = carry; d->cnt->total_seeds = carry; }
+    if (err) atomicOr(&d->cnt->err, err);
+    __syncthreads();
+    if (d->cnt->err) return;
+    // longest first: key = cost (hits x seeds) high, event index low (ties: batch order)
+    const bool sorted = E <= kPlanSortCap;
+    int64_t n_pad = 1;
+    while (n_pad < E) n_pad <<= 1;
+    if (sorted) {
+        for (int64_t e = t; e < n_pad; e += 1024) {
+            uint64_t key = 0;
+            if (e < E) {
+                const uint64_t ns = (uint64_t)(d->seed_off[e + 1] - d->seed_off[e]);
+                uint64_t cost = (uint64_t)d->ev_nhits[e] * ns + ns;  // + ns: hit-less events still cost
+                if (cost > 0xFFFFFFFFull) cost = 0xFFFFFFFFull;
+                key = (cost << 32) | (uint64_t)(0xFFFFFFFFu - (uint32_t)e);
+            }
+            s_key[e] = key;
+        }
+        __syncthreads();
+        for (int64_t k = 2; k <= n_pad; k <<= 1) {
+            for (int64_t j = k >> 1; j > 0; j >>= 1) {
+                for (int64_t i = t; i < n_pad; i += 1024) {
+                    const int64_t l = i ^ j;
+                    if (l > i) {
+                        const uint64_t a = s_key[i], b = s_key[l];
+                        const bool desc = (i & k) == 0;
+                        if (desc ? (a < b) : (a > b)) { s_key[i] = b; s_key[l] = a; }
+                    }
+                }
+                __syncthreads();
+            }
+        }
+        for (int64_t r = t; r < E; r += 1024) d->order[r] = (int32_t)(0xFFFFFFFFu - (uint32_t)(s_key[r] & 0xFFFFFFFFull));
+    } else {
+        for (int64_t r = t; r < E; r += 1024) d->order[r] = (int32_t)r;
+    }
+    __syncthreads();
+    // items in rank order
+    const int spi = d->seeds_per_item;
+    carry = 0;
+    for (int64_t r0 = 0; r0 < E; r0 += 1024) {
+        const int64_t r = r0 + t;
+        int64_t nb = 0;
+        int e = 0;
+        if (r < E) {
+            e = d->order[r];
+            const int64_t ns = d->seed_off[e + 1] - d->seed_off[e];
+            nb = (ns + spi - 1) / spi;
+        }
+        int64_t tot;
+        const int64_t ex = block_excl_scan(nb, s_tmp, tot);
+        if (r < E) {
+            for (int64_t b = 0; b < nb; ++b) {
+                const int64_t it = carry + ex + b;
+                if (it < d->items_cap) d->items[it] = make_int2(e, (int)(b * spi));
+            }
+        }
+        carry += tot;
+    }
+    if (t == 0) {
+        if (carry > d->items_cap) atomicOr(&d->cnt->err, kErrSeedOff);
+        d->cnt->n_items = carry;
+    }
+}
+
+void launch_reset(const Desc* d, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_reset, dim3(1), dim3(64), 0, st, d);
+}
+
+void launch_stage(const Desc* d, int grid, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_stage, dim3(grid), dim3(kBlock), 0, st, d);
+}
+
+void launch_plan_tracks(const Desc* d, hipStream_t st)
+{
+    // the host sets seed_mode 0 (lattice) or 1 (explicit) in the descriptor; the
+    // kernel's mode argument mirrors it so a captured graph needs no host branch
+    hipLaunchKernelGGL(k_plan, dim3(1), dim3(1024), 0, st, d, -1);
+}
+
+void launch_plan_response(const Desc* d, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_plan, dim3(1), dim3(1024), 0, st, d, 2);
+}
+
+}  // namespace rt

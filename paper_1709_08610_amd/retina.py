@@ -1,0 +1,358 @@
+"""ctypes binding of libretina (include/retina.h): argument marshalling only.
+
+Every computation runs in the HIP library; this module converts numpy arrays
+(host memory) or torch tensors on the GPU (device memory) into the C
+structures and calls the entry point of the same name.  A missing or
+unloadable libretina.so raises immediately: there is no fallback.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from typing import Optional
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libretina.so")
+
+OK, ERR_INVALID_ARG, ERR_OUT_OF_MEMORY, ERR_DEVICE, ERR_CAPACITY, ERR_INTERNAL = 0, -1, -2, -3, -4, -6
+MEM_HOST, MEM_DEVICE = 0, 1
+WANT_R, WANT_GRAD, WANT_HESS = 1, 2, 4
+SEED_LATTICE, SEED_EXPLICIT = 0, 1
+CONVERGED, STALLED, NOT_PD, NEGCURV = 1, 2, 4, 8
+MAX_PLANES, MAX_SIGMA = 64, 16
+
+
+class RetinaError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__("libretina error %d: %s" % (code, msg))
+        self.code = code
+
+
+class Geometry(ctypes.Structure):
+    _fields_ = [("meas_dim", ctypes.c_int32), ("n_planes", ctypes.c_int32),
+                ("plane_z", ctypes.POINTER(ctypes.c_float))]
+
+
+class Hits(ctypes.Structure):
+    _fields_ = [("mem", ctypes.c_int32), ("n_events", ctypes.c_int64),
+                ("event_offsets", ctypes.c_void_p), ("x", ctypes.c_void_p),
+                ("y", ctypes.c_void_p), ("plane", ctypes.c_void_p)]
+
+
+class Params(ctypes.Structure):
+    _fields_ = [("n_sigma", ctypes.c_int32), ("sigma", ctypes.POINTER(ctypes.c_float)),
+                ("sigma_final", ctypes.c_float), ("n_final_steps", ctypes.c_int32),
+                ("n_polish", ctypes.c_int32), ("ls_trials", ctypes.c_int32),
+                ("armijo_c1", ctypes.c_float), ("step_cap_sigmas", ctypes.c_float),
+                ("small_step_sigmas", ctypes.c_float), ("n_slope_steps", ctypes.c_int32),
+                ("conv_tol", ctypes.c_float), ("R0", ctypes.c_float), ("d_merge", ctypes.c_float),
+                ("seed_mode", ctypes.c_int32), ("lattice_n", ctypes.c_int32 * 2),
+                ("lattice_lo", ctypes.c_float * 2), ("lattice_hi", ctypes.c_float * 2),
+                ("seeds", ctypes.c_void_p), ("seed_offsets", ctypes.c_void_p)]
+
+
+class Track(ctypes.Structure):
+    _fields_ = [("theta", ctypes.c_double * 4), ("R", ctypes.c_float), ("n_members", ctypes.c_int32),
+                ("seed_index", ctypes.c_int32), ("flags", ctypes.c_int32)]
+
+
+TRACK_DTYPE = np.dtype([("theta", np.float64, (4,)), ("R", np.float32), ("n_members", np.int32),
+                        ("seed_index", np.int32), ("flags", np.int32)])
+assert TRACK_DTYPE.itemsize == ctypes.sizeof(Track) == 48
+
+
+class SeedOut(ctypes.Structure):
+    _fields_ = [("theta", ctypes.c_void_p), ("R", ctypes.c_void_p), ("flags", ctypes.c_void_p),
+                ("n_reval", ctypes.c_void_p), ("capacity", ctypes.c_int64)]
+
+
+_lib = None
+
+class Profile(ctypes.Structure):
+    _fields_ = [("calls", ctypes.c_int64), ("ms_stage", ctypes.c_double), ("ms_plan", ctypes.c_double),
+                ("ms_hot", ctypes.c_double), ("ms_merge", ctypes.c_double), ("ms_total", ctypes.c_double)]
+
+
+EXPORTS = ["retina_create", "retina_destroy", "retina_last_error", "retina_set_stream",
+           "retina_set_max_device_bytes", "retina_set_tuning", "retina_get_tuning",
+           "retina_set_profiling", "retina_get_profile", "retina_profile_reset",
+           "retina_response", "retina_find_tracks"]
+
+
+def load(path: str = LIB_PATH):
+    """Load libretina.so; raises if it was not built."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise RuntimeError("libretina.so is not built (%s); run __graft_entry__.build()" % path)
+    # One HIP runtime per process: PyTorch resolves "libamdhip64.so" from its own
+    # directory, libretina resolves "libamdhip64.so.7" (the same SONAME).  Loading
+    # torch's copy first lets libretina bind to it; the other order would leave two
+    # runtimes in the process and torch would see no GPU.
+    try:
+        import torch  # noqa: F401
+        if torch.version.hip is not None:
+            ctypes.CDLL(os.path.join(os.path.dirname(torch.__file__), "lib", "libamdhip64.so"),
+                        mode=ctypes.RTLD_GLOBAL)
+    except ImportError:
+        pass
+    lib = ctypes.CDLL(path)
+    V, P = ctypes.c_void_p, ctypes.c_void_p
+    lib.retina_create.argtypes = [ctypes.c_int, ctypes.POINTER(ctypes.c_void_p)]
+    lib.retina_create.restype = ctypes.c_int
+    lib.retina_destroy.argtypes = [V]
+    lib.retina_destroy.restype = None
+    lib.retina_last_error.argtypes = [V]
+    lib.retina_last_error.restype = ctypes.c_char_p
+    lib.retina_set_stream.argtypes = [V, V]
+    lib.retina_set_stream.restype = ctypes.c_int
+    lib.retina_set_max_device_bytes.argtypes = [V, ctypes.c_int64]
+    lib.retina_set_max_device_bytes.restype = ctypes.c_int
+    I32 = ctypes.c_int32
+    lib.retina_set_profiling.argtypes = [V, I32]
+    lib.retina_set_profiling.restype = ctypes.c_int
+    lib.retina_get_profile.argtypes = [V, ctypes.POINTER(Profile)]
+    lib.retina_get_profile.restype = ctypes.c_int
+    lib.retina_profile_reset.argtypes = [V]
+    lib.retina_profile_reset.restype = ctypes.c_int
+    lib.retina_set_tuning.argtypes = [V, I32, I32, I32, I32]
+    lib.retina_set_tuning.restype = ctypes.c_int
+    lib.retina_get_tuning.argtypes = [V, I32, I32, ctypes.POINTER(I32), ctypes.POINTER(I32), ctypes.POINTER(I32)]
+    lib.retina_get_tuning.restype = ctypes.c_int
+    lib.retina_response.argtypes = [V, ctypes.POINTER(Geometry), ctypes.POINTER(Hits), P, ctypes.c_int64,
+                                    P, ctypes.c_float, ctypes.c_uint32, P, P, P]
+    lib.retina_response.restype = ctypes.c_int
+    lib.retina_find_tracks.argtypes = [V, ctypes.POINTER(Geometry), ctypes.POINTER(Hits),
+                                       ctypes.POINTER(Params), P, ctypes.c_int64, P, P,
+                                       ctypes.POINTER(SeedOut)]
+    lib.retina_find_tracks.restype = ctypes.c_int
+    _lib = lib
+    return lib
+
+
+def _is_torch(a):
+    return type(a).__module__.startswith("torch")
+
+
+def _ptr(a):
+    if a is None:
+        return None
+    if _is_torch(a):
+        return ctypes.c_void_p(a.data_ptr())
+    return a.ctypes.data_as(ctypes.c_void_p)
+
+
+def _mem_of(a):
+    if _is_torch(a):
+        if not a.is_cuda:
+            raise TypeError("torch tensors must live on the GPU (use numpy for host memory)")
+        return MEM_DEVICE
+    return MEM_HOST
+
+
+def _host(a, dt):
+    return None if a is None else np.ascontiguousarray(a, dtype=dt)
+
+
+def _dev(a, dt):
+    import torch
+    if a is None:
+        return None
+    if a.dtype != dt or not a.is_contiguous():
+        raise TypeError("device array must be a contiguous %s tensor" % dt)
+    return a
+
+
+class Context:
+    """One libretina context (device pool + stream) on a gfx950 device."""
+
+    def __init__(self, device: int = 0):
+        self.lib = load()
+        h = ctypes.c_void_p()
+        rc = self.lib.retina_create(int(device), ctypes.byref(h))
+        if rc != OK:
+            raise RetinaError(rc, "retina_create(%d) failed: no usable gfx950 device" % device)
+        self.h = h
+        self.device = device
+
+    def close(self):
+        if getattr(self, "h", None):
+            self.lib.retina_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def _check(self, rc):
+        if rc != OK:
+            raise RetinaError(rc, self.lib.retina_last_error(self.h).decode())
+
+    def set_stream(self, stream_handle: Optional[int]):
+        self._check(self.lib.retina_set_stream(self.h, ctypes.c_void_p(stream_handle or 0)))
+
+    def set_max_device_bytes(self, n: int):
+        self._check(self.lib.retina_set_max_device_bytes(self.h, int(n)))
+
+    def retina_set_profiling(self, enable: bool):
+        self._check(self.lib.retina_set_profiling(self.h, int(bool(enable))))
+
+    def retina_get_profile(self) -> dict:
+        p = Profile()
+        self._check(self.lib.retina_get_profile(self.h, ctypes.byref(p)))
+        return {k: getattr(p, k) for k, _ in Profile._fields_}
+
+    def retina_profile_reset(self):
+        self._check(self.lib.retina_profile_reset(self.h))
+
+    def retina_set_tuning(self, meas_dim: int, kernel: int, cand: int, tile_hits: int):
+        self._check(self.lib.retina_set_tuning(self.h, meas_dim, kernel, cand, tile_hits))
+
+    def retina_get_tuning(self, meas_dim: int, kernel: int):
+        c, t, g = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32()
+        self._check(self.lib.retina_get_tuning(self.h, meas_dim, kernel, ctypes.byref(c),
+                                               ctypes.byref(t), ctypes.byref(g)))
+        return dict(cand=c.value, tile_hits=t.value, grid=g.value)
+
+    # ------------------------------------------------------------ marshalling
+    @staticmethod
+    def _geometry(meas_dim, plane_z):
+        z = np.ascontiguousarray(plane_z, dtype=np.float32)
+        g = Geometry(int(meas_dim), int(z.shape[0]), z.ctypes.data_as(ctypes.POINTER(ctypes.c_float)))
+        return g, z
+
+    def _hits(self, meas_dim, event_offsets, x, y, plane):
+        mem = _mem_of(x)
+        if mem == MEM_HOST:
+            off = _host(event_offsets, np.int64)
+            x = _host(x, np.float32)
+            y = _host(y, np.float32) if meas_dim == 2 else None
+            plane = _host(plane, np.int32)
+        else:
+            import torch
+            off = _dev(event_offsets, torch.int64)
+            x = _dev(x, torch.float32)
+            y = _dev(y, torch.float32) if meas_dim == 2 else None
+            plane = _dev(plane, torch.int32)
+        hits = Hits(mem, int(off.shape[0]) - 1, _ptr(off), _ptr(x), _ptr(y), _ptr(plane))
+        return hits, (off, x, y, plane), mem
+
+    # ------------------------------------------------------------- entries
+    def retina_response(self, meas_dim, plane_z, event_offsets, x, y, plane, theta,
+                        theta_offsets=None, sigma=1.0, want=WANT_R | WANT_GRAD | WANT_HESS):
+        """Eq. (1) (+ gradient, packed Hessian) at each row of theta.
+        Returns (R, grad, hess) in the memory space of the inputs."""
+        g, zkeep = self._geometry(meas_dim, plane_z)
+        hits, keep, mem = self._hits(meas_dim, event_offsets, x, y, plane)
+        npar = 2 * meas_dim
+        nh = npar * (npar + 1) // 2
+        if mem == MEM_HOST:
+            th = _host(theta, np.float32).reshape(-1, npar)
+            to = _host(theta_offsets, np.int64) if theta_offsets is not None else None
+            n = th.shape[0]
+            R = np.zeros(n, np.float32)
+            G = np.zeros((n, npar), np.float32) if want & WANT_GRAD else None
+            H = np.zeros((n, nh), np.float32) if want & WANT_HESS else None
+        else:
+            import torch
+            th = _dev(theta, torch.float32)
+            to = _dev(theta_offsets, torch.int64) if theta_offsets is not None else None
+            n = th.numel() // npar
+            R = torch.zeros(n, dtype=torch.float32, device=th.device)
+            G = torch.zeros((n, npar), dtype=torch.float32, device=th.device) if want & WANT_GRAD else None
+            H = torch.zeros((n, nh), dtype=torch.float32, device=th.device) if want & WANT_HESS else None
+            self.set_stream(torch.cuda.current_stream(th.device).cuda_stream)
+        rc = self.lib.retina_response(self.h, ctypes.byref(g), ctypes.byref(hits), _ptr(th), int(n),
+                                      _ptr(to), float(sigma), int(want), _ptr(R), _ptr(G), _ptr(H))
+        self._check(rc)
+        return R, G, H
+
+    def retina_find_tracks(self, meas_dim, plane_z, event_offsets, x, y, plane, params: dict,
+                           seeds=None, seed_offsets=None, capacity=None, want_seeds=False):
+        """Algorithm 1 over the batch.  Returns dict(tracks (structured numpy
+        array or uint8 tensor view), track_offsets, event_flags, seeds...)."""
+        g, zkeep = self._geometry(meas_dim, plane_z)
+        hits, keep, mem = self._hits(meas_dim, event_offsets, x, y, plane)
+        npar = 2 * meas_dim
+        E = hits.n_events
+        sig = np.ascontiguousarray(params["sigma"], dtype=np.float32)
+        P = Params()
+        P.n_sigma = len(sig)
+        P.sigma = sig.ctypes.data_as(ctypes.POINTER(ctypes.c_float))
+        for k in ("sigma_final", "n_final_steps", "n_polish", "ls_trials", "armijo_c1",
+                  "step_cap_sigmas", "small_step_sigmas", "conv_tol", "R0", "d_merge"):
+            setattr(P, k, params[k])
+        P.n_slope_steps = params.get("n_slope_steps", 0)
+        P.lattice_n[:] = list(params["lattice_n"])
+        P.lattice_lo[:] = list(params["lattice_lo"])
+        P.lattice_hi[:] = list(params["lattice_hi"])
+        if seeds is not None:
+            P.seed_mode = SEED_EXPLICIT
+            if mem == MEM_HOST:
+                seeds = _host(seeds, np.float64).reshape(-1, npar)
+                seed_offsets = _host(seed_offsets, np.int64)
+                n_seeds = int(seed_offsets[-1])
+            else:
+                import torch
+                seeds = _dev(seeds, torch.float64)
+                seed_offsets = _dev(seed_offsets, torch.int64)
+                n_seeds = int(seed_offsets[-1].item())
+            P.seeds = _ptr(seeds)
+            P.seed_offsets = _ptr(seed_offsets)
+        else:
+            P.seed_mode = SEED_LATTICE
+            n_seeds = E * params["lattice_n"][0] * params["lattice_n"][1]
+        cap = n_seeds if capacity is None else int(capacity)
+        if mem == MEM_HOST:
+            tracks = np.zeros(max(cap, 1), TRACK_DTYPE)
+            toff = np.zeros(E + 1, np.int64)
+            evf = np.zeros(max(E, 1), np.int32)
+            so = None
+            if want_seeds:
+                st = np.zeros((max(n_seeds, 1), npar))
+                sR = np.zeros(max(n_seeds, 1), np.float32)
+                sf = np.zeros(max(n_seeds, 1), np.int32)
+                snr = np.zeros(max(n_seeds, 1), np.int32)
+        else:
+            import torch
+            dev = x.device
+            self.set_stream(torch.cuda.current_stream(dev).cuda_stream)
+            tracks = torch.zeros(max(cap, 1) * 48, dtype=torch.uint8, device=dev)
+            toff = torch.zeros(E + 1, dtype=torch.int64, device=dev)
+            evf = torch.zeros(max(E, 1), dtype=torch.int32, device=dev)
+            if want_seeds:
+                st = torch.zeros((max(n_seeds, 1), npar), dtype=torch.float64, device=dev)
+                sR = torch.zeros(max(n_seeds, 1), dtype=torch.float32, device=dev)
+                sf = torch.zeros(max(n_seeds, 1), dtype=torch.int32, device=dev)
+                snr = torch.zeros(max(n_seeds, 1), dtype=torch.int32, device=dev)
+        so_struct = SeedOut(_ptr(st), _ptr(sR), _ptr(sf), _ptr(snr), n_seeds) if want_seeds else None
+        rc = self.lib.retina_find_tracks(self.h, ctypes.byref(g), ctypes.byref(hits), ctypes.byref(P),
+                                         _ptr(tracks), cap, _ptr(toff), _ptr(evf),
+                                         ctypes.byref(so_struct) if so_struct is not None else None)
+        if rc == ERR_CAPACITY:
+            need = int(toff[-1]) if mem == MEM_HOST else int(toff[-1].item())
+            err = RetinaError(rc, self.lib.retina_last_error(self.h).decode())
+            err.required = need
+            raise err
+        self._check(rc)
+        out = dict(track_offsets=toff, event_flags=evf[:E])
+        if mem == MEM_HOST:
+            out["tracks"] = tracks[:int(toff[-1])]
+        else:
+            out["tracks_bytes"] = tracks
+        if want_seeds:
+            out.update(seed_theta=st[:n_seeds], seed_R=sR[:n_seeds], seed_flags=sf[:n_seeds],
+                       seed_nreval=snr[:n_seeds])
+        return out
+
+
+def tracks_from_device(res) -> np.ndarray:
+    """Copy a device-memory find_tracks result's tracks to a structured array."""
+    raw = res["tracks_bytes"].cpu().numpy()
+    n = int(res["track_offsets"][-1].item())
+    return raw[: n * 48].view(TRACK_DTYPE)

@@ -1,0 +1,273 @@
+"""GPU parity: the HIP path through the C-ABI against the FP64 oracle.
+
+Tolerances (FP32 on the GPU, FP64 in the oracle): R within 1e-5 relative,
+gradient / Hessian entries within 1e-4 relative (with a small floor relative
+to the largest entry), track sets identical after matching within d_merge,
+track parameters within 1e-4 relative to max(|p|, s_p)."""
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_1709_08610_amd import events, retina
+
+from gpu_util import assert_response_bounded, assert_tracks_match, event_tracks, fp32_error_model
+
+pytestmark = pytest.mark.gpu
+
+
+def _say(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    return retina.Context(0)
+
+
+def _ref_response(b, e, theta, sigma):
+    ev = b.event(e)
+    return oracle.response(b.meas_dim, b.plane_z, ev.x, ev.y, ev.plane, theta, sigma)
+
+
+def _check_response(b, e, theta, sigma, R, G=None, H=None):
+    """GPU values at identical FP32 theta against the oracle, within 1e-5 (R) /
+    1e-4 (G, H) relative widened by the FP32 forward error bound."""
+    ev = b.event(e)
+    th = np.asarray(theta, np.float32).astype(np.float64)
+    Rr, Gr, Hr = oracle.response(b.meas_dim, b.plane_z, ev.x, ev.y, ev.plane, th, sigma)
+    model = fp32_error_model(b.meas_dim, b.plane_z, ev.x, ev.y, ev.plane, th, sigma)
+    assert_response_bounded(R, Rr, G, Gr if G is not None else None, H, Hr if H is not None else None,
+                            model, ev.n_hits, sigma, float(np.abs(b.plane_z).max()))
+
+
+# ----------------------------------------------------------------- response
+@pytest.mark.parametrize("sigma", [2.0, 0.25, 0.03])
+def test_response_parity_c2(ctx, sigma):
+    _say("response c2 sigma=%g" % sigma)
+    cfg = events.load_config("c2")
+    b = events.make_batch(cfg, 1)
+    ev = b.event(0)
+    rng = np.random.default_rng(11)
+    lat = oracle.lattice(2, cfg["params"])[::7]
+    near = ev.truth[rng.integers(0, 200, 1500)] + rng.normal(0, 1, (1500, 4)) * np.array(
+        [sigma, sigma, sigma / 400, sigma / 400])
+    theta = np.concatenate([lat, near]).astype(np.float32)
+    R, G, H = ctx.retina_response(2, b.plane_z, b.event_offsets, b.x, b.y, b.plane, theta, sigma=sigma)
+    _check_response(b, 0, theta, sigma, R, G, H)
+
+
+def test_response_parity_c1_grid(ctx):
+    """The c1 brute-force 400 x 400 grid of (alpha, beta) lines, D = 1."""
+    _say("response c1 grid")
+    cfg = events.load_config("c1")
+    b = events.make_batch(cfg, 1)
+    ta = np.linspace(-1, 1, 400)
+    xb = np.linspace(-0.5, 0.5, 400)
+    TT, XX = np.meshgrid(ta, xb, indexing="ij")
+    theta = np.stack([XX.ravel(), TT.ravel()], axis=1).astype(np.float32)
+    R, G, H = ctx.retina_response(1, b.plane_z, b.event_offsets, b.x, None, b.plane, theta, sigma=0.02)
+    _check_response(b, 0, theta, 0.02, R, G, H)
+
+
+def test_response_multi_event_ragged(ctx):
+    """Several events with uneven hit and theta counts, including an event without
+    hits and an event without thetas; R-only request."""
+    _say("response ragged batch")
+    cfg = events.load_config("c3")
+    evs = [events.make_event(cfg, i) for i in range(3)]
+    empty = events.Event(np.zeros(0, np.float32), np.zeros(0, np.float32), np.zeros(0, np.int32),
+                         np.zeros(0, np.int32), np.zeros((0, 4)), np.zeros(0, np.int32))
+    evs = [evs[0], empty, evs[1], evs[2]]
+    b = events.batch_from_events(2, events.plane_z(cfg), evs)
+    rng = np.random.default_rng(3)
+    counts = [300, 17, 0, 1025]
+    th = [np.c_[rng.normal(0, 0.05, (n, 2)), rng.uniform(-0.3, 0.3, (n, 2))] for n in counts]
+    theta = np.concatenate(th).astype(np.float32)
+    toff = np.r_[0, np.cumsum(counts)].astype(np.int64)
+    R, G, H = ctx.retina_response(2, b.plane_z, b.event_offsets, b.x, b.y, b.plane, theta, toff,
+                                  sigma=0.5, want=retina.WANT_R)
+    assert G is None and H is None
+    for e in range(4):
+        if counts[e] == 0:
+            continue
+        if evs[e].n_hits == 0:
+            assert np.all(R[toff[e]:toff[e + 1]] == 0)
+        else:
+            _check_response(b, e, theta[toff[e]:toff[e + 1]], 0.5, R[toff[e]:toff[e + 1]])
+
+
+@pytest.mark.parametrize("cand,tile", [(1, 512), (2, 512), (2, 6144), (1, 16384)])
+def test_response_launch_shapes_agree(ctx, cand, tile):
+    """Every tuning shape (candidates per lane, LDS tile, tiled streaming of events
+    larger than the tile) gives the oracle's values."""
+    _say("response shape cand=%d tile=%d" % (cand, tile))
+    cfg = events.load_config("c2")
+    b = events.make_batch(cfg, 1)
+    theta = oracle.lattice(2, cfg["params"])[::3].astype(np.float32)
+    old = ctx.retina_get_tuning(2, 1)
+    try:
+        ctx.retina_set_tuning(2, 1, cand, tile)
+        R, G, H = ctx.retina_response(2, b.plane_z, b.event_offsets, b.x, b.y, b.plane, theta, sigma=1.0)
+    finally:
+        ctx.retina_set_tuning(2, 1, old["cand"], old["tile_hits"])
+    _check_response(b, 0, theta, 1.0, R, G, H)
+
+
+def test_response_device_memory_matches_host(ctx):
+    import torch
+    _say("response device memory")
+    cfg = events.load_config("c2")
+    b = events.make_batch(cfg, 1)
+    theta = oracle.lattice(2, cfg["params"])[::5].astype(np.float32)
+    R1, G1, H1 = ctx.retina_response(2, b.plane_z, b.event_offsets, b.x, b.y, b.plane, theta, sigma=0.5)
+    dv = lambda a: torch.from_numpy(np.ascontiguousarray(a)).cuda()
+    R2, G2, H2 = ctx.retina_response(2, b.plane_z, dv(b.event_offsets), dv(b.x), dv(b.y), dv(b.plane),
+                                     dv(theta), sigma=0.5)
+    torch.cuda.synchronize()
+    np.testing.assert_array_equal(R2.cpu().numpy(), R1)
+    np.testing.assert_array_equal(H2.cpu().numpy(), H1)
+
+
+# ------------------------------------------------------------- find_tracks
+def _find(ctx, b, P, **kw):
+    return ctx.retina_find_tracks(b.meas_dim, b.plane_z, b.event_offsets, b.x, b.y, b.plane, P, **kw)
+
+
+def test_find_tracks_parity_c1(ctx):
+    _say("find_tracks c1")
+    cfg = events.load_config("c1")
+    P = cfg["params"]
+    for idx in range(4):
+        b = events.make_batch(cfg, 1, start=idx)
+        res = _find(ctx, b, P)
+        ref = oracle.find_tracks(b, P)
+        th, R = event_tracks(res, 0, 1)
+        assert_tracks_match(1, th, R, ref["theta"], ref["R"], P["d_merge"], 1.0, 8.0)
+
+
+def test_find_tracks_parity_c2(ctx):
+    _say("find_tracks c2")
+    cfg = events.load_config("c2")
+    P = cfg["params"]
+    b = events.make_batch(cfg, 1)
+    res = _find(ctx, b, P, want_seeds=True)
+    ref = oracle.find_tracks(b, P)
+    th, R = event_tracks(res, 0, 2)
+    err = assert_tracks_match(2, th, R, ref["theta"], ref["R"], P["d_merge"], 20.0, 750.0)
+    _say("c2: %d tracks, max parameter error %.2e" % (len(R), err.max()))
+    # most individual trajectories agree too (a seed on a basin boundary may not)
+    conv_both = (res["seed_flags"] & 1).astype(bool) & (ref["seed_flags"] & 1).astype(bool)
+    d = np.abs(res["seed_theta"] - ref["seed_theta"]).max(axis=1)
+    assert np.mean(d[conv_both] < 1e-6) > 0.97
+
+
+def test_find_tracks_parity_c3_subset(ctx):
+    _say("find_tracks c3 subset")
+    cfg = events.load_config("c3")
+    P = cfg["params"]
+    b = events.make_batch(cfg, 4)
+    res = _find(ctx, b, P)
+    ref = oracle.find_tracks(b, P)
+    for e in range(4):
+        th, R = event_tracks(res, e, 2)
+        a, c = ref["track_offsets"][e], ref["track_offsets"][e + 1]
+        assert_tracks_match(2, th, R, ref["theta"][a:c], ref["R"][a:c], P["d_merge"], 20.0, 750.0)
+
+
+def test_find_tracks_explicit_seeds(ctx):
+    _say("find_tracks explicit seeds")
+    cfg = events.load_config("c3")
+    P = cfg["params"]
+    b = events.make_batch(cfg, 3, start=10)
+    rng = np.random.default_rng(5)
+    seeds, offs = [], [0]
+    for e in range(3):
+        t = b.truth[e]
+        s = np.zeros((len(t) + 40, 4))
+        s[: len(t), 2:] = t[:, 2:] + rng.normal(0, 0.002, (len(t), 2))
+        s[len(t):, 2:] = rng.uniform(-0.3, 0.3, (40, 2))
+        seeds.append(s.astype(np.float32).astype(np.float64))
+        offs.append(offs[-1] + len(s))
+    seeds = np.concatenate(seeds)
+    offs = np.array(offs, np.int64)
+    res = _find(ctx, b, P, seeds=seeds, seed_offsets=offs)
+    ref = oracle.find_tracks(b, P, seeds=seeds, seed_offsets=offs)
+    for e in range(3):
+        th, R = event_tracks(res, e, 2)
+        a, c = ref["track_offsets"][e], ref["track_offsets"][e + 1]
+        assert_tracks_match(2, th, R, ref["theta"][a:c], ref["R"][a:c], P["d_merge"], 20.0, 750.0)
+
+
+def test_find_tracks_tiled_ascent_matches(ctx):
+    """Events streamed through a small LDS tile give the same track set."""
+    _say("find_tracks tiled")
+    cfg = events.load_config("c2")
+    P = cfg["params"]
+    b = events.make_batch(cfg, 1)
+    old = ctx.retina_get_tuning(2, 0)
+    try:
+        ctx.retina_set_tuning(2, 0, 1, 1024)
+        res = _find(ctx, b, P)
+    finally:
+        ctx.retina_set_tuning(2, 0, old["cand"], old["tile_hits"])
+    ref = oracle.find_tracks(b, P)
+    th, R = event_tracks(res, 0, 2)
+    assert_tracks_match(2, th, R, ref["theta"], ref["R"], P["d_merge"], 20.0, 750.0)
+
+
+def test_find_tracks_deterministic_and_device_memory(ctx):
+    import torch
+    _say("find_tracks determinism")
+    cfg = events.load_config("c3")
+    P = cfg["params"]
+    b = events.make_batch(cfg, 6)
+    r1 = _find(ctx, b, P)
+    r2 = _find(ctx, b, P)
+    np.testing.assert_array_equal(r1["tracks"], r2["tracks"])
+    dv = lambda a: torch.from_numpy(np.ascontiguousarray(a)).cuda()
+    r3 = ctx.retina_find_tracks(2, b.plane_z, dv(b.event_offsets), dv(b.x), dv(b.y), dv(b.plane), P)
+    torch.cuda.synchronize()
+    np.testing.assert_array_equal(retina.tracks_from_device(r3), r1["tracks"])
+    np.testing.assert_array_equal(r3["track_offsets"].cpu().numpy(), r1["track_offsets"])
+
+
+def test_find_tracks_edge_cases(ctx):
+    _say("find_tracks edge cases")
+    cfg = events.load_config("c2")
+    P = cfg["params"]
+    zp = events.plane_z(cfg)
+    # no events
+    res = ctx.retina_find_tracks(2, zp, np.zeros(1, np.int64), np.zeros(0, np.float32),
+                                 np.zeros(0, np.float32), np.zeros(0, np.int32), P)
+    assert len(res["tracks"]) == 0 and list(res["track_offsets"]) == [0]
+    # an event without hits next to a real one
+    ev = events.make_event(cfg, 0)
+    empty = events.Event(np.zeros(0, np.float32), np.zeros(0, np.float32), np.zeros(0, np.int32),
+                         np.zeros(0, np.int32), np.zeros((0, 4)), np.zeros(0, np.int32))
+    b = events.batch_from_events(2, zp, [empty, ev])
+    res = _find(ctx, b, P)
+    assert res["track_offsets"][1] == 0 and res["track_offsets"][2] > 150
+    # capacity too small: the required total is reported
+    with pytest.raises(retina.RetinaError) as ei:
+        _find(ctx, b, P, capacity=10)
+    assert ei.value.code == retina.ERR_CAPACITY and ei.value.required == res["track_offsets"][2]
+
+
+@pytest.mark.parametrize("defect", ["nan", "plane", "offsets"])
+def test_find_tracks_rejects_invalid_hits(ctx, defect):
+    _say("invalid input %s" % defect)
+    cfg = events.load_config("c2")
+    b = events.make_batch(cfg, 2)
+    x, pl, off = b.x.copy(), b.plane.copy(), b.event_offsets.copy()
+    if defect == "nan":
+        x[17] = np.nan
+    elif defect == "plane":
+        pl[5] = 26
+    else:
+        off[1] = off[2] + 1
+    with pytest.raises(retina.RetinaError) as ei:
+        ctx.retina_find_tracks(2, b.plane_z, off, x, b.y, pl, cfg["params"])
+    assert ei.value.code == retina.ERR_INVALID_ARG
