@@ -127,6 +127,14 @@ def main():
     prof = ctx.retina_get_profile()
     ctx.retina_set_profiling(False)
     dt = t1 - t0
+    # the same steps replayed through the captured graph (no per-kernel events)
+    step()
+    torch.cuda.synchronize()
+    tg0 = time.perf_counter()
+    for i in range(args.steps):
+        step()
+    torch.cuda.synchronize()
+    ms_graph = (time.perf_counter() - tg0) / args.steps * 1e3
     ms_step = dt / args.steps * 1e3
     hot_ms = prof["ms_hot"] / max(prof["calls"], 1)
     achieved = flops / (hot_ms * 1e-3) / 1e12
@@ -145,6 +153,7 @@ def main():
         "steps": args.steps,
         "warmup": args.warmup,
         "ms_per_step": ms_step,
+        "ms_per_step_graph_replay": ms_graph,
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
@@ -158,6 +167,9 @@ def main():
                       "plan": prof["ms_plan"] / max(prof["calls"], 1), "ascent": hot_ms,
                       "merge": prof["ms_merge"] / max(prof["calls"], 1)},
         "response_evals_per_s": pairs / (hot_ms * 1e-3),
+        "pairs_per_launch": {"algorithmic": pairs,
+                             "executed": prof["exec_pairs"] / max(prof["calls"], 1),
+                             "executed_line_search": prof["exec_rpairs"] / max(prof["calls"], 1)},
         "roofline": {"bound": "alu", "achieved": achieved, "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s",
                      "frac": achieved / PEAK_FP32_TFLOPS, "frac_unpacked_peak": achieved / PEAK_FP32_UNPACKED,
                      "traffic": None, "kernel": "k_ascent (persistent truncated-Newton ascent)",

@@ -174,6 +174,9 @@ typedef struct {
     double ms_hot;        /* ascent (find_tracks) or response kernel */
     double ms_merge;      /* clustering + selection + output */
     double ms_total;      /* first kernel start to last kernel end */
+    double exec_pairs;    /* hit-candidate pairs the ascent kernel executed, all lanes
+                             (including lanes idle in another lane's line search) */
+    double exec_rpairs;   /* ... of which in R-only line-search passes */
 } retina_profile;
 
 int retina_set_profiling(retina_ctx* ctx, int32_t enable);
@@ -194,6 +197,22 @@ int retina_set_tuning(retina_ctx* ctx, int32_t meas_dim, int32_t kernel, int32_t
 /* Current shape: *cand, *tile_hits and the persistent grid size *grid. */
 int retina_get_tuning(const retina_ctx* ctx, int32_t meas_dim, int32_t kernel, int32_t* cand,
                       int32_t* tile_hits, int32_t* grid);
+
+/* retina_find_tracks replays one captured HIP graph per (meas_dim, launch
+ * shape, profiling) for every batch (default on); 0 launches the kernels one
+ * by one.  Results are identical either way. */
+int retina_set_graphs(retina_ctx* ctx, int32_t enable);
+
+/* Autotuner: time retina_find_tracks on `sample` (a batch representative of
+ * the workload, with `params`) for each ascent launch shape (cand 1, 2 x
+ * tile_hits 2048 .. 12288 that fit the device's LDS) and install the
+ * fastest.  With cache_path != NULL the choice is stored in that text file
+ * keyed by (device arch, meas_dim, workload class = floor(log2(mean hits per
+ * event)), seeds per event class) and later calls with the same key reuse it
+ * without timing.  *cand / *tile_hits (may be NULL) receive the choice. */
+int retina_autotune(retina_ctx* ctx, const retina_geometry* geom, const retina_hits* sample,
+                    const retina_params* params, const char* cache_path, int32_t* cand,
+                    int32_t* tile_hits);
 
 /* Eq. (1) and its derivatives at caller-given line parameters.
  *   theta        n_theta * n_par FP32 values, in the hits' memory space
@@ -230,6 +249,80 @@ int retina_find_tracks(retina_ctx* ctx, const retina_geometry* geom, const retin
                        const retina_params* params, retina_track* tracks, int64_t capacity,
                        int64_t* track_offsets, int32_t* event_flags,
                        const retina_seed_out* seeds_out);
+
+/* ------------------------------------------------------------------------
+ * Learned seed proposer (a workload extension, not part of the paper).
+ *
+ * An event's hits are binned into a 128 x 128 image over slope space
+ * (x/z, y/z) in [-0.35, 0.35)^2 with two channels (planes of the first and of
+ * the second half of the detector), counts log1p-scaled, stored BF16.  A
+ * four-layer 3x3 convolutional network (2 -> 64 -> 128 -> 96 -> 1 channels,
+ * ReLU between layers, zero padding, 186,625 parameters) maps it to a heatmap
+ * whose sigmoid is the probability that a track's slopes fall in the bin.
+ * Products run on BF16 MFMA with FP32 accumulation; the FP32 master weights
+ * are trained by Adam on a weighted binary cross-entropy (positive weight
+ * pos_weight) against targets placed at the bins of given track slopes.
+ * Seeds are the bin centres of the best k_max local maxima (3 x 3, strict;
+ * ties to the lower bin index) whose probability exceeds tau, with x0 = y0 =
+ * 0; an event whose best probability is below conf_min (or that has no
+ * maximum above tau) falls back to the lattice of the parameters.
+ * Parameter layout (retina_model_get_params): per layer W[co][tap][ci] with
+ * tap = 3 (dr + 1) + (dc + 1) for input offset (dr, dc) in (row, column) =
+ * (tx bin, ty bin), then b[co]; layers in order.
+ * ---------------------------------------------------------------------- */
+typedef struct retina_model retina_model;
+
+#define RETINA_MODEL_PARAMS 186625
+
+/* New model on ctx's device: He-normal weights (sd sqrt(2 / (9 Cin))) drawn
+ * from a counter-based generator keyed by init_key, zero biases except the
+ * last layer's (logit of 0.01). */
+int retina_model_create(retina_ctx* ctx, uint64_t init_key, retina_model** out);
+/* Binary file: magic, version, step, parameters, Adam moments, checksum. */
+int retina_model_save(const retina_model* model, const char* path);
+int retina_model_load(retina_ctx* ctx, const char* path, retina_model** out);
+void retina_model_free(retina_model* model);
+/* RETINA_MODEL_PARAMS FP32 values in the layout above (host memory). */
+int retina_model_get_params(const retina_model* model, float* out);
+int retina_model_set_params(retina_model* model, const float* in);
+/* Adam steps taken so far. */
+int64_t retina_model_step(const retina_model* model);
+
+/* One Adam step on a batch: hits (meas_dim 2) and, per event, the slope pairs
+ * (tx, ty) to mark in the target heatmap (target_offsets: n_events+1), all in
+ * the hits' memory space.  *loss receives the batch's mean loss before the
+ * step.  With lr = 0 the step only computes (grad may be non-NULL then:
+ * RETINA_MODEL_PARAMS FP32 host values, the gradient of the mean loss). */
+int retina_train_step(retina_ctx* ctx, retina_model* model, const retina_geometry* geom,
+                      const retina_hits* hits, const double* targets,
+                      const int64_t* target_offsets, float lr, float pos_weight, float* loss,
+                      float* grad);
+
+/* Network evaluation for inspection: the binned images (n_events * 128 * 128
+ * * 2 BF16 values as uint16, may be NULL) and the logits (n_events * 128 *
+ * 128 FP32, may be NULL), both in the hits' memory space, row = tx bin. */
+int retina_model_forward(retina_ctx* ctx, const retina_model* model, const retina_geometry* geom,
+                         const retina_hits* hits, uint16_t* image, float* logits);
+
+/* Seeds from the network for every event: seeds (4 doubles each, (0, 0, tx,
+ * ty)) in slots seed_offsets[e] .. seed_offsets[e+1]-1; confidence[e] = the
+ * event's best probability; fallback[e] = 1 when the event got the lattice of
+ * `params` instead.  Arrays in the hits' memory space; RETINA_ERR_CAPACITY
+ * (with seed_offsets[n_events] = the required count) when seeds do not fit. */
+int retina_propose_seeds(retina_ctx* ctx, const retina_geometry* geom, const retina_hits* hits,
+                         const retina_model* model, int32_t k_max, float tau, float conf_min,
+                         const retina_params* params, double* seeds, int64_t capacity,
+                         int64_t* seed_offsets, float* confidence, int32_t* fallback);
+
+/* Algorithm 1 with learned seeds: retina_propose_seeds followed by
+ * retina_find_tracks on those seeds, on the device without a host round
+ * trip.  params gives the method's constants and the fallback lattice;
+ * event_flags bit 4 (value 16) marks events that fell back to the lattice. */
+int retina_find_tracks_learned(retina_ctx* ctx, const retina_geometry* geom,
+                               const retina_hits* hits, const retina_params* params,
+                               const retina_model* model, int32_t k_max, float tau,
+                               float conf_min, retina_track* tracks, int64_t capacity,
+                               int64_t* track_offsets, int32_t* event_flags);
 
 #ifdef __cplusplus
 }

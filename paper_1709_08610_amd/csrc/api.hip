@@ -9,6 +9,7 @@
 #include <string>
 #include <vector>
 
+#include "proposer.h"
 #include "rt_internal.h"
 
 using namespace rt;
@@ -26,6 +27,10 @@ enum BufId {
     // staging copies for host-memory calls
     B_INX, B_INY, B_INPL, B_INOFF, B_INSEEDS, B_INSOFF, B_INTH, B_INTHOFF, B_OUTTR, B_OUTTOFF,
     B_OUTEVF, B_OUTSTH, B_OUTSR, B_OUTSFL, B_OUTSNR, B_OUTR, B_OUTG, B_OUTH,
+    // learned proposer workspace
+    B_IMG, B_ACT1, B_ACT2, B_ACT3, B_LOGIT, B_DZ4, B_DZ3, B_DZ2, B_DZ1, B_TGT, B_TGTIN, B_TGTOFF,
+    B_DWPART, B_WT, B_LOSSPART, B_LOSS, B_BPART, B_PSCORE, B_PPIX, B_PCOUNT, B_PCONF, B_PFB,
+    B_PSOFF, B_PSEEDS, B_OUTIMG, B_OUTLOGIT,
     B_COUNT
 };
 
@@ -33,6 +38,8 @@ enum BufId {
 
 struct retina_ctx {
     int device = 0;
+    char arch[64] = {0};
+    size_t lds_max = 65536;       // LDS bytes per work-group on this device
     hipStream_t own = nullptr;
     hipStream_t stream = nullptr;
     int n_cu = 0;
@@ -48,6 +55,15 @@ struct retina_ctx {
     bool prof = false;
     hipEvent_t ev[5] = {};
     retina_profile prof_acc = {};
+    // captured find_tracks launch sequences: every kernel reads its sizes from the
+    // device descriptor and runs a fixed persistent grid, so one graph per
+    // (meas_dim, launch shape, profiling) serves any batch
+    bool use_graphs = true;
+    struct GraphEntry {
+        int D, cand, tile, grid, prof;
+        hipGraphExec_t exec;
+    };
+    std::vector<GraphEntry> graphs;
 };
 
 namespace {
@@ -256,7 +272,9 @@ HotConfig default_hot(const retina_ctx* c, int D, bool ascent)
 {
     HotConfig h;
     h.cand = ascent ? 2 : 1;
-    h.tile_hits = D == 2 ? 6144 : 8192;
+    // ascent: 5632 hits (44 KB) + the line-search list (8.5 KB) keep three
+    // work-groups per CU within 160 KB of LDS
+    h.tile_hits = D == 2 ? (ascent ? 5632 : 6144) : 8192;
     h.grid = c->n_cu * hot_max_blocks_per_cu(D, h, ascent);
     return h;
 }
@@ -276,12 +294,75 @@ void prof_collect(retina_ctx* c)
         if (hipEventElapsedTime(&t[i], c->ev[i], c->ev[i + 1]) != hipSuccess) t[i] = 0.0f;
     float tot = 0.0f;
     if (hipEventElapsedTime(&tot, c->ev[0], c->ev[4]) != hipSuccess) tot = 0.0f;
+    (void)hipGetLastError();  // a failed timing query must not linger as the thread's last error
     c->prof_acc.calls += 1;
     c->prof_acc.ms_stage += t[0];
     c->prof_acc.ms_plan += t[1];
     c->prof_acc.ms_hot += t[2];
     c->prof_acc.ms_merge += t[3];
     c->prof_acc.ms_total += tot;
+    c->prof_acc.exec_pairs += (double)c->h_cnt->exec_pairs;
+    c->prof_acc.exec_rpairs += (double)c->h_cnt->exec_rpairs;
+}
+
+// The find_tracks device sequence on stream st (profiling marks included when on).
+void tracks_sequence(retina_ctx* c, int D, const HotConfig& hc, hipStream_t st)
+{
+    auto mark = [&](int i) {
+        if (c->prof) (void)hipEventRecord(c->ev[i], st);
+    };
+    mark(0);
+    launch_reset(c->d_desc, st);
+    launch_stage(c->d_desc, c->n_cu * 8, st);
+    mark(1);
+    launch_plan_tracks(c->d_desc, st);
+    mark(2);
+    launch_ascent(c->d_desc, D, hc, st);
+    mark(3);
+    launch_merge(c->d_desc, D, c->n_cu, st);
+    launch_finalize(c->d_desc, st);
+    launch_emit(c->d_desc, D, c->n_cu * 4, st);
+    mark(4);
+}
+
+// Run the sequence, through a captured graph when possible.  Capture happens
+// on the library's own stream (the caller's may be the legacy null stream);
+// the instantiated graph is then launched on the context's stream.
+int run_tracks(retina_ctx* c, int D, const HotConfig& hc)
+{
+    // profiled calls launch eagerly: the per-kernel events are recorded on the
+    // caller-visible stream, not inside a graph
+    if (c->use_graphs && !c->prof) {
+        hipGraphExec_t exec = nullptr;
+        for (auto& g : c->graphs)
+            if (g.D == D && g.cand == hc.cand && g.tile == hc.tile_hits && g.grid == hc.grid &&
+                g.prof == (int)c->prof)
+                exec = g.exec;
+        if (!exec) {
+            hipGraph_t graph = nullptr;
+            HIP_TRY(c, hipStreamSynchronize(c->stream));
+            bool ok = hipStreamBeginCapture(c->own, hipStreamCaptureModeThreadLocal) == hipSuccess;
+            if (ok) {
+                tracks_sequence(c, D, hc, c->own);
+                ok = hipStreamEndCapture(c->own, &graph) == hipSuccess && graph;
+            }
+            if (ok) ok = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0) == hipSuccess;
+            if (graph) (void)hipGraphDestroy(graph);
+            if (!ok) {
+                (void)hipGetLastError();
+                c->use_graphs = false;  // capture unsupported here: launch eagerly from now on
+            } else {
+                c->graphs.push_back({D, hc.cand, hc.tile_hits, hc.grid, (int)c->prof, exec});
+            }
+        }
+        if (exec) {
+            HIP_TRY(c, hipGraphLaunch(exec, c->stream));
+            return RETINA_OK;
+        }
+    }
+    tracks_sequence(c, D, hc, c->stream);
+    HIP_TRY(c, hipGetLastError());
+    return RETINA_OK;
 }
 
 int upload_desc(retina_ctx* c)
@@ -318,6 +399,10 @@ int retina_create(int device_ordinal, retina_ctx** out)
     retina_ctx* c = new retina_ctx();
     c->device = device_ordinal;
     c->n_cu = prop.multiProcessorCount;
+    snprintf(c->arch, sizeof(c->arch), "%.20s", prop.gcnArchName);
+    for (char* p = c->arch; *p; ++p)
+        if (*p == ':' || *p == ' ') { *p = 0; break; }
+    c->lds_max = prop.sharedMemPerBlock;
     if (hipStreamCreateWithFlags(&c->own, hipStreamNonBlocking) != hipSuccess ||
         hipMalloc(&c->d_desc, sizeof(Desc)) != hipSuccess ||
         hipHostMalloc(&c->h_desc, sizeof(Desc), hipHostMallocDefault) != hipSuccess ||
@@ -346,9 +431,11 @@ void retina_destroy(retina_ctx* c)
     if (c->h_desc) (void)hipHostFree(c->h_desc);
     if (c->d_cnt) (void)hipFree(c->d_cnt);
     if (c->h_cnt) (void)hipHostFree(c->h_cnt);
+    for (auto& g : c->graphs) (void)hipGraphExecDestroy(g.exec);
     for (int i = 0; i < 5; ++i)
         if (c->ev[i]) (void)hipEventDestroy(c->ev[i]);
     if (c->own) (void)hipStreamDestroy(c->own);
+    (void)hipGetLastError();  // leave no error of ours behind for the caller's next check
     delete c;
 }
 
@@ -409,6 +496,9 @@ int retina_set_tuning(retina_ctx* c, int32_t meas_dim, int32_t kernel, int32_t c
     const int max_tile = meas_dim == 2 ? 16384 : 32768;
     if (tile_hits < 256 || tile_hits > max_tile)
         return fail(c, RETINA_ERR_INVALID_ARG, "tile_hits must be in [256, %d]", max_tile);
+    if ((size_t)tile_hits * meas_dim * sizeof(float) + 4096 > c->lds_max)
+        return fail(c, RETINA_ERR_INVALID_ARG, "tile_hits %d exceeds this device's %zu bytes of LDS per work-group",
+                    tile_hits, c->lds_max);
     DeviceGuard guard(c->device);
     HotConfig h;
     h.cand = cand;
@@ -533,9 +623,12 @@ int retina_response(retina_ctx* c, const retina_geometry* g, const retina_hits* 
     return RETINA_OK;
 }
 
-int retina_find_tracks(retina_ctx* c, const retina_geometry* g, const retina_hits* h,
-                       const retina_params* P, retina_track* tracks, int64_t capacity,
-                       int64_t* track_offsets, int32_t* event_flags, const retina_seed_out* so)
+// seeds_dev: explicit seeds live in device memory (the learned path passes its
+// own device-resident seeds together with host or device hits)
+static int find_tracks_impl(retina_ctx* c, const retina_geometry* g, const retina_hits* h,
+                            const retina_params* P, retina_track* tracks, int64_t capacity,
+                            int64_t* track_offsets, int32_t* event_flags, const retina_seed_out* so,
+                            bool seeds_dev)
 {
     if (!c) return RETINA_ERR_INVALID_ARG;
     c->err.clear();
@@ -579,7 +672,7 @@ int retina_find_tracks(retina_ctx* c, const retina_geometry* g, const retina_hit
     const bool host = h->mem == RETINA_MEM_HOST;
     if (host && !host_offsets_ok(h->event_offsets, E))
         return fail(c, RETINA_ERR_INVALID_ARG, "event_offsets must start at 0 and be non-decreasing");
-    if (host && P->seed_mode == RETINA_SEED_EXPLICIT && !host_offsets_ok(P->seed_offsets, E))
+    if (!seeds_dev && P->seed_mode == RETINA_SEED_EXPLICIT && !host_offsets_ok(P->seed_offsets, E))
         return fail(c, RETINA_ERR_INVALID_ARG, "seed_offsets must start at 0 and be non-decreasing");
     if (E == 0) {
         if (host) track_offsets[0] = 0;
@@ -591,9 +684,9 @@ int retina_find_tracks(retina_ctx* c, const retina_geometry* g, const retina_hit
     if ((rc = read_i64(c, h->mem, h->event_offsets, E, &n_hits))) return rc;
     if (n_hits < 0 || n_hits > 0x7FFFFFFF) return fail(c, RETINA_ERR_INVALID_ARG, "bad total hit count");
     if (P->seed_mode == RETINA_SEED_EXPLICIT) {
-        if ((rc = read_i64(c, h->mem, P->seed_offsets, E, &n_seeds))) return rc;
+        if ((rc = read_i64(c, seeds_dev ? RETINA_MEM_DEVICE : RETINA_MEM_HOST, P->seed_offsets, E, &n_seeds))) return rc;
         if (n_seeds < 0 || n_seeds > 0x7FFFFFFF) return fail(c, RETINA_ERR_INVALID_ARG, "bad total seed count");
-        if (host)
+        if (!seeds_dev)
             for (int64_t i = 0; i < n_seeds * NP; ++i)
                 if (!isfinite(P->seeds[i])) return fail(c, RETINA_ERR_INVALID_ARG, "an explicit seed is NaN or infinite");
     } else {
@@ -631,7 +724,7 @@ int retina_find_tracks(retina_ctx* c, const retina_geometry* g, const retina_hit
     d.R0 = P->R0;
     d.d_merge = P->d_merge;
     if (P->seed_mode == RETINA_SEED_EXPLICIT) {
-        if (host) {
+        if (!seeds_dev) {
             double* s;
             int64_t* o;
             if ((rc = ensure_t(c, B_INSEEDS, (size_t)std::max<int64_t>(n_seeds, 1) * NP, &s))) return rc;
@@ -680,19 +773,7 @@ int retina_find_tracks(retina_ctx* c, const retina_geometry* g, const retina_hit
         }
     }
     if ((rc = upload_desc(c))) return rc;
-    prof_mark(c, 0);
-    launch_reset(c->d_desc, c->stream);
-    launch_stage(c->d_desc, (int)std::min<int64_t>((E + 3) / 4, (int64_t)c->n_cu * 8), c->stream);
-    prof_mark(c, 1);
-    launch_plan_tracks(c->d_desc, c->stream);
-    prof_mark(c, 2);
-    launch_ascent(c->d_desc, D, hc, c->stream);
-    prof_mark(c, 3);
-    launch_merge(c->d_desc, D, (int)std::min<int64_t>(E, (int64_t)c->n_cu), c->stream);
-    launch_finalize(c->d_desc, c->stream);
-    launch_emit(c->d_desc, D, (int)std::min<int64_t>(E, (int64_t)c->n_cu * 4), c->stream);
-    prof_mark(c, 4);
-    HIP_TRY(c, hipGetLastError());
+    if ((rc = run_tracks(c, D, hc))) return rc;
     if ((rc = download_counters(c))) return rc;
     prof_collect(c);
     const uint32_t err = c->h_cnt->err;
@@ -715,6 +796,649 @@ int retina_find_tracks(retina_ctx* c, const retina_geometry* g, const retina_hit
             if (so->flags) HIP_TRY(c, hipMemcpyAsync(so->flags, d.out_s_flags, sizeof(int32_t) * n_seeds, hipMemcpyDeviceToHost, c->stream));
             if (so->n_reval) HIP_TRY(c, hipMemcpyAsync(so->n_reval, d.out_s_nreval, sizeof(int32_t) * n_seeds, hipMemcpyDeviceToHost, c->stream));
         }
+        HIP_TRY(c, hipStreamSynchronize(c->stream));
+    }
+    return RETINA_OK;
+}
+
+int retina_find_tracks(retina_ctx* c, const retina_geometry* g, const retina_hits* h,
+                       const retina_params* P, retina_track* tracks, int64_t capacity,
+                       int64_t* track_offsets, int32_t* event_flags, const retina_seed_out* so)
+{
+    return find_tracks_impl(c, g, h, P, tracks, capacity, track_offsets, event_flags, so,
+                            h != nullptr && h->mem == RETINA_MEM_DEVICE);
+}
+
+int retina_set_graphs(retina_ctx* c, int32_t enable)
+{
+    if (!c) return RETINA_ERR_INVALID_ARG;
+    c->use_graphs = enable != 0;
+    return RETINA_OK;
+}
+
+int retina_autotune(retina_ctx* c, const retina_geometry* g, const retina_hits* h, const retina_params* P,
+                    const char* cache_path, int32_t* out_cand, int32_t* out_tile)
+{
+    if (!c) return RETINA_ERR_INVALID_ARG;
+    c->err.clear();
+    int rc;
+    if ((rc = check_geometry(c, g)) || (rc = check_hits(c, g, h))) return rc;
+    if (!P) return fail(c, RETINA_ERR_INVALID_ARG, "params is NULL");
+    if (h->n_events < 1) return fail(c, RETINA_ERR_INVALID_ARG, "the sample needs at least one event");
+    DeviceGuard guard(c->device);
+    const int D = g->meas_dim;
+    const int64_t E = h->n_events;
+    int64_t n_hits, n_seeds;
+    if ((rc = read_i64(c, h->mem, h->event_offsets, E, &n_hits))) return rc;
+    if (P->seed_mode == RETINA_SEED_EXPLICIT) {
+        if (!P->seed_offsets) return fail(c, RETINA_ERR_INVALID_ARG, "seed_offsets is NULL");
+        if ((rc = read_i64(c, h->mem, P->seed_offsets, E, &n_seeds))) return rc;
+    } else {
+        n_seeds = E * (int64_t)P->lattice_n[0] * P->lattice_n[1];
+    }
+    const int hit_class = (int)floor(log2(std::max<double>(1.0, (double)n_hits / (double)E)));
+    const int seed_class = (int)floor(log2(std::max<double>(1.0, (double)n_seeds / (double)E)));
+    char key[160];
+    snprintf(key, sizeof(key), "%s meas_dim=%d hits=%d seeds=%d", c->arch, D, hit_class, seed_class);
+    // cached choice?
+    if (cache_path) {
+        FILE* f = fopen(cache_path, "r");
+        if (f) {
+            char line[320];
+            int best_c = 0, best_t = 0;
+            while (fgets(line, sizeof(line), f)) {
+                const size_t kl = strlen(key);
+                int cc, tt;
+                if (strncmp(line, key, kl) == 0 && line[kl] == ' ' &&
+                    sscanf(line + kl, " cand=%d tile=%d", &cc, &tt) == 2) {
+                    best_c = cc;
+                    best_t = tt;
+                }
+            }
+            fclose(f);
+            if (best_c && retina_set_tuning(c, D, 0, best_c, best_t) == RETINA_OK) {
+                if (out_cand) *out_cand = best_c;
+                if (out_tile) *out_tile = best_t;
+                return RETINA_OK;
+            }
+        }
+    }
+    // time every shape: outputs go nowhere (capacity 0: the pipeline still runs)
+    int64_t* toff = nullptr;
+    std::vector<int64_t> host_toff;
+    if (h->mem == RETINA_MEM_DEVICE) {
+        if ((rc = ensure_t(c, B_OUTTOFF, (size_t)E + 1, &toff))) return rc;
+    } else {
+        host_toff.resize(E + 1);
+        toff = host_toff.data();
+    }
+    const HotConfig saved = c->ascent_cfg[D];
+    const bool saved_prof = c->prof;
+    const retina_profile saved_acc = c->prof_acc;
+    if ((rc = retina_set_profiling(c, 1))) return rc;
+    const int tiles[] = {2048, 4096, 5632, 6144, 8192, 12288};
+    double best_ms = 1e300;
+    int best_c = saved.cand, best_t = saved.tile_hits;
+    for (int cand = 1; cand <= 2; ++cand) {
+        for (int tile : tiles) {
+            if ((size_t)tile * D * sizeof(float) + 4096 > c->lds_max) continue;
+            if (retina_set_tuning(c, D, 0, cand, tile) != RETINA_OK) continue;
+            double ms = 0.0;
+            for (int rep = 0; rep < 2; ++rep) {  // first run warms up (graph capture, pool)
+                c->prof_acc = retina_profile{};
+                rc = retina_find_tracks(c, g, h, P, nullptr, 0, toff, nullptr, nullptr);
+                if (rc != RETINA_OK && rc != RETINA_ERR_CAPACITY) {
+                    c->ascent_cfg[D] = saved;
+                    c->prof = saved_prof;
+                    c->prof_acc = saved_acc;
+                    return rc;
+                }
+                ms = c->prof_acc.ms_hot;
+            }
+            if (ms < best_ms) {
+                best_ms = ms;
+                best_c = cand;
+                best_t = tile;
+            }
+        }
+    }
+    c->prof = saved_prof;
+    c->prof_acc = saved_acc;
+    c->err.clear();
+    if ((rc = retina_set_tuning(c, D, 0, best_c, best_t))) return rc;
+    if (cache_path) {
+        FILE* f = fopen(cache_path, "a");
+        if (f) {
+            fprintf(f, "%s cand=%d tile=%d ms=%.3f\n", key, best_c, best_t, best_ms);
+            fclose(f);
+        }
+    }
+    if (out_cand) *out_cand = best_c;
+    if (out_tile) *out_tile = best_t;
+    return RETINA_OK;
+}
+
+}  // extern "C"
+
+// ====================================================================== model
+struct retina_model {
+    retina_ctx* ctx = nullptr;
+    NetLayout L;
+    float* w32 = nullptr;     // FP32 master weights (padded layout)
+    uint16_t* wbf = nullptr;  // BF16 copy used by the kernels
+    float* m = nullptr;       // Adam moments
+    float* v = nullptr;
+    float* g = nullptr;       // gradient of the last step
+    int64_t step = 0;
+};
+
+namespace {
+
+constexpr int kPixPerChunk = 2048;  // pixels per weight-gradient partial (GEMM K of one work-group)
+const char kModelMagic[8] = {'R', 'E', 'T', 'I', 'N', 'A', 'M', '1'};
+
+int model_alloc(retina_ctx* c, retina_model* md)
+{
+    md->ctx = c;
+    md->L = net_layout();
+    const size_t n = (size_t)md->L.total;
+    if (hipMalloc(&md->w32, n * 4) != hipSuccess || hipMalloc(&md->wbf, n * 2) != hipSuccess ||
+        hipMalloc(&md->m, n * 4) != hipSuccess || hipMalloc(&md->v, n * 4) != hipSuccess ||
+        hipMalloc(&md->g, n * 4) != hipSuccess) {
+        (void)hipGetLastError();
+        return fail(c, RETINA_ERR_OUT_OF_MEMORY, "model allocation failed");
+    }
+    HIP_TRY(c, hipMemsetAsync(md->m, 0, n * 4, c->stream));
+    HIP_TRY(c, hipMemsetAsync(md->v, 0, n * 4, c->stream));
+    HIP_TRY(c, hipMemsetAsync(md->g, 0, n * 4, c->stream));
+    return RETINA_OK;
+}
+
+// logical (W[co][tap][ci], b[co] per layer) <-> padded device layout
+void logical_to_padded(const NetLayout& L, const float* in, std::vector<float>& out)
+{
+    out.assign((size_t)L.total, 0.0f);
+    int64_t q = 0;
+    for (int l = 0; l < kLayers; ++l) {
+        const int cin = kChan[l], cout = kChan[l + 1], K = conv_k(cin), Kp = conv_kp(cin);
+        for (int co = 0; co < cout; ++co)
+            for (int k = 0; k < K; ++k) out[L.w_off[l] + (int64_t)co * Kp + k] = in[q++];
+        for (int co = 0; co < cout; ++co) out[L.b_off[l] + co] = in[q++];
+    }
+}
+
+void padded_to_logical(const NetLayout& L, const float* in, float* out)
+{
+    int64_t q = 0;
+    for (int l = 0; l < kLayers; ++l) {
+        const int cin = kChan[l], cout = kChan[l + 1], K = conv_k(cin), Kp = conv_kp(cin);
+        for (int co = 0; co < cout; ++co)
+            for (int k = 0; k < K; ++k) out[q++] = in[L.w_off[l] + (int64_t)co * Kp + k];
+        for (int co = 0; co < cout; ++co) out[q++] = in[L.b_off[l] + co];
+    }
+}
+
+uint64_t splitmix64(uint64_t& s)
+{
+    uint64_t z = (s += 0x9E3779B97F4A7C15ull);
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+    return z ^ (z >> 31);
+}
+
+uint64_t fnv1a(const void* p, size_t n, uint64_t h = 1469598103934665603ull)
+{
+    const unsigned char* b = (const unsigned char*)p;
+    for (size_t i = 0; i < n; ++i) { h ^= b[i]; h *= 1099511628211ull; }
+    return h;
+}
+
+// validate + stage hits (per-plane order, plane offsets) for the proposer;
+// fills c->h_desc and leaves the staged arrays in the pool
+int proposer_stage(retina_ctx* c, const retina_geometry* g, const retina_hits* h)
+{
+    int rc;
+    if ((rc = check_geometry(c, g)) || (rc = check_hits(c, g, h))) return rc;
+    if (g->meas_dim != 2) return fail(c, RETINA_ERR_INVALID_ARG, "the proposer needs meas_dim 2");
+    const int64_t E = h->n_events;
+    if (h->mem == RETINA_MEM_HOST && !host_offsets_ok(h->event_offsets, E))
+        return fail(c, RETINA_ERR_INVALID_ARG, "event_offsets must start at 0 and be non-decreasing");
+    int64_t n_hits;
+    if ((rc = read_i64(c, h->mem, h->event_offsets, E, &n_hits))) return rc;
+    if (n_hits < 0 || n_hits > 0x7FFFFFFF) return fail(c, RETINA_ERR_INVALID_ARG, "bad total hit count");
+    Desc& d = *c->h_desc;
+    memset(&d, 0, sizeof(Desc));
+    fill_geometry(d, g);
+    d.cnt = c->d_cnt;
+    if ((rc = stage_inputs(c, d, g, h, n_hits))) return rc;
+    if ((rc = upload_desc(c))) return rc;
+    launch_reset(c->d_desc, c->stream);
+    launch_stage(c->d_desc, c->n_cu * 8, c->stream);
+    HIP_TRY(c, hipGetLastError());
+    if ((rc = download_counters(c))) return rc;
+    if (c->h_cnt->err) return device_error(c, c->h_cnt->err);
+    return RETINA_OK;
+}
+
+struct Acts {
+    uint16_t* act[kLayers];  // act[0] = image, act[l] = output of layer l-1 (post-ReLU)
+    float* logits;
+};
+
+int ensure_acts(retina_ctx* c, int64_t E, Acts& A)
+{
+    int rc;
+    const size_t px = (size_t)E * kPix;
+    if ((rc = ensure_t(c, B_IMG, px * kChan[0], &A.act[0])) || (rc = ensure_t(c, B_ACT1, px * kChan[1], &A.act[1])) ||
+        (rc = ensure_t(c, B_ACT2, px * kChan[2], &A.act[2])) || (rc = ensure_t(c, B_ACT3, px * kChan[3], &A.act[3])) ||
+        (rc = ensure_t(c, B_LOGIT, px, &A.logits)))
+        return rc;
+    return RETINA_OK;
+}
+
+// image + 4 conv layers on the staged hits of c->h_desc
+void forward_net(retina_ctx* c, const retina_model* md, int64_t E, const Acts& A)
+{
+    const Desc& d = *c->h_desc;
+    launch_bin_image(d.hits, d.plane_off, d.n_planes, 2, c->d_desc->plane_z, E, A.act[0], c->stream);
+    for (int l = 0; l < kLayers; ++l) {
+        GemmArgs a = {};
+        a.mode = kFwd;
+        a.B = (int)E;
+        a.cin = kChan[l];
+        a.cout = kChan[l + 1];
+        a.act = l < kLayers - 1 ? 1 : 0;
+        a.x = A.act[l];
+        a.w = md->wbf + md->L.w_off[l];
+        a.bias = md->w32 + md->L.b_off[l];
+        if (l < kLayers - 1) a.y_bf16 = A.act[l + 1];
+        else a.y_f32 = A.logits;
+        launch_gemm(a, c->stream);
+    }
+}
+
+}  // namespace
+
+extern "C" {
+
+int retina_model_create(retina_ctx* c, uint64_t key, retina_model** out)
+{
+    if (!c || !out) return RETINA_ERR_INVALID_ARG;
+    c->err.clear();
+    *out = nullptr;
+    DeviceGuard guard(c->device);
+    retina_model* md = new retina_model();
+    int rc = model_alloc(c, md);
+    if (rc) { retina_model_free(md); return rc; }
+    // He-normal weights from a counter-based generator keyed by `key`
+    std::vector<float> logical(md->L.logical);
+    uint64_t s = key;
+    int64_t q = 0;
+    for (int l = 0; l < kLayers; ++l) {
+        const int cin = kChan[l], cout = kChan[l + 1];
+        const double sd = sqrt(2.0 / (9.0 * cin));
+        for (int64_t i = 0; i < (int64_t)cout * conv_k(cin); ++i) {
+            const double u1 = ((splitmix64(s) >> 11) + 0.5) * (1.0 / 9007199254740992.0);
+            const double u2 = ((splitmix64(s) >> 11) + 0.5) * (1.0 / 9007199254740992.0);
+            logical[q++] = (float)(sd * sqrt(-2.0 * log(u1)) * cos(6.283185307179586 * u2));
+        }
+        for (int co = 0; co < cout; ++co) logical[q++] = l == kLayers - 1 ? (float)log(0.01 / 0.99) : 0.0f;
+    }
+    if ((rc = retina_model_set_params(md, logical.data()))) { retina_model_free(md); return rc; }
+    *out = md;
+    return RETINA_OK;
+}
+
+void retina_model_free(retina_model* md)
+{
+    if (!md) return;
+    DeviceGuard guard(md->ctx ? md->ctx->device : 0);
+    if (md->ctx) (void)hipStreamSynchronize(md->ctx->stream);
+    (void)hipFree(md->w32);
+    (void)hipFree(md->wbf);
+    (void)hipFree(md->m);
+    (void)hipFree(md->v);
+    (void)hipFree(md->g);
+    (void)hipGetLastError();
+    delete md;
+}
+
+int64_t retina_model_step(const retina_model* md) { return md ? md->step : -1; }
+
+int retina_model_set_params(retina_model* md, const float* in)
+{
+    if (!md || !in) return RETINA_ERR_INVALID_ARG;
+    retina_ctx* c = md->ctx;
+    DeviceGuard guard(c->device);
+    for (int64_t i = 0; i < md->L.logical; ++i)
+        if (!isfinite(in[i])) return fail(c, RETINA_ERR_INVALID_ARG, "parameter %lld is not finite", (long long)i);
+    std::vector<float> pad;
+    logical_to_padded(md->L, in, pad);
+    HIP_TRY(c, hipMemcpyAsync(md->w32, pad.data(), pad.size() * 4, hipMemcpyHostToDevice, c->stream));
+    launch_to_bf16(md->w32, md->wbf, md->L.total, c->stream);
+    HIP_TRY(c, hipGetLastError());
+    HIP_TRY(c, hipStreamSynchronize(c->stream));
+    return RETINA_OK;
+}
+
+int retina_model_get_params(const retina_model* md, float* out)
+{
+    if (!md || !out) return RETINA_ERR_INVALID_ARG;
+    retina_ctx* c = md->ctx;
+    DeviceGuard guard(c->device);
+    std::vector<float> pad((size_t)md->L.total);
+    HIP_TRY(c, hipMemcpyAsync(pad.data(), md->w32, pad.size() * 4, hipMemcpyDeviceToHost, c->stream));
+    HIP_TRY(c, hipStreamSynchronize(c->stream));
+    padded_to_logical(md->L, pad.data(), out);
+    return RETINA_OK;
+}
+
+int retina_model_save(const retina_model* md, const char* path)
+{
+    if (!md || !path) return RETINA_ERR_INVALID_ARG;
+    retina_ctx* c = md->ctx;
+    DeviceGuard guard(c->device);
+    const size_t n = (size_t)md->L.total;
+    std::vector<float> buf(3 * n);
+    HIP_TRY(c, hipMemcpyAsync(buf.data(), md->w32, n * 4, hipMemcpyDeviceToHost, c->stream));
+    HIP_TRY(c, hipMemcpyAsync(buf.data() + n, md->m, n * 4, hipMemcpyDeviceToHost, c->stream));
+    HIP_TRY(c, hipMemcpyAsync(buf.data() + 2 * n, md->v, n * 4, hipMemcpyDeviceToHost, c->stream));
+    HIP_TRY(c, hipStreamSynchronize(c->stream));
+    const uint64_t sum = fnv1a(buf.data(), buf.size() * 4);
+    FILE* f = fopen(path, "wb");
+    if (!f) return fail(c, RETINA_ERR_INVALID_ARG, "cannot open %s for writing", path);
+    const uint32_t version = 1, layers = kLayers;
+    const int64_t total = md->L.total, step = md->step;
+    bool ok = fwrite(kModelMagic, 8, 1, f) == 1 && fwrite(&version, 4, 1, f) == 1 && fwrite(&layers, 4, 1, f) == 1 &&
+              fwrite(&total, 8, 1, f) == 1 && fwrite(&step, 8, 1, f) == 1 && fwrite(&sum, 8, 1, f) == 1 &&
+              fwrite(buf.data(), 4, buf.size(), f) == buf.size();
+    ok = (fclose(f) == 0) && ok;
+    if (!ok) return fail(c, RETINA_ERR_INVALID_ARG, "writing %s failed", path);
+    return RETINA_OK;
+}
+
+int retina_model_load(retina_ctx* c, const char* path, retina_model** out)
+{
+    if (!c || !path || !out) return RETINA_ERR_INVALID_ARG;
+    c->err.clear();
+    *out = nullptr;
+    DeviceGuard guard(c->device);
+    FILE* f = fopen(path, "rb");
+    if (!f) return fail(c, RETINA_ERR_INVALID_ARG, "cannot open %s", path);
+    char magic[8];
+    uint32_t version = 0, layers = 0;
+    int64_t total = 0, step = 0;
+    uint64_t sum = 0;
+    bool ok = fread(magic, 8, 1, f) == 1 && fread(&version, 4, 1, f) == 1 && fread(&layers, 4, 1, f) == 1 &&
+              fread(&total, 8, 1, f) == 1 && fread(&step, 8, 1, f) == 1 && fread(&sum, 8, 1, f) == 1;
+    const NetLayout L = net_layout();
+    if (!ok || memcmp(magic, kModelMagic, 8) != 0 || version != 1 || layers != (uint32_t)kLayers || total != L.total) {
+        fclose(f);
+        return fail(c, RETINA_ERR_INVALID_ARG, "%s is not a libretina model file of this layout", path);
+    }
+    std::vector<float> buf(3 * (size_t)total);
+    ok = fread(buf.data(), 4, buf.size(), f) == buf.size();
+    fclose(f);
+    if (!ok || fnv1a(buf.data(), buf.size() * 4) != sum)
+        return fail(c, RETINA_ERR_INVALID_ARG, "%s is truncated or corrupted (checksum)", path);
+    retina_model* md = new retina_model();
+    int rc = model_alloc(c, md);
+    if (rc) { retina_model_free(md); return rc; }
+    const size_t n = (size_t)total;
+    HIP_TRY(c, hipMemcpyAsync(md->w32, buf.data(), n * 4, hipMemcpyHostToDevice, c->stream));
+    HIP_TRY(c, hipMemcpyAsync(md->m, buf.data() + n, n * 4, hipMemcpyHostToDevice, c->stream));
+    HIP_TRY(c, hipMemcpyAsync(md->v, buf.data() + 2 * n, n * 4, hipMemcpyHostToDevice, c->stream));
+    launch_to_bf16(md->w32, md->wbf, md->L.total, c->stream);
+    HIP_TRY(c, hipStreamSynchronize(c->stream));
+    md->step = step;
+    *out = md;
+    return RETINA_OK;
+}
+
+int retina_model_forward(retina_ctx* c, const retina_model* md, const retina_geometry* g, const retina_hits* h,
+                         uint16_t* image, float* logits)
+{
+    if (!c || !md) return RETINA_ERR_INVALID_ARG;
+    c->err.clear();
+    DeviceGuard guard(c->device);
+    int rc;
+    if ((rc = proposer_stage(c, g, h))) return rc;
+    const int64_t E = h->n_events;
+    if (E == 0) return RETINA_OK;
+    Acts A;
+    if ((rc = ensure_acts(c, E, A))) return rc;
+    forward_net(c, md, E, A);
+    HIP_TRY(c, hipGetLastError());
+    const size_t px = (size_t)E * kPix;
+    const hipMemcpyKind k = h->mem == RETINA_MEM_HOST ? hipMemcpyDeviceToHost : hipMemcpyDeviceToDevice;
+    if (image) HIP_TRY(c, hipMemcpyAsync(image, A.act[0], px * 2 * 2, k, c->stream));
+    if (logits) HIP_TRY(c, hipMemcpyAsync(logits, A.logits, px * 4, k, c->stream));
+    HIP_TRY(c, hipStreamSynchronize(c->stream));
+    return RETINA_OK;
+}
+
+int retina_train_step(retina_ctx* c, retina_model* md, const retina_geometry* g, const retina_hits* h,
+                      const double* targets, const int64_t* toff, float lr, float pos_weight, float* loss,
+                      float* grad_out)
+{
+    if (!c || !md) return RETINA_ERR_INVALID_ARG;
+    c->err.clear();
+    if (!toff) return fail(c, RETINA_ERR_INVALID_ARG, "target_offsets is NULL");
+    if (!(lr >= 0.0f) || !isfinite(lr) || !(pos_weight > 0.0f) || !isfinite(pos_weight))
+        return fail(c, RETINA_ERR_INVALID_ARG, "lr must be >= 0 and pos_weight > 0");
+    DeviceGuard guard(c->device);
+    int rc;
+    if ((rc = proposer_stage(c, g, h))) return rc;
+    const int64_t E = h->n_events;
+    if (E == 0) return fail(c, RETINA_ERR_INVALID_ARG, "empty batch");
+    int64_t n_tg;
+    const bool host = h->mem == RETINA_MEM_HOST;
+    if (host && !host_offsets_ok(toff, E))
+        return fail(c, RETINA_ERR_INVALID_ARG, "target_offsets must start at 0 and be non-decreasing");
+    if ((rc = read_i64(c, h->mem, toff, E, &n_tg))) return rc;
+    if (n_tg > 0 && !targets) return fail(c, RETINA_ERR_INVALID_ARG, "targets is NULL");
+    const double* tg = targets;
+    const int64_t* to = toff;
+    if (host) {
+        double* dt;
+        int64_t* dto;
+        if ((rc = ensure_t(c, B_TGTIN, (size_t)std::max<int64_t>(n_tg, 1) * 2, &dt)) ||
+            (rc = ensure_t(c, B_TGTOFF, (size_t)E + 1, &dto)))
+            return rc;
+        if (n_tg) HIP_TRY(c, hipMemcpyAsync(dt, targets, sizeof(double) * 2 * n_tg, hipMemcpyHostToDevice, c->stream));
+        HIP_TRY(c, hipMemcpyAsync(dto, toff, sizeof(int64_t) * (E + 1), hipMemcpyHostToDevice, c->stream));
+        tg = dt;
+        to = dto;
+    }
+    Acts A;
+    uint16_t* dz[kLayers];
+    uint8_t* tgt;
+    float *part, *lpart, *lsum, *bpart;
+    uint16_t* wt;
+    const size_t px = (size_t)E * kPix;
+    const int n_chunks = (int)(px / kPixPerChunk);
+    int64_t max_part = 0, max_wt = 0;
+    for (int l = 0; l < kLayers; ++l) {
+        max_part = std::max<int64_t>(max_part, (int64_t)kChan[l + 1] * conv_kp(kChan[l]));
+        max_wt = std::max<int64_t>(max_wt, (int64_t)kChan[l] * conv_kp(kChan[l + 1]));
+    }
+    if ((rc = ensure_acts(c, E, A)) || (rc = ensure_t(c, B_DZ4, px * kChan[4], &dz[3])) ||
+        (rc = ensure_t(c, B_DZ3, px * kChan[3], &dz[2])) || (rc = ensure_t(c, B_DZ2, px * kChan[2], &dz[1])) ||
+        (rc = ensure_t(c, B_DZ1, px * kChan[1], &dz[0])) || (rc = ensure_t(c, B_TGT, px, &tgt)) ||
+        (rc = ensure_t(c, B_DWPART, (size_t)n_chunks * max_part, &part)) || (rc = ensure_t(c, B_WT, (size_t)max_wt, &wt)) ||
+        (rc = ensure_t(c, B_LOSSPART, 1024, &lpart)) || (rc = ensure_t(c, B_LOSS, 1, &lsum)) ||
+        (rc = ensure_t(c, B_BPART, (size_t)n_chunks * 128, &bpart)))
+        return rc;
+    // forward
+    forward_net(c, md, E, A);
+    launch_target_image(tg, to, E, tgt, c->stream);
+    launch_bce(A.logits, tgt, (int64_t)px, pos_weight, lpart, dz[3], c->stream);
+    launch_sum(lpart, 1024, lsum, c->stream);
+    // backward, last layer first; dz[l] = gradient wrt layer l's pre-activation
+    for (int l = kLayers - 1; l >= 0; --l) {
+        const int cin = kChan[l], cout = kChan[l + 1];
+        GemmArgs a = {};
+        a.mode = kBwdW;
+        a.B = (int)E;
+        a.cin = cin;
+        a.cout = cout;
+        a.x = A.act[l];
+        a.dz = dz[l];
+        a.partial = part;
+        a.pix_per_chunk = kPixPerChunk;
+        launch_gemm(a, c->stream);
+        launch_reduce_dw(part, n_chunks, (int64_t)cout * conv_kp(cin), md->g + md->L.w_off[l], c->stream);
+        launch_bias_grad(dz[l], (int64_t)px, cout, n_chunks, bpart, md->g + md->L.b_off[l], c->stream);
+        if (l > 0) {
+            launch_transpose_w(md->wbf + md->L.w_off[l], cin, cout, wt, c->stream);
+            GemmArgs b = {};
+            b.mode = kBwdData;
+            b.B = (int)E;
+            b.cin = cin;
+            b.cout = cout;
+            b.w = wt;
+            b.dz = dz[l];
+            b.xprev = A.act[l];
+            b.y_bf16 = dz[l - 1];
+            launch_gemm(b, c->stream);
+        }
+    }
+    if (lr > 0.0f) {
+        md->step += 1;
+        launch_adam(md->w32, md->m, md->v, md->g, md->wbf, md->L.total, lr, 0.9f, 0.999f, 1e-8f, md->step, c->stream);
+    }
+    HIP_TRY(c, hipGetLastError());
+    float l_host = 0.0f;
+    HIP_TRY(c, hipMemcpyAsync(&l_host, lsum, 4, hipMemcpyDeviceToHost, c->stream));
+    std::vector<float> gpad;
+    if (grad_out) {
+        gpad.resize((size_t)md->L.total);
+        HIP_TRY(c, hipMemcpyAsync(gpad.data(), md->g, gpad.size() * 4, hipMemcpyDeviceToHost, c->stream));
+    }
+    HIP_TRY(c, hipStreamSynchronize(c->stream));
+    if (grad_out) padded_to_logical(md->L, gpad.data(), grad_out);
+    if (loss) *loss = l_host;
+    return RETINA_OK;
+}
+
+}  // extern "C"
+
+namespace {
+
+// proposer seeds into the pool (device): returns the total through *n_seeds
+int propose_device(retina_ctx* c, const retina_geometry* g, const retina_hits* h, const retina_model* md,
+                   int32_t k_max, float tau, float conf_min, const retina_params* P, ProposeArgs& pa,
+                   int64_t* n_seeds)
+{
+    int rc;
+    if (!P) return fail(c, RETINA_ERR_INVALID_ARG, "params is NULL");
+    if (k_max < 1 || k_max > 4096) return fail(c, RETINA_ERR_INVALID_ARG, "k_max must be in [1, 4096]");
+    if (!(tau > 0.0f && tau < 1.0f) || !(conf_min >= 0.0f && conf_min <= 1.0f))
+        return fail(c, RETINA_ERR_INVALID_ARG, "tau must be in (0, 1) and conf_min in [0, 1]");
+    if (P->lattice_n[0] < 1 || P->lattice_n[1] < 1 || (int64_t)P->lattice_n[0] * P->lattice_n[1] > (1 << 24))
+        return fail(c, RETINA_ERR_INVALID_ARG, "fallback lattice_n must be >= 1 with at most 2^24 seeds");
+    if ((rc = proposer_stage(c, g, h))) return rc;
+    const int64_t E = h->n_events;
+    Acts A;
+    if ((rc = ensure_acts(c, E, A))) return rc;
+    forward_net(c, md, E, A);
+    const int64_t lat = (int64_t)P->lattice_n[0] * P->lattice_n[1];
+    const int64_t cap = E * std::max<int64_t>(k_max, lat);
+    pa = ProposeArgs{};
+    pa.logits = A.logits;
+    pa.n_events = E;
+    pa.k_max = k_max;
+    pa.tau = tau;
+    pa.conf_min = conf_min;
+    for (int i = 0; i < 2; ++i) {
+        pa.lattice_n[i] = P->lattice_n[i];
+        pa.lattice_lo[i] = P->lattice_lo[i];
+        pa.lattice_hi[i] = P->lattice_hi[i];
+    }
+    if ((rc = ensure_t(c, B_PSCORE, (size_t)E * k_max, &pa.cand_score)) ||
+        (rc = ensure_t(c, B_PPIX, (size_t)E * k_max, &pa.cand_pix)) || (rc = ensure_t(c, B_PCOUNT, (size_t)E, &pa.count)) ||
+        (rc = ensure_t(c, B_PCONF, (size_t)E, &pa.confidence)) || (rc = ensure_t(c, B_PFB, (size_t)E, &pa.fallback)) ||
+        (rc = ensure_t(c, B_PSOFF, (size_t)E + 1, &pa.seed_off)))
+        return rc;
+    launch_propose_select(pa, c->stream);
+    launch_propose_offsets(pa, c->stream);
+    HIP_TRY(c, hipGetLastError());
+    if ((rc = read_i64(c, RETINA_MEM_DEVICE, pa.seed_off, E, n_seeds))) return rc;
+    if (*n_seeds > cap) return fail(c, RETINA_ERR_INTERNAL, "seed count exceeds its bound");
+    if ((rc = ensure_t(c, B_PSEEDS, (size_t)std::max<int64_t>(*n_seeds, 1) * 4, &pa.seeds))) return rc;
+    launch_propose_write(pa, c->stream);
+    HIP_TRY(c, hipGetLastError());
+    return RETINA_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int retina_propose_seeds(retina_ctx* c, const retina_geometry* g, const retina_hits* h, const retina_model* md,
+                         int32_t k_max, float tau, float conf_min, const retina_params* P, double* seeds,
+                         int64_t capacity, int64_t* seed_offsets, float* confidence, int32_t* fallback)
+{
+    if (!c || !md) return RETINA_ERR_INVALID_ARG;
+    c->err.clear();
+    if (!seed_offsets || capacity < 0 || (capacity > 0 && !seeds))
+        return fail(c, RETINA_ERR_INVALID_ARG, "seeds / seed_offsets / capacity invalid");
+    DeviceGuard guard(c->device);
+    int rc;
+    if (h && h->n_events == 0) {
+        if (h->mem == RETINA_MEM_HOST) seed_offsets[0] = 0;
+        else HIP_TRY(c, hipMemsetAsync(seed_offsets, 0, 8, c->stream));
+        HIP_TRY(c, hipStreamSynchronize(c->stream));
+        return RETINA_OK;
+    }
+    ProposeArgs pa;
+    int64_t n;
+    if ((rc = propose_device(c, g, h, md, k_max, tau, conf_min, P, pa, &n))) return rc;
+    const int64_t E = h->n_events;
+    const hipMemcpyKind k = h->mem == RETINA_MEM_HOST ? hipMemcpyDeviceToHost : hipMemcpyDeviceToDevice;
+    if (n > capacity) {
+        HIP_TRY(c, hipMemcpyAsync(seed_offsets + E, pa.seed_off + E, 8, k, c->stream));
+        HIP_TRY(c, hipStreamSynchronize(c->stream));
+        return fail(c, RETINA_ERR_CAPACITY, "%lld seeds, capacity %lld", (long long)n, (long long)capacity);
+    }
+    if (n) HIP_TRY(c, hipMemcpyAsync(seeds, pa.seeds, sizeof(double) * 4 * n, k, c->stream));
+    HIP_TRY(c, hipMemcpyAsync(seed_offsets, pa.seed_off, 8 * (E + 1), k, c->stream));
+    if (confidence) HIP_TRY(c, hipMemcpyAsync(confidence, pa.confidence, 4 * E, k, c->stream));
+    if (fallback) HIP_TRY(c, hipMemcpyAsync(fallback, pa.fallback, 4 * E, k, c->stream));
+    HIP_TRY(c, hipStreamSynchronize(c->stream));
+    return RETINA_OK;
+}
+
+int retina_find_tracks_learned(retina_ctx* c, const retina_geometry* g, const retina_hits* h,
+                               const retina_params* P, const retina_model* md, int32_t k_max, float tau,
+                               float conf_min, retina_track* tracks, int64_t capacity, int64_t* track_offsets,
+                               int32_t* event_flags)
+{
+    if (!c || !md) return RETINA_ERR_INVALID_ARG;
+    c->err.clear();
+    DeviceGuard guard(c->device);
+    int rc;
+    if (h && h->n_events == 0)
+        return retina_find_tracks(c, g, h, P, tracks, capacity, track_offsets, event_flags, nullptr);
+    ProposeArgs pa;
+    int64_t n;
+    if ((rc = propose_device(c, g, h, md, k_max, tau, conf_min, P, pa, &n))) return rc;
+    retina_params Q = *P;
+    Q.seed_mode = RETINA_SEED_EXPLICIT;
+    Q.seeds = pa.seeds;
+    Q.seed_offsets = pa.seed_off;
+    rc = find_tracks_impl(c, g, h, &Q, tracks, capacity, track_offsets, event_flags, nullptr, true);
+    if (rc) return rc;
+    if (event_flags) {
+        const int64_t E = h->n_events;
+        std::vector<int32_t> fb(E), ef(E);
+        HIP_TRY(c, hipMemcpyAsync(fb.data(), pa.fallback, 4 * E, hipMemcpyDeviceToHost, c->stream));
+        const hipMemcpyKind k = h->mem == RETINA_MEM_HOST ? hipMemcpyHostToHost : hipMemcpyDeviceToHost;
+        HIP_TRY(c, hipMemcpyAsync(ef.data(), event_flags, 4 * E, k, c->stream));
+        HIP_TRY(c, hipStreamSynchronize(c->stream));
+        for (int64_t e = 0; e < E; ++e) ef[e] |= fb[e] ? 16 : 0;
+        const hipMemcpyKind k2 = h->mem == RETINA_MEM_HOST ? hipMemcpyHostToHost : hipMemcpyHostToDevice;
+        HIP_TRY(c, hipMemcpyAsync(event_flags, ef.data(), 4 * E, k2, c->stream));
         HIP_TRY(c, hipStreamSynchronize(c->stream));
     }
     return RETINA_OK;

@@ -52,9 +52,7 @@ __device__ __forceinline__ void seg_accumulate(const float* __restrict__ s_hits,
     for (int j = 0; j < C; ++j) { pe[j] = px[j] = py[j] = pxx[j] = pyy[j] = pxy[j] = 0.0f; }
     if constexpr (D == 2) {
         const float2* h = reinterpret_cast<const float2*>(s_hits);
-#pragma unroll 2
-        for (int k = lo; k < hi; ++k) {
-            const float2 v = h[k];
+        auto pair = [&](const float2 v) {
 #pragma unroll
             for (int j = 0; j < C; ++j) {
                 float rx = __builtin_fmaf(-c.t[j][0], z, v.x);
@@ -82,7 +80,20 @@ __device__ __forceinline__ void seg_accumulate(const float* __restrict__ s_hits,
                     pxy[j] = __builtin_fmaf(ex, ry, pxy[j]);
                 }
             }
+        };
+        // two hits per iteration; the next two are read from LDS while these
+        // are processed (indices clamped to the segment: every read is in bounds)
+        const int last = hi - 1;
+        float2 a = h[lo], b = h[min(lo + 1, last)];
+        int k = lo;
+        for (; k + 1 < hi; k += 2) {
+            const float2 na = h[min(k + 2, last)], nb = h[min(k + 3, last)];
+            pair(a);
+            pair(b);
+            a = na;
+            b = nb;
         }
+        if (k < hi) pair(a);
     } else {
 #pragma unroll 4
         for (int k = lo; k < hi; ++k) {
@@ -172,10 +183,49 @@ __device__ __forceinline__ void event_pass(const Desc* __restrict__ d, float* s_
             __syncthreads();
         }
         for (int p = 0; p < ev.P; ++p) {
-            const int lo = max(s_poff[p], t0);
-            const int hi = min(s_poff[p + 1], t1);
+            // LDS values are the same in every lane: keep the loop bounds scalar
+            const int lo = __builtin_amdgcn_readfirstlane(max(s_poff[p], t0));
+            const int hi = __builtin_amdgcn_readfirstlane(min(s_poff[p + 1], t1));
             if (lo >= hi) continue;
             seg_accumulate<D, C, DERIV, DF>(s_hits, lo - t0, hi - t0, d->plane_z[p], c, cl, nc, acc);
+        }
+    }
+}
+
+// R-only pass over part `part` of `parts` of every plane segment (the waves of a
+// work-group split the hits; their partial sums are added afterwards in a
+// fixed order).  Same barrier rule as event_pass.
+template <int D, int C>
+__device__ __forceinline__ void event_pass_part(const Desc* __restrict__ d, float* s_hits,
+                                                const int* s_poff, const EventView& ev,
+                                                const Cands<C>& c, float nc, int part, int parts,
+                                                float (&acc)[C][Acc<D>::N])
+{
+    const Cands<C> zero_c = {};
+#pragma unroll
+    for (int j = 0; j < C; ++j) acc[j][0] = 0.0f;
+    for (int t0 = 0; t0 < ev.n; t0 += ev.tile_cap) {
+        const int t1 = min(ev.n, t0 + ev.tile_cap);
+        if (!ev.resident) {
+            __syncthreads();
+            if (D == 2) {
+                const float2* src = reinterpret_cast<const float2*>(ev.g_hits) + t0;
+                float2* dst = reinterpret_cast<float2*>(s_hits);
+                for (int i = threadIdx.x; i < t1 - t0; i += blockDim.x) dst[i] = src[i];
+            } else {
+                for (int i = threadIdx.x; i < t1 - t0; i += blockDim.x) s_hits[i] = ev.g_hits[t0 + i];
+            }
+            __syncthreads();
+        }
+        for (int p = 0; p < ev.P; ++p) {
+            const int lo = __builtin_amdgcn_readfirstlane(max(s_poff[p], t0));
+            const int hi = __builtin_amdgcn_readfirstlane(min(s_poff[p + 1], t1));
+            if (lo >= hi) continue;
+            const int len = hi - lo;
+            const int a = lo + (len * part) / parts;
+            const int b = lo + (len * (part + 1)) / parts;
+            if (a >= b) continue;
+            seg_accumulate<D, C, false, false>(s_hits, a - t0, b - t0, d->plane_z[p], c, zero_c, nc, acc);
         }
     }
 }
@@ -405,11 +455,17 @@ __global__ __launch_bounds__(kBlock) void k_ascent(const Desc* __restrict__ d, i
 {
     constexpr int NP = 2 * D;
     constexpr int NA = Acc<D>::N;
-    extern __shared__ float s_hits[];
+    // dynamic LDS follows the static arrays: declared float4 so it starts 16-byte
+    // aligned (the (x, y) hit pairs are read with 8-byte LDS loads)
+    extern __shared__ float4 s_dyn[];
+    float* s_hits = reinterpret_cast<float*>(s_dyn);
     __shared__ int s_poff[kMaxPlanes + 1];
     __shared__ int s_item;
+    __shared__ int s_npend;                 // line-search list: pending trial points,
+    __shared__ float s_lth[kBlock * C][4];  // then the waves' partial responses
+    static_assert(kBlock / kWave == 4, "the partial responses use one slot per wave");
     if (d->cnt->err) return;
-    const int wave = threadIdx.x / kWave;
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);  // scalar: same in every lane
     const int lane = threadIdx.x & (kWave - 1);
     const int64_t n_items = d->cnt->n_items;
     const int n_steps = d->n_sigma + d->n_final_steps;
@@ -422,10 +478,10 @@ __global__ __launch_bounds__(kBlock) void k_ascent(const Desc* __restrict__ d, i
     for (;;) {
         if (threadIdx.x == 0) s_item = (int)atomicAdd(&d->cnt->item, 1u);
         __syncthreads();
-        const int item = s_item;
+        const int item = __builtin_amdgcn_readfirstlane(s_item);
         if (item >= n_items) break;
         const int2 it = d->items[item];
-        const int e = it.x;
+        const int e = __builtin_amdgcn_readfirstlane(it.x);
         const EventView ev = begin_event(d, e, s_hits, s_poff, tile_cap);
         const int64_t sbase = d->seed_off[e];
         const int ns = (int)(d->seed_off[e + 1] - sbase);
@@ -457,6 +513,7 @@ __global__ __launch_bounds__(kBlock) void k_ascent(const Desc* __restrict__ d, i
             }
         }
 
+        int n_rpass_c1 = 0;  // single-candidate R-only passes this wave executed (line searches)
         for (int s = 0; s < n_steps; ++s) {
             const float sig = s < d->n_sigma ? d->sigma[s] : d->sigma_final;
             const float nc = -kLog2e / (sig * sig);
@@ -505,27 +562,63 @@ __global__ __launch_bounds__(kBlock) void k_ascent(const Desc* __restrict__ d, i
                     pend[j] = true;
                 }
             }
-            // backtracking line search, one R-only pass per round of trials
+            // Backtracking line search.  Each round gathers the work-group's
+            // pending trial points into an LDS list and evaluates R only for
+            // those, 64 per wave per pass: a wave no longer runs a whole pass
+            // because one of its lanes still searches.  A candidate's R does not
+            // depend on the slot that computes it (same arithmetic, same order).
             for (;;) {
-                bool any = false;
-#pragma unroll
-                for (int j = 0; j < C; ++j) any |= pend[j];
-                if (!wg_or(any, ev.resident)) break;
+                __syncthreads();
+                if (threadIdx.x == 0) s_npend = 0;
+                __syncthreads();
                 float tt[C][NP];
+                int slot[C];
 #pragma unroll
-                for (int j = 0; j < C; ++j)
+                for (int j = 0; j < C; ++j) {
+                    slot[j] = -1;
+                    if (!pend[j]) continue;
 #pragma unroll
-                    for (int a = 0; a < NP; ++a)
-                        tt[j][a] = pend[j] ? __builtin_fmaf(alpha[j], p[j][a], th[j][a]) : th[j][a];
+                    for (int a = 0; a < NP; ++a) tt[j][a] = __builtin_fmaf(alpha[j], p[j][a], th[j][a]);
+                    slot[j] = atomicAdd(&s_npend, 1);
 #pragma unroll
-                for (int j = 0; j < C; ++j) set_cand<D, C>(c, j, tt[j]);
-                float racc[C][NA];
-                event_pass<D, C, false, false>(d, s_hits, s_poff, ev, c, zero_c, nc, racc);
+                    for (int a = 0; a < NP; ++a) s_lth[slot[j]][a] = tt[j][a];
+                }
+                __syncthreads();
+                const int npend = __builtin_amdgcn_readfirstlane(s_npend);
+                if (npend == 0) break;
+                // rounds of 64*C entries; every wave evaluates all entries of a
+                // round over its quarter of each plane segment
+                const int per_round = kWave * C;
+                const int rounds = (npend + per_round - 1) / per_round;
+                for (int r = 0; r < rounds; ++r) {
+                    Cands<C> cc;
+                    bool live[C];
+                    int ent[C];
+#pragma unroll
+                    for (int j = 0; j < C; ++j) {
+                        ent[j] = r * per_round + j * kWave + lane;
+                        live[j] = ent[j] < npend;
+                        float lt[NP];
+#pragma unroll
+                        for (int a = 0; a < NP; ++a) lt[a] = live[j] ? s_lth[ent[j]][a] : 0.0f;
+                        set_cand<D, C>(cc, j, lt);
+                    }
+                    __syncthreads();  // all waves hold the round's points before partials overwrite them
+                    float racc[C][NA];
+                    event_pass_part<D, C>(d, s_hits, s_poff, ev, cc, nc, wave, kBlock / kWave, racc);
+#pragma unroll
+                    for (int j = 0; j < C; ++j)
+                        if (live[j]) s_lth[ent[j]][wave] = racc[j][0];
+                }
+                n_rpass_c1 += rounds * C;  // each round: a quarter pass over 64*C candidates per wave
+                __syncthreads();
 #pragma unroll
                 for (int j = 0; j < C; ++j) {
                     if (!pend[j]) continue;
                     ++nre[j];
-                    if (racc[j][0] >= Rc[j] + d->armijo_c1 * alpha[j] * gp[j]) {
+                    const float* pr = s_lth[slot[j]];
+                    const float Rt = ((pr[0] + pr[1]) + pr[2]) + pr[3];
+                    if (Rt >= Rc[j] + d->armijo_c1 * alpha[j] * gp[j]) {
 #pragma unroll
                         for (int a = 0; a < NP; ++a) th[j][a] = tt[j][a];
                         pend[j] = false;
@@ -603,6 +696,13 @@ __global__ __launch_bounds__(kBlock) void k_ascent(const Desc* __restrict__ d, i
             d->s_flags[gs] = flags[j];
             d->s_nreval[gs] = nre[j];
         }
+        if (lane == 0) {
+            const uint64_t per_pass = (uint64_t)ev.n * kWave;
+            const uint64_t rp = per_pass * (uint64_t)n_rpass_c1 / 4;  // quarter passes
+            atomicAdd((unsigned long long*)&d->cnt->exec_pairs,
+                      (unsigned long long)(per_pass * C * (uint64_t)(n_steps + d->n_polish) + rp));
+            atomicAdd((unsigned long long*)&d->cnt->exec_rpairs, (unsigned long long)rp);
+        }
         __syncthreads();
     }
 }
@@ -613,11 +713,14 @@ __global__ __launch_bounds__(kBlock) void k_response(const Desc* __restrict__ d,
 {
     constexpr int NP = 2 * D;
     constexpr int NA = Acc<D>::N;
-    extern __shared__ float s_hits[];
+    // dynamic LDS follows the static arrays: declared float4 so it starts 16-byte
+    // aligned (the (x, y) hit pairs are read with 8-byte LDS loads)
+    extern __shared__ float4 s_dyn[];
+    float* s_hits = reinterpret_cast<float*>(s_dyn);
     __shared__ int s_poff[kMaxPlanes + 1];
     __shared__ int s_item;
     if (d->cnt->err) return;
-    const int wave = threadIdx.x / kWave;
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);  // scalar: same in every lane
     const int lane = threadIdx.x & (kWave - 1);
     const int64_t n_items = d->cnt->n_items;
     const float sig = d->resp_sigma;
@@ -626,10 +729,10 @@ __global__ __launch_bounds__(kBlock) void k_response(const Desc* __restrict__ d,
     for (;;) {
         if (threadIdx.x == 0) s_item = (int)atomicAdd(&d->cnt->item, 1u);
         __syncthreads();
-        const int item = s_item;
+        const int item = __builtin_amdgcn_readfirstlane(s_item);
         if (item >= n_items) break;
         const int2 it = d->items[item];
-        const int e = it.x;
+        const int e = __builtin_amdgcn_readfirstlane(it.x);
         const EventView ev = begin_event(d, e, s_hits, s_poff, tile_cap);
         const int64_t sbase = d->seed_off[e];
         const int ns = (int)(d->seed_off[e + 1] - sbase);

@@ -1,0 +1,609 @@
+// Learned seed proposer kernels (gfx950).
+//
+// A four-layer 3x3 convolutional network (2 -> 64 -> 128 -> 96 -> 1 channels,
+// ReLU between layers, a sigmoid heatmap at the end) maps an event's binned
+// slope image (x/z, y/z) to a heatmap of likely track slopes.  All three
+// convolution products (forward, backward to the input, backward to the
+// weights) run through one implicit-GEMM kernel on BF16 MFMA with FP32
+// accumulation; activations and gradients are stored in BF16, weights keep an
+// FP32 master copy updated by Adam.
+//
+// Layout: images NHWC (batch, row = tx bin, column = ty bin, channel), channel
+// fastest.  Weights W[co][tap * Cin + ci] with tap = 3 * (dr + 1) + (dc + 1),
+// rows padded with zeros to a multiple of 32 (the GEMM K tile).
+#include "proposer.h"
+#include "rt_internal.h"
+
+namespace rt {
+
+typedef short v4s __attribute__((ext_vector_type(4)));
+typedef float v4f __attribute__((ext_vector_type(4)));
+
+__device__ __forceinline__ uint16_t f2bf(float f)
+{
+    uint32_t u = __float_as_uint(f);
+    u += 0x7FFFu + ((u >> 16) & 1u);  // round to nearest even
+    return (uint16_t)(u >> 16);
+}
+__device__ __forceinline__ float bf2f(uint16_t h) { return __uint_as_float((uint32_t)h << 16); }
+
+NetLayout net_layout()
+{
+    NetLayout L;
+    int64_t off = 0, logical = 0;
+    for (int l = 0; l < kLayers; ++l) {
+        const int cin = kChan[l], cout = kChan[l + 1];
+        L.w_off[l] = off;
+        off += (int64_t)cout * conv_kp(cin);
+        L.b_off[l] = off;
+        off += cout;
+        logical += (int64_t)cout * conv_k(cin) + cout;
+    }
+    L.total = off;
+    L.logical = logical;
+    return L;
+}
+
+// ------------------------------------------------------------------ binning
+// One work-group per event: a 2 x 128 x 128 histogram of hit slopes (x/z,
+// y/z) in LDS (16-bit counts, two per word), channel 0 for the first half of
+// the planes, 1 for the second; written as log1p(count) in BF16.
+__global__ __launch_bounds__(256) void k_bin_image(const float* __restrict__ hits,
+                                                   const int32_t* __restrict__ plane_off, int P, int D,
+                                                   const float* __restrict__ plane_z, int64_t E,
+                                                   uint16_t* __restrict__ img)
+{
+    __shared__ uint32_t s_h[kPix];  // 2 * kPix 16-bit counts
+    const float w = (kSlopeHi - kSlopeLo) / kImg;
+    for (int64_t e = blockIdx.x; e < E; e += gridDim.x) {
+        for (int i = threadIdx.x; i < kPix; i += blockDim.x) s_h[i] = 0;
+        __syncthreads();
+        const int32_t* po = plane_off + e * (P + 1);
+        for (int p = 0; p < P; ++p) {
+            const float z = plane_z[p];
+            const int ch = p < P / 2 ? 0 : 1;
+            for (int k = po[p] + threadIdx.x; k < po[p + 1]; k += blockDim.x) {
+                const float x = hits[(int64_t)k * D];
+                const float y = D == 2 ? hits[(int64_t)k * D + 1] : 0.0f;
+                const float u = (x / z - kSlopeLo) / w;
+                const float v = (y / z - kSlopeLo) / w;
+                if (u >= 0.0f && u < (float)kImg && v >= 0.0f && v < (float)kImg) {
+                    const int idx = (((int)u * kImg + (int)v) << 1) | ch;
+                    atomicAdd(&s_h[idx >> 1], 1u << (16 * (idx & 1)));
+                }
+            }
+        }
+        __syncthreads();
+        uint32_t* out = reinterpret_cast<uint32_t*>(img + e * kPix * 2);
+        for (int i = threadIdx.x; i < kPix; i += blockDim.x) {
+            const uint32_t c = s_h[i];
+            const float a = log1pf((float)(c & 0xFFFFu)), b = log1pf((float)(c >> 16));
+            out[i] = (uint32_t)f2bf(a) | ((uint32_t)f2bf(b) << 16);
+        }
+        __syncthreads();
+    }
+}
+
+void launch_bin_image(const float* hits, const int32_t* plane_off, int P, int D, const float* plane_z,
+                      int64_t E, uint16_t* img, hipStream_t st)
+{
+    const int grid = (int)std::min<int64_t>(E, 2048);
+    hipLaunchKernelGGL(k_bin_image, dim3(grid), dim3(256), 0, st, hits, plane_off, P, D, plane_z, E, img);
+}
+
+// Target heatmap: 1 at the bin of every target slope pair, else 0.
+__global__ void k_target_image(const double* __restrict__ tg, const int64_t* __restrict__ off, int64_t E,
+                               uint8_t* __restrict__ out)
+{
+    const double w = ((double)kSlopeHi - (double)kSlopeLo) / kImg;
+    for (int64_t e = blockIdx.x; e < E; e += gridDim.x) {
+        uint8_t* o = out + e * kPix;
+        for (int i = threadIdx.x; i < kPix; i += blockDim.x) o[i] = 0;
+        __syncthreads();
+        for (int64_t t = off[e] + threadIdx.x; t < off[e + 1]; t += blockDim.x) {
+            const double u = (tg[2 * t] - kSlopeLo) / w, v = (tg[2 * t + 1] - kSlopeLo) / w;
+            if (u >= 0.0 && u < kImg && v >= 0.0 && v < kImg) o[(int)u * kImg + (int)v] = 1;
+        }
+        __syncthreads();
+    }
+}
+
+void launch_target_image(const double* targets, const int64_t* off, int64_t E, uint8_t* tgt, hipStream_t st)
+{
+    const int grid = (int)std::min<int64_t>(E, 2048);
+    hipLaunchKernelGGL(k_target_image, dim3(grid), dim3(256), 0, st, targets, off, E, tgt);
+}
+
+// ------------------------------------------------------------ implicit GEMM
+// C[m][n] = sum_k A(m, k) B(k, n) on 64 x 64 tiles, K tile 32, four waves of
+// 32 x 32 (2 x 2 MFMA 16x16x16 bf16 blocks).  Both operands are staged in LDS
+// with k contiguous (A as [m][k], B as [n][k]); an MFMA fragment is then one
+// 8-byte LDS read per lane.  Index maps (pixel m = (b, r, c)):
+//   kFwd     A(m, k) = x[b, r + dr, c + dc, ci]      k = tap * Cin + ci
+//            B(k, n) = W[n][k]                         n = co
+//   kBwdData A(m, k) = dz[b, r - dr, c - dc, co]     k = tap * Cout + co
+//            B(k, n) = Wt[n][k] = W[co][tap * Cin + n] n = ci
+//   kBwdW    A(m, k) = dz[p, m]                        m = co, k = pixel p of the chunk
+//            B(k, n) = x[p + (dr, dc), ci]            n = tap * Cin + ci
+// (zero outside the image and beyond the logical K).
+constexpr int GBM = 64, GBN = 64, GBK = 32, GLD = GBK + 8;
+
+struct GemmShape {
+    int64_t M;
+    int N, K;
+};
+
+__device__ __forceinline__ uint16_t load_px(const uint16_t* __restrict__ t, int64_t m, int dr, int dc, int ch,
+                                            int C)
+{
+    const int64_t b = m / kPix;
+    const int r = (int)((m / kImg) % kImg) + dr, c = (int)(m % kImg) + dc;
+    if (r < 0 || r >= kImg || c < 0 || c >= kImg) return 0;
+    return t[((b * kPix) + (int64_t)r * kImg + c) * C + ch];
+}
+
+// 8 consecutive channels [ch, ch + 8) of one (shifted) pixel: one 16-byte load
+__device__ __forceinline__ uint4 load_px8(const uint16_t* __restrict__ t, int64_t m, int dr, int dc, int ch, int C)
+{
+    const int64_t b = m / kPix;
+    const int r = (int)((m / kImg) % kImg) + dr, c = (int)(m % kImg) + dc;
+    if (r < 0 || r >= kImg || c < 0 || c >= kImg) return make_uint4(0, 0, 0, 0);
+    return *reinterpret_cast<const uint4*>(t + ((b * kPix) + (int64_t)r * kImg + c) * C + ch);
+}
+
+__global__ __launch_bounds__(256) void k_gemm(GemmArgs a, GemmShape s)
+{
+    __shared__ __align__(16) uint16_t As[GBM][GLD];
+    __shared__ __align__(16) uint16_t Bs[GBN][GLD];
+    const int t = threadIdx.x;
+    const int lane = t & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(t >> 6);
+    const int wm = wave >> 1, wn = wave & 1;
+    const int64_t m0 = (int64_t)blockIdx.x * GBM;
+    const int n0 = blockIdx.y * GBN;
+    const int chunk = blockIdx.z;
+    v4f acc[2][2];
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int j = 0; j < 2; ++j) acc[i][j] = (v4f){0.f, 0.f, 0.f, 0.f};
+
+    const int cin = a.cin, cout = a.cout;
+    for (int k0 = 0; k0 < s.K; k0 += GBK) {
+        // ---- stage A and B (8 elements per thread each)
+        if (a.mode == kFwd || a.mode == kBwdData) {
+            // A: row = t / 4, k = k0 + (t % 4) * 8 .. + 7
+            const int row = t >> 2, kk = k0 + (t & 3) * 8;
+            const int64_t m = m0 + row;
+            const int C = a.mode == kFwd ? cin : cout;
+            const uint16_t* src = a.mode == kFwd ? a.x : a.dz;
+            const int sgn = a.mode == kFwd ? 1 : -1;
+            const int Klog = 9 * C;
+            uint16_t v[8];
+            if (C % 8 == 0 && kk + 8 <= Klog && m < s.M) {
+                const int tap = kk / C, ch = kk % C;
+                const uint4 q = load_px8(src, m, sgn * (tap / 3 - 1), sgn * (tap % 3 - 1), ch, C);
+                *reinterpret_cast<uint4*>(v) = q;
+            } else {
+#pragma unroll
+                for (int j = 0; j < 8; ++j) {
+                    const int k = kk + j;
+                    v[j] = 0;
+                    if (k < Klog && m < s.M) {
+                        const int tap = k / C, ch = k % C;
+                        v[j] = load_px(src, m, sgn * (tap / 3 - 1), sgn * (tap % 3 - 1), ch, C);
+                    }
+                }
+            }
+            *reinterpret_cast<uint4*>(&As[row][(t & 3) * 8]) = *reinterpret_cast<uint4*>(v);
+            // B: row n = t / 4 of W (kFwd) or Wt (kBwdData), padded rows of length K
+            const int n = n0 + row;
+            uint4 q = make_uint4(0, 0, 0, 0);
+            if (n < s.N) q = *reinterpret_cast<const uint4*>(a.w + (int64_t)n * s.K + kk);
+            *reinterpret_cast<uint4*>(&Bs[row][(t & 3) * 8]) = q;
+        } else {
+            // kBwdW: thread -> pixel kk = k0 + t / 8, 8 consecutive rows (co) / columns (n)
+            const int kkl = t >> 3, seg = (t & 7) * 8;
+            const int64_t p = (int64_t)chunk * a.pix_per_chunk + k0 + kkl;
+            // A rows m = co (dz[p][co .. co+7])
+            uint16_t v[8];
+            const int co0 = (int)m0 + seg;
+            if (cout % 8 == 0 && co0 + 8 <= cout) {
+                *reinterpret_cast<uint4*>(v) = *reinterpret_cast<const uint4*>(a.dz + p * cout + co0);
+            } else {
+#pragma unroll
+                for (int j = 0; j < 8; ++j) v[j] = co0 + j < cout ? a.dz[p * cout + co0 + j] : (uint16_t)0;
+            }
+#pragma unroll
+            for (int j = 0; j < 8; ++j) As[seg + j][kkl] = v[j];
+            // B rows n = tap * cin + ci (x[p + shift][ci .. ci+7])
+            const int nb = n0 + seg;
+            const int Klog = 9 * cin;
+            if (cin % 8 == 0 && nb + 8 <= Klog) {
+                const int tap = nb / cin, ci = nb % cin;
+                *reinterpret_cast<uint4*>(v) = load_px8(a.x, p, tap / 3 - 1, tap % 3 - 1, ci, cin);
+            } else {
+#pragma unroll
+                for (int j = 0; j < 8; ++j) {
+                    const int n = nb + j;
+                    v[j] = 0;
+                    if (n < Klog) {
+                        const int tap = n / cin, ci = n % cin;
+                        v[j] = load_px(a.x, p, tap / 3 - 1, tap % 3 - 1, ci, cin);
+                    }
+                }
+            }
+#pragma unroll
+            for (int j = 0; j < 8; ++j) Bs[seg + j][kkl] = v[j];
+        }
+        __syncthreads();
+        // ---- 2 x 2 blocks x 2 K halves of MFMA 16x16x16
+#pragma unroll
+        for (int kh = 0; kh < 2; ++kh) {
+            const int kq = kh * 16 + 4 * (lane >> 4);
+            v4s af[2], bf[2];
+#pragma unroll
+            for (int i = 0; i < 2; ++i)
+                af[i] = *reinterpret_cast<const v4s*>(&As[wm * 32 + i * 16 + (lane & 15)][kq]);
+#pragma unroll
+            for (int j = 0; j < 2; ++j)
+                bf[j] = *reinterpret_cast<const v4s*>(&Bs[wn * 32 + j * 16 + (lane & 15)][kq]);
+#pragma unroll
+            for (int i = 0; i < 2; ++i)
+#pragma unroll
+                for (int j = 0; j < 2; ++j)
+                    acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(af[i], bf[j], acc[i][j], 0, 0, 0);
+        }
+        __syncthreads();
+    }
+    // ---- epilogue: lane holds rows 4 * (lane / 16) + r, column lane % 16 of each block
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int j = 0; j < 2; ++j)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const int64_t m = m0 + wm * 32 + i * 16 + 4 * (lane >> 4) + r;
+                const int n = n0 + wn * 32 + j * 16 + (lane & 15);
+                if (m >= s.M || n >= s.N) continue;
+                const float v = acc[i][j][r];
+                if (a.mode == kFwd) {
+                    const float z = v + a.bias[n];
+                    if (a.act) a.y_bf16[m * cout + n] = f2bf(fmaxf(z, 0.0f));
+                    else a.y_f32[m * cout + n] = z;
+                } else if (a.mode == kBwdData) {
+                    float g = v;
+                    if (a.xprev && bf2f(a.xprev[m * cin + n]) <= 0.0f) g = 0.0f;
+                    a.y_bf16[m * cin + n] = f2bf(g);
+                } else {
+                    a.partial[((int64_t)chunk * cout + m) * s.N + n] = v;
+                }
+            }
+}
+
+void launch_gemm(const GemmArgs& a, hipStream_t st)
+{
+    GemmShape s;
+    dim3 grid;
+    if (a.mode == kFwd) {
+        s.M = (int64_t)a.B * kPix;
+        s.N = a.cout;
+        s.K = conv_kp(a.cin);
+        grid = dim3((unsigned)(s.M / GBM), (unsigned)((s.N + GBN - 1) / GBN), 1);
+    } else if (a.mode == kBwdData) {
+        s.M = (int64_t)a.B * kPix;
+        s.N = a.cin;
+        s.K = conv_kp(a.cout);
+        grid = dim3((unsigned)(s.M / GBM), (unsigned)((s.N + GBN - 1) / GBN), 1);
+    } else {
+        s.M = a.cout;
+        s.N = conv_kp(a.cin);
+        s.K = a.pix_per_chunk;
+        const int64_t chunks = (int64_t)a.B * kPix / a.pix_per_chunk;
+        grid = dim3((unsigned)((s.M + GBM - 1) / GBM), (unsigned)((s.N + GBN - 1) / GBN), (unsigned)chunks);
+    }
+    hipLaunchKernelGGL(k_gemm, grid, dim3(256), 0, st, a, s);
+}
+
+// ------------------------------------------------------------------ losses
+// Weighted binary cross-entropy on logits z with targets y in {0, 1}:
+//   l = w y softplus(-z) + (1 - y) softplus(z),  dl/dz = (w y + 1 - y) sigma(z) - w y
+// mean over all pixels; per-block partial sums of l (fixed order reduction).
+__global__ __launch_bounds__(256) void k_bce(const float* __restrict__ z, const uint8_t* __restrict__ y,
+                                             int64_t n, float pw, float* __restrict__ part,
+                                             uint16_t* __restrict__ dz)
+{
+    __shared__ float s[256];
+    float acc = 0.0f;
+    const float inv = 1.0f / (float)n;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+        const float zi = z[i];
+        const float yi = (float)y[i];
+        const float sp_pos = fmaxf(zi, 0.0f) + log1pf(expf(-fabsf(zi)));  // softplus(z)
+        const float sp_neg = sp_pos - zi;                                  // softplus(-z)
+        acc += pw * yi * sp_neg + (1.0f - yi) * sp_pos;
+        const float sig = 1.0f / (1.0f + expf(-zi));
+        dz[i] = f2bf(((pw * yi + 1.0f - yi) * sig - pw * yi) * inv);
+    }
+    s[threadIdx.x] = acc;
+    __syncthreads();
+    for (int o = 128; o > 0; o >>= 1) {
+        if ((int)threadIdx.x < o) s[threadIdx.x] += s[threadIdx.x + o];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) part[blockIdx.x] = s[0] * inv;
+}
+
+void launch_bce(const float* z, const uint8_t* y, int64_t n, float pw, float* part, uint16_t* dz, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_bce, dim3(1024), dim3(256), 0, st, z, y, n, pw, part, dz);
+}
+
+__global__ void k_sum(const float* __restrict__ part, int n, float* __restrict__ out)
+{
+    if (threadIdx.x == 0 && blockIdx.x == 0) {
+        float s = 0.0f;
+        for (int i = 0; i < n; ++i) s += part[i];
+        *out = s;
+    }
+}
+
+void launch_sum(const float* part, int n, float* out, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_sum, dim3(1), dim3(64), 0, st, part, n, out);
+}
+
+// Wt[ci][tap * Cout + co] = W[co][tap * Cin + ci] (rows padded to conv_kp(Cout))
+__global__ void k_transpose_w(const uint16_t* __restrict__ w, int cin, int cout, uint16_t* __restrict__ wt)
+{
+    const int kpo = conv_kp(cout), kpi = conv_kp(cin);
+    const int64_t n = (int64_t)cin * kpo;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+        const int ci = (int)(i / kpo), k = (int)(i % kpo);
+        uint16_t v = 0;
+        if (k < 9 * cout) {
+            const int tap = k / cout, co = k % cout;
+            v = w[(int64_t)co * kpi + tap * cin + ci];
+        }
+        wt[i] = v;
+    }
+}
+
+void launch_transpose_w(const uint16_t* w, int cin, int cout, uint16_t* wt, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_transpose_w, dim3(256), dim3(256), 0, st, w, cin, cout, wt);
+}
+
+// grad[i] = sum over chunks c (in order) of partial[c][i]
+__global__ void k_reduce_dw(const float* __restrict__ part, int nc, int64_t n, float* __restrict__ g)
+{
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+        float s = 0.0f;
+        for (int c = 0; c < nc; ++c) s += part[(int64_t)c * n + i];
+        g[i] = s;
+    }
+}
+
+void launch_reduce_dw(const float* part, int nc, int64_t n, float* g, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_reduce_dw, dim3(512), dim3(256), 0, st, part, nc, n, g);
+}
+
+// bias gradient: per chunk of pixels a partial sum of dz over the chunk (one
+// thread per channel, pixels in order), then an ordered sum over chunks
+__global__ void k_bias_part(const uint16_t* __restrict__ dz, int64_t npix, int cout, int nchunk,
+                            float* __restrict__ part)
+{
+    const int co = threadIdx.x;
+    const int c = blockIdx.x;
+    if (co >= cout) return;
+    const int64_t per = npix / nchunk;
+    float s = 0.0f;
+    for (int64_t p = c * per; p < (c + 1) * per; ++p) s += bf2f(dz[p * cout + co]);
+    part[(int64_t)c * cout + co] = s;
+}
+
+__global__ void k_bias_reduce(const float* __restrict__ part, int cout, int nchunk, float* __restrict__ g)
+{
+    const int co = threadIdx.x;
+    if (co >= cout) return;
+    float s = 0.0f;
+    for (int c = 0; c < nchunk; ++c) s += part[(int64_t)c * cout + co];
+    g[co] = s;
+}
+
+void launch_bias_grad(const uint16_t* dz, int64_t npix, int cout, int nchunk, float* part, float* gb, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_bias_part, dim3(nchunk), dim3(128), 0, st, dz, npix, cout, nchunk, part);
+    hipLaunchKernelGGL(k_bias_reduce, dim3(1), dim3(128), 0, st, part, cout, nchunk, gb);
+}
+
+// Adam (Kingma & Ba) on the FP32 master weights, then the BF16 copy
+__global__ void k_adam(float* __restrict__ w, float* __restrict__ m, float* __restrict__ v,
+                       const float* __restrict__ g, uint16_t* __restrict__ wbf, int64_t n, float lr, float b1,
+                       float b2, float eps, float c1, float c2)
+{
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+        const float gi = g[i];
+        const float mi = b1 * m[i] + (1.0f - b1) * gi;
+        const float vi = b2 * v[i] + (1.0f - b2) * gi * gi;
+        m[i] = mi;
+        v[i] = vi;
+        const float wi = w[i] - lr * (mi / c1) / (sqrtf(vi / c2) + eps);
+        w[i] = wi;
+        wbf[i] = f2bf(wi);
+    }
+}
+
+void launch_adam(float* w, float* m, float* v, const float* g, uint16_t* wbf, int64_t n, float lr, float b1,
+                 float b2, float eps, int64_t step, hipStream_t st)
+{
+    const float c1 = 1.0f - powf(b1, (float)step), c2 = 1.0f - powf(b2, (float)step);
+    hipLaunchKernelGGL(k_adam, dim3(512), dim3(256), 0, st, w, m, v, g, wbf, n, lr, b1, b2, eps, c1, c2);
+}
+
+__global__ void k_to_bf16(const float* __restrict__ w, uint16_t* __restrict__ wbf, int64_t n)
+{
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+        wbf[i] = f2bf(w[i]);
+}
+
+void launch_to_bf16(const float* w, uint16_t* wbf, int64_t n, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_to_bf16, dim3(512), dim3(256), 0, st, w, wbf, n);
+}
+
+// ------------------------------------------------------------ seed proposal
+// Per event (one work-group): pixels whose logit is above logit(tau) and
+// strictly above their 8 neighbours (ties: the lower pixel index wins) are
+// candidates; the best k_max by score (ties: lower index) become seeds at
+// their bin centres, x0 = y0 = 0.  The event's confidence is its best sigmoid
+// value; below conf_min the event falls back to the lattice.
+constexpr int kCandCap = 4096;
+
+__global__ __launch_bounds__(256) void k_propose_select(ProposeArgs a)
+{
+    __shared__ uint64_t s_key[kCandCap];
+    __shared__ int s_n;
+    __shared__ float s_best[256];
+    const float ltau = logf(a.tau / (1.0f - a.tau));
+    for (int64_t e = blockIdx.x; e < a.n_events; e += gridDim.x) {
+        const float* z = a.logits + e * kPix;
+        if (threadIdx.x == 0) s_n = 0;
+        float best = -INFINITY;
+        __syncthreads();
+        for (int i = threadIdx.x; i < kPix; i += blockDim.x) {
+            const float v = z[i];
+            best = fmaxf(best, v);
+            if (!(v > ltau)) continue;
+            const int r = i / kImg, c = i % kImg;
+            bool peak = true;
+            for (int dr = -1; dr <= 1 && peak; ++dr)
+                for (int dc = -1; dc <= 1; ++dc) {
+                    if (!dr && !dc) continue;
+                    const int rr = r + dr, cc = c + dc;
+                    if (rr < 0 || rr >= kImg || cc < 0 || cc >= kImg) continue;
+                    const int j = rr * kImg + cc;
+                    const float u = z[j];
+                    if (u > v || (u == v && j < i)) { peak = false; break; }
+                }
+            if (!peak) continue;
+            const int slot = atomicAdd(&s_n, 1);
+            if (slot < kCandCap) {
+                // descending by score: order-preserving float bits (scores may be negative)
+                uint32_t b = __float_as_uint(v);
+                b = (b & 0x80000000u) ? ~b : (b | 0x80000000u);
+                s_key[slot] = ((uint64_t)b << 32) | (uint32_t)(0xFFFFFFFFu - (uint32_t)i);
+            }
+        }
+        s_best[threadIdx.x] = best;
+        __syncthreads();
+        for (int o = 128; o > 0; o >>= 1) {
+            if ((int)threadIdx.x < o) s_best[threadIdx.x] = fmaxf(s_best[threadIdx.x], s_best[threadIdx.x + o]);
+            __syncthreads();
+        }
+        const int nc = min(s_n, kCandCap);
+        int np2 = 1;
+        while (np2 < nc) np2 <<= 1;
+        for (int i = nc + threadIdx.x; i < np2; i += blockDim.x) s_key[i] = 0;
+        __syncthreads();
+        for (int k = 2; k <= np2; k <<= 1)
+            for (int j = k >> 1; j > 0; j >>= 1) {
+                for (int i = threadIdx.x; i < np2; i += blockDim.x) {
+                    const int l = i ^ j;
+                    if (l > i) {
+                        const uint64_t x = s_key[i], y = s_key[l];
+                        const bool desc = (i & k) == 0;
+                        if (desc ? (x < y) : (x > y)) { s_key[i] = y; s_key[l] = x; }
+                    }
+                }
+                __syncthreads();
+            }
+        const int keep = min(nc, a.k_max);
+        for (int i = threadIdx.x; i < keep; i += blockDim.x) {
+            const uint64_t key = s_key[i];
+            uint32_t b = (uint32_t)(key >> 32);
+            b = (b & 0x80000000u) ? (b & 0x7FFFFFFFu) : ~b;
+            a.cand_score[e * a.k_max + i] = __uint_as_float(b);
+            a.cand_pix[e * a.k_max + i] = (int32_t)(0xFFFFFFFFu - (uint32_t)(key & 0xFFFFFFFFull));
+        }
+        if (threadIdx.x == 0) {
+            const float conf = 1.0f / (1.0f + expf(-s_best[0]));
+            a.confidence[e] = conf;
+            const bool fb = !(conf >= a.conf_min) || keep == 0;
+            a.fallback[e] = fb ? 1 : 0;
+            a.count[e] = fb ? a.lattice_n[0] * a.lattice_n[1] : keep;
+        }
+        __syncthreads();
+    }
+}
+
+__global__ __launch_bounds__(1024) void k_propose_offsets(ProposeArgs a)
+{
+    __shared__ int64_t s[1024];
+    int64_t carry = 0;
+    for (int64_t e0 = 0; e0 < a.n_events; e0 += 1024) {
+        const int64_t e = e0 + threadIdx.x;
+        const int64_t v = e < a.n_events ? a.count[e] : 0;
+        s[threadIdx.x] = v;
+        __syncthreads();
+        for (int o = 1; o < 1024; o <<= 1) {
+            const int64_t add = (int)threadIdx.x >= o ? s[threadIdx.x - o] : 0;
+            __syncthreads();
+            s[threadIdx.x] += add;
+            __syncthreads();
+        }
+        if (e < a.n_events) a.seed_off[e] = carry + s[threadIdx.x] - v;
+        const int64_t tot = s[1023];
+        __syncthreads();
+        carry += tot;
+    }
+    if (threadIdx.x == 0) a.seed_off[a.n_events] = carry;
+}
+
+__global__ __launch_bounds__(256) void k_propose_write(ProposeArgs a)
+{
+    const double w = ((double)kSlopeHi - (double)kSlopeLo) / kImg;
+    for (int64_t e = blockIdx.x; e < a.n_events; e += gridDim.x) {
+        double* out = a.seeds + a.seed_off[e] * 4;
+        const int n = a.count[e];
+        if (a.fallback[e]) {
+            const int n1 = a.lattice_n[1];
+            const double lo0 = a.lattice_lo[0], hi0 = a.lattice_hi[0], lo1 = a.lattice_lo[1], hi1 = a.lattice_hi[1];
+            for (int i = threadIdx.x; i < n; i += blockDim.x) {
+                const int i0 = i / n1, i1 = i % n1;
+                out[4 * i + 0] = 0.0;
+                out[4 * i + 1] = 0.0;
+                out[4 * i + 2] = (double)(float)(lo0 + ((double)i0 + 0.5) * (hi0 - lo0) / (double)a.lattice_n[0]);
+                out[4 * i + 3] = (double)(float)(lo1 + ((double)i1 + 0.5) * (hi1 - lo1) / (double)n1);
+            }
+        } else {
+            for (int i = threadIdx.x; i < n; i += blockDim.x) {
+                const int pix = a.cand_pix[e * a.k_max + i];
+                out[4 * i + 0] = 0.0;
+                out[4 * i + 1] = 0.0;
+                out[4 * i + 2] = (double)(float)(kSlopeLo + ((pix / kImg) + 0.5) * w);
+                out[4 * i + 3] = (double)(float)(kSlopeLo + ((pix % kImg) + 0.5) * w);
+            }
+        }
+    }
+}
+
+void launch_propose_select(const ProposeArgs& a, hipStream_t st)
+{
+    const int grid = (int)std::min<int64_t>(a.n_events, 2048);
+    hipLaunchKernelGGL(k_propose_select, dim3(grid), dim3(256), 0, st, a);
+}
+
+void launch_propose_offsets(const ProposeArgs& a, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_propose_offsets, dim3(1), dim3(1024), 0, st, a);
+}
+
+void launch_propose_write(const ProposeArgs& a, hipStream_t st)
+{
+    const int grid = (int)std::min<int64_t>(a.n_events, 2048);
+    hipLaunchKernelGGL(k_propose_write, dim3(grid), dim3(256), 0, st, a);
+}
+
+}  // namespace rt

@@ -37,7 +37,9 @@ struct Counters {
     int64_t n_items;        // produced by the planner
     int64_t total_tracks;   // produced by the finaliser
     int64_t total_seeds;
-    int64_t pad2[5];
+    uint64_t exec_pairs;    // hit-candidate pairs the hot kernel executed (all lanes)
+    uint64_t exec_rpairs;   // ... of which in R-only line-search passes
+    int64_t pad2[3];
 };
 
 // Everything a launch needs; lives in device memory and is refreshed by one

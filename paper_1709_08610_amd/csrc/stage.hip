@@ -21,6 +21,8 @@ __global__ void k_reset(const Desc* __restrict__ d)
         c->n_items = 0;
         c->total_tracks = 0;
         c->total_seeds = 0;
+        c->exec_pairs = 0;
+        c->exec_rpairs = 0;
     }
 }
 
@@ -36,7 +38,7 @@ __device__ __forceinline__ uint64_t lanemask_lt()
 __global__ __launch_bounds__(kBlock) void k_stage(const Desc* __restrict__ d)
 {
     __shared__ int s_cnt[kBlock / kWave][kMaxPlanes];
-    const int wave = threadIdx.x / kWave;
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);  // scalar: same in every lane
     const int lane = threadIdx.x & (kWave - 1);
     const int P = d->n_planes;
     const int D = d->meas_dim;

@@ -72,13 +72,21 @@ _lib = None
 
 class Profile(ctypes.Structure):
     _fields_ = [("calls", ctypes.c_int64), ("ms_stage", ctypes.c_double), ("ms_plan", ctypes.c_double),
-                ("ms_hot", ctypes.c_double), ("ms_merge", ctypes.c_double), ("ms_total", ctypes.c_double)]
+                ("ms_hot", ctypes.c_double), ("ms_merge", ctypes.c_double), ("ms_total", ctypes.c_double),
+                ("exec_pairs", ctypes.c_double), ("exec_rpairs", ctypes.c_double)]
 
 
 EXPORTS = ["retina_create", "retina_destroy", "retina_last_error", "retina_set_stream",
            "retina_set_max_device_bytes", "retina_set_tuning", "retina_get_tuning",
            "retina_set_profiling", "retina_get_profile", "retina_profile_reset",
-           "retina_response", "retina_find_tracks"]
+           "retina_set_graphs", "retina_autotune", "retina_response", "retina_find_tracks",
+           "retina_model_create", "retina_model_save", "retina_model_load", "retina_model_free",
+           "retina_model_get_params", "retina_model_set_params", "retina_model_step",
+           "retina_train_step", "retina_model_forward", "retina_propose_seeds",
+           "retina_find_tracks_learned"]
+MODEL_PARAMS = 186625
+IMG = 128
+SLOPE_LO, SLOPE_HI = -0.35, 0.35
 
 
 def load(path: str = LIB_PATH):
@@ -118,6 +126,37 @@ def load(path: str = LIB_PATH):
     lib.retina_get_profile.restype = ctypes.c_int
     lib.retina_profile_reset.argtypes = [V]
     lib.retina_profile_reset.restype = ctypes.c_int
+    I64, F = ctypes.c_int64, ctypes.c_float
+    lib.retina_model_create.argtypes = [V, ctypes.c_uint64, ctypes.POINTER(ctypes.c_void_p)]
+    lib.retina_model_create.restype = ctypes.c_int
+    lib.retina_model_save.argtypes = [V, ctypes.c_char_p]
+    lib.retina_model_save.restype = ctypes.c_int
+    lib.retina_model_load.argtypes = [V, ctypes.c_char_p, ctypes.POINTER(ctypes.c_void_p)]
+    lib.retina_model_load.restype = ctypes.c_int
+    lib.retina_model_free.argtypes = [V]
+    lib.retina_model_free.restype = None
+    lib.retina_model_get_params.argtypes = [V, P]
+    lib.retina_model_get_params.restype = ctypes.c_int
+    lib.retina_model_set_params.argtypes = [V, P]
+    lib.retina_model_set_params.restype = ctypes.c_int
+    lib.retina_model_step.argtypes = [V]
+    lib.retina_model_step.restype = I64
+    lib.retina_train_step.argtypes = [V, V, ctypes.POINTER(Geometry), ctypes.POINTER(Hits), P, P, F, F,
+                                      ctypes.POINTER(F), P]
+    lib.retina_train_step.restype = ctypes.c_int
+    lib.retina_model_forward.argtypes = [V, V, ctypes.POINTER(Geometry), ctypes.POINTER(Hits), P, P]
+    lib.retina_model_forward.restype = ctypes.c_int
+    lib.retina_propose_seeds.argtypes = [V, ctypes.POINTER(Geometry), ctypes.POINTER(Hits), V, I32, F, F,
+                                         ctypes.POINTER(Params), P, I64, P, P, P]
+    lib.retina_propose_seeds.restype = ctypes.c_int
+    lib.retina_find_tracks_learned.argtypes = [V, ctypes.POINTER(Geometry), ctypes.POINTER(Hits),
+                                               ctypes.POINTER(Params), V, I32, F, F, P, I64, P, P]
+    lib.retina_find_tracks_learned.restype = ctypes.c_int
+    lib.retina_set_graphs.argtypes = [V, I32]
+    lib.retina_set_graphs.restype = ctypes.c_int
+    lib.retina_autotune.argtypes = [V, ctypes.POINTER(Geometry), ctypes.POINTER(Hits), ctypes.POINTER(Params),
+                                    ctypes.c_char_p, ctypes.POINTER(I32), ctypes.POINTER(I32)]
+    lib.retina_autotune.restype = ctypes.c_int
     lib.retina_set_tuning.argtypes = [V, I32, I32, I32, I32]
     lib.retina_set_tuning.restype = ctypes.c_int
     lib.retina_get_tuning.argtypes = [V, I32, I32, ctypes.POINTER(I32), ctypes.POINTER(I32), ctypes.POINTER(I32)]
@@ -242,6 +281,55 @@ class Context:
         hits = Hits(mem, int(off.shape[0]) - 1, _ptr(off), _ptr(x), _ptr(y), _ptr(plane))
         return hits, (off, x, y, plane), mem
 
+    @staticmethod
+    def _params(params, seeds, seed_offsets, mem, npar, E):
+        sig = np.ascontiguousarray(params["sigma"], dtype=np.float32)
+        P = Params()
+        P.n_sigma = len(sig)
+        P.sigma = sig.ctypes.data_as(ctypes.POINTER(ctypes.c_float))
+        for k in ("sigma_final", "n_final_steps", "n_polish", "ls_trials", "armijo_c1",
+                  "step_cap_sigmas", "small_step_sigmas", "conv_tol", "R0", "d_merge"):
+            setattr(P, k, params[k])
+        P.n_slope_steps = params.get("n_slope_steps", 0)
+        P.lattice_n[:] = list(params["lattice_n"])
+        P.lattice_lo[:] = list(params["lattice_lo"])
+        P.lattice_hi[:] = list(params["lattice_hi"])
+        if seeds is not None:
+            P.seed_mode = SEED_EXPLICIT
+            if mem == MEM_HOST:
+                seeds = _host(seeds, np.float64).reshape(-1, npar)
+                seed_offsets = _host(seed_offsets, np.int64)
+                n_seeds = int(seed_offsets[-1])
+            else:
+                import torch
+                seeds = _dev(seeds, torch.float64)
+                seed_offsets = _dev(seed_offsets, torch.int64)
+                n_seeds = int(seed_offsets[-1].item())
+            P.seeds = _ptr(seeds)
+            P.seed_offsets = _ptr(seed_offsets)
+        else:
+            P.seed_mode = SEED_LATTICE
+            n_seeds = E * params["lattice_n"][0] * params["lattice_n"][1]
+        return P, (sig, seeds, seed_offsets), n_seeds
+
+    def retina_set_graphs(self, enable: bool):
+        self._check(self.lib.retina_set_graphs(self.h, int(bool(enable))))
+
+    def retina_autotune(self, meas_dim, plane_z, event_offsets, x, y, plane, params: dict,
+                        cache_path: Optional[str] = None, seeds=None, seed_offsets=None):
+        """Time the ascent launch shapes on this sample batch and install the fastest."""
+        g, zkeep = self._geometry(meas_dim, plane_z)
+        hits, keep, mem = self._hits(meas_dim, event_offsets, x, y, plane)
+        P, pkeep, _ = self._params(params, seeds, seed_offsets, mem, 2 * meas_dim, hits.n_events)
+        if mem == MEM_DEVICE:
+            import torch
+            self.set_stream(torch.cuda.current_stream(x.device).cuda_stream)
+        c, t = ctypes.c_int32(), ctypes.c_int32()
+        rc = self.lib.retina_autotune(self.h, ctypes.byref(g), ctypes.byref(hits), ctypes.byref(P),
+                                      cache_path.encode() if cache_path else None, ctypes.byref(c), ctypes.byref(t))
+        self._check(rc)
+        return dict(cand=c.value, tile_hits=t.value)
+
     # ------------------------------------------------------------- entries
     def retina_response(self, meas_dim, plane_z, event_offsets, x, y, plane, theta,
                         theta_offsets=None, sigma=1.0, want=WANT_R | WANT_GRAD | WANT_HESS):
@@ -280,33 +368,7 @@ class Context:
         hits, keep, mem = self._hits(meas_dim, event_offsets, x, y, plane)
         npar = 2 * meas_dim
         E = hits.n_events
-        sig = np.ascontiguousarray(params["sigma"], dtype=np.float32)
-        P = Params()
-        P.n_sigma = len(sig)
-        P.sigma = sig.ctypes.data_as(ctypes.POINTER(ctypes.c_float))
-        for k in ("sigma_final", "n_final_steps", "n_polish", "ls_trials", "armijo_c1",
-                  "step_cap_sigmas", "small_step_sigmas", "conv_tol", "R0", "d_merge"):
-            setattr(P, k, params[k])
-        P.n_slope_steps = params.get("n_slope_steps", 0)
-        P.lattice_n[:] = list(params["lattice_n"])
-        P.lattice_lo[:] = list(params["lattice_lo"])
-        P.lattice_hi[:] = list(params["lattice_hi"])
-        if seeds is not None:
-            P.seed_mode = SEED_EXPLICIT
-            if mem == MEM_HOST:
-                seeds = _host(seeds, np.float64).reshape(-1, npar)
-                seed_offsets = _host(seed_offsets, np.int64)
-                n_seeds = int(seed_offsets[-1])
-            else:
-                import torch
-                seeds = _dev(seeds, torch.float64)
-                seed_offsets = _dev(seed_offsets, torch.int64)
-                n_seeds = int(seed_offsets[-1].item())
-            P.seeds = _ptr(seeds)
-            P.seed_offsets = _ptr(seed_offsets)
-        else:
-            P.seed_mode = SEED_LATTICE
-            n_seeds = E * params["lattice_n"][0] * params["lattice_n"][1]
+        P, pkeep, n_seeds = self._params(params, seeds, seed_offsets, mem, npar, E)
         cap = n_seeds if capacity is None else int(capacity)
         if mem == MEM_HOST:
             tracks = np.zeros(max(cap, 1), TRACK_DTYPE)
