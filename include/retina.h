@@ -262,10 +262,12 @@ int retina_find_tracks(retina_ctx* ctx, const retina_geometry* geom, const retin
  * Products run on BF16 MFMA with FP32 accumulation; the FP32 master weights
  * are trained by Adam on a weighted binary cross-entropy (positive weight
  * pos_weight) against targets placed at the bins of given track slopes.
- * Seeds are the bin centres of the best k_max local maxima (3 x 3, strict;
- * ties to the lower bin index) whose probability exceeds tau, with x0 = y0 =
- * 0; an event whose best probability is below conf_min (or that has no
- * maximum above tau) falls back to the lattice of the parameters.
+ * Seeds (retina_proposal) are the bin centres, with x0 = y0 = 0, of the best
+ * k_max candidate bins by probability (ties to the lower bin index); a bin is
+ * a candidate when its probability exceeds tau and, with nms = 1, it is also
+ * a strict 3 x 3 local maximum (equal neighbours: the lower index wins).  An
+ * event whose best probability is below conf_min (or that has no candidate)
+ * falls back to the lattice of the parameters.
  * Parameter layout (retina_model_get_params): per layer W[co][tap][ci] with
  * tap = 3 (dr + 1) + (dc + 1) for input offset (dr, dc) in (row, column) =
  * (tx bin, ty bin), then b[co]; layers in order.
@@ -273,6 +275,13 @@ int retina_find_tracks(retina_ctx* ctx, const retina_geometry* geom, const retin
 typedef struct retina_model retina_model;
 
 #define RETINA_MODEL_PARAMS 186625
+
+typedef struct retina_proposal {
+    int32_t k_max;    /* seeds per event at most, 1 .. 4096 */
+    float tau;        /* candidate threshold on the probability, in (0, 1) */
+    float conf_min;   /* per-event lattice fallback threshold, in [0, 1] */
+    int32_t nms;      /* 1: candidates must be strict 3 x 3 local maxima; 0: any bin */
+} retina_proposal;
 
 /* New model on ctx's device: He-normal weights (sd sqrt(2 / (9 Cin))) drawn
  * from a counter-based generator keyed by init_key, zero biases except the
@@ -310,7 +319,7 @@ int retina_model_forward(retina_ctx* ctx, const retina_model* model, const retin
  * `params` instead.  Arrays in the hits' memory space; RETINA_ERR_CAPACITY
  * (with seed_offsets[n_events] = the required count) when seeds do not fit. */
 int retina_propose_seeds(retina_ctx* ctx, const retina_geometry* geom, const retina_hits* hits,
-                         const retina_model* model, int32_t k_max, float tau, float conf_min,
+                         const retina_model* model, const retina_proposal* proposal,
                          const retina_params* params, double* seeds, int64_t capacity,
                          int64_t* seed_offsets, float* confidence, int32_t* fallback);
 
@@ -320,8 +329,8 @@ int retina_propose_seeds(retina_ctx* ctx, const retina_geometry* geom, const ret
  * event_flags bit 4 (value 16) marks events that fell back to the lattice. */
 int retina_find_tracks_learned(retina_ctx* ctx, const retina_geometry* geom,
                                const retina_hits* hits, const retina_params* params,
-                               const retina_model* model, int32_t k_max, float tau,
-                               float conf_min, retina_track* tracks, int64_t capacity,
+                               const retina_model* model, const retina_proposal* proposal,
+                               retina_track* tracks, int64_t capacity,
                                int64_t* track_offsets, int32_t* event_flags);
 
 #ifdef __cplusplus

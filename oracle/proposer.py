@@ -10,7 +10,9 @@ Plain numpy, direct definitions:
   * conv3x3_back   gradients of a scalar loss through conv3x3
   * bce_logits     weighted binary cross-entropy on logits, mean over pixels
   * adam_step      Kingma & Ba's update with bias correction
-  * nms_topk       strict 3x3 local maxima above a threshold, best k
+  * nms_topk       bins above a threshold (optionally strict 3x3 local
+                   maxima), best k
+  * target_image / seeds_from_pixels   slope pair <-> bin maps
   * forward / backward of the four-layer network, optionally rounding the
     stored activations and gradients to BF16 where the device stores them
 
@@ -52,6 +54,32 @@ def bin_image(x, y, plane, plane_z):
     return np.log1p(bin_counts(x, y, plane, plane_z).astype(np.float64))
 
 
+def target_image(targets):
+    """[128, 128] 0/1 image with a 1 at the bin of every (tx, ty) pair (FP64 bin
+    decision; pairs outside the image range are dropped)."""
+    lo = float(np.float32(SLOPE_LO))
+    w = (float(np.float32(SLOPE_HI)) - lo) / IMG
+    t = np.asarray(targets, np.float64).reshape(-1, 2)
+    u = (t[:, 0] - lo) / w
+    v = (t[:, 1] - lo) / w
+    ok = (u >= 0) & (u < IMG) & (v >= 0) & (v < IMG)
+    y = np.zeros((IMG, IMG))
+    y[u[ok].astype(np.int64), v[ok].astype(np.int64)] = 1.0
+    return y
+
+
+def seeds_from_pixels(pix):
+    """Seeds (x0, y0, tx, ty) = (0, 0, bin centre) of flat pixel indices, the
+    centre computed in FP64 and rounded to FP32."""
+    lo = float(np.float32(SLOPE_LO))
+    w = (float(np.float32(SLOPE_HI)) - lo) / IMG
+    pix = np.asarray(pix, np.int64)
+    out = np.zeros((pix.shape[0], 4))
+    out[:, 2] = np.float32(lo + (pix // IMG + 0.5) * w)
+    out[:, 3] = np.float32(lo + (pix % IMG + 0.5) * w)
+    return out
+
+
 def conv3x3(x, W, b):
     """x [H, W, Cin], W [Cout, 9, Cin], b [Cout] -> [H, W, Cout] (FP64)."""
     H, Wd, Cin = x.shape
@@ -78,7 +106,7 @@ def conv3x3_back(x, W, dy):
             tap = 3 * (dr + 1) + (dc + 1)
             sl = (slice(1 + dr, 1 + dr + H), slice(1 + dc, 1 + dc + Wd))
             dxp[sl] += dy @ W[:, tap, :]
-            dW[:, tap, :] = np.einsum("hwo,hwi->oi", dy, xp[sl])
+            dW[:, tap, :] = dy.reshape(-1, dy.shape[-1]).T @ xp[sl].reshape(-1, Cin)
     return dxp[1:-1, 1:-1], dW, dy.sum(axis=(0, 1))
 
 
@@ -102,13 +130,23 @@ def adam_step(w, m, v, g, lr, step, b1=0.9, b2=0.999, eps=1e-8):
     return w, m, v
 
 
-def nms_topk(z, tau, k_max):
-    """Pixels whose value exceeds logit(tau) and every 8-neighbour (equal
-    neighbours with a lower flat index win), best k_max by value (ties: lower
-    index).  Returns flat indices."""
+def logit_threshold(p):
+    """logit(p) computed in FP64 and rounded to FP32: the threshold a bin's
+    FP32 logit is compared with (p = 0 and 1 give -inf and +inf)."""
+    if p <= 0:
+        return -np.inf
+    if p >= 1:
+        return np.inf
+    return float(np.float32(np.log(p / (1 - p))))
+
+
+def nms_topk(z, tau, k_max, nms=True):
+    """Candidate bins: logit above logit_threshold(tau) and, with nms, above
+    every 8-neighbour (equal neighbours: the lower flat index wins); the best
+    k_max by value (ties: lower index).  Returns flat indices."""
     z = np.asarray(z)
     H, Wd = z.shape
-    thr = np.log(tau / (1 - tau))
+    thr = logit_threshold(tau)
     cands = []
     for r in range(H):
         for c in range(Wd):
@@ -118,7 +156,7 @@ def nms_topk(z, tau, k_max):
             peak = True
             for dr in (-1, 0, 1):
                 for dc in (-1, 0, 1):
-                    if dr == 0 and dc == 0:
+                    if not nms or (dr == 0 and dc == 0):
                         continue
                     rr, cc = r + dr, c + dc
                     if 0 <= rr < H and 0 <= cc < Wd:

@@ -1327,14 +1327,16 @@ namespace {
 
 // proposer seeds into the pool (device): returns the total through *n_seeds
 int propose_device(retina_ctx* c, const retina_geometry* g, const retina_hits* h, const retina_model* md,
-                   int32_t k_max, float tau, float conf_min, const retina_params* P, ProposeArgs& pa,
-                   int64_t* n_seeds)
+                   const retina_proposal* pr, const retina_params* P, ProposeArgs& pa, int64_t* n_seeds)
 {
     int rc;
-    if (!P) return fail(c, RETINA_ERR_INVALID_ARG, "params is NULL");
+    if (!P || !pr) return fail(c, RETINA_ERR_INVALID_ARG, "params or proposal is NULL");
+    const int32_t k_max = pr->k_max;
+    const float tau = pr->tau, conf_min = pr->conf_min;
     if (k_max < 1 || k_max > 4096) return fail(c, RETINA_ERR_INVALID_ARG, "k_max must be in [1, 4096]");
     if (!(tau > 0.0f && tau < 1.0f) || !(conf_min >= 0.0f && conf_min <= 1.0f))
         return fail(c, RETINA_ERR_INVALID_ARG, "tau must be in (0, 1) and conf_min in [0, 1]");
+    if (pr->nms != 0 && pr->nms != 1) return fail(c, RETINA_ERR_INVALID_ARG, "nms must be 0 or 1");
     if (P->lattice_n[0] < 1 || P->lattice_n[1] < 1 || (int64_t)P->lattice_n[0] * P->lattice_n[1] > (1 << 24))
         return fail(c, RETINA_ERR_INVALID_ARG, "fallback lattice_n must be >= 1 with at most 2^24 seeds");
     if ((rc = proposer_stage(c, g, h))) return rc;
@@ -1348,8 +1350,11 @@ int propose_device(retina_ctx* c, const retina_geometry* g, const retina_hits* h
     pa.logits = A.logits;
     pa.n_events = E;
     pa.k_max = k_max;
-    pa.tau = tau;
-    pa.conf_min = conf_min;
+    // thresholds as logits, computed in FP64 and rounded once to FP32
+    pa.ltau = (float)log((double)tau / (1.0 - (double)tau));
+    pa.lconf = conf_min <= 0.0f ? -INFINITY
+             : conf_min >= 1.0f ? INFINITY : (float)log((double)conf_min / (1.0 - (double)conf_min));
+    pa.nms = pr->nms;
     for (int i = 0; i < 2; ++i) {
         pa.lattice_n[i] = P->lattice_n[i];
         pa.lattice_lo[i] = P->lattice_lo[i];
@@ -1376,7 +1381,7 @@ int propose_device(retina_ctx* c, const retina_geometry* g, const retina_hits* h
 extern "C" {
 
 int retina_propose_seeds(retina_ctx* c, const retina_geometry* g, const retina_hits* h, const retina_model* md,
-                         int32_t k_max, float tau, float conf_min, const retina_params* P, double* seeds,
+                         const retina_proposal* pr, const retina_params* P, double* seeds,
                          int64_t capacity, int64_t* seed_offsets, float* confidence, int32_t* fallback)
 {
     if (!c || !md) return RETINA_ERR_INVALID_ARG;
@@ -1393,7 +1398,7 @@ int retina_propose_seeds(retina_ctx* c, const retina_geometry* g, const retina_h
     }
     ProposeArgs pa;
     int64_t n;
-    if ((rc = propose_device(c, g, h, md, k_max, tau, conf_min, P, pa, &n))) return rc;
+    if ((rc = propose_device(c, g, h, md, pr, P, pa, &n))) return rc;
     const int64_t E = h->n_events;
     const hipMemcpyKind k = h->mem == RETINA_MEM_HOST ? hipMemcpyDeviceToHost : hipMemcpyDeviceToDevice;
     if (n > capacity) {
@@ -1410,8 +1415,8 @@ int retina_propose_seeds(retina_ctx* c, const retina_geometry* g, const retina_h
 }
 
 int retina_find_tracks_learned(retina_ctx* c, const retina_geometry* g, const retina_hits* h,
-                               const retina_params* P, const retina_model* md, int32_t k_max, float tau,
-                               float conf_min, retina_track* tracks, int64_t capacity, int64_t* track_offsets,
+                               const retina_params* P, const retina_model* md, const retina_proposal* pr,
+                               retina_track* tracks, int64_t capacity, int64_t* track_offsets,
                                int32_t* event_flags)
 {
     if (!c || !md) return RETINA_ERR_INVALID_ARG;
@@ -1422,7 +1427,7 @@ int retina_find_tracks_learned(retina_ctx* c, const retina_geometry* g, const re
         return retina_find_tracks(c, g, h, P, tracks, capacity, track_offsets, event_flags, nullptr);
     ProposeArgs pa;
     int64_t n;
-    if ((rc = propose_device(c, g, h, md, k_max, tau, conf_min, P, pa, &n))) return rc;
+    if ((rc = propose_device(c, g, h, md, pr, P, pa, &n))) return rc;
     retina_params Q = *P;
     Q.seed_mode = RETINA_SEED_EXPLICIT;
     Q.seeds = pa.seeds;

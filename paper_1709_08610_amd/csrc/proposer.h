@@ -60,13 +60,15 @@ void launch_adam(float* w, float* m, float* v, const float* g, uint16_t* wbf, in
 void launch_to_bf16(const float* w, uint16_t* wbf, int64_t n, hipStream_t st);
 void launch_sum(const float* part, int n, float* out, hipStream_t st);
 
-// seeds from the heatmap (logits): local maxima above tau, best k_max per
-// event; events whose best score is below conf_min fall back to the lattice
+// seeds from the heatmap (logits): bins above tau (local maxima with nms),
+// best k_max per event; events whose best score is below conf_min fall back to the lattice
 struct ProposeArgs {
     const float* logits;       // (E, kPix)
     int64_t n_events;
     int k_max;
-    float tau, conf_min;
+    float ltau;                // logit(tau): candidate threshold
+    float lconf;               // logit(conf_min): events whose best logit is below fall back
+    int nms;                   // 1: strict 3x3 local maxima only
     int lattice_n[2];
     float lattice_lo[2], lattice_hi[2];
     float* cand_score;         // scratch (E, k_max)

@@ -454,47 +454,64 @@ void launch_to_bf16(const float* w, uint16_t* wbf, int64_t n, hipStream_t st)
 }
 
 // ------------------------------------------------------------ seed proposal
-// Per event (one work-group): pixels whose logit is above logit(tau) and
-// strictly above their 8 neighbours (ties: the lower pixel index wins) are
-// candidates; the best k_max by score (ties: lower index) become seeds at
-// their bin centres, x0 = y0 = 0.  The event's confidence is its best sigmoid
-// value; below conf_min the event falls back to the lattice.
-constexpr int kCandCap = 4096;
+// Per event (one work-group): candidate bins are those whose logit exceeds
+// logit(tau) (and, with nms, every one of their 8 neighbours; equal
+// neighbours: the lower bin index wins); the best k_max by score (ties: lower
+// index) become seeds at their bin centres, x0 = y0 = 0.  The event falls
+// back to the lattice when its best logit is below logit(conf_min) or it has
+// no candidate.  Both thresholds arrive as FP32 logits rounded from FP64.
+constexpr int kCandCap = 4096;  // >= k_max; also the most strict maxima a 128 x 128 image can hold
+
+// descending order of score, then ascending bin index, as an ascending u64 key;
+// distinct bins give distinct keys, and every key is non-zero
+__device__ __forceinline__ uint64_t cand_key(float v, int i)
+{
+    uint32_t b = __float_as_uint(v);
+    b = (b & 0x80000000u) ? ~b : (b | 0x80000000u);
+    return ((uint64_t)b << 32) | (uint32_t)(0xFFFFFFFFu - (uint32_t)i);
+}
+
+__device__ __forceinline__ bool is_cand(const float* __restrict__ z, int i, float v, float ltau, int nms)
+{
+    if (!(v > ltau)) return false;
+    if (!nms) return true;
+    const int r = i / kImg, c = i % kImg;
+    for (int dr = -1; dr <= 1; ++dr)
+        for (int dc = -1; dc <= 1; ++dc) {
+            if (!dr && !dc) continue;
+            const int rr = r + dr, cc = c + dc;
+            if (rr < 0 || rr >= kImg || cc < 0 || cc >= kImg) continue;
+            const int j = rr * kImg + cc;
+            const float u = z[j];
+            if (u > v || (u == v && j < i)) return false;
+        }
+    return true;
+}
 
 __global__ __launch_bounds__(256) void k_propose_select(ProposeArgs a)
 {
     __shared__ uint64_t s_key[kCandCap];
-    __shared__ int s_n;
+    __shared__ int s_n, s_n2, s_rem;
+    __shared__ uint64_t s_prefix;
+    __shared__ uint32_t s_hist[256];
     __shared__ float s_best[256];
-    const float ltau = logf(a.tau / (1.0f - a.tau));
+    const float ltau = a.ltau;
     for (int64_t e = blockIdx.x; e < a.n_events; e += gridDim.x) {
         const float* z = a.logits + e * kPix;
-        if (threadIdx.x == 0) s_n = 0;
+        if (threadIdx.x == 0) {
+            s_n = 0;
+            s_n2 = 0;
+            s_rem = a.k_max;
+            s_prefix = 0;
+        }
         float best = -INFINITY;
         __syncthreads();
         for (int i = threadIdx.x; i < kPix; i += blockDim.x) {
             const float v = z[i];
             best = fmaxf(best, v);
-            if (!(v > ltau)) continue;
-            const int r = i / kImg, c = i % kImg;
-            bool peak = true;
-            for (int dr = -1; dr <= 1 && peak; ++dr)
-                for (int dc = -1; dc <= 1; ++dc) {
-                    if (!dr && !dc) continue;
-                    const int rr = r + dr, cc = c + dc;
-                    if (rr < 0 || rr >= kImg || cc < 0 || cc >= kImg) continue;
-                    const int j = rr * kImg + cc;
-                    const float u = z[j];
-                    if (u > v || (u == v && j < i)) { peak = false; break; }
-                }
-            if (!peak) continue;
+            if (!is_cand(z, i, v, ltau, a.nms)) continue;
             const int slot = atomicAdd(&s_n, 1);
-            if (slot < kCandCap) {
-                // descending by score: order-preserving float bits (scores may be negative)
-                uint32_t b = __float_as_uint(v);
-                b = (b & 0x80000000u) ? ~b : (b | 0x80000000u);
-                s_key[slot] = ((uint64_t)b << 32) | (uint32_t)(0xFFFFFFFFu - (uint32_t)i);
-            }
+            if (slot < kCandCap) s_key[slot] = cand_key(v, i);
         }
         s_best[threadIdx.x] = best;
         __syncthreads();
@@ -502,7 +519,47 @@ __global__ __launch_bounds__(256) void k_propose_select(ProposeArgs a)
             if ((int)threadIdx.x < o) s_best[threadIdx.x] = fmaxf(s_best[threadIdx.x], s_best[threadIdx.x + o]);
             __syncthreads();
         }
-        const int nc = min(s_n, kCandCap);
+        int nc = s_n;
+        if (nc > kCandCap) {
+            // more candidates than fit (only without nms): radix-select the
+            // k_max-th largest key, eight bits at a time from the top, then keep
+            // exactly the keys at or above it
+            for (int shift = 56; shift >= 0; shift -= 8) {
+                for (int j = threadIdx.x; j < 256; j += blockDim.x) s_hist[j] = 0;
+                __syncthreads();
+                const uint64_t pfx = s_prefix;
+                const uint64_t hm = shift == 56 ? 0ull : (~0ull << (shift + 8));
+                for (int i = threadIdx.x; i < kPix; i += blockDim.x) {
+                    const float v = z[i];
+                    if (!is_cand(z, i, v, ltau, a.nms)) continue;
+                    const uint64_t key = cand_key(v, i);
+                    if ((key & hm) == pfx) atomicAdd(&s_hist[(key >> shift) & 255u], 1u);
+                }
+                __syncthreads();
+                if (threadIdx.x == 0) {
+                    int rem = s_rem;
+                    for (int d = 255; d >= 0; --d) {
+                        const int cnt = (int)s_hist[d];
+                        if (cnt >= rem) {
+                            s_prefix = pfx | ((uint64_t)d << shift);
+                            break;
+                        }
+                        rem -= cnt;
+                    }
+                    s_rem = rem;
+                }
+                __syncthreads();
+            }
+            const uint64_t kth = s_prefix;
+            for (int i = threadIdx.x; i < kPix; i += blockDim.x) {
+                const float v = z[i];
+                if (!is_cand(z, i, v, ltau, a.nms)) continue;
+                const uint64_t key = cand_key(v, i);
+                if (key >= kth) s_key[atomicAdd(&s_n2, 1)] = key;  // exactly k_max keys
+            }
+            __syncthreads();
+            nc = a.k_max;
+        }
         int np2 = 1;
         while (np2 < nc) np2 <<= 1;
         for (int i = nc + threadIdx.x; i < np2; i += blockDim.x) s_key[i] = 0;
@@ -528,9 +585,8 @@ __global__ __launch_bounds__(256) void k_propose_select(ProposeArgs a)
             a.cand_pix[e * a.k_max + i] = (int32_t)(0xFFFFFFFFu - (uint32_t)(key & 0xFFFFFFFFull));
         }
         if (threadIdx.x == 0) {
-            const float conf = 1.0f / (1.0f + expf(-s_best[0]));
-            a.confidence[e] = conf;
-            const bool fb = !(conf >= a.conf_min) || keep == 0;
+            a.confidence[e] = 1.0f / (1.0f + expf(-s_best[0]));
+            const bool fb = !(s_best[0] >= a.lconf) || keep == 0;
             a.fallback[e] = fb ? 1 : 0;
             a.count[e] = fb ? a.lattice_n[0] * a.lattice_n[1] : keep;
         }

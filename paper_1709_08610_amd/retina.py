@@ -63,6 +63,11 @@ TRACK_DTYPE = np.dtype([("theta", np.float64, (4,)), ("R", np.float32), ("n_memb
 assert TRACK_DTYPE.itemsize == ctypes.sizeof(Track) == 48
 
 
+class Proposal(ctypes.Structure):
+    _fields_ = [("k_max", ctypes.c_int32), ("tau", ctypes.c_float), ("conf_min", ctypes.c_float),
+                ("nms", ctypes.c_int32)]
+
+
 class SeedOut(ctypes.Structure):
     _fields_ = [("theta", ctypes.c_void_p), ("R", ctypes.c_void_p), ("flags", ctypes.c_void_p),
                 ("n_reval", ctypes.c_void_p), ("capacity", ctypes.c_int64)]
@@ -146,11 +151,11 @@ def load(path: str = LIB_PATH):
     lib.retina_train_step.restype = ctypes.c_int
     lib.retina_model_forward.argtypes = [V, V, ctypes.POINTER(Geometry), ctypes.POINTER(Hits), P, P]
     lib.retina_model_forward.restype = ctypes.c_int
-    lib.retina_propose_seeds.argtypes = [V, ctypes.POINTER(Geometry), ctypes.POINTER(Hits), V, I32, F, F,
-                                         ctypes.POINTER(Params), P, I64, P, P, P]
+    lib.retina_propose_seeds.argtypes = [V, ctypes.POINTER(Geometry), ctypes.POINTER(Hits), V,
+                                         ctypes.POINTER(Proposal), ctypes.POINTER(Params), P, I64, P, P, P]
     lib.retina_propose_seeds.restype = ctypes.c_int
     lib.retina_find_tracks_learned.argtypes = [V, ctypes.POINTER(Geometry), ctypes.POINTER(Hits),
-                                               ctypes.POINTER(Params), V, I32, F, F, P, I64, P, P]
+                                               ctypes.POINTER(Params), V, ctypes.POINTER(Proposal), P, I64, P, P]
     lib.retina_find_tracks_learned.restype = ctypes.c_int
     lib.retina_set_graphs.argtypes = [V, I32]
     lib.retina_set_graphs.restype = ctypes.c_int
@@ -413,8 +418,165 @@ class Context:
         return out
 
 
+    # ------------------------------------------------ learned seed proposer
+    def retina_model_create(self, init_key: int) -> Model:
+        h = ctypes.c_void_p()
+        self._check(self.lib.retina_model_create(self.h, int(init_key), ctypes.byref(h)))
+        return Model(self, h)
+
+    def retina_model_load(self, path: str) -> Model:
+        h = ctypes.c_void_p()
+        self._check(self.lib.retina_model_load(self.h, path.encode(), ctypes.byref(h)))
+        return Model(self, h)
+
+    def _model_io(self, plane_z, event_offsets, x, y, plane):
+        g, zkeep = self._geometry(2, plane_z)
+        hits, keep, mem = self._hits(2, event_offsets, x, y, plane)
+        if mem == MEM_DEVICE:
+            import torch
+            self.set_stream(torch.cuda.current_stream(x.device).cuda_stream)
+        return g, hits, (zkeep, keep), mem
+
+    def retina_train_step(self, model: Model, plane_z, event_offsets, x, y, plane, targets,
+                          target_offsets, lr: float, pos_weight: float, want_grad=False):
+        """One Adam step (lr > 0) or a gradient evaluation (lr = 0).
+        Returns (loss, grad or None); grad is host FP32 in the logical layout."""
+        g, hits, keep, mem = self._model_io(plane_z, event_offsets, x, y, plane)
+        if mem == MEM_HOST:
+            tg = _host(targets, np.float64).reshape(-1, 2)
+            to = _host(target_offsets, np.int64)
+        else:
+            import torch
+            tg = _dev(targets, torch.float64)
+            to = _dev(target_offsets, torch.int64)
+        loss = ctypes.c_float()
+        grad = np.zeros(MODEL_PARAMS, np.float32) if want_grad else None
+        self._check(self.lib.retina_train_step(self.h, model.h, ctypes.byref(g), ctypes.byref(hits),
+                                               _ptr(tg), _ptr(to), float(lr), float(pos_weight),
+                                               ctypes.byref(loss), _ptr(grad)))
+        return loss.value, grad
+
+    def retina_model_forward(self, model: Model, plane_z, event_offsets, x, y, plane):
+        """Binned images (uint16 BF16 bits, [E, 128, 128, 2]) and logits ([E, 128, 128])."""
+        g, hits, keep, mem = self._model_io(plane_z, event_offsets, x, y, plane)
+        E = hits.n_events
+        if mem == MEM_HOST:
+            img = np.zeros((E, IMG, IMG, 2), np.uint16)
+            logits = np.zeros((E, IMG, IMG), np.float32)
+        else:
+            import torch
+            img = torch.zeros((E, IMG, IMG, 2), dtype=torch.int16, device=x.device)
+            logits = torch.zeros((E, IMG, IMG), dtype=torch.float32, device=x.device)
+        self._check(self.lib.retina_model_forward(self.h, model.h, ctypes.byref(g), ctypes.byref(hits),
+                                                  _ptr(img), _ptr(logits)))
+        return img, logits
+
+    def retina_propose_seeds(self, model: Model, plane_z, event_offsets, x, y, plane, k_max: int,
+                             tau: float, conf_min: float, params: dict, capacity=None, nms: bool = False):
+        """Seeds from the network (lattice fallback per event).  Returns dict(seeds
+        [n, 4], seed_offsets, confidence, fallback)."""
+        g, hits, keep, mem = self._model_io(plane_z, event_offsets, x, y, plane)
+        E = hits.n_events
+        P, pkeep, _ = self._params(params, None, None, mem, 4, E)
+        lat = params["lattice_n"][0] * params["lattice_n"][1]
+        cap = E * max(int(k_max), lat) if capacity is None else int(capacity)
+        if mem == MEM_HOST:
+            seeds = np.zeros((max(cap, 1), 4))
+            so = np.zeros(E + 1, np.int64)
+            conf = np.zeros(max(E, 1), np.float32)
+            fb = np.zeros(max(E, 1), np.int32)
+        else:
+            import torch
+            dev = x.device
+            seeds = torch.zeros((max(cap, 1), 4), dtype=torch.float64, device=dev)
+            so = torch.zeros(E + 1, dtype=torch.int64, device=dev)
+            conf = torch.zeros(max(E, 1), dtype=torch.float32, device=dev)
+            fb = torch.zeros(max(E, 1), dtype=torch.int32, device=dev)
+        pr = Proposal(int(k_max), float(tau), float(conf_min), int(bool(nms)))
+        rc = self.lib.retina_propose_seeds(self.h, ctypes.byref(g), ctypes.byref(hits), model.h, ctypes.byref(pr),
+                                           ctypes.byref(P), _ptr(seeds), cap, _ptr(so), _ptr(conf), _ptr(fb))
+        if rc == ERR_CAPACITY:
+            err = RetinaError(rc, self.lib.retina_last_error(self.h).decode())
+            err.required = int(so[-1]) if mem == MEM_HOST else int(so[-1].item())
+            raise err
+        self._check(rc)
+        n = int(so[-1]) if mem == MEM_HOST else int(so[-1].item())
+        return dict(seeds=seeds[:n], seed_offsets=so, confidence=conf[:E], fallback=fb[:E])
+
+    def retina_find_tracks_learned(self, model: Model, plane_z, event_offsets, x, y, plane, params: dict,
+                                   k_max: int, tau: float, conf_min: float, capacity=None, nms: bool = False):
+        """Algorithm 1 on learned seeds.  Same result layout as retina_find_tracks."""
+        g, hits, keep, mem = self._model_io(plane_z, event_offsets, x, y, plane)
+        E = hits.n_events
+        P, pkeep, _ = self._params(params, None, None, mem, 4, E)
+        lat = params["lattice_n"][0] * params["lattice_n"][1]
+        cap = E * max(int(k_max), lat) if capacity is None else int(capacity)
+        if mem == MEM_HOST:
+            tracks = np.zeros(max(cap, 1), TRACK_DTYPE)
+            toff = np.zeros(E + 1, np.int64)
+            evf = np.zeros(max(E, 1), np.int32)
+        else:
+            import torch
+            dev = x.device
+            tracks = torch.zeros(max(cap, 1) * 48, dtype=torch.uint8, device=dev)
+            toff = torch.zeros(E + 1, dtype=torch.int64, device=dev)
+            evf = torch.zeros(max(E, 1), dtype=torch.int32, device=dev)
+        pr = Proposal(int(k_max), float(tau), float(conf_min), int(bool(nms)))
+        rc = self.lib.retina_find_tracks_learned(self.h, ctypes.byref(g), ctypes.byref(hits), ctypes.byref(P),
+                                                 model.h, ctypes.byref(pr), _ptr(tracks), cap, _ptr(toff),
+                                                 _ptr(evf))
+        if rc == ERR_CAPACITY:
+            err = RetinaError(rc, self.lib.retina_last_error(self.h).decode())
+            err.required = int(toff[-1]) if mem == MEM_HOST else int(toff[-1].item())
+            raise err
+        self._check(rc)
+        out = dict(track_offsets=toff, event_flags=evf[:E])
+        if mem == MEM_HOST:
+            out["tracks"] = tracks[:int(toff[-1])]
+        else:
+            out["tracks_bytes"] = tracks
+        return out
+
+
 def tracks_from_device(res) -> np.ndarray:
     """Copy a device-memory find_tracks result's tracks to a structured array."""
     raw = res["tracks_bytes"].cpu().numpy()
     n = int(res["track_offsets"][-1].item())
     return raw[: n * 48].view(TRACK_DTYPE)
+
+
+class Model:
+    """Handle of a retina_model (learned seed proposer) on a context's device."""
+
+    def __init__(self, ctx: Context, handle):
+        self.ctx = ctx
+        self.h = handle
+
+    def close(self):
+        if getattr(self, "h", None):
+            self.ctx.lib.retina_model_free(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    @property
+    def step(self) -> int:
+        return int(self.ctx.lib.retina_model_step(self.h))
+
+    def retina_model_get_params(self) -> np.ndarray:
+        out = np.zeros(MODEL_PARAMS, np.float32)
+        self.ctx._check(self.ctx.lib.retina_model_get_params(self.h, _ptr(out)))
+        return out
+
+    def retina_model_set_params(self, params):
+        p = np.ascontiguousarray(params, dtype=np.float32)
+        if p.shape != (MODEL_PARAMS,):
+            raise ValueError("expected %d parameters" % MODEL_PARAMS)
+        self.ctx._check(self.ctx.lib.retina_model_set_params(self.h, _ptr(p)))
+
+    def retina_model_save(self, path: str):
+        self.ctx._check(self.ctx.lib.retina_model_save(self.h, path.encode()))

@@ -130,6 +130,8 @@ def assert_tracks_match(D, gpu_theta, gpu_R, ref_theta, ref_R, d_merge, z0, z1):
     ref_theta = np.asarray(ref_theta, np.float64).reshape(-1, 2 * D)
     assert gpu_theta.shape[0] == ref_theta.shape[0], \
         "track counts differ: gpu %d oracle %d" % (gpu_theta.shape[0], ref_theta.shape[0])
+    if ref_theta.shape[0] == 0:
+        return np.zeros(0)
     f2t, t2f, d = match_tracks(D, gpu_theta, ref_theta, d_merge, z0, z1)
     assert np.all(f2t >= 0) and np.all(t2f >= 0), "unmatched tracks: gpu %s oracle %s" % (
         np.nonzero(f2t < 0)[0], np.nonzero(t2f < 0)[0])

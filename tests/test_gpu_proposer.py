@@ -1,0 +1,368 @@
+"""GPU parity of the learned seed proposer against the FP64 proposer oracle.
+
+* binned images: bit-exact (same FP32 bin decision, BF16 of log1p(count));
+* logits: within a forward error bound that propagates one BF16 rounding
+  (2^-8 relative, doubled because two roundings of nearly equal values may
+  straddle a rounding boundary) of every stored activation through the
+  absolute-value network, plus FP32 accumulation;
+* gradients of the mean loss: per-layer relative L2 error below 1e-3 and
+  cosine above 0.99999 (the device and the oracle store activations and
+  gradients in BF16 at the same points, so only rare straddled roundings and
+  ReLU masks flipped by them differ; a wrong index, sign or transposition
+  gives O(1) errors);
+* seed proposal on a network whose logits are exact in FP32: bit-exact seeds,
+  counts and fallback flags;
+* Adam's first step against its closed form, checkpoint save / load / resume
+  bit-exact."""
+import os
+import sys
+import tempfile
+
+import numpy as np
+import pytest
+
+import oracle
+from oracle import proposer as op
+from paper_1709_08610_amd import events, retina
+
+from gpu_util import assert_tracks_match, event_tracks
+
+pytestmark = pytest.mark.gpu
+
+U_BF16 = 2.0 ** -8
+INIT_KEY = 20170925
+
+
+def _say(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    return retina.Context(0)
+
+
+@pytest.fixture(scope="module")
+def batch():
+    """Three training-workload events (ragged hit counts) plus an empty event."""
+    cfg = events.load_config("c4")
+    evs = [events.make_event(cfg, i) for i in range(3)]
+    empty = events.Event(np.zeros(0, np.float32), np.zeros(0, np.float32), np.zeros(0, np.int32),
+                         np.zeros(0, np.int32), np.zeros((0, 4)), np.zeros(0, np.int32))
+    return events.batch_from_events(2, events.plane_z(cfg), evs + [empty])
+
+
+def _targets(b):
+    t = [np.asarray(b.truth[e], np.float64)[:, 2:4] for e in range(b.n_events)]
+    off = np.concatenate([[0], np.cumsum([len(a) for a in t])]).astype(np.int64)
+    return np.concatenate(t), off
+
+
+def _bf16_bits_to_f64(u16):
+    return (np.asarray(u16).astype(np.uint32) << 16).view(np.float32).astype(np.float64)
+
+
+def _oracle_images(b):
+    return [op.bin_image(*(lambda ev: (ev.x, ev.y, ev.plane))(b.event(e)), b.plane_z) for e in range(b.n_events)]
+
+
+def _logit_bound(img, params):
+    """Elementwise bound on |logits_gpu - logits_oracle| (see module docstring)."""
+    acts, _ = op.forward(img, params, store_bf16=True)
+    absW = [(np.abs(op.bf16_round(W)), np.zeros_like(bb)) for W, bb in params]
+    err = np.zeros_like(acts[0])
+    mag = np.abs(acts[0])
+    for l in range(4):
+        err = op.conv3x3(err, absW[l][0], absW[l][1])
+        mag = op.conv3x3(mag, absW[l][0], np.abs(np.asarray(params[l][1], np.float64)))
+        err = err + 1e-5 * mag                           # FP32 accumulation (K <= 1152)
+        if l < 3:
+            err = err + 2 * U_BF16 * acts[l + 1]         # rounding of the stored activation
+            mag = acts[l + 1]
+    return err[..., 0]
+
+
+# ------------------------------------------------------------------ images
+def test_bin_image_exact(ctx, batch):
+    _say("proposer: bin image")
+    m = ctx.retina_model_create(INIT_KEY)
+    img, _ = ctx.retina_model_forward(m, batch.plane_z, batch.event_offsets, batch.x, batch.y, batch.plane)
+    ref = _oracle_images(batch)
+    for e in range(batch.n_events):
+        want = op.bf16_round(ref[e])
+        got = _bf16_bits_to_f64(img[e])
+        assert np.array_equal(got, want), "event %d: %d bins differ" % (e, int((got != want).sum()))
+    assert not _bf16_bits_to_f64(img[3]).any()
+
+
+def test_model_params_round_trip(ctx):
+    m = ctx.retina_model_create(INIT_KEY)
+    p = m.retina_model_get_params()
+    assert p.shape == (retina.MODEL_PARAMS,) and np.isfinite(p).all()
+    layers = op.unpack_params(p)
+    for l, (W, bb) in enumerate(layers):
+        sd = np.sqrt(2.0 / (9 * op.CHANNELS[l]))
+        assert abs(W.std() / sd - 1) < 0.1 and abs(W.mean()) < 0.1 * sd
+        assert np.all(bb == (0 if l < 3 else np.float32(np.log(0.01 / 0.99))))
+    q = np.random.default_rng(1).normal(size=p.shape).astype(np.float32)
+    m.retina_model_set_params(q)
+    assert np.array_equal(m.retina_model_get_params(), q)
+    m2 = ctx.retina_model_create(INIT_KEY)
+    assert np.array_equal(m2.retina_model_get_params(), p)   # same key, same weights
+
+
+# ------------------------------------------------------------------ forward
+def test_forward_logits_parity(ctx, batch):
+    _say("proposer: forward logits")
+    m = ctx.retina_model_create(INIT_KEY)
+    # a model with non-trivial biases so every layer's bias path is exercised
+    p = m.retina_model_get_params()
+    rng = np.random.default_rng(7)
+    layers = op.unpack_params(p)
+    q = np.concatenate([np.concatenate([W.ravel(), rng.normal(0, 0.05, bb.shape)]) for W, bb in layers])
+    m.retina_model_set_params(q.astype(np.float32))
+    params = op.unpack_params(m.retina_model_get_params())
+    _, logits = ctx.retina_model_forward(m, batch.plane_z, batch.event_offsets, batch.x, batch.y, batch.plane)
+    for e, img in enumerate(_oracle_images(batch)):
+        _, zr = op.forward(img, params, store_bf16=True)
+        bound = _logit_bound(img, params)
+        d = np.abs(logits[e].astype(np.float64) - zr)
+        bad = d > 1.5 * bound + 1e-6
+        assert not bad.any(), "event %d: %d logits outside the bound (max excess %g)" % (
+            e, int(bad.sum()), float((d - 1.5 * bound).max()))
+        rel = np.linalg.norm(d) / np.linalg.norm(zr)
+        assert rel < 1e-3, "event %d: relative L2 error %g" % (e, rel)
+
+
+# ------------------------------------------------------------------ gradients
+def _oracle_loss_grad(b, params, pos_weight):
+    tg, toff = _targets(b)
+    imgs = _oracle_images(b)
+    outs = [op.forward(img, params, store_bf16=True) for img in imgs]
+    z = np.stack([o[1] for o in outs])
+    y = np.stack([op.target_image(tg[toff[e]:toff[e + 1]]) for e in range(b.n_events)])
+    loss, dz = op.bce_logits(z, y, pos_weight)
+    grads = None
+    for e, (acts, _) in enumerate(outs):
+        g = op.backward(acts, params, dz[e], store_bf16=True)
+        grads = g if grads is None else [(a[0] + c[0], a[1] + c[1]) for a, c in zip(grads, g)]
+    return loss, op.pack_grads(grads), y
+
+
+def _layer_slices():
+    out, q = [], 0
+    for l in range(4):
+        ci, co = op.CHANNELS[l], op.CHANNELS[l + 1]
+        out.append((slice(q, q + 9 * ci * co), slice(q + 9 * ci * co, q + 9 * ci * co + co)))
+        q += 9 * ci * co + co
+    return out
+
+
+def test_train_step_gradient_parity(ctx, batch):
+    _say("proposer: gradient")
+    pw = 20.0
+    m = ctx.retina_model_create(INIT_KEY)
+    p0 = m.retina_model_get_params()
+    params = op.unpack_params(p0)
+    tg, toff = _targets(batch)
+    loss, grad = ctx.retina_train_step(m, batch.plane_z, batch.event_offsets, batch.x, batch.y, batch.plane,
+                                       tg, toff, 0.0, pw, want_grad=True)
+    assert m.step == 0
+    lref, gref, y = _oracle_loss_grad(batch, params, pw)
+    assert y.sum() > 100
+    assert loss == pytest.approx(lref, rel=1e-3)
+    g = grad.astype(np.float64)
+    for l, (sw, sb) in enumerate(_layer_slices()):
+        for name, s in (("W", sw), ("b", sb)):
+            a, r = g[s], gref[s]
+            rel = np.linalg.norm(a - r) / np.linalg.norm(r)
+            cos = a @ r / (np.linalg.norm(a) * np.linalg.norm(r))
+            _say("  layer %d %s: rel L2 %.2e cos %.7f" % (l, name, rel, cos))
+            assert rel < 1e-3 and cos > 0.99999, "layer %d %s: rel %g cos %g" % (l, name, rel, cos)
+    # an lr = 0 call leaves the weights alone
+    assert np.array_equal(m.retina_model_get_params(), p0)
+
+
+def test_adam_first_step_closed_form(ctx, batch):
+    """From zero moments Adam's first step is lr g / (|g| + eps) (bias
+    corrections cancel): every weight moves by lr times the sign of its
+    gradient, up to the eps term."""
+    _say("proposer: adam step")
+    lr, pw = 1e-3, 20.0
+    m = ctx.retina_model_create(INIT_KEY)
+    w0 = m.retina_model_get_params().astype(np.float64)
+    tg, toff = _targets(batch)
+    _, g = ctx.retina_train_step(m, batch.plane_z, batch.event_offsets, batch.x, batch.y, batch.plane,
+                                 tg, toff, 0.0, pw, want_grad=True)
+    ctx.retina_train_step(m, batch.plane_z, batch.event_offsets, batch.x, batch.y, batch.plane,
+                          tg, toff, lr, pw)
+    assert m.step == 1
+    w1 = m.retina_model_get_params().astype(np.float64)
+    want = w0 - lr * g / (np.abs(g.astype(np.float64)) + 1e-8)
+    np.testing.assert_allclose(w1, want, rtol=0, atol=4e-6 * lr + 2 * np.abs(w0).max() * 2 ** -24)
+    big = np.abs(g) > 1e-6
+    assert big.mean() > 0.9
+    np.testing.assert_allclose(np.abs(w1 - w0)[big], lr, rtol=2e-2)
+
+
+def test_training_reduces_loss(ctx, batch):
+    _say("proposer: training")
+    m = ctx.retina_model_create(INIT_KEY)
+    tg, toff = _targets(batch)
+    args = (batch.plane_z, batch.event_offsets, batch.x, batch.y, batch.plane, tg, toff)
+    losses = [ctx.retina_train_step(m, *args, 1e-3, 20.0)[0] for _ in range(30)]
+    _say("  loss %.4f -> %.4f" % (losses[0], losses[-1]))
+    assert m.step == 30
+    assert losses[-1] < 0.5 * losses[0]
+
+
+def test_save_load_resume_bit_exact(ctx, batch):
+    _say("proposer: save/load")
+    tg, toff = _targets(batch)
+    args = (batch.plane_z, batch.event_offsets, batch.x, batch.y, batch.plane, tg, toff)
+    m = ctx.retina_model_create(INIT_KEY)
+    for _ in range(2):
+        ctx.retina_train_step(m, *args, 1e-3, 20.0)
+    with tempfile.TemporaryDirectory() as d:
+        path = os.path.join(d, "m.bin")
+        m.retina_model_save(path)
+        m2 = ctx.retina_model_load(path)
+        assert m2.step == 2
+        assert np.array_equal(m2.retina_model_get_params(), m.retina_model_get_params())
+        l1 = ctx.retina_train_step(m, *args, 1e-3, 20.0)[0]
+        l2 = ctx.retina_train_step(m2, *args, 1e-3, 20.0)[0]
+        assert l1 == l2
+        assert np.array_equal(m2.retina_model_get_params(), m.retina_model_get_params())
+        raw = bytearray(open(path, "rb").read())
+        raw[100] ^= 1
+        open(path, "wb").write(bytes(raw))
+        with pytest.raises(retina.RetinaError, match="checksum"):
+            ctx.retina_model_load(path)
+
+
+# ------------------------------------------------------------------ proposal
+def _exact_net(bias=-3.0):
+    """Weights under which the logits are exact in FP32: the centre taps carry
+    channel 0 + channel 1 through three ReLU layers, the last bias is `bias`,
+    so logit = bf16(img0 + img1) + bias at every bin."""
+    layers = []
+    for l in range(4):
+        ci, co = op.CHANNELS[l], op.CHANNELS[l + 1]
+        W = np.zeros((co, 9, ci))
+        W[0, 4, 0] = 1.0
+        if l == 0:
+            W[0, 4, 1] = 1.0
+        b = np.zeros(co)
+        if l == 3:
+            b[0] = bias
+        layers.append((W, b))
+    return layers
+
+
+def _pack(layers):
+    return np.concatenate([np.concatenate([W.ravel(), b]) for W, b in layers]).astype(np.float32)
+
+
+@pytest.fixture(scope="module")
+def prop_batch():
+    """Two training-workload events, an empty event and a one-hit event."""
+    cfg = events.load_config("c4")
+    evs = [events.make_event(cfg, 10 + i) for i in range(2)]
+    z = np.zeros(0)
+    empty = events.Event(z.astype(np.float32), z.astype(np.float32), z.astype(np.int32), z.astype(np.int32),
+                         np.zeros((0, 4)), z.astype(np.int32))
+    one = events.Event(np.array([3.0], np.float32), np.array([-2.0], np.float32), np.array([7], np.int32),
+                       np.array([-1], np.int32), np.zeros((0, 4)), z.astype(np.int32))
+    return events.batch_from_events(2, events.plane_z(cfg), evs + [empty, one])
+
+
+TAU, CONF_MIN, K_MAX = 0.07, 0.11, 48
+
+
+def _oracle_seeds(b, layers, lattice_params, nms, k_max=K_MAX, tau=TAU, conf_min=CONF_MIN):
+    seeds, off, conf, fb = [], [0], [], []
+    lat = oracle.lattice(2, lattice_params)
+    for e, img in enumerate(_oracle_images(b)):
+        _, z = op.forward(img, layers, store_bf16=True)
+        picks = op.nms_topk(z, tau, k_max, nms=nms)
+        conf.append(1.0 / (1.0 + np.exp(-z.max())))
+        if not picks or z.max() < op.logit_threshold(conf_min):
+            fb.append(1)
+            s = lat
+        else:
+            fb.append(0)
+            s = op.seeds_from_pixels(picks)
+        seeds.append(s)
+        off.append(off[-1] + len(s))
+    return np.concatenate(seeds), np.array(off, np.int64), np.array(conf), np.array(fb)
+
+
+@pytest.mark.parametrize("nms", [True, False])
+def test_propose_seeds_exact(ctx, prop_batch, nms):
+    _say("proposer: seeds nms=%d" % nms)
+    b = prop_batch
+    params = dict(events.load_config("c4")["params"])
+    layers = _exact_net()
+    m = ctx.retina_model_create(INIT_KEY)
+    m.retina_model_set_params(_pack(layers))
+    _, logits = ctx.retina_model_forward(m, b.plane_z, b.event_offsets, b.x, b.y, b.plane)
+    # the logits are exact: the oracle's FP64 values are the same numbers
+    for e, img in enumerate(_oracle_images(b)):
+        assert np.array_equal(logits[e].astype(np.float64), op.forward(img, layers)[1])
+    res = ctx.retina_propose_seeds(m, b.plane_z, b.event_offsets, b.x, b.y, b.plane, K_MAX, TAU, CONF_MIN, params,
+                                   nms=nms)
+    s_ref, off_ref, conf_ref, fb_ref = _oracle_seeds(b, layers, params, nms)
+    assert list(fb_ref) == [0, 0, 1, 1]
+    np.testing.assert_array_equal(res["fallback"], fb_ref)
+    np.testing.assert_array_equal(res["seed_offsets"], off_ref)
+    np.testing.assert_array_equal(res["seeds"], s_ref)
+    np.testing.assert_allclose(res["confidence"], conf_ref, rtol=1e-6)
+    # too small a buffer reports the size it needs
+    with pytest.raises(retina.RetinaError) as ei:
+        ctx.retina_propose_seeds(m, b.plane_z, b.event_offsets, b.x, b.y, b.plane, K_MAX, TAU, CONF_MIN,
+                                 params, capacity=5, nms=nms)
+    assert ei.value.code == retina.ERR_CAPACITY and ei.value.required == off_ref[-1]
+
+
+@pytest.mark.parametrize("k_max", [4096, 77])
+def test_propose_seeds_more_candidates_than_fit(ctx, prop_batch, k_max):
+    """Every bin above the threshold (16,384 candidates, long runs of equal
+    logits): the selection of the k_max best must still follow (score desc,
+    index asc) exactly."""
+    _say("proposer: selection overflow k_max=%d" % k_max)
+    b = prop_batch
+    params = dict(events.load_config("c4")["params"])
+    layers = _exact_net(bias=3.0)
+    m = ctx.retina_model_create(INIT_KEY)
+    m.retina_model_set_params(_pack(layers))
+    res = ctx.retina_propose_seeds(m, b.plane_z, b.event_offsets, b.x, b.y, b.plane, k_max, TAU, CONF_MIN, params,
+                                   nms=False)
+    s_ref, off_ref, _, fb_ref = _oracle_seeds(b, layers, params, False, k_max=k_max)
+    assert not fb_ref.any()
+    np.testing.assert_array_equal(res["seed_offsets"], off_ref)
+    np.testing.assert_array_equal(res["seeds"], s_ref)
+
+
+def test_find_tracks_learned_parity(ctx, prop_batch):
+    """Algorithm 1 on the proposer's seeds (device hand-off) against the oracle
+    on the oracle's seeds."""
+    _say("proposer: learned find_tracks")
+    b = prop_batch
+    cfg = events.load_config("c4")
+    params = dict(cfg["params"])
+    params.update(sigma=[2.0, 1.0, 0.5, 0.25, 0.125, 0.0625], n_slope_steps=3)
+    layers = _exact_net()
+    m = ctx.retina_model_create(INIT_KEY)
+    m.retina_model_set_params(_pack(layers))
+    res = ctx.retina_find_tracks_learned(m, b.plane_z, b.event_offsets, b.x, b.y, b.plane, params,
+                                         K_MAX, TAU, CONF_MIN, nms=True)
+    s_ref, off_ref, _, fb_ref = _oracle_seeds(b, layers, params, True)
+    ref = oracle.find_tracks(b, params, s_ref, off_ref)
+    assert list((res["event_flags"] >> 4) & 1) == list(fb_ref)
+    z0, z1 = float(b.plane_z[0]), float(b.plane_z[-1])
+    for e in range(b.n_events):
+        a, c = int(ref["track_offsets"][e]), int(ref["track_offsets"][e + 1])
+        gt, gR = event_tracks(res, e, 2)
+        assert_tracks_match(2, gt, gR, ref["theta"][a:c], ref["R"][a:c], params["d_merge"], z0, z1)
+    assert int(res["track_offsets"][2]) > 50

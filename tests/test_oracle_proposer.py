@@ -154,3 +154,35 @@ def test_network_gradient_finite_differences():
             pm[l] = (Wm, b)
             fd = (loss(pp)[0] - loss(pm)[0]) / (2 * eps)
             assert fd == pytest.approx(grads[l][0][idx], rel=2e-4, abs=1e-9)
+
+
+def test_target_image_and_seed_centres_round_trip():
+    """A seed at a bin's centre lands back in that bin; values on the edges of
+    the range follow the half-open rule."""
+    pix = np.array([0, 127, 128 * 64 + 5, 128 * 128 - 1])
+    s = op.seeds_from_pixels(pix)
+    assert np.all(s[:, :2] == 0)
+    assert s[0, 2] == pytest.approx(-0.35 + 0.7 / 256, abs=1e-7)
+    assert s[3, 3] == pytest.approx(0.35 - 0.7 / 256, abs=1e-7)
+    y = op.target_image(s[:, 2:])
+    assert y.sum() == 4 and all(y.ravel()[p] == 1 for p in pix)
+    edge = op.target_image([[np.float32(0.35), 0.0], [np.float32(-0.35), 0.0]])
+    assert edge.sum() == 1 and edge[0, 64] == 1
+
+
+def test_topk_without_nms_is_a_sort():
+    """Without suppression the selection is the k largest values above the
+    threshold, ties to the lower index: a stable argsort of -z."""
+    z = np.round(np.random.default_rng(3).normal(size=(12, 10)), 1)   # many ties
+    thr = op.logit_threshold(0.4)
+    flat = z.ravel()
+    order = [i for i in np.argsort(-flat, kind="stable") if flat[i] > thr]
+    assert op.nms_topk(z, 0.4, 30, nms=False) == order[:30]
+    assert op.nms_topk(z, 0.4, 1000, nms=False) == order
+
+
+def test_logit_threshold():
+    assert op.logit_threshold(0.5) == 0.0
+    assert op.logit_threshold(0.0) == -np.inf and op.logit_threshold(1.0) == np.inf
+    assert op.logit_threshold(0.9) == pytest.approx(np.log(9), rel=1e-7)
+    assert op.logit_threshold(0.9) == float(np.float32(op.logit_threshold(0.9)))
