@@ -1041,20 +1041,7 @@ void forward_net(retina_ctx* c, const retina_model* md, int64_t E, const Acts& A
 {
     const Desc& d = *c->h_desc;
     launch_bin_image(d.hits, d.plane_off, d.n_planes, 2, c->d_desc->plane_z, E, A.act[0], c->stream);
-    for (int l = 0; l < kLayers; ++l) {
-        GemmArgs a = {};
-        a.mode = kFwd;
-        a.B = (int)E;
-        a.cin = kChan[l];
-        a.cout = kChan[l + 1];
-        a.act = l < kLayers - 1 ? 1 : 0;
-        a.x = A.act[l];
-        a.w = md->wbf + md->L.w_off[l];
-        a.bias = md->w32 + md->L.b_off[l];
-        if (l < kLayers - 1) a.y_bf16 = A.act[l + 1];
-        else a.y_f32 = A.logits;
-        launch_gemm(a, c->stream);
-    }
+    launch_forward(A.act[0], md->wbf, md->w32, md->L, E, A.act[1], A.act[2], A.act[3], A.logits, c->stream);
 }
 
 }  // namespace

@@ -305,6 +305,258 @@ void launch_gemm(const GemmArgs& a, hipStream_t st)
     hipLaunchKernelGGL(k_gemm, grid, dim3(256), 0, st, a, s);
 }
 
+// ------------------------------------------------------- forward (inference)
+// Direct convolutions for the forward pass, one kernel shape per layer kind:
+//   k_conv_in   2 -> 64 channels: K = 18 is too short for MFMA; one thread per
+//               (pixel, 8 output channels), FP32 FMAs, weights in LDS.
+//   k_conv_mid  64 -> 128 and 128 -> 96: BF16 MFMA 32x32x16 (gfx950).  A
+//               work-group (8 waves) owns 4 output rows x 128 columns x all
+//               output channels.  The input rows it needs (with the zero halo)
+//               sit in LDS once per 64-channel chunk and serve all nine taps;
+//               the weights stream through LDS one (tap, chunk) slice at a
+//               time, double-buffered.  Each wave computes 64 pixels x COUT;
+//               the result goes back through LDS for coalesced 16-byte stores.
+//   k_conv_head 96 -> 1: per pixel q the nine dot products U[q][tap] = sum_c
+//               W[tap][c] x[q][c] (one read of the activations), then
+//               logit[p] = b + sum_tap U[p + offset(tap)][tap] from LDS.
+typedef __bf16 v8bf __attribute__((ext_vector_type(8)));
+typedef float v16f __attribute__((ext_vector_type(16)));
+
+__global__ __launch_bounds__(256) void k_conv_in(const uint16_t* __restrict__ x, const uint16_t* __restrict__ w,
+                                                 const float* __restrict__ bias, uint16_t* __restrict__ y,
+                                                 int64_t npix)
+{
+    constexpr int CO = 64, K = 18, KP = conv_kp(2);
+    __shared__ float s_w[CO * K];
+    __shared__ float s_b[CO];
+    for (int i = threadIdx.x; i < CO * K; i += blockDim.x) s_w[i] = bf2f(w[(i / K) * KP + i % K]);
+    for (int i = threadIdx.x; i < CO; i += blockDim.x) s_b[i] = bias[i];
+    __syncthreads();
+    for (int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; g < npix * 8;
+         g += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t m = g >> 3;
+        const int cg = (int)(g & 7);
+        const int64_t b = m / kPix;
+        const int r = (int)((m / kImg) % kImg), c = (int)(m % kImg);
+        float in[K];
+#pragma unroll
+        for (int tap = 0; tap < 9; ++tap) {
+            const int rr = r + tap / 3 - 1, cc = c + tap % 3 - 1;
+            uint32_t v = 0;
+            if (rr >= 0 && rr < kImg && cc >= 0 && cc < kImg)
+                v = *reinterpret_cast<const uint32_t*>(x + ((b * kPix) + (int64_t)rr * kImg + cc) * 2);
+            in[2 * tap] = bf2f((uint16_t)(v & 0xFFFFu));
+            in[2 * tap + 1] = bf2f((uint16_t)(v >> 16));
+        }
+        uint16_t o[8];
+#pragma unroll
+        for (int j = 0; j < 8; ++j) {
+            const float* wr = s_w + (8 * cg + j) * K;
+            float acc = s_b[8 * cg + j];
+#pragma unroll
+            for (int k = 0; k < K; ++k) acc = fmaf(wr[k], in[k], acc);
+            o[j] = f2bf(fmaxf(acc, 0.0f));
+        }
+        *reinterpret_cast<uint4*>(y + m * CO + 8 * cg) = *reinterpret_cast<const uint4*>(o);
+    }
+}
+
+constexpr int kCvRows = 4;                 // output rows per work-group
+constexpr int kCvThreads = 512;            // 8 waves: (output row, half row)
+constexpr int kCvChunk = 64;               // input channels staged per pass
+constexpr int kCvPitch = kCvChunk + 8;     // LDS elements per staged pixel (144 B)
+constexpr int kCvCols = kImg + 2;          // staged columns incl. the zero halo
+
+template <int CIN, int COUT>
+constexpr size_t conv_mid_lds()
+{
+    constexpr size_t in = (size_t)(kCvRows + 2) * kCvCols * kCvPitch * 2;
+    constexpr size_t wt = (size_t)2 * COUT * kCvPitch * 2;
+    constexpr size_t out = (size_t)(kCvThreads / 64) * 64 * (COUT + 8) * 2;
+    return in + wt > out ? in + wt : out;
+}
+
+template <int CIN, int COUT>
+__global__ __launch_bounds__(kCvThreads) void k_conv_mid(const uint16_t* __restrict__ x,
+                                                         const uint16_t* __restrict__ w,
+                                                         const float* __restrict__ bias,
+                                                         uint16_t* __restrict__ y)
+{
+    static_assert(CIN % kCvChunk == 0 && COUT % 32 == 0 && conv_kp(CIN) == 9 * CIN, "layer shape");
+    constexpr int NB = COUT / 32, NCH = CIN / kCvChunk, KP = 9 * CIN;
+    constexpr int WU = COUT * (kCvChunk / 8);                    // 16-byte units of one weight slice
+    constexpr int WPT = (WU + kCvThreads - 1) / kCvThreads;
+    constexpr int IU = (kCvRows + 2) * kCvCols * (kCvChunk / 8);  // 16-byte units of one input tile
+    extern __shared__ float4 s_dyn[];
+    uint16_t* s_in = reinterpret_cast<uint16_t*>(s_dyn);
+    uint16_t* s_w = s_in + (kCvRows + 2) * kCvCols * kCvPitch;
+    const int t = threadIdx.x, lane = t & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(t >> 6);
+    const int orow = wave >> 1, ocol0 = (wave & 1) * 64;
+    const int64_t e = blockIdx.x / (kImg / kCvRows);
+    const int r0 = (int)(blockIdx.x % (kImg / kCvRows)) * kCvRows;
+
+    v16f acc[2][NB];
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int j = 0; j < NB; ++j)
+#pragma unroll
+            for (int r = 0; r < 16; ++r) acc[i][j][r] = 0.0f;
+
+    uint4 wreg[WPT];
+    for (int c = 0; c < NCH; ++c) {
+        __syncthreads();
+        for (int u = t; u < IU; u += kCvThreads) {
+            const int q = u & 7, pc = (u >> 3) % kCvCols, pr = (u >> 3) / kCvCols;
+            const int r = r0 - 1 + pr, col = pc - 1;
+            uint4 v = make_uint4(0, 0, 0, 0);
+            if (r >= 0 && r < kImg && col >= 0 && col < kImg)
+                v = *reinterpret_cast<const uint4*>(x + ((e * kImg + r) * kImg + col) * CIN + c * kCvChunk + q * 8);
+            *reinterpret_cast<uint4*>(s_in + (pr * kCvCols + pc) * kCvPitch + q * 8) = v;
+        }
+        for (int tap = -1; tap < 9; ++tap) {
+            // stage the next weight slice (tap + 1) while this tap computes
+            if (tap < 8) {
+#pragma unroll
+                for (int i = 0; i < WPT; ++i) {
+                    const int u = t + i * kCvThreads;
+                    if (u < WU)
+                        wreg[i] = *reinterpret_cast<const uint4*>(w + (int64_t)(u >> 3) * KP + (tap + 1) * CIN +
+                                                                  c * kCvChunk + (u & 7) * 8);
+                }
+            }
+            if (tap >= 0) {
+                const int dr = tap / 3 - 1, dc = tap % 3 - 1;
+                const uint16_t* arow = s_in + ((orow + 1 + dr) * kCvCols + (ocol0 + 1 + dc)) * kCvPitch;
+                const uint16_t* wb = s_w + (tap & 1) * COUT * kCvPitch;
+#pragma unroll
+                for (int kk = 0; kk < kCvChunk / 16; ++kk) {
+                    const int ko = kk * 16 + 8 * (lane >> 5);
+                    v8bf af[2], bfr[NB];
+#pragma unroll
+                    for (int mb = 0; mb < 2; ++mb)
+                        af[mb] = *reinterpret_cast<const v8bf*>(arow + (mb * 32 + (lane & 31)) * kCvPitch + ko);
+#pragma unroll
+                    for (int nb = 0; nb < NB; ++nb)
+                        bfr[nb] = *reinterpret_cast<const v8bf*>(wb + (nb * 32 + (lane & 31)) * kCvPitch + ko);
+#pragma unroll
+                    for (int mb = 0; mb < 2; ++mb)
+#pragma unroll
+                        for (int nb = 0; nb < NB; ++nb)
+                            acc[mb][nb] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(af[mb], bfr[nb], acc[mb][nb], 0, 0, 0);
+                }
+            }
+            if (tap < 8) {
+                // buffer (tap + 1) & 1 was last read at tap - 1, before the barrier below it
+                uint16_t* wn = s_w + ((tap + 1) & 1) * COUT * kCvPitch;
+#pragma unroll
+                for (int i = 0; i < WPT; ++i) {
+                    const int u = t + i * kCvThreads;
+                    if (u < WU) *reinterpret_cast<uint4*>(wn + (u >> 3) * kCvPitch + (u & 7) * 8) = wreg[i];
+                }
+            }
+            __syncthreads();
+        }
+    }
+    // epilogue: bias, ReLU, BF16 through LDS; lane holds rows 8 (r / 4) + 4 (lane / 32) + r % 4,
+    // column lane % 32 of each 32 x 32 block
+    uint16_t* s_out = reinterpret_cast<uint16_t*>(s_dyn) + wave * 64 * (COUT + 8);
+#pragma unroll
+    for (int nb = 0; nb < NB; ++nb) {
+        const int co = nb * 32 + (lane & 31);
+        const float bb = bias[co];
+#pragma unroll
+        for (int mb = 0; mb < 2; ++mb)
+#pragma unroll
+            for (int r = 0; r < 16; ++r) {
+                const int px = mb * 32 + 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3);
+                s_out[px * (COUT + 8) + co] = f2bf(fmaxf(acc[mb][nb][r] + bb, 0.0f));
+            }
+    }
+    __syncthreads();
+    uint16_t* dst = y + ((e * kImg + r0 + orow) * kImg + ocol0) * COUT;
+    constexpr int OU = 64 * COUT / 8;
+    for (int u = lane; u < OU; u += 64) {
+        const int px = u / (COUT / 8), q = u % (COUT / 8);
+        *reinterpret_cast<uint4*>(dst + px * COUT + q * 8) =
+            *reinterpret_cast<const uint4*>(s_out + px * (COUT + 8) + q * 8);
+    }
+}
+
+constexpr int kHeadRows = 8;  // output rows per work-group of k_conv_head
+
+__global__ __launch_bounds__(256) void k_conv_head(const uint16_t* __restrict__ x, const uint16_t* __restrict__ w,
+                                                   const float* __restrict__ bias, float* __restrict__ logits)
+{
+    constexpr int CIN = 96, KP = conv_kp(CIN), UR = kHeadRows + 2;
+    __shared__ float s_w[9 * CIN];          // W[tap][c]
+    __shared__ float s_u[UR * kImg * 9];    // U for the rows r0 - 1 .. r0 + kHeadRows
+    const int64_t e = blockIdx.x / (kImg / kHeadRows);
+    const int r0 = (int)(blockIdx.x % (kImg / kHeadRows)) * kHeadRows;
+    for (int i = threadIdx.x; i < 9 * CIN; i += blockDim.x) s_w[i] = bf2f(w[i]);
+    __syncthreads();
+    for (int q = threadIdx.x; q < UR * kImg; q += blockDim.x) {
+        const int r = r0 - 1 + q / kImg, col = q % kImg;
+        float u[9];
+#pragma unroll
+        for (int tap = 0; tap < 9; ++tap) u[tap] = 0.0f;
+        if (r >= 0 && r < kImg) {
+            const uint16_t* px = x + ((e * kImg + r) * kImg + col) * CIN;
+            for (int c8 = 0; c8 < CIN / 8; ++c8) {
+                const uint4 raw = *reinterpret_cast<const uint4*>(px + c8 * 8);
+                const uint16_t* h = reinterpret_cast<const uint16_t*>(&raw);
+                float v[8];
+#pragma unroll
+                for (int j = 0; j < 8; ++j) v[j] = bf2f(h[j]);
+#pragma unroll
+                for (int tap = 0; tap < 9; ++tap)
+#pragma unroll
+                    for (int j = 0; j < 8; ++j) u[tap] = fmaf(s_w[tap * CIN + c8 * 8 + j], v[j], u[tap]);
+            }
+        }
+#pragma unroll
+        for (int tap = 0; tap < 9; ++tap) s_u[q * 9 + tap] = u[tap];
+    }
+    __syncthreads();
+    const float b = bias[0];
+    for (int p = threadIdx.x; p < kHeadRows * kImg; p += blockDim.x) {
+        const int rl = p / kImg, col = p % kImg;  // output row r0 + rl = staged row rl + 1
+        float z = b;
+#pragma unroll
+        for (int tap = 0; tap < 9; ++tap) {
+            const int sr = rl + 1 + tap / 3 - 1, cc = col + tap % 3 - 1;
+            if (cc >= 0 && cc < kImg) z += s_u[(sr * kImg + cc) * 9 + tap];
+        }
+        logits[(e * kImg + r0 + rl) * kImg + col] = z;
+    }
+    static_assert(KP == 9 * CIN, "head weights are unpadded");
+}
+
+void launch_forward(const uint16_t* img, const uint16_t* wbf, const float* w32, const NetLayout& L, int64_t E,
+                    uint16_t* act1, uint16_t* act2, uint16_t* act3, float* logits, hipStream_t st)
+{
+    constexpr size_t l1 = conv_mid_lds<64, 128>(), l2 = conv_mid_lds<128, 96>();
+    static bool attr = false;
+    if (!attr) {
+        const void* f1 = reinterpret_cast<const void*>(&k_conv_mid<64, 128>);
+        const void* f2 = reinterpret_cast<const void*>(&k_conv_mid<128, 96>);
+        (void)hipFuncSetAttribute(f1, hipFuncAttributeMaxDynamicSharedMemorySize, (int)l1);
+        (void)hipFuncSetAttribute(f2, hipFuncAttributeMaxDynamicSharedMemorySize, (int)l2);
+        attr = true;
+    }
+    const int64_t npix = E * kPix;
+    const int g0 = (int)std::min<int64_t>((npix * 8 + 255) / 256, 65536);
+    hipLaunchKernelGGL(k_conv_in, dim3(g0), dim3(256), 0, st, img, wbf + L.w_off[0], w32 + L.b_off[0], act1, npix);
+    const unsigned gm = (unsigned)(E * (kImg / kCvRows));
+    hipLaunchKernelGGL((k_conv_mid<64, 128>), dim3(gm), dim3(kCvThreads), l1, st, act1,
+                       wbf + L.w_off[1], w32 + L.b_off[1], act2);
+    hipLaunchKernelGGL((k_conv_mid<128, 96>), dim3(gm), dim3(kCvThreads), l2, st, act2,
+                       wbf + L.w_off[2], w32 + L.b_off[2], act3);
+    hipLaunchKernelGGL(k_conv_head, dim3((unsigned)(E * (kImg / kHeadRows))), dim3(256), 0, st, act3,
+                       wbf + L.w_off[3], w32 + L.b_off[3], logits);
+}
+
 // ------------------------------------------------------------------ losses
 // Weighted binary cross-entropy on logits z with targets y in {0, 1}:
 //   l = w y softplus(-z) + (1 - y) softplus(z),  dl/dz = (w y + 1 - y) sigma(z) - w y
