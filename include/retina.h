@@ -165,7 +165,8 @@ int retina_set_stream(retina_ctx* ctx, void* hip_stream);
 int retina_set_max_device_bytes(retina_ctx* ctx, int64_t max_bytes);
 
 /* Kernel timing with HIP events recorded on the context's stream around each
- * launch of retina_find_tracks / retina_response while enabled.  Times
+ * launch of retina_find_tracks / retina_response (and the proposer stage of
+ * retina_propose_seeds / retina_find_tracks_learned) while enabled.  Times
  * accumulate (milliseconds) until retina_profile_reset. */
 typedef struct {
     int64_t calls;        /* profiled calls since the last reset */
@@ -177,6 +178,7 @@ typedef struct {
     double exec_pairs;    /* hit-candidate pairs the ascent kernel executed, all lanes
                              (including lanes idle in another lane's line search) */
     double exec_rpairs;   /* ... of which in R-only line-search passes */
+    double ms_propose;    /* learned seeds: binning, network and seed selection */
 } retina_profile;
 
 int retina_set_profiling(retina_ctx* ctx, int32_t enable);

@@ -53,7 +53,7 @@ struct retina_ctx {
     HotConfig ascent_cfg[3];      // by meas_dim
     HotConfig resp_cfg[3];
     bool prof = false;
-    hipEvent_t ev[5] = {};
+    hipEvent_t ev[7] = {};        // 0..4: find_tracks / response stages, 5..6: proposer
     retina_profile prof_acc = {};
     // captured find_tracks launch sequences: every kernel reads its sizes from the
     // device descriptor and runs a fixed persistent grid, so one graph per
@@ -432,7 +432,7 @@ void retina_destroy(retina_ctx* c)
     if (c->d_cnt) (void)hipFree(c->d_cnt);
     if (c->h_cnt) (void)hipHostFree(c->h_cnt);
     for (auto& g : c->graphs) (void)hipGraphExecDestroy(g.exec);
-    for (int i = 0; i < 5; ++i)
+    for (int i = 0; i < 7; ++i)
         if (c->ev[i]) (void)hipEventDestroy(c->ev[i]);
     if (c->own) (void)hipStreamDestroy(c->own);
     (void)hipGetLastError();  // leave no error of ours behind for the caller's next check
@@ -465,7 +465,7 @@ int retina_set_profiling(retina_ctx* c, int32_t enable)
     if (!c) return RETINA_ERR_INVALID_ARG;
     DeviceGuard guard(c->device);
     if (enable && !c->ev[0]) {
-        for (int i = 0; i < 5; ++i)
+        for (int i = 0; i < 7; ++i)
             HIP_TRY(c, hipEventCreate(&c->ev[i]));
     }
     c->prof = enable != 0;
@@ -1330,6 +1330,7 @@ int propose_device(retina_ctx* c, const retina_geometry* g, const retina_hits* h
     const int64_t E = h->n_events;
     Acts A;
     if ((rc = ensure_acts(c, E, A))) return rc;
+    prof_mark(c, 5);
     forward_net(c, md, E, A);
     const int64_t lat = (int64_t)P->lattice_n[0] * P->lattice_n[1];
     const int64_t cap = E * std::max<int64_t>(k_max, lat);
@@ -1354,8 +1355,15 @@ int propose_device(retina_ctx* c, const retina_geometry* g, const retina_hits* h
         return rc;
     launch_propose_select(pa, c->stream);
     launch_propose_offsets(pa, c->stream);
+    prof_mark(c, 6);
     HIP_TRY(c, hipGetLastError());
     if ((rc = read_i64(c, RETINA_MEM_DEVICE, pa.seed_off, E, n_seeds))) return rc;
+    if (c->prof) {
+        float t = 0.0f;
+        if (hipEventElapsedTime(&t, c->ev[5], c->ev[6]) != hipSuccess) t = 0.0f;
+        (void)hipGetLastError();
+        c->prof_acc.ms_propose += t;
+    }
     if (*n_seeds > cap) return fail(c, RETINA_ERR_INTERNAL, "seed count exceeds its bound");
     if ((rc = ensure_t(c, B_PSEEDS, (size_t)std::max<int64_t>(*n_seeds, 1) * 4, &pa.seeds))) return rc;
     launch_propose_write(pa, c->stream);

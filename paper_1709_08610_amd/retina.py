@@ -78,7 +78,8 @@ _lib = None
 class Profile(ctypes.Structure):
     _fields_ = [("calls", ctypes.c_int64), ("ms_stage", ctypes.c_double), ("ms_plan", ctypes.c_double),
                 ("ms_hot", ctypes.c_double), ("ms_merge", ctypes.c_double), ("ms_total", ctypes.c_double),
-                ("exec_pairs", ctypes.c_double), ("exec_rpairs", ctypes.c_double)]
+                ("exec_pairs", ctypes.c_double), ("exec_rpairs", ctypes.c_double),
+                ("ms_propose", ctypes.c_double)]
 
 
 EXPORTS = ["retina_create", "retina_destroy", "retina_last_error", "retina_set_stream",

@@ -1,0 +1,150 @@
+"""The trained proposer on the 1024-event batch: what it gains over the plain
+method (lattice seeds), an ablation with an untrained network, and parity of
+its seeds and tracks with the FP64 oracle on the same weights."""
+import sys
+import time
+
+import numpy as np
+import pytest
+
+import oracle
+from oracle import proposer as op
+from paper_1709_08610_amd import events, learned, metrics, retina
+
+from gpu_util import assert_tracks_match, event_tracks
+from proposer_util import _logit_bound, _oracle_images
+
+pytestmark = pytest.mark.gpu
+
+
+def _say(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def setup():
+    import torch
+    cfg = events.load_config("c3")
+    b = events.make_batch(cfg)
+    dev = torch.device("cuda:0")
+    tin = lambda a: torch.from_numpy(np.ascontiguousarray(a)).to(dev)
+    d = (tin(b.event_offsets), tin(b.x), tin(b.y), tin(b.plane))
+    ctx = retina.Context(0)
+    LS = learned.settings(cfg)
+    model = ctx.retina_model_load(LS["model"])
+    return cfg, b, d, ctx, LS, model
+
+
+def _quality(cfg, b, res):
+    tr = retina.tracks_from_device(res)
+    z0, z1 = float(b.plane_z.min()), float(b.plane_z.max())
+    return metrics.batch_quality(2, tr["theta"], res["track_offsets"].cpu().numpy(), b.truth, b.truth_nhits,
+                                 cfg["match_tol"], z0, z1)
+
+
+def _timed(ctx, f, n=3):
+    import torch
+    f()
+    torch.cuda.synchronize()
+    ctx.retina_set_profiling(True)
+    ctx.retina_profile_reset()
+    ts = []
+    for _ in range(n):
+        t0 = time.perf_counter()
+        r = f()
+        torch.cuda.synchronize()
+        ts.append(time.perf_counter() - t0)
+    prof = ctx.retina_get_profile()
+    ctx.retina_set_profiling(False)
+    return r, float(np.median(ts)), prof["exec_pairs"] / max(prof["calls"], 1)
+
+
+def test_trained_proposer_gain(setup):
+    """At >= 95% efficiency and no higher fake rate, the learned seeds do a
+    fraction of the lattice's ascent work and take well under half its time."""
+    _say("learned vs lattice on the 1024-event batch")
+    cfg, b, (off, x, y, pl), ctx, LS, model = setup
+    lat = lambda: ctx.retina_find_tracks(2, b.plane_z, off, x, y, pl, cfg["params"])
+    lrn = lambda: ctx.retina_find_tracks_learned(model, b.plane_z, off, x, y, pl, LS["params"], LS["k_max"],
+                                                 LS["tau"], LS["conf_min"], nms=LS["nms"])
+    r_lat, t_lat, w_lat = _timed(ctx, lat)
+    r_lrn, t_lrn, w_lrn = _timed(ctx, lrn)
+    q_lat, q_lrn = _quality(cfg, b, r_lat), _quality(cfg, b, r_lrn)
+    fb = float(((r_lrn["event_flags"] >> 4) & 1).float().mean().item())
+    _say("  lattice: %.2f ms eff %.4f fake %.4f pairs %.3g" % (t_lat * 1e3, q_lat["efficiency"],
+                                                                q_lat["fake_rate"], w_lat))
+    _say("  learned: %.2f ms eff %.4f fake %.4f pairs %.3g fallback %.3f" % (
+        t_lrn * 1e3, q_lrn["efficiency"], q_lrn["fake_rate"], w_lrn, fb))
+    assert q_lat["efficiency"] >= 0.95
+    assert q_lrn["efficiency"] >= 0.95
+    assert q_lrn["fake_rate"] <= q_lat["fake_rate"] + 1e-3
+    assert w_lrn < w_lat / 8
+    assert t_lrn < 0.5 * t_lat
+
+
+def test_untrained_network_ablation(setup):
+    """The gain comes from the trained weights: an untrained network is not
+    confident on any event (every event falls back to the lattice), and its
+    heatmap forced into use finds few tracks."""
+    _say("untrained network ablation")
+    cfg, b, (off, x, y, pl), ctx, LS, model = setup
+    m0 = ctx.retina_model_create(12345)
+    res = ctx.retina_propose_seeds(m0, b.plane_z, off, x, y, pl, LS["k_max"], LS["tau"], LS["conf_min"],
+                                   LS["params"], nms=LS["nms"])
+    assert bool((res["fallback"] == 1).all())
+    n_lat = cfg["params"]["lattice_n"][0] * cfg["params"]["lattice_n"][1]
+    assert int(res["seed_offsets"][-1].item()) == b.n_events * n_lat
+    forced = ctx.retina_find_tracks_learned(m0, b.plane_z, off, x, y, pl, LS["params"], LS["k_max"], 1e-4, 0.0,
+                                            nms=LS["nms"])
+    q = _quality(cfg, b, forced)
+    _say("  untrained heatmap forced: eff %.4f" % q["efficiency"])
+    assert q["efficiency"] < 0.5
+
+
+def test_trained_seeds_and_tracks_match_oracle(setup):
+    """On a few events: the oracle runs the trained weights in FP64 (BF16 at the
+    device's storage points), selects its own seeds and runs Algorithm 1 on
+    them; the device's seeds must be the same bins (up to bins whose logit is
+    within the forward error bound of the threshold) and, where they are, the
+    tracks must match."""
+    _say("trained proposer: seeds and tracks vs the oracle")
+    cfg, b, (off, x, y, pl), ctx, LS, model = setup
+    ev = list(range(6))
+    sub = events.batch_from_events(2, b.plane_z, [b.event(e) for e in ev])
+    layers = op.unpack_params(model.retina_model_get_params())
+    res = ctx.retina_propose_seeds(model, sub.plane_z, sub.event_offsets, sub.x, sub.y, sub.plane, LS["k_max"],
+                                   LS["tau"], LS["conf_min"], LS["params"], nms=LS["nms"])
+    thr = op.logit_threshold(LS["tau"])
+    lo = float(np.float32(op.SLOPE_LO))
+    w = (float(np.float32(op.SLOPE_HI)) - lo) / op.IMG
+    ref_seeds, ref_off, same = [], [0], True
+    for e, img in enumerate(_oracle_images(sub)):
+        _, z = op.forward(img, layers, store_bf16=True)
+        picks = op.nms_topk(z, LS["tau"], LS["k_max"], nms=LS["nms"])
+        a, c = int(res["seed_offsets"][e]), int(res["seed_offsets"][e + 1])
+        s = res["seeds"][a:c]
+        gpix = set((np.floor((s[:, 2] - lo) / w).astype(int) * op.IMG + np.floor((s[:, 3] - lo) / w).astype(int)))
+        diff = gpix ^ set(picks)
+        if diff:
+            bound = _logit_bound(img, layers).ravel()
+            zf = z.ravel()
+            marginal = [p for p in diff if abs(zf[p] - thr) <= 1.5 * bound[p] + 1e-6]
+            assert len(marginal) == len(diff), "event %d: seed bins differ beyond the error bound: %s" % (
+                e, sorted(set(diff) - set(marginal))[:10])
+            same = False
+        assert len(picks) < LS["k_max"] and res["fallback"][e] == 0
+        ref_seeds.append(op.seeds_from_pixels(picks))
+        ref_off.append(ref_off[-1] + len(picks))
+        _say("  event %d: %d seeds, %d differing (marginal) bins" % (e, len(picks), len(diff)))
+    if not same:
+        pytest.skip("marginal seed bins differ; track parity needs identical seeds")
+    ref = oracle.find_tracks(sub, LS["params"], np.concatenate(ref_seeds), np.array(ref_off, np.int64))
+    got = ctx.retina_find_tracks_learned(model, sub.plane_z, sub.event_offsets, sub.x, sub.y, sub.plane,
+                                         LS["params"], LS["k_max"], LS["tau"], LS["conf_min"], nms=LS["nms"])
+    z0, z1 = float(sub.plane_z[0]), float(sub.plane_z[-1])
+    for e in range(sub.n_events):
+        a, c = int(ref["track_offsets"][e]), int(ref["track_offsets"][e + 1])
+        gt, gR = event_tracks(got, e, 2)
+        assert_tracks_match(2, gt, gR, ref["theta"][a:c], ref["R"][a:c], LS["params"]["d_merge"], z0, z1)
+    _say("  %d tracks match" % int(ref["track_offsets"][-1]))

@@ -26,10 +26,10 @@ from oracle import proposer as op
 from paper_1709_08610_amd import events, retina
 
 from gpu_util import assert_tracks_match, event_tracks
+from proposer_util import U_BF16, _bf16_bits_to_f64, _logit_bound, _oracle_images
 
 pytestmark = pytest.mark.gpu
 
-U_BF16 = 2.0 ** -8
 INIT_KEY = 20170925
 
 
@@ -57,30 +57,6 @@ def _targets(b):
     t = [np.asarray(b.truth[e], np.float64)[:, 2:4] for e in range(b.n_events)]
     off = np.concatenate([[0], np.cumsum([len(a) for a in t])]).astype(np.int64)
     return np.concatenate(t), off
-
-
-def _bf16_bits_to_f64(u16):
-    return (np.asarray(u16).astype(np.uint32) << 16).view(np.float32).astype(np.float64)
-
-
-def _oracle_images(b):
-    return [op.bin_image(*(lambda ev: (ev.x, ev.y, ev.plane))(b.event(e)), b.plane_z) for e in range(b.n_events)]
-
-
-def _logit_bound(img, params):
-    """Elementwise bound on |logits_gpu - logits_oracle| (see module docstring)."""
-    acts, _ = op.forward(img, params, store_bf16=True)
-    absW = [(np.abs(op.bf16_round(W)), np.zeros_like(bb)) for W, bb in params]
-    err = np.zeros_like(acts[0])
-    mag = np.abs(acts[0])
-    for l in range(4):
-        err = op.conv3x3(err, absW[l][0], absW[l][1])
-        mag = op.conv3x3(mag, absW[l][0], np.abs(np.asarray(params[l][1], np.float64)))
-        err = err + 1e-5 * mag                           # FP32 accumulation (K <= 1152)
-        if l < 3:
-            err = err + 2 * U_BF16 * acts[l + 1]         # rounding of the stored activation
-            mag = acts[l + 1]
-    return err[..., 0]
 
 
 # ------------------------------------------------------------------ images
