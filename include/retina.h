@@ -186,7 +186,10 @@ int retina_get_profile(const retina_ctx* ctx, retina_profile* out);
 int retina_profile_reset(retina_ctx* ctx);
 
 /* Launch shape of the hot kernels (the autotuner's knobs).
- *   kernel     0: the ascent kernel of retina_find_tracks; 1: retina_response
+ *   kernel     0: the ascent kernel of retina_find_tracks for batches of at
+ *              least 512 seeds per event on average (dense seeding, e.g. a
+ *              lattice); 2: the same kernel for sparser batches (e.g. learned
+ *              seeds); 1: retina_response
  *   cand       candidate lines per lane: 1 or 2
  *   tile_hits  hits held in LDS per work-group (events with more hits are
  *              streamed through it tile by tile): 256 .. 16384 for
@@ -211,7 +214,9 @@ int retina_set_graphs(retina_ctx* ctx, int32_t enable);
  * fastest.  With cache_path != NULL the choice is stored in that text file
  * keyed by (device arch, meas_dim, workload class = floor(log2(mean hits per
  * event)), seeds per event class) and later calls with the same key reuse it
- * without timing.  *cand / *tile_hits (may be NULL) receive the choice. */
+ * without timing.  The sample's mean seeds per event decide which ascent
+ * shape (kernel 0 or 2 of retina_set_tuning) is tuned.  *cand / *tile_hits
+ * (may be NULL) receive the choice. */
 int retina_autotune(retina_ctx* ctx, const retina_geometry* geom, const retina_hits* sample,
                     const retina_params* params, const char* cache_path, int32_t* cand,
                     int32_t* tile_hits);

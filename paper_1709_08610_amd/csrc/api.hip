@@ -50,7 +50,8 @@ struct retina_ctx {
     Desc* h_desc = nullptr;       // pinned
     Counters* d_cnt = nullptr;
     Counters* h_cnt = nullptr;    // pinned
-    HotConfig ascent_cfg[3];      // by meas_dim
+    HotConfig ascent_cfg[3];      // by meas_dim: dense seeding (>= kSparseSeeds per event)
+    HotConfig sparse_cfg[3];      // by meas_dim: sparse seeding (fewer per event)
     HotConfig resp_cfg[3];
     bool prof = false;
     hipEvent_t ev[7] = {};        // 0..4: find_tracks / response stages, 5..6: proposer
@@ -268,6 +269,15 @@ int device_error(retina_ctx* c, uint32_t err)
     return fail(c, RETINA_ERR_INTERNAL, "device error bits 0x%x", err);
 }
 
+// find_tracks batches averaging fewer seeds per event than this run the
+// ascent with the sparse-seeding launch shape (tuning kernel 2)
+constexpr int64_t kSparseSeeds = 512;
+
+HotConfig& tuning_slot(retina_ctx* c, int D, int kernel)
+{
+    return kernel == 0 ? c->ascent_cfg[D] : kernel == 2 ? c->sparse_cfg[D] : c->resp_cfg[D];
+}
+
 HotConfig default_hot(const retina_ctx* c, int D, bool ascent)
 {
     HotConfig h;
@@ -415,6 +425,14 @@ int retina_create(int device_ordinal, retina_ctx** out)
     for (int D = 1; D <= 2; ++D) {
         c->ascent_cfg[D] = default_hot(c, D, true);
         c->resp_cfg[D] = default_hot(c, D, false);
+        // few seeds per event (learned seeding): one candidate per lane keeps the
+        // 256-seed work items full, and a smaller tile leaves room for more
+        // work-groups per CU
+        HotConfig h = c->ascent_cfg[D];
+        h.cand = 1;
+        h.tile_hits = D == 2 ? 4096 : 8192;
+        h.grid = c->n_cu * hot_max_blocks_per_cu(D, h, true);
+        c->sparse_cfg[D] = h;
     }
     *out = c;
     return RETINA_OK;
@@ -491,7 +509,7 @@ int retina_set_tuning(retina_ctx* c, int32_t meas_dim, int32_t kernel, int32_t c
     if (!c) return RETINA_ERR_INVALID_ARG;
     c->err.clear();
     if (meas_dim != 1 && meas_dim != 2) return fail(c, RETINA_ERR_INVALID_ARG, "meas_dim must be 1 or 2");
-    if (kernel != 0 && kernel != 1) return fail(c, RETINA_ERR_INVALID_ARG, "kernel must be 0 or 1");
+    if (kernel < 0 || kernel > 2) return fail(c, RETINA_ERR_INVALID_ARG, "kernel must be 0, 1 or 2");
     if (cand != 1 && cand != 2) return fail(c, RETINA_ERR_INVALID_ARG, "cand must be 1 or 2");
     const int max_tile = meas_dim == 2 ? 16384 : 32768;
     if (tile_hits < 256 || tile_hits > max_tile)
@@ -503,17 +521,17 @@ int retina_set_tuning(retina_ctx* c, int32_t meas_dim, int32_t kernel, int32_t c
     HotConfig h;
     h.cand = cand;
     h.tile_hits = tile_hits;
-    const int per_cu = hot_max_blocks_per_cu(meas_dim, h, kernel == 0);
+    const int per_cu = hot_max_blocks_per_cu(meas_dim, h, kernel != 1);
     h.grid = c->n_cu * per_cu;
-    (kernel == 0 ? c->ascent_cfg : c->resp_cfg)[meas_dim] = h;
+    tuning_slot(c, meas_dim, kernel) = h;
     return RETINA_OK;
 }
 
 int retina_get_tuning(const retina_ctx* c, int32_t meas_dim, int32_t kernel, int32_t* cand,
                       int32_t* tile_hits, int32_t* grid)
 {
-    if (!c || (meas_dim != 1 && meas_dim != 2) || (kernel != 0 && kernel != 1)) return RETINA_ERR_INVALID_ARG;
-    const HotConfig& h = (kernel == 0 ? c->ascent_cfg : c->resp_cfg)[meas_dim];
+    if (!c || (meas_dim != 1 && meas_dim != 2) || kernel < 0 || kernel > 2) return RETINA_ERR_INVALID_ARG;
+    const HotConfig& h = tuning_slot(const_cast<retina_ctx*>(c), meas_dim, kernel);
     if (cand) *cand = h.cand;
     if (tile_hits) *tile_hits = h.tile_hits;
     if (grid) *grid = h.grid;
@@ -702,7 +720,7 @@ static int find_tracks_impl(retina_ctx* c, const retina_geometry* g, const retin
     fill_geometry(d, g);
     d.cnt = c->d_cnt;
     if ((rc = stage_inputs(c, d, g, h, n_hits))) return rc;
-    const HotConfig hc = c->ascent_cfg[D];
+    const HotConfig hc = n_seeds < kSparseSeeds * E ? c->sparse_cfg[D] : c->ascent_cfg[D];
     d.seeds_per_item = hot_seeds_per_item(hc);
     d.items_cap = n_seeds / d.seeds_per_item + E + 1;
     if ((rc = ensure_t(c, B_ITEMS, (size_t)d.items_cap, &d.items))) return rc;
@@ -836,6 +854,7 @@ int retina_autotune(retina_ctx* c, const retina_geometry* g, const retina_hits* 
     } else {
         n_seeds = E * (int64_t)P->lattice_n[0] * P->lattice_n[1];
     }
+    const int kern = n_seeds < kSparseSeeds * E ? 2 : 0;  // the ascent slot this sample's seeding uses
     const int hit_class = (int)floor(log2(std::max<double>(1.0, (double)n_hits / (double)E)));
     const int seed_class = (int)floor(log2(std::max<double>(1.0, (double)n_seeds / (double)E)));
     char key[160];
@@ -856,7 +875,7 @@ int retina_autotune(retina_ctx* c, const retina_geometry* g, const retina_hits* 
                 }
             }
             fclose(f);
-            if (best_c && retina_set_tuning(c, D, 0, best_c, best_t) == RETINA_OK) {
+            if (best_c && retina_set_tuning(c, D, kern, best_c, best_t) == RETINA_OK) {
                 if (out_cand) *out_cand = best_c;
                 if (out_tile) *out_tile = best_t;
                 return RETINA_OK;
@@ -872,7 +891,7 @@ int retina_autotune(retina_ctx* c, const retina_geometry* g, const retina_hits* 
         host_toff.resize(E + 1);
         toff = host_toff.data();
     }
-    const HotConfig saved = c->ascent_cfg[D];
+    const HotConfig saved = tuning_slot(c, D, kern);
     const bool saved_prof = c->prof;
     const retina_profile saved_acc = c->prof_acc;
     if ((rc = retina_set_profiling(c, 1))) return rc;
@@ -882,13 +901,13 @@ int retina_autotune(retina_ctx* c, const retina_geometry* g, const retina_hits* 
     for (int cand = 1; cand <= 2; ++cand) {
         for (int tile : tiles) {
             if ((size_t)tile * D * sizeof(float) + 4096 > c->lds_max) continue;
-            if (retina_set_tuning(c, D, 0, cand, tile) != RETINA_OK) continue;
+            if (retina_set_tuning(c, D, kern, cand, tile) != RETINA_OK) continue;
             double ms = 0.0;
             for (int rep = 0; rep < 2; ++rep) {  // first run warms up (graph capture, pool)
                 c->prof_acc = retina_profile{};
                 rc = retina_find_tracks(c, g, h, P, nullptr, 0, toff, nullptr, nullptr);
                 if (rc != RETINA_OK && rc != RETINA_ERR_CAPACITY) {
-                    c->ascent_cfg[D] = saved;
+                    tuning_slot(c, D, kern) = saved;
                     c->prof = saved_prof;
                     c->prof_acc = saved_acc;
                     return rc;
@@ -905,7 +924,7 @@ int retina_autotune(retina_ctx* c, const retina_geometry* g, const retina_hits* 
     c->prof = saved_prof;
     c->prof_acc = saved_acc;
     c->err.clear();
-    if ((rc = retina_set_tuning(c, D, 0, best_c, best_t))) return rc;
+    if ((rc = retina_set_tuning(c, D, kern, best_c, best_t))) return rc;
     if (cache_path) {
         FILE* f = fopen(cache_path, "a");
         if (f) {

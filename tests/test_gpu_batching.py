@@ -25,8 +25,8 @@ def ctx():
     return retina.Context(0)
 
 
-def _find(ctx, b, P):
-    return ctx.retina_find_tracks(b.meas_dim, b.plane_z, b.event_offsets, b.x, b.y, b.plane, P)
+def _find(ctx, b, P, **kw):
+    return ctx.retina_find_tracks(b.meas_dim, b.plane_z, b.event_offsets, b.x, b.y, b.plane, P, **kw)
 
 
 def test_graph_replays_equal_eager(ctx):
@@ -88,6 +88,36 @@ def test_autotune_installs_valid_shape_and_keeps_parity(ctx, tmp_path):
     res = _find(ctx, b, P)
     ref = oracle.find_tracks(b, P)
     for e in range(2):
+        th, R = event_tracks(res, e, 2)
+        a, c = ref["track_offsets"][e], ref["track_offsets"][e + 1]
+        assert_tracks_match(2, th, R, ref["theta"][a:c], ref["R"][a:c], P["d_merge"], 20.0, 750.0)
+
+
+def test_sparse_seeding_has_its_own_tuned_shape(ctx, tmp_path):
+    """A batch with few explicit seeds per event (as from the proposer) is timed
+    and installed in the sparse-seeding slot (kernel 2); the lattice slot stays."""
+    cfg = events.load_config("c3")
+    P = cfg["params"]
+    sample = events.make_batch(cfg, 16, start=200)
+    seeds, offs = [], [0]
+    for e in range(sample.n_events):
+        t = sample.truth[e].copy()
+        t[:, :2] = 0.0
+        seeds.append(np.round(t, 2))
+        offs.append(offs[-1] + len(t))
+    seeds = np.concatenate(seeds)
+    offs = np.array(offs, np.int64)
+    assert offs[-1] < 512 * sample.n_events
+    dense = ctx.retina_get_tuning(2, 0)
+    _say("autotune sparse")
+    choice = ctx.retina_autotune(2, sample.plane_z, sample.event_offsets, sample.x, sample.y, sample.plane,
+                                 P, cache_path=str(tmp_path / "tune.txt"), seeds=seeds, seed_offsets=offs)
+    got = ctx.retina_get_tuning(2, 2)
+    assert (got["cand"], got["tile_hits"]) == (choice["cand"], choice["tile_hits"])
+    assert ctx.retina_get_tuning(2, 0) == dense
+    res = _find(ctx, sample, P, seeds=seeds, seed_offsets=offs)
+    ref = oracle.find_tracks(sample, P, seeds=seeds, seed_offsets=offs)
+    for e in range(3):
         th, R = event_tracks(res, e, 2)
         a, c = ref["track_offsets"][e], ref["track_offsets"][e + 1]
         assert_tracks_match(2, th, R, ref["theta"][a:c], ref["R"][a:c], P["d_merge"], 20.0, 750.0)
