@@ -28,7 +28,7 @@ enum BufId {
     B_INX, B_INY, B_INPL, B_INOFF, B_INSEEDS, B_INSOFF, B_INTH, B_INTHOFF, B_OUTTR, B_OUTTOFF,
     B_OUTEVF, B_OUTSTH, B_OUTSR, B_OUTSFL, B_OUTSNR, B_OUTR, B_OUTG, B_OUTH,
     // learned proposer workspace
-    B_IMG, B_ACT1, B_ACT2, B_ACT3, B_LOGIT, B_DZ4, B_DZ3, B_DZ2, B_DZ1, B_TGT, B_TGTIN, B_TGTOFF,
+    B_IMG, B_ACT1, B_ACT2, B_ACT3, B_LOGIT, B_HEADU, B_DZ4, B_DZ3, B_DZ2, B_DZ1, B_TGT, B_TGTIN, B_TGTOFF,
     B_DWPART, B_WT, B_LOSSPART, B_LOSS, B_BPART, B_PSCORE, B_PPIX, B_PCOUNT, B_PCONF, B_PFB,
     B_PSOFF, B_PSEEDS, B_OUTIMG, B_OUTLOGIT,
     B_COUNT
@@ -1041,26 +1041,34 @@ int proposer_stage(retina_ctx* c, const retina_geometry* g, const retina_hits* h
 
 struct Acts {
     uint16_t* act[kLayers];  // act[0] = image, act[l] = output of layer l-1 (post-ReLU)
+    float* u;                // inference: the head's per-tap partial sums
     float* logits;
 };
 
-int ensure_acts(retina_ctx* c, int64_t E, Acts& A)
+int ensure_acts(retina_ctx* c, int64_t E, Acts& A, bool train)
 {
     int rc;
     const size_t px = (size_t)E * kPix;
-    if ((rc = ensure_t(c, B_IMG, px * kChan[0], &A.act[0])) || (rc = ensure_t(c, B_ACT1, px * kChan[1], &A.act[1])) ||
-        (rc = ensure_t(c, B_ACT2, px * kChan[2], &A.act[2])) || (rc = ensure_t(c, B_ACT3, px * kChan[3], &A.act[3])) ||
+    A = Acts{};
+    if ((rc = ensure_t(c, B_IMG, px * kChan[0], &A.act[0])) || (rc = ensure_t(c, B_ACT2, px * kChan[2], &A.act[2])) ||
         (rc = ensure_t(c, B_LOGIT, px, &A.logits)))
         return rc;
+    if (train) {
+        if ((rc = ensure_t(c, B_ACT1, px * kChan[1], &A.act[1])) || (rc = ensure_t(c, B_ACT3, px * kChan[3], &A.act[3])))
+            return rc;
+    } else if ((rc = ensure_t(c, B_HEADU, px * 9, &A.u))) {
+        return rc;
+    }
     return RETINA_OK;
 }
 
 // image + 4 conv layers on the staged hits of c->h_desc
-void forward_net(retina_ctx* c, const retina_model* md, int64_t E, const Acts& A)
+void forward_net(retina_ctx* c, const retina_model* md, int64_t E, const Acts& A, bool train)
 {
     const Desc& d = *c->h_desc;
     launch_bin_image(d.hits, d.plane_off, d.n_planes, 2, c->d_desc->plane_z, E, A.act[0], c->stream);
-    launch_forward(A.act[0], md->wbf, md->w32, md->L, E, A.act[1], A.act[2], A.act[3], A.logits, c->stream);
+    launch_forward(A.act[0], md->wbf, md->w32, md->L, E, A.act[1], A.act[2], A.act[3], A.u, A.logits, train,
+                   c->stream);
 }
 
 }  // namespace
@@ -1212,8 +1220,8 @@ int retina_model_forward(retina_ctx* c, const retina_model* md, const retina_geo
     const int64_t E = h->n_events;
     if (E == 0) return RETINA_OK;
     Acts A;
-    if ((rc = ensure_acts(c, E, A))) return rc;
-    forward_net(c, md, E, A);
+    if ((rc = ensure_acts(c, E, A, false))) return rc;
+    forward_net(c, md, E, A, false);
     HIP_TRY(c, hipGetLastError());
     const size_t px = (size_t)E * kPix;
     const hipMemcpyKind k = h->mem == RETINA_MEM_HOST ? hipMemcpyDeviceToHost : hipMemcpyDeviceToDevice;
@@ -1268,7 +1276,7 @@ int retina_train_step(retina_ctx* c, retina_model* md, const retina_geometry* g,
         max_part = std::max<int64_t>(max_part, (int64_t)kChan[l + 1] * conv_kp(kChan[l]));
         max_wt = std::max<int64_t>(max_wt, (int64_t)kChan[l] * conv_kp(kChan[l + 1]));
     }
-    if ((rc = ensure_acts(c, E, A)) || (rc = ensure_t(c, B_DZ4, px * kChan[4], &dz[3])) ||
+    if ((rc = ensure_acts(c, E, A, true)) || (rc = ensure_t(c, B_DZ4, px * kChan[4], &dz[3])) ||
         (rc = ensure_t(c, B_DZ3, px * kChan[3], &dz[2])) || (rc = ensure_t(c, B_DZ2, px * kChan[2], &dz[1])) ||
         (rc = ensure_t(c, B_DZ1, px * kChan[1], &dz[0])) || (rc = ensure_t(c, B_TGT, px, &tgt)) ||
         (rc = ensure_t(c, B_DWPART, (size_t)n_chunks * max_part, &part)) || (rc = ensure_t(c, B_WT, (size_t)max_wt, &wt)) ||
@@ -1276,7 +1284,7 @@ int retina_train_step(retina_ctx* c, retina_model* md, const retina_geometry* g,
         (rc = ensure_t(c, B_BPART, (size_t)n_chunks * 128, &bpart)))
         return rc;
     // forward
-    forward_net(c, md, E, A);
+    forward_net(c, md, E, A, true);
     launch_target_image(tg, to, E, tgt, c->stream);
     launch_bce(A.logits, tgt, (int64_t)px, pos_weight, lpart, dz[3], c->stream);
     launch_sum(lpart, 1024, lsum, c->stream);
@@ -1348,9 +1356,9 @@ int propose_device(retina_ctx* c, const retina_geometry* g, const retina_hits* h
     if ((rc = proposer_stage(c, g, h))) return rc;
     const int64_t E = h->n_events;
     Acts A;
-    if ((rc = ensure_acts(c, E, A))) return rc;
+    if ((rc = ensure_acts(c, E, A, false))) return rc;
     prof_mark(c, 5);
-    forward_net(c, md, E, A);
+    forward_net(c, md, E, A, false);
     const int64_t lat = (int64_t)P->lattice_n[0] * P->lattice_n[1];
     const int64_t cap = E * std::max<int64_t>(k_max, lat);
     pa = ProposeArgs{};

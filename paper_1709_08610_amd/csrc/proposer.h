@@ -45,9 +45,12 @@ struct GemmArgs {
 };
 void launch_gemm(const GemmArgs& a, hipStream_t st);
 
-// forward pass of the four layers (direct convolutions; see proposer.hip)
+// forward pass of the four layers (direct convolutions; see proposer.hip).
+// train: store act1..act3 for the backward pass; otherwise only act2 and the
+// head's per-tap partial sums u (E * kPix * 9 floats) pass through HBM.
 void launch_forward(const uint16_t* img, const uint16_t* wbf, const float* w32, const NetLayout& L, int64_t E,
-                    uint16_t* act1, uint16_t* act2, uint16_t* act3, float* logits, hipStream_t st);
+                    uint16_t* act1, uint16_t* act2, uint16_t* act3, float* u, float* logits, bool train,
+                    hipStream_t st);
 
 void launch_bin_image(const float* hits, const int32_t* plane_off, int n_planes, int meas_dim,
                       const float* plane_z, int64_t n_events, uint16_t* img, hipStream_t st);

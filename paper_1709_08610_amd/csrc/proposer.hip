@@ -533,28 +533,403 @@ __global__ __launch_bounds__(256) void k_conv_head(const uint16_t* __restrict__ 
     static_assert(KP == 9 * CIN, "head weights are unpadded");
 }
 
-void launch_forward(const uint16_t* img, const uint16_t* wbf, const float* w32, const NetLayout& L, int64_t E,
-                    uint16_t* act1, uint16_t* act2, uint16_t* act3, float* logits, hipStream_t st)
+// ------------------------------------------------- fused inference kernels
+// Inference needs only the logits, so two fusions keep activations on chip:
+//   k_conv12  layer 1 computed into the LDS input tile of layer 2 (act1 never
+//             reaches HBM); layer 1 runs on MFMA with K = 18 padded to 32;
+//   k_conv3   layer 3 with its 128 input channels streamed in 32-channel
+//             chunks, the next chunk's rows loaded while this one computes;
+//             for inference its epilogue multiplies the BF16 act3 tile by the
+//             head's weights on MFMA (U[q][tap], 9 floats per pixel) instead
+//             of storing act3, and k_head_sum adds the nine shifted U values.
+// Training keeps every activation (k_conv_in, k_conv_mid<64, 128>,
+// k_conv3<0>, k_conv_head).
+constexpr int kC12ImgRows = kCvRows + 4;          // image rows staged (halo 2)
+constexpr int kC12ImgCols = kImg + 4;             // image columns staged
+constexpr int kC12A1 = (kCvRows + 2) * kCvCols;   // act1 positions of the tile (780)
+
+constexpr size_t conv12_lds()
 {
-    constexpr size_t l1 = conv_mid_lds<64, 128>(), l2 = conv_mid_lds<128, 96>();
+    return (size_t)(kCvRows + 2) * kCvCols * kCvPitch * 2 + (size_t)2 * 128 * kCvPitch * 2 +
+           (size_t)kC12ImgRows * kC12ImgCols * 4;
+}
+
+__device__ __forceinline__ __bf16 bits_bf(uint16_t h) { return __builtin_bit_cast(__bf16, h); }
+
+// layer 2's weight slice (tap) of all 128 output channels: 1024 16-byte units, two per thread
+__device__ __forceinline__ void c12_load_w(const uint16_t* __restrict__ w2, int tap, int t, uint4 (&r)[2])
+{
+#pragma unroll
+    for (int i = 0; i < 2; ++i) {
+        const int u = t + i * kCvThreads;
+        r[i] = *reinterpret_cast<const uint4*>(w2 + (int64_t)(u >> 3) * 576 + tap * 64 + (u & 7) * 8);
+    }
+}
+
+__device__ __forceinline__ void c12_store_w(uint16_t* dst, int t, const uint4 (&r)[2])
+{
+#pragma unroll
+    for (int i = 0; i < 2; ++i) {
+        const int u = t + i * kCvThreads;
+        *reinterpret_cast<uint4*>(dst + (u >> 3) * kCvPitch + (u & 7) * 8) = r[i];
+    }
+}
+
+__global__ __launch_bounds__(kCvThreads) void k_conv12(const uint16_t* __restrict__ img,
+                                                       const uint16_t* __restrict__ w1,
+                                                       const float* __restrict__ b1,
+                                                       const uint16_t* __restrict__ w2,
+                                                       const float* __restrict__ b2, uint16_t* __restrict__ y)
+{
+    constexpr int COUT = 128, NB = 4;
+    extern __shared__ float4 s_dyn[];
+    uint16_t* s_in = reinterpret_cast<uint16_t*>(s_dyn);
+    uint16_t* s_w = s_in + (kCvRows + 2) * kCvCols * kCvPitch;
+    uint32_t* s_img = reinterpret_cast<uint32_t*>(s_w + 2 * COUT * kCvPitch);
+    const int t = threadIdx.x, lane = t & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(t >> 6);
+    const int orow = wave >> 1, ocol0 = (wave & 1) * 64;
+    const int64_t e = blockIdx.x / (kImg / kCvRows);
+    const int r0 = (int)(blockIdx.x % (kImg / kCvRows)) * kCvRows;
+
+    // image rows r0 - 2 .. r0 + 5, columns -2 .. 129 (both channels in one word)
+    for (int u = t; u < kC12ImgRows * kC12ImgCols; u += kCvThreads) {
+        const int r = r0 - 2 + u / kC12ImgCols, col = u % kC12ImgCols - 2;
+        uint32_t v = 0;
+        if (r >= 0 && r < kImg && col >= 0 && col < kImg)
+            v = *reinterpret_cast<const uint32_t*>(img + ((e * kImg + r) * kImg + col) * 2);
+        s_img[u] = v;
+    }
+    uint4 wreg[2];
+    c12_load_w(w2, 0, t, wreg);
+    __syncthreads();
+
+    // layer 1 on the act1 tile (rows r0 - 1 .. r0 + 4, columns -1 .. 128):
+    // M = 780 positions in 25 blocks of 32, N = 64 in 2 blocks, K = 18 -> 32
+    v8bf bw[2][2];
+#pragma unroll
+    for (int nb = 0; nb < 2; ++nb)
+#pragma unroll
+        for (int ks = 0; ks < 2; ++ks)
+            bw[nb][ks] = *reinterpret_cast<const v8bf*>(w1 + (nb * 32 + (lane & 31)) * conv_kp(2) + ks * 16 +
+                                                       8 * (lane >> 5));
+    for (int task = wave; task < 25 * 2; task += kCvThreads / 64) {
+        const int pb = task >> 1, nb = task & 1;
+        const int p = pb * 32 + (lane & 31);
+        const int jr = p / kCvCols, ic = p % kCvCols;
+        v16f a1;
+#pragma unroll
+        for (int r = 0; r < 16; ++r) a1[r] = 0.0f;
+#pragma unroll
+        for (int ks = 0; ks < 2; ++ks) {
+            v8bf av;
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                const int tap = (ks * 16 + 8 * (lane >> 5)) / 2 + q;
+                uint32_t v = 0;
+                // act1 position (jr, ic) is image (r0 - 1 + jr, ic - 1); the tap adds
+                // (tap / 3 - 1, tap % 3 - 1); s_img starts at image (r0 - 2, -2)
+                if (tap < 9 && p < kC12A1)
+                    v = s_img[(jr + tap / 3) * kC12ImgCols + ic + tap % 3];
+                av[2 * q] = bits_bf((uint16_t)(v & 0xFFFFu));
+                av[2 * q + 1] = bits_bf((uint16_t)(v >> 16));
+            }
+            a1 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(av, bw[nb][ks], a1, 0, 0, 0);
+        }
+        const int co = nb * 32 + (lane & 31);
+        const float bb = b1[co];
+#pragma unroll
+        for (int r = 0; r < 16; ++r) {
+            const int pix = pb * 32 + 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3);
+            if (pix < kC12A1) {
+                const int pr = pix / kCvCols, pc = pix % kCvCols;
+                const int ar = r0 - 1 + pr, ac = pc - 1;
+                const bool inside = ar >= 0 && ar < kImg && ac >= 0 && ac < kImg;
+                s_in[pix * kCvPitch + co] = f2bf(inside ? fmaxf(a1[r] + bb, 0.0f) : 0.0f);
+            }
+        }
+    }
+    c12_store_w(s_w, t, wreg);
+    __syncthreads();
+
+    // layer 2 (64 -> 128) on the act1 tile, as in k_conv_mid
+    v16f acc[2][NB];
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int j = 0; j < NB; ++j)
+#pragma unroll
+            for (int r = 0; r < 16; ++r) acc[i][j][r] = 0.0f;
+    for (int tap = 0; tap < 9; ++tap) {
+        if (tap < 8) c12_load_w(w2, tap + 1, t, wreg);
+        const int dr = tap / 3 - 1, dc = tap % 3 - 1;
+        const uint16_t* arow = s_in + ((orow + 1 + dr) * kCvCols + (ocol0 + 1 + dc)) * kCvPitch;
+        const uint16_t* wb = s_w + (tap & 1) * COUT * kCvPitch;
+#pragma unroll
+        for (int kk = 0; kk < 4; ++kk) {
+            const int ko = kk * 16 + 8 * (lane >> 5);
+            v8bf af[2], bfr[NB];
+#pragma unroll
+            for (int mb = 0; mb < 2; ++mb)
+                af[mb] = *reinterpret_cast<const v8bf*>(arow + (mb * 32 + (lane & 31)) * kCvPitch + ko);
+#pragma unroll
+            for (int nb = 0; nb < NB; ++nb)
+                bfr[nb] = *reinterpret_cast<const v8bf*>(wb + (nb * 32 + (lane & 31)) * kCvPitch + ko);
+#pragma unroll
+            for (int mb = 0; mb < 2; ++mb)
+#pragma unroll
+                for (int nb = 0; nb < NB; ++nb)
+                    acc[mb][nb] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(af[mb], bfr[nb], acc[mb][nb], 0, 0, 0);
+        }
+        if (tap < 8) c12_store_w(s_w + ((tap + 1) & 1) * COUT * kCvPitch, t, wreg);
+        __syncthreads();
+    }
+    uint16_t* s_out = reinterpret_cast<uint16_t*>(s_dyn) + wave * 64 * (COUT + 8);
+#pragma unroll
+    for (int nb = 0; nb < NB; ++nb) {
+        const int co = nb * 32 + (lane & 31);
+        const float bb = b2[co];
+#pragma unroll
+        for (int mb = 0; mb < 2; ++mb)
+#pragma unroll
+            for (int r = 0; r < 16; ++r) {
+                const int px = mb * 32 + 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3);
+                s_out[px * (COUT + 8) + co] = f2bf(fmaxf(acc[mb][nb][r] + bb, 0.0f));
+            }
+    }
+    __syncthreads();
+    uint16_t* dst = y + ((e * kImg + r0 + orow) * kImg + ocol0) * COUT;
+    for (int u = lane; u < 64 * COUT / 8; u += 64) {
+        const int px = u / (COUT / 8), q = u % (COUT / 8);
+        *reinterpret_cast<uint4*>(dst + px * COUT + q * 8) =
+            *reinterpret_cast<const uint4*>(s_out + px * (COUT + 8) + q * 8);
+    }
+}
+
+constexpr int kC3Chunk = 32;                    // input channels per chunk
+constexpr int kC3Pitch = kC3Chunk + 8;          // LDS elements per staged pixel (80 B)
+constexpr int kC3Tile = (kCvRows + 2) * kCvCols * kC3Pitch;   // elements of one staged chunk
+constexpr int kC3TU = (kCvRows + 2) * kCvCols * (kC3Chunk / 8);  // 16-byte units of one chunk (3120)
+constexpr int kC3TPT = (kC3TU + kCvThreads - 1) / kCvThreads;    // per thread (7)
+
+constexpr size_t conv3_lds()
+{
+    constexpr size_t main = (size_t)2 * kC3Tile * 2 + (size_t)2 * 96 * kC3Pitch * 2;
+    constexpr size_t out = (size_t)(kCvThreads / 64) * 64 * (96 + 8) * 2;
+    return main > out ? main : out;
+}
+
+// MODE 0: store act3 (training); MODE 1: store U[pixel][tap] = sum_c W4[tap][c] act3[pixel][c]
+template <int MODE>
+__global__ __launch_bounds__(kCvThreads) void k_conv3(const uint16_t* __restrict__ x,
+                                                      const uint16_t* __restrict__ w,
+                                                      const float* __restrict__ bias,
+                                                      const uint16_t* __restrict__ w4,
+                                                      uint16_t* __restrict__ y, float* __restrict__ u_out)
+{
+    constexpr int CIN = 128, COUT = 96, NB = 3, NCH = CIN / kC3Chunk, KP = 9 * CIN;
+    constexpr int WU = COUT * (kC3Chunk / 8);  // 384 units per weight slice
+    extern __shared__ float4 s_dyn[];
+    uint16_t* s_in = reinterpret_cast<uint16_t*>(s_dyn);
+    uint16_t* s_w = s_in + 2 * kC3Tile;
+    const int t = threadIdx.x, lane = t & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(t >> 6);
+    const int orow = wave >> 1, ocol0 = (wave & 1) * 64;
+    const int64_t e = blockIdx.x / (kImg / kCvRows);
+    const int r0 = (int)(blockIdx.x % (kImg / kCvRows)) * kCvRows;
+
+    uint4 treg[kC3TPT];
+    auto load_tile = [&](int c) {
+#pragma unroll
+        for (int i = 0; i < kC3TPT; ++i) {
+            const int u = t + i * kCvThreads;
+            uint4 v = make_uint4(0, 0, 0, 0);
+            if (u < kC3TU) {
+                const int q = u & 3, pc = (u >> 2) % kCvCols, pr = (u >> 2) / kCvCols;
+                const int r = r0 - 1 + pr, col = pc - 1;
+                if (r >= 0 && r < kImg && col >= 0 && col < kImg)
+                    v = *reinterpret_cast<const uint4*>(x + ((e * kImg + r) * kImg + col) * CIN + c * kC3Chunk + q * 8);
+            }
+            treg[i] = v;
+        }
+    };
+    auto store_tile = [&](int buf) {
+#pragma unroll
+        for (int i = 0; i < kC3TPT; ++i) {
+            const int u = t + i * kCvThreads;
+            if (u < kC3TU) {
+                const int q = u & 3, pix = u >> 2;
+                *reinterpret_cast<uint4*>(s_in + buf * kC3Tile + pix * kC3Pitch + q * 8) = treg[i];
+            }
+        }
+    };
+    uint4 wreg[9];
+    auto store_w = [&](int buf, const uint4& v) {
+        if (t < WU) *reinterpret_cast<uint4*>(s_w + buf * COUT * kC3Pitch + (t >> 2) * kC3Pitch + (t & 3) * 8) = v;
+    };
+
+    v16f acc[2][NB];
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int j = 0; j < NB; ++j)
+#pragma unroll
+            for (int r = 0; r < 16; ++r) acc[i][j][r] = 0.0f;
+
+    load_tile(0);
+    store_tile(0);
+    for (int c = 0; c < NCH; ++c) {
+        // this chunk's nine weight slices first, then the next chunk's rows: the
+        // per-tap waits for the weights then never wait for the row loads
+#pragma unroll
+        for (int tap = 0; tap < 9; ++tap)
+            wreg[tap] = t < WU ? *reinterpret_cast<const uint4*>(w + (int64_t)(t >> 2) * KP + tap * CIN +
+                                                                 c * kC3Chunk + (t & 3) * 8)
+                               : make_uint4(0, 0, 0, 0);
+        if (c + 1 < NCH) load_tile(c + 1);
+        store_w(0, wreg[0]);
+        __syncthreads();
+        const uint16_t* tile = s_in + (c & 1) * kC3Tile;
+#pragma unroll
+        for (int tap = 0; tap < 9; ++tap) {
+            const int dr = tap / 3 - 1, dc = tap % 3 - 1;
+            const uint16_t* arow = tile + ((orow + 1 + dr) * kCvCols + (ocol0 + 1 + dc)) * kC3Pitch;
+            const uint16_t* wb = s_w + (tap & 1) * COUT * kC3Pitch;
+#pragma unroll
+            for (int kk = 0; kk < kC3Chunk / 16; ++kk) {
+                const int ko = kk * 16 + 8 * (lane >> 5);
+                v8bf af[2], bfr[NB];
+#pragma unroll
+                for (int mb = 0; mb < 2; ++mb)
+                    af[mb] = *reinterpret_cast<const v8bf*>(arow + (mb * 32 + (lane & 31)) * kC3Pitch + ko);
+#pragma unroll
+                for (int nb = 0; nb < NB; ++nb)
+                    bfr[nb] = *reinterpret_cast<const v8bf*>(wb + (nb * 32 + (lane & 31)) * kC3Pitch + ko);
+#pragma unroll
+                for (int mb = 0; mb < 2; ++mb)
+#pragma unroll
+                    for (int nb = 0; nb < NB; ++nb)
+                        acc[mb][nb] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(af[mb], bfr[nb], acc[mb][nb], 0, 0, 0);
+            }
+            if (tap < 8) store_w((tap + 1) & 1, wreg[tap + 1]);
+            __syncthreads();
+        }
+        // the other tile buffer was last read in chunk c - 1, before the barriers above
+        if (c + 1 < NCH) store_tile((c + 1) & 1);
+    }
+
+    uint16_t* s_out = reinterpret_cast<uint16_t*>(s_dyn) + wave * 64 * (COUT + 8);
+#pragma unroll
+    for (int nb = 0; nb < NB; ++nb) {
+        const int co = nb * 32 + (lane & 31);
+        const float bb = bias[co];
+#pragma unroll
+        for (int mb = 0; mb < 2; ++mb)
+#pragma unroll
+            for (int r = 0; r < 16; ++r) {
+                const int px = mb * 32 + 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3);
+                s_out[px * (COUT + 8) + co] = f2bf(fmaxf(acc[mb][nb][r] + bb, 0.0f));
+            }
+    }
+    __syncthreads();
+    const int64_t pix0 = (e * kImg + r0 + orow) * kImg + ocol0;
+    if (MODE == 0) {
+        uint16_t* dst = y + pix0 * COUT;
+        for (int u = lane; u < 64 * COUT / 8; u += 64) {
+            const int px = u / (COUT / 8), q = u % (COUT / 8);
+            *reinterpret_cast<uint4*>(dst + px * COUT + q * 8) =
+                *reinterpret_cast<const uint4*>(s_out + px * (COUT + 8) + q * 8);
+        }
+    } else {
+        // U = act3 (64 x 96, this wave's pixels) x W4^T (96 x 9, padded to 32 columns)
+        v8bf bu[COUT / 16];
+        const int n = lane & 31;
+#pragma unroll
+        for (int kk = 0; kk < COUT / 16; ++kk) {
+            const int k0 = kk * 16 + 8 * (lane >> 5);
+            if (n < 9) {
+                bu[kk] = *reinterpret_cast<const v8bf*>(w4 + n * COUT + k0);
+            } else {
+#pragma unroll
+                for (int j = 0; j < 8; ++j) bu[kk][j] = bits_bf(0);
+            }
+        }
+#pragma unroll
+        for (int mb = 0; mb < 2; ++mb) {
+            v16f au;
+#pragma unroll
+            for (int r = 0; r < 16; ++r) au[r] = 0.0f;
+#pragma unroll
+            for (int kk = 0; kk < COUT / 16; ++kk) {
+                const v8bf a = *reinterpret_cast<const v8bf*>(s_out + (mb * 32 + (lane & 31)) * (COUT + 8) + kk * 16 +
+                                                              8 * (lane >> 5));
+                au = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, bu[kk], au, 0, 0, 0);
+            }
+            if (n < 9) {
+#pragma unroll
+                for (int r = 0; r < 16; ++r) {
+                    const int px = mb * 32 + 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3);
+                    u_out[(pix0 + px) * 9 + n] = au[r];
+                }
+            }
+        }
+    }
+}
+
+// logit[p] = b + sum_tap U[p + offset(tap)][tap] (zero outside the image)
+__global__ __launch_bounds__(256) void k_head_sum(const float* __restrict__ u, const float* __restrict__ bias,
+                                                  int64_t npix, float* __restrict__ logits)
+{
+    const float b = bias[0];
+    for (int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; p < npix; p += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t ev = p / kPix;
+        const int r = (int)((p / kImg) % kImg), c = (int)(p % kImg);
+        float z = b;
+#pragma unroll
+        for (int tap = 0; tap < 9; ++tap) {
+            const int rr = r + tap / 3 - 1, cc = c + tap % 3 - 1;
+            if (rr >= 0 && rr < kImg && cc >= 0 && cc < kImg) z += u[(ev * kPix + rr * kImg + cc) * 9 + tap];
+        }
+        logits[p] = z;
+    }
+}
+
+void launch_forward(const uint16_t* img, const uint16_t* wbf, const float* w32, const NetLayout& L, int64_t E,
+                    uint16_t* act1, uint16_t* act2, uint16_t* act3, float* u, float* logits, bool train,
+                    hipStream_t st)
+{
+    constexpr size_t l1 = conv_mid_lds<64, 128>(), l12 = conv12_lds(), l3 = conv3_lds();
     static bool attr = false;
     if (!attr) {
         const void* f1 = reinterpret_cast<const void*>(&k_conv_mid<64, 128>);
-        const void* f2 = reinterpret_cast<const void*>(&k_conv_mid<128, 96>);
+        const void* f12 = reinterpret_cast<const void*>(&k_conv12);
+        const void* f30 = reinterpret_cast<const void*>(&k_conv3<0>);
+        const void* f31 = reinterpret_cast<const void*>(&k_conv3<1>);
         (void)hipFuncSetAttribute(f1, hipFuncAttributeMaxDynamicSharedMemorySize, (int)l1);
-        (void)hipFuncSetAttribute(f2, hipFuncAttributeMaxDynamicSharedMemorySize, (int)l2);
+        (void)hipFuncSetAttribute(f12, hipFuncAttributeMaxDynamicSharedMemorySize, (int)l12);
+        (void)hipFuncSetAttribute(f30, hipFuncAttributeMaxDynamicSharedMemorySize, (int)l3);
+        (void)hipFuncSetAttribute(f31, hipFuncAttributeMaxDynamicSharedMemorySize, (int)l3);
         attr = true;
     }
     const int64_t npix = E * kPix;
-    const int g0 = (int)std::min<int64_t>((npix * 8 + 255) / 256, 65536);
-    hipLaunchKernelGGL(k_conv_in, dim3(g0), dim3(256), 0, st, img, wbf + L.w_off[0], w32 + L.b_off[0], act1, npix);
     const unsigned gm = (unsigned)(E * (kImg / kCvRows));
-    hipLaunchKernelGGL((k_conv_mid<64, 128>), dim3(gm), dim3(kCvThreads), l1, st, act1,
-                       wbf + L.w_off[1], w32 + L.b_off[1], act2);
-    hipLaunchKernelGGL((k_conv_mid<128, 96>), dim3(gm), dim3(kCvThreads), l2, st, act2,
-                       wbf + L.w_off[2], w32 + L.b_off[2], act3);
-    hipLaunchKernelGGL(k_conv_head, dim3((unsigned)(E * (kImg / kHeadRows))), dim3(256), 0, st, act3,
-                       wbf + L.w_off[3], w32 + L.b_off[3], logits);
+    if (train) {
+        const int g0 = (int)std::min<int64_t>((npix * 8 + 255) / 256, 65536);
+        hipLaunchKernelGGL(k_conv_in, dim3(g0), dim3(256), 0, st, img, wbf + L.w_off[0], w32 + L.b_off[0], act1, npix);
+        hipLaunchKernelGGL((k_conv_mid<64, 128>), dim3(gm), dim3(kCvThreads), l1, st, act1, wbf + L.w_off[1],
+                           w32 + L.b_off[1], act2);
+        hipLaunchKernelGGL(k_conv3<0>, dim3(gm), dim3(kCvThreads), l3, st, act2, wbf + L.w_off[2], w32 + L.b_off[2],
+                           wbf + L.w_off[3], act3, (float*)nullptr);
+        hipLaunchKernelGGL(k_conv_head, dim3((unsigned)(E * (kImg / kHeadRows))), dim3(256), 0, st, act3,
+                           wbf + L.w_off[3], w32 + L.b_off[3], logits);
+    } else {
+        hipLaunchKernelGGL(k_conv12, dim3(gm), dim3(kCvThreads), l12, st, img, wbf + L.w_off[0], w32 + L.b_off[0],
+                           wbf + L.w_off[1], w32 + L.b_off[1], act2);
+        hipLaunchKernelGGL(k_conv3<1>, dim3(gm), dim3(kCvThreads), l3, st, act2, wbf + L.w_off[2], w32 + L.b_off[2],
+                           wbf + L.w_off[3], (uint16_t*)nullptr, u);
+        const int gh = (int)std::min<int64_t>((npix + 255) / 256, 65536);
+        hipLaunchKernelGGL(k_head_sum, dim3(gh), dim3(256), 0, st, u, w32 + L.b_off[3], npix, logits);
+    }
 }
 
 // ------------------------------------------------------------------ losses
