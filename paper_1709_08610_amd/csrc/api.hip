@@ -1056,7 +1056,7 @@ int ensure_acts(retina_ctx* c, int64_t E, Acts& A, bool train)
     if (train) {
         if ((rc = ensure_t(c, B_ACT1, px * kChan[1], &A.act[1])) || (rc = ensure_t(c, B_ACT3, px * kChan[3], &A.act[3])))
             return rc;
-    } else if ((rc = ensure_t(c, B_HEADU, px * 9, &A.u))) {
+    } else if ((rc = ensure_t(c, B_HEADU, px * 12, &A.u))) {
         return rc;
     }
     return RETINA_OK;

@@ -547,6 +547,7 @@ __global__ __launch_bounds__(256) void k_conv_head(const uint16_t* __restrict__ 
 constexpr int kC12ImgRows = kCvRows + 4;          // image rows staged (halo 2)
 constexpr int kC12ImgCols = kImg + 4;             // image columns staged
 constexpr int kC12A1 = (kCvRows + 2) * kCvCols;   // act1 positions of the tile (780)
+constexpr int kUPitch = 12;                       // floats per pixel of U (9 used, 16-byte rows)
 
 constexpr size_t conv12_lds()
 {
@@ -555,6 +556,36 @@ constexpr size_t conv12_lds()
 }
 
 __device__ __forceinline__ __bf16 bits_bf(uint16_t h) { return __builtin_bit_cast(__bf16, h); }
+
+__device__ __forceinline__ uint2 pack4_bf16(float a, float b, float c, float d)
+{
+    return make_uint2((uint32_t)f2bf(a) | ((uint32_t)f2bf(b) << 16), (uint32_t)f2bf(c) | ((uint32_t)f2bf(d) << 16));
+}
+
+// The fused kernels compute D = W x X^T (rows = output channels, columns =
+// pixels), so a lane's 16 results are four runs of 4 consecutive channels of
+// one pixel: channel 8 (r / 4) + 4 (lane / 32) + r % 4, pixel lane % 32.  Bias,
+// ReLU and BF16 packing then give one 8-byte LDS store per run.
+template <int NB, int COUT>
+__device__ __forceinline__ void stage_act(uint16_t* s_out, const v16f (&acc)[NB][2], const float* __restrict__ bias,
+                                          int lane)
+{
+#pragma unroll
+    for (int nb = 0; nb < NB; ++nb)
+#pragma unroll
+        for (int g = 0; g < 4; ++g) {
+            const int co = nb * 32 + 8 * g + 4 * (lane >> 5);
+            const float4 bb = *reinterpret_cast<const float4*>(bias + co);
+#pragma unroll
+            for (int mb = 0; mb < 2; ++mb) {
+                const int px = mb * 32 + (lane & 31);
+                const v16f& a = acc[nb][mb];
+                *reinterpret_cast<uint2*>(s_out + px * (COUT + 8) + co) =
+                    pack4_bf16(fmaxf(a[4 * g] + bb.x, 0.0f), fmaxf(a[4 * g + 1] + bb.y, 0.0f),
+                               fmaxf(a[4 * g + 2] + bb.z, 0.0f), fmaxf(a[4 * g + 3] + bb.w, 0.0f));
+            }
+        }
+}
 
 // layer 2's weight slice (tap) of all 128 output channels: 1024 16-byte units, two per thread
 __device__ __forceinline__ void c12_load_w(const uint16_t* __restrict__ w2, int tap, int t, uint4 (&r)[2])
@@ -573,6 +604,13 @@ __device__ __forceinline__ void c12_store_w(uint16_t* dst, int t, const uint4 (&
         const int u = t + i * kCvThreads;
         *reinterpret_cast<uint4*>(dst + (u >> 3) * kCvPitch + (u & 7) * 8) = r[i];
     }
+}
+
+// act2 for inference is stored channel-chunked, [E][4][128][128][32], so that
+// k_conv3 reads whole 64-byte runs per pixel and chunk
+__device__ __forceinline__ int64_t chunked_off(int64_t e, int chunk, int r, int col)
+{
+    return (((e * 4 + chunk) * kImg + r) * kImg + col) * 32;
 }
 
 __global__ __launch_bounds__(kCvThreads) void k_conv12(const uint16_t* __restrict__ img,
@@ -605,103 +643,95 @@ __global__ __launch_bounds__(kCvThreads) void k_conv12(const uint16_t* __restric
     __syncthreads();
 
     // layer 1 on the act1 tile (rows r0 - 1 .. r0 + 4, columns -1 .. 128):
-    // M = 780 positions in 25 blocks of 32, N = 64 in 2 blocks, K = 18 -> 32
-    v8bf bw[2][2];
+    // D = W1 (64 x 32, K = 18 zero-padded) x X^T (32 x 32 positions) per block
+    // of 32 tile positions; act1 outside the image is the zero padding of layer 2
+    v8bf aw[2][2];
 #pragma unroll
-    for (int nb = 0; nb < 2; ++nb)
+    for (int cb = 0; cb < 2; ++cb)
 #pragma unroll
         for (int ks = 0; ks < 2; ++ks)
-            bw[nb][ks] = *reinterpret_cast<const v8bf*>(w1 + (nb * 32 + (lane & 31)) * conv_kp(2) + ks * 16 +
+            aw[cb][ks] = *reinterpret_cast<const v8bf*>(w1 + (cb * 32 + (lane & 31)) * conv_kp(2) + ks * 16 +
                                                        8 * (lane >> 5));
-    for (int task = wave; task < 25 * 2; task += kCvThreads / 64) {
-        const int pb = task >> 1, nb = task & 1;
+    for (int pb = wave; pb < (kC12A1 + 31) / 32; pb += kCvThreads / 64) {
         const int p = pb * 32 + (lane & 31);
-        const int jr = p / kCvCols, ic = p % kCvCols;
-        v16f a1;
+        const int jr = p / kCvCols, ic = p % kCvCols;  // act1 position = image (r0 - 1 + jr, ic - 1)
+        v8bf xv[2];
 #pragma unroll
-        for (int r = 0; r < 16; ++r) a1[r] = 0.0f;
-#pragma unroll
-        for (int ks = 0; ks < 2; ++ks) {
-            v8bf av;
+        for (int ks = 0; ks < 2; ++ks)
 #pragma unroll
             for (int q = 0; q < 4; ++q) {
                 const int tap = (ks * 16 + 8 * (lane >> 5)) / 2 + q;
                 uint32_t v = 0;
-                // act1 position (jr, ic) is image (r0 - 1 + jr, ic - 1); the tap adds
-                // (tap / 3 - 1, tap % 3 - 1); s_img starts at image (r0 - 2, -2)
-                if (tap < 9 && p < kC12A1)
-                    v = s_img[(jr + tap / 3) * kC12ImgCols + ic + tap % 3];
-                av[2 * q] = bits_bf((uint16_t)(v & 0xFFFFu));
-                av[2 * q + 1] = bits_bf((uint16_t)(v >> 16));
+                // the tap adds (tap / 3 - 1, tap % 3 - 1); s_img starts at image (r0 - 2, -2)
+                if (tap < 9 && p < kC12A1) v = s_img[(jr + tap / 3) * kC12ImgCols + ic + tap % 3];
+                xv[ks][2 * q] = bits_bf((uint16_t)(v & 0xFFFFu));
+                xv[ks][2 * q + 1] = bits_bf((uint16_t)(v >> 16));
             }
-            a1 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(av, bw[nb][ks], a1, 0, 0, 0);
-        }
-        const int co = nb * 32 + (lane & 31);
-        const float bb = b1[co];
+        const int ar = r0 - 1 + jr, ac = ic - 1;
+        const bool inside = p < kC12A1 && ar >= 0 && ar < kImg && ac >= 0 && ac < kImg;
 #pragma unroll
-        for (int r = 0; r < 16; ++r) {
-            const int pix = pb * 32 + 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3);
-            if (pix < kC12A1) {
-                const int pr = pix / kCvCols, pc = pix % kCvCols;
-                const int ar = r0 - 1 + pr, ac = pc - 1;
-                const bool inside = ar >= 0 && ar < kImg && ac >= 0 && ac < kImg;
-                s_in[pix * kCvPitch + co] = f2bf(inside ? fmaxf(a1[r] + bb, 0.0f) : 0.0f);
+        for (int cb = 0; cb < 2; ++cb) {
+            v16f a1;
+#pragma unroll
+            for (int r = 0; r < 16; ++r) a1[r] = 0.0f;
+#pragma unroll
+            for (int ks = 0; ks < 2; ++ks) a1 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(aw[cb][ks], xv[ks], a1, 0, 0, 0);
+            if (p < kC12A1) {
+#pragma unroll
+                for (int g = 0; g < 4; ++g) {
+                    const int co = cb * 32 + 8 * g + 4 * (lane >> 5);
+                    const float4 bb = *reinterpret_cast<const float4*>(b1 + co);
+                    const uint2 v = inside ? pack4_bf16(fmaxf(a1[4 * g] + bb.x, 0.0f), fmaxf(a1[4 * g + 1] + bb.y, 0.0f),
+                                                        fmaxf(a1[4 * g + 2] + bb.z, 0.0f),
+                                                        fmaxf(a1[4 * g + 3] + bb.w, 0.0f))
+                                           : make_uint2(0u, 0u);
+                    *reinterpret_cast<uint2*>(s_in + p * kCvPitch + co) = v;
+                }
             }
         }
     }
     c12_store_w(s_w, t, wreg);
     __syncthreads();
 
-    // layer 2 (64 -> 128) on the act1 tile, as in k_conv_mid
-    v16f acc[2][NB];
+    // layer 2 (64 -> 128) on the act1 tile
+    v16f acc[NB][2];
 #pragma unroll
-    for (int i = 0; i < 2; ++i)
+    for (int i = 0; i < NB; ++i)
 #pragma unroll
-        for (int j = 0; j < NB; ++j)
+        for (int j = 0; j < 2; ++j)
 #pragma unroll
             for (int r = 0; r < 16; ++r) acc[i][j][r] = 0.0f;
     for (int tap = 0; tap < 9; ++tap) {
         if (tap < 8) c12_load_w(w2, tap + 1, t, wreg);
         const int dr = tap / 3 - 1, dc = tap % 3 - 1;
-        const uint16_t* arow = s_in + ((orow + 1 + dr) * kCvCols + (ocol0 + 1 + dc)) * kCvPitch;
+        const uint16_t* xrow = s_in + ((orow + 1 + dr) * kCvCols + (ocol0 + 1 + dc)) * kCvPitch;
         const uint16_t* wb = s_w + (tap & 1) * COUT * kCvPitch;
 #pragma unroll
         for (int kk = 0; kk < 4; ++kk) {
             const int ko = kk * 16 + 8 * (lane >> 5);
-            v8bf af[2], bfr[NB];
+            v8bf xf[2], wf[NB];
 #pragma unroll
             for (int mb = 0; mb < 2; ++mb)
-                af[mb] = *reinterpret_cast<const v8bf*>(arow + (mb * 32 + (lane & 31)) * kCvPitch + ko);
+                xf[mb] = *reinterpret_cast<const v8bf*>(xrow + (mb * 32 + (lane & 31)) * kCvPitch + ko);
 #pragma unroll
             for (int nb = 0; nb < NB; ++nb)
-                bfr[nb] = *reinterpret_cast<const v8bf*>(wb + (nb * 32 + (lane & 31)) * kCvPitch + ko);
+                wf[nb] = *reinterpret_cast<const v8bf*>(wb + (nb * 32 + (lane & 31)) * kCvPitch + ko);
 #pragma unroll
-            for (int mb = 0; mb < 2; ++mb)
+            for (int nb = 0; nb < NB; ++nb)
 #pragma unroll
-                for (int nb = 0; nb < NB; ++nb)
-                    acc[mb][nb] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(af[mb], bfr[nb], acc[mb][nb], 0, 0, 0);
+                for (int mb = 0; mb < 2; ++mb)
+                    acc[nb][mb] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(wf[nb], xf[mb], acc[nb][mb], 0, 0, 0);
         }
         if (tap < 8) c12_store_w(s_w + ((tap + 1) & 1) * COUT * kCvPitch, t, wreg);
         __syncthreads();
     }
     uint16_t* s_out = reinterpret_cast<uint16_t*>(s_dyn) + wave * 64 * (COUT + 8);
-#pragma unroll
-    for (int nb = 0; nb < NB; ++nb) {
-        const int co = nb * 32 + (lane & 31);
-        const float bb = b2[co];
-#pragma unroll
-        for (int mb = 0; mb < 2; ++mb)
-#pragma unroll
-            for (int r = 0; r < 16; ++r) {
-                const int px = mb * 32 + 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3);
-                s_out[px * (COUT + 8) + co] = f2bf(fmaxf(acc[mb][nb][r] + bb, 0.0f));
-            }
-    }
+    stage_act<NB, COUT>(s_out, acc, b2, lane);
     __syncthreads();
-    uint16_t* dst = y + ((e * kImg + r0 + orow) * kImg + ocol0) * COUT;
+    // this wave's 64 pixels x 128 channels -> four chunks of 64 x 32 channels
     for (int u = lane; u < 64 * COUT / 8; u += 64) {
         const int px = u / (COUT / 8), q = u % (COUT / 8);
-        *reinterpret_cast<uint4*>(dst + px * COUT + q * 8) =
+        *reinterpret_cast<uint4*>(y + chunked_off(e, q >> 2, r0 + orow, ocol0 + px) + (q & 3) * 8) =
             *reinterpret_cast<const uint4*>(s_out + px * (COUT + 8) + q * 8);
     }
 }
@@ -719,7 +749,8 @@ constexpr size_t conv3_lds()
     return main > out ? main : out;
 }
 
-// MODE 0: store act3 (training); MODE 1: store U[pixel][tap] = sum_c W4[tap][c] act3[pixel][c]
+// MODE 0 (training): act2 NHWC in, act3 NHWC out.  MODE 1 (inference): act2
+// channel-chunked in, U[pixel][tap] = sum_c W4[tap][c] act3[pixel][c] out.
 template <int MODE>
 __global__ __launch_bounds__(kCvThreads) void k_conv3(const uint16_t* __restrict__ x,
                                                       const uint16_t* __restrict__ w,
@@ -747,8 +778,11 @@ __global__ __launch_bounds__(kCvThreads) void k_conv3(const uint16_t* __restrict
             if (u < kC3TU) {
                 const int q = u & 3, pc = (u >> 2) % kCvCols, pr = (u >> 2) / kCvCols;
                 const int r = r0 - 1 + pr, col = pc - 1;
-                if (r >= 0 && r < kImg && col >= 0 && col < kImg)
-                    v = *reinterpret_cast<const uint4*>(x + ((e * kImg + r) * kImg + col) * CIN + c * kC3Chunk + q * 8);
+                if (r >= 0 && r < kImg && col >= 0 && col < kImg) {
+                    const int64_t off = MODE == 0 ? ((e * kImg + r) * kImg + col) * CIN + c * kC3Chunk + q * 8
+                                                  : chunked_off(e, c, r, col) + q * 8;
+                    v = *reinterpret_cast<const uint4*>(x + off);
+                }
             }
             treg[i] = v;
         }
@@ -768,11 +802,11 @@ __global__ __launch_bounds__(kCvThreads) void k_conv3(const uint16_t* __restrict
         if (t < WU) *reinterpret_cast<uint4*>(s_w + buf * COUT * kC3Pitch + (t >> 2) * kC3Pitch + (t & 3) * 8) = v;
     };
 
-    v16f acc[2][NB];
+    v16f acc[NB][2];
 #pragma unroll
-    for (int i = 0; i < 2; ++i)
+    for (int i = 0; i < NB; ++i)
 #pragma unroll
-        for (int j = 0; j < NB; ++j)
+        for (int j = 0; j < 2; ++j)
 #pragma unroll
             for (int r = 0; r < 16; ++r) acc[i][j][r] = 0.0f;
 
@@ -793,23 +827,23 @@ __global__ __launch_bounds__(kCvThreads) void k_conv3(const uint16_t* __restrict
 #pragma unroll
         for (int tap = 0; tap < 9; ++tap) {
             const int dr = tap / 3 - 1, dc = tap % 3 - 1;
-            const uint16_t* arow = tile + ((orow + 1 + dr) * kCvCols + (ocol0 + 1 + dc)) * kC3Pitch;
+            const uint16_t* xrow = tile + ((orow + 1 + dr) * kCvCols + (ocol0 + 1 + dc)) * kC3Pitch;
             const uint16_t* wb = s_w + (tap & 1) * COUT * kC3Pitch;
 #pragma unroll
             for (int kk = 0; kk < kC3Chunk / 16; ++kk) {
                 const int ko = kk * 16 + 8 * (lane >> 5);
-                v8bf af[2], bfr[NB];
+                v8bf xf[2], wf[NB];
 #pragma unroll
                 for (int mb = 0; mb < 2; ++mb)
-                    af[mb] = *reinterpret_cast<const v8bf*>(arow + (mb * 32 + (lane & 31)) * kC3Pitch + ko);
+                    xf[mb] = *reinterpret_cast<const v8bf*>(xrow + (mb * 32 + (lane & 31)) * kC3Pitch + ko);
 #pragma unroll
                 for (int nb = 0; nb < NB; ++nb)
-                    bfr[nb] = *reinterpret_cast<const v8bf*>(wb + (nb * 32 + (lane & 31)) * kC3Pitch + ko);
+                    wf[nb] = *reinterpret_cast<const v8bf*>(wb + (nb * 32 + (lane & 31)) * kC3Pitch + ko);
 #pragma unroll
-                for (int mb = 0; mb < 2; ++mb)
+                for (int nb = 0; nb < NB; ++nb)
 #pragma unroll
-                    for (int nb = 0; nb < NB; ++nb)
-                        acc[mb][nb] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(af[mb], bfr[nb], acc[mb][nb], 0, 0, 0);
+                    for (int mb = 0; mb < 2; ++mb)
+                        acc[nb][mb] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(wf[nb], xf[mb], acc[nb][mb], 0, 0, 0);
             }
             if (tap < 8) store_w((tap + 1) & 1, wreg[tap + 1]);
             __syncthreads();
@@ -819,18 +853,7 @@ __global__ __launch_bounds__(kCvThreads) void k_conv3(const uint16_t* __restrict
     }
 
     uint16_t* s_out = reinterpret_cast<uint16_t*>(s_dyn) + wave * 64 * (COUT + 8);
-#pragma unroll
-    for (int nb = 0; nb < NB; ++nb) {
-        const int co = nb * 32 + (lane & 31);
-        const float bb = bias[co];
-#pragma unroll
-        for (int mb = 0; mb < 2; ++mb)
-#pragma unroll
-            for (int r = 0; r < 16; ++r) {
-                const int px = mb * 32 + 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3);
-                s_out[px * (COUT + 8) + co] = f2bf(fmaxf(acc[mb][nb][r] + bb, 0.0f));
-            }
-    }
+    stage_act<NB, COUT>(s_out, acc, bias, lane);
     __syncthreads();
     const int64_t pix0 = (e * kImg + r0 + orow) * kImg + ocol0;
     if (MODE == 0) {
@@ -841,17 +864,18 @@ __global__ __launch_bounds__(kCvThreads) void k_conv3(const uint16_t* __restrict
                 *reinterpret_cast<const uint4*>(s_out + px * (COUT + 8) + q * 8);
         }
     } else {
-        // U = act3 (64 x 96, this wave's pixels) x W4^T (96 x 9, padded to 32 columns)
-        v8bf bu[COUT / 16];
+        // U^T = W4 (9 taps padded to 32 rows, 96) x act3^T (96 x this wave's 64 pixels):
+        // lane < 32 holds taps 0-3 and 8 (rows 0-3, 16), lane >= 32 taps 4-7, of pixel lane % 32
+        v8bf wu[COUT / 16];
         const int n = lane & 31;
 #pragma unroll
         for (int kk = 0; kk < COUT / 16; ++kk) {
             const int k0 = kk * 16 + 8 * (lane >> 5);
             if (n < 9) {
-                bu[kk] = *reinterpret_cast<const v8bf*>(w4 + n * COUT + k0);
+                wu[kk] = *reinterpret_cast<const v8bf*>(w4 + n * COUT + k0);
             } else {
 #pragma unroll
-                for (int j = 0; j < 8; ++j) bu[kk][j] = bits_bf(0);
+                for (int j = 0; j < 8; ++j) wu[kk][j] = bits_bf(0);
             }
         }
 #pragma unroll
@@ -861,17 +885,13 @@ __global__ __launch_bounds__(kCvThreads) void k_conv3(const uint16_t* __restrict
             for (int r = 0; r < 16; ++r) au[r] = 0.0f;
 #pragma unroll
             for (int kk = 0; kk < COUT / 16; ++kk) {
-                const v8bf a = *reinterpret_cast<const v8bf*>(s_out + (mb * 32 + (lane & 31)) * (COUT + 8) + kk * 16 +
-                                                              8 * (lane >> 5));
-                au = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, bu[kk], au, 0, 0, 0);
+                const v8bf xa = *reinterpret_cast<const v8bf*>(s_out + (mb * 32 + (lane & 31)) * (COUT + 8) +
+                                                               kk * 16 + 8 * (lane >> 5));
+                au = __builtin_amdgcn_mfma_f32_32x32x16_bf16(wu[kk], xa, au, 0, 0, 0);
             }
-            if (n < 9) {
-#pragma unroll
-                for (int r = 0; r < 16; ++r) {
-                    const int px = mb * 32 + 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3);
-                    u_out[(pix0 + px) * 9 + n] = au[r];
-                }
-            }
+            float* dst = u_out + (pix0 + mb * 32 + (lane & 31)) * kUPitch;
+            *reinterpret_cast<float4*>(dst + 4 * (lane >> 5)) = make_float4(au[0], au[1], au[2], au[3]);
+            if (lane < 32) dst[8] = au[4];
         }
     }
 }
@@ -888,7 +908,7 @@ __global__ __launch_bounds__(256) void k_head_sum(const float* __restrict__ u, c
 #pragma unroll
         for (int tap = 0; tap < 9; ++tap) {
             const int rr = r + tap / 3 - 1, cc = c + tap % 3 - 1;
-            if (rr >= 0 && rr < kImg && cc >= 0 && cc < kImg) z += u[(ev * kPix + rr * kImg + cc) * 9 + tap];
+            if (rr >= 0 && rr < kImg && cc >= 0 && cc < kImg) z += u[(ev * kPix + rr * kImg + cc) * kUPitch + tap];
         }
         logits[p] = z;
     }
