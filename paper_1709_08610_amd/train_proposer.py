@@ -3,12 +3,12 @@
   python -m paper_1709_08610_amd.train_proposer --events 100000 --epochs 2 \\
       --out paper_1709_08610_amd/models/proposer_c4.bin
 
-1. Events of the training workload (c4: the generator of the 1024-event batch,
-   its own key) are drawn on the host cores in parallel and moved to the GPU
-   once.
+1. Events of the training workload (c4: the generator of the 1024-event batch
+   with its own key; c6: likewise for the high-multiplicity batch) are drawn
+   on the host cores in parallel and moved to the GPU once.
 2. Labels: the maxima the plain method finds, i.e. the tracks of
-   retina_find_tracks with the 64 x 64 seed lattice (Algorithm 1 with its FP64
-   polish and merge); their slopes (tx, ty) mark the target heatmap.
+   retina_find_tracks with the workload's seed lattice (Algorithm 1 with its
+   FP64 polish and merge); their slopes (tx, ty) mark the target heatmap.
 3. Adam on the weighted binary cross-entropy through retina_train_step, batches
    of consecutive events visited in a seeded random order per epoch, cosine
    learning-rate decay after a short linear warm-up.
@@ -89,6 +89,7 @@ def label(ctx, zp, dev: DeviceEvents, params: dict, chunk: int = 4096):
         th = res["tracks_bytes"][: n * 48].view(torch.float64).view(n, 6)[:, 2:4].clone()
         tg.append(th)
         counts.append(toff.diff())
+        print("labelled events %d..%d: %d tracks" % (e0, e1 - 1, n), flush=True)
     cnt = torch.cat(counts)
     toff = torch.zeros(dev.n_events + 1, dtype=torch.int64, device=cnt.device)
     toff[1:] = torch.cumsum(cnt, 0)
