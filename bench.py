@@ -39,6 +39,29 @@ FLOP_POLISH_PAIR = 25          # RGH pair with the two-float residual (4 more)
 FLOP_FOLD = 26                 # per (candidate, plane) per derivative pass
 # proposer network: 2 x 16384 pixels x (9 x (2x64 + 64x128 + 128x96 + 96x1)) per event
 FLOP_NET_EVENT = 2 * 16384 * 9 * (2 * 64 + 64 * 128 + 128 * 96 + 96 * 1)
+# HBM bytes per launch of the ascent kernel from rocprofv3 --pmc FETCH_SIZE and
+# WRITE_SIZE runs of this script (profiles/k_ascent_c3_learned.md), each scaled
+# by the counter's reading for a 1 GiB device copy (FETCH_SIZE x 2.0, WRITE_SIZE
+# x 1.0).  Valid only for the kernel source they were taken with (hash of
+# csrc/hot.hip + csrc/rt_internal.h); reported as null otherwise.
+MEASURED_TRAFFIC = {("c3", "learned"): {"bytes": 83.2e6, "fetch": 75.7e6, "write": 7.3e6,
+                                         "source_sha256_16": "670bf742c546b5b0"}}
+
+
+def kernel_source_hash():
+    import hashlib
+    h = hashlib.sha256()
+    for f in ("hot.hip", "rt_internal.h"):
+        with open(os.path.join(ROOT, "paper_1709_08610_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic(workload):
+    m = MEASURED_TRAFFIC.get((workload, "learned"))
+    if m is None or m["source_sha256_16"] != kernel_source_hash():
+        return None
+    return m["bytes"]
 
 
 def log(msg):
@@ -238,7 +261,7 @@ def main():
                              "executed_line_search": prof_lrn["exec_rpairs"]},
         "roofline": {"bound": "alu", "achieved": achieved, "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s",
                      "frac": achieved / PEAK_FP32_TFLOPS, "frac_unpacked_peak": achieved / PEAK_FP32_UNPACKED,
-                     "traffic": None, "kernel": "k_ascent (persistent truncated-Newton ascent, learned seeds)",
+                     "traffic": measured_traffic(cfg["name"]), "traffic_unit": "bytes per launch", "kernel": "k_ascent (persistent truncated-Newton ascent, learned seeds)",
                      "flops_per_launch": fl_lrn},
         "roofline_proposer": {"bound": "mfma", "achieved": net_tflops, "peak": PEAK_BF16_TFLOPS,
                               "unit": "TFLOP/s", "frac": net_tflops / PEAK_BF16_TFLOPS,
