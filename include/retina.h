@@ -175,9 +175,10 @@ typedef struct {
     double ms_hot;        /* ascent (find_tracks) or response kernel */
     double ms_merge;      /* clustering + selection + output */
     double ms_total;      /* first kernel start to last kernel end */
-    double exec_pairs;    /* hit-candidate pairs the ascent kernel executed, all lanes
-                             (including lanes idle in another lane's line search) */
-    double exec_rpairs;   /* ... of which in R-only line-search passes */
+    double exec_pairs;    /* hit-candidate pairs the ascent kernel executed: every lane
+                             of a wave holding a seed in the full passes, every
+                             thread in the line-search rounds */
+    double exec_rpairs;   /* ... of which in R-only line-search rounds */
     double ms_propose;    /* learned seeds: binning, network and seed selection */
 } retina_profile;
 

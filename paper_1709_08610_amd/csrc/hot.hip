@@ -159,11 +159,13 @@ struct EventView {
 // One pass over all of the event's hits for the lane's C candidates.
 // Tiled events are streamed through LDS; the work-group must call this
 // uniformly then (it contains barriers).
+// `work` (wave-uniform) false: the wave holds no live candidate and only takes
+// part in the tile loads and barriers; its sums stay zero.
 template <int D, int C, bool DERIV, bool DF>
 __device__ __forceinline__ void event_pass(const Desc* __restrict__ d, float* s_hits,
                                            const int* s_poff, const EventView& ev,
                                            const Cands<C>& c, const Cands<C>& cl, float nc,
-                                           float (&acc)[C][Acc<D>::N])
+                                           float (&acc)[C][Acc<D>::N], bool work = true)
 {
 #pragma unroll
     for (int j = 0; j < C; ++j)
@@ -182,6 +184,7 @@ __device__ __forceinline__ void event_pass(const Desc* __restrict__ d, float* s_
             }
             __syncthreads();
         }
+        if (!work) continue;
         for (int p = 0; p < ev.P; ++p) {
             // LDS values are the same in every lane: keep the loop bounds scalar
             const int lo = __builtin_amdgcn_readfirstlane(max(s_poff[p], t0));
@@ -190,6 +193,75 @@ __device__ __forceinline__ void event_pass(const Desc* __restrict__ d, float* s_
             seg_accumulate<D, C, DERIV, DF>(s_hits, lo - t0, hi - t0, d->plane_z[p], c, cl, nc, acc);
         }
     }
+}
+
+// R only, one candidate per thread, over the hits of every plane segment whose
+// index within the segment is congruent to `part` modulo `parts` (threads of a
+// wave may hold different parts: hit reads are then per lane).  The per-pair
+// arithmetic is seg_accumulate's; per-plane sums are added in plane order.
+// Same barrier rule as event_pass.
+template <int D>
+__device__ __forceinline__ float event_pass_split(const Desc* __restrict__ d, float* s_hits, const int* s_poff,
+                                                  const EventView& ev, const float* th, float nc, int part,
+                                                  int parts)
+{
+    float R = 0.0f;
+    for (int t0 = 0; t0 < ev.n; t0 += ev.tile_cap) {
+        const int t1 = min(ev.n, t0 + ev.tile_cap);
+        if (!ev.resident) {
+            __syncthreads();
+            if (D == 2) {
+                const float2* src = reinterpret_cast<const float2*>(ev.g_hits) + t0;
+                float2* dst = reinterpret_cast<float2*>(s_hits);
+                for (int i = threadIdx.x; i < t1 - t0; i += blockDim.x) dst[i] = src[i];
+            } else {
+                for (int i = threadIdx.x; i < t1 - t0; i += blockDim.x) s_hits[i] = ev.g_hits[t0 + i];
+            }
+            __syncthreads();
+        }
+        for (int p = 0; p < ev.P; ++p) {
+            const int lo = __builtin_amdgcn_readfirstlane(max(s_poff[p], t0));
+            const int hi = __builtin_amdgcn_readfirstlane(min(s_poff[p + 1], t1));
+            if (lo >= hi) continue;
+            const float z = d->plane_z[p];
+            float pe = 0.0f;
+            // two hits per iteration, the next two read while these are summed;
+            // indices are clamped to the segment, so every read is in bounds
+            const int last = hi - 1 - t0;
+            int k = lo - t0 + part;
+            if constexpr (D == 2) {
+                const float2* h = reinterpret_cast<const float2*>(s_hits);
+                auto term = [&](const float2 v) {
+                    const float rx = __builtin_fmaf(-th[2], z, v.x) - th[0];
+                    const float ry = __builtin_fmaf(-th[3], z, v.y) - th[1];
+                    return __builtin_amdgcn_exp2f(__builtin_fmaf(ry, ry, rx * rx) * nc);
+                };
+                float2 a = h[min(k, last)], b = h[min(k + parts, last)];
+                for (; k <= last; k += 2 * parts) {
+                    const float2 na = h[min(k + 2 * parts, last)], nb = h[min(k + 3 * parts, last)];
+                    pe += term(a);
+                    if (k + parts <= last) pe += term(b);
+                    a = na;
+                    b = nb;
+                }
+            } else {
+                auto term = [&](const float v) {
+                    const float r = __builtin_fmaf(-th[1], z, v) - th[0];
+                    return __builtin_amdgcn_exp2f((r * r) * nc);
+                };
+                float a = s_hits[min(k, last)], b = s_hits[min(k + parts, last)];
+                for (; k <= last; k += 2 * parts) {
+                    const float na = s_hits[min(k + 2 * parts, last)], nb = s_hits[min(k + 3 * parts, last)];
+                    pe += term(a);
+                    if (k + parts <= last) pe += term(b);
+                    a = na;
+                    b = nb;
+                }
+            }
+            R += pe;
+        }
+    }
+    return R;
 }
 
 // R-only pass over part `part` of `parts` of every plane segment (the waves of a
@@ -462,8 +534,8 @@ __global__ __launch_bounds__(kBlock) void k_ascent(const Desc* __restrict__ d, i
     __shared__ int s_poff[kMaxPlanes + 1];
     __shared__ int s_item;
     __shared__ int s_npend;                 // line-search list: pending trial points,
-    __shared__ float s_lth[kBlock * C][4];  // then the waves' partial responses
-    static_assert(kBlock / kWave == 4, "the partial responses use one slot per wave");
+    __shared__ float s_lth[kBlock * C][4];  // then their responses (slot 0)
+    __shared__ float s_red[kBlock];         // partial responses of a line-search round
     if (d->cnt->err) return;
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);  // scalar: same in every lane
     const int lane = threadIdx.x & (kWave - 1);
@@ -513,7 +585,12 @@ __global__ __launch_bounds__(kBlock) void k_ascent(const Desc* __restrict__ d, i
             }
         }
 
-        int n_rpass_c1 = 0;  // single-candidate R-only passes this wave executed (line searches)
+        // waves without a live seed skip the arithmetic of every pass
+        bool any_active = false;
+#pragma unroll
+        for (int j = 0; j < C; ++j) any_active = any_active || active[j];
+        const bool wave_work = __builtin_amdgcn_readfirstlane((int)(__any(any_active) != 0)) != 0;
+        uint64_t ls_pairs = 0;  // executed line-search pair evaluations (same in every thread)
         for (int s = 0; s < n_steps; ++s) {
             const float sig = s < d->n_sigma ? d->sigma[s] : d->sigma_final;
             const float nc = -kLog2e / (sig * sig);
@@ -521,7 +598,7 @@ __global__ __launch_bounds__(kBlock) void k_ascent(const Desc* __restrict__ d, i
 #pragma unroll
             for (int j = 0; j < C; ++j) set_cand<D, C>(c, j, th[j]);
             float acc[C][NA];
-            event_pass<D, C, true, false>(d, s_hits, s_poff, ev, c, zero_c, nc, acc);
+            event_pass<D, C, true, false>(d, s_hits, s_poff, ev, c, zero_c, nc, acc, wave_work);
             float p[C][NP], Rc[C], gp[C], alpha[C];
             bool pend[C];
             int trial[C];
@@ -554,7 +631,9 @@ __global__ __launch_bounds__(kBlock) void k_ascent(const Desc* __restrict__ d, i
                 gp[j] = dot;
                 alpha[j] = 1.0f;
                 trial[j] = 0;
-                if (!neg && pn <= d->small_step * sig) {
+                if (!active[j]) {
+                    pend[j] = false;  // an empty slot never searches
+                } else if (!neg && pn <= d->small_step * sig) {
 #pragma unroll
                     for (int a = 0; a < NP; ++a) th[j][a] += p[j][a];
                     pend[j] = false;
@@ -564,9 +643,14 @@ __global__ __launch_bounds__(kBlock) void k_ascent(const Desc* __restrict__ d, i
             }
             // Backtracking line search.  Each round gathers the work-group's
             // pending trial points into an LDS list and evaluates R only for
-            // those, 64 per wave per pass: a wave no longer runs a whole pass
-            // because one of its lanes still searches.  A candidate's R does not
-            // depend on the slot that computes it (same arithmetic, same order).
+            // those.  One candidate per lane and up to 64 pending points: the
+            // 256 threads split into 256 / P parts per point (P = the count
+            // rounded up to a power of two), each summing R over every
+            // (256 / P)-th hit of each plane segment.  Otherwise: rounds of
+            // 64 * C points per wave, every wave over its quarter of each plane
+            // segment (C candidates per lane share each hit read; measured
+            // faster for C = 2 even when few points are pending).  Partial sums
+            // are added in a fixed order.
             for (;;) {
                 __syncthreads();
                 if (threadIdx.x == 0) s_npend = 0;
@@ -586,38 +670,64 @@ __global__ __launch_bounds__(kBlock) void k_ascent(const Desc* __restrict__ d, i
                 __syncthreads();
                 const int npend = __builtin_amdgcn_readfirstlane(s_npend);
                 if (npend == 0) break;
-                // rounds of 64*C entries; every wave evaluates all entries of a
-                // round over its quarter of each plane segment
-                const int per_round = kWave * C;
-                const int rounds = (npend + per_round - 1) / per_round;
-                for (int r = 0; r < rounds; ++r) {
-                    Cands<C> cc;
-                    bool live[C];
-                    int ent[C];
+                if (C == 1 && npend <= kWave) {
+                    int per = 1;  // points: a power of two, <= 64
+                    while (per < npend) per <<= 1;
+                    const int parts = kBlock / per;
+                    const int pt = threadIdx.x & (per - 1), part = threadIdx.x / per;
+                    float lt[NP];
+#pragma unroll
+                    for (int a = 0; a < NP; ++a) lt[a] = pt < npend ? s_lth[pt][a] : 0.0f;
+                    s_red[threadIdx.x] = event_pass_split<D>(d, s_hits, s_poff, ev, lt, nc, part, parts);
+                    __syncthreads();  // every thread holds its point and partial
+                    if (part == 0 && pt < npend) {
+                        float Rt = 0.0f;
+                        for (int q = 0; q < parts; ++q) Rt += s_red[q * per + pt];
+                        s_lth[pt][0] = Rt;
+                    }
+                    ls_pairs += (uint64_t)per * (uint64_t)ev.n;
+                } else {
+                    const int per_round = kWave * C;
+                    const int rounds = (npend + per_round - 1) / per_round;
+                    for (int r = 0; r < rounds; ++r) {
+                        Cands<C> cc;
+                        bool live[C];
+                        int ent[C];
+#pragma unroll
+                        for (int j = 0; j < C; ++j) {
+                            ent[j] = r * per_round + j * kWave + lane;
+                            live[j] = ent[j] < npend;
+                            float lt[NP];
+#pragma unroll
+                            for (int a = 0; a < NP; ++a) lt[a] = live[j] ? s_lth[ent[j]][a] : 0.0f;
+                            set_cand<D, C>(cc, j, lt);
+                        }
+                        __syncthreads();  // all waves hold the round's points before partials overwrite them
+                        float racc[C][NA];
+                        event_pass_part<D, C>(d, s_hits, s_poff, ev, cc, nc, wave, kBlock / kWave, racc);
+#pragma unroll
+                        for (int j = 0; j < C; ++j)
+                            if (live[j]) s_lth[ent[j]][wave] = racc[j][0];
+                    }
+                    __syncthreads();
+                    // ((wave 0 + wave 1) + wave 2) + wave 3, into slot 0
 #pragma unroll
                     for (int j = 0; j < C; ++j) {
-                        ent[j] = r * per_round + j * kWave + lane;
-                        live[j] = ent[j] < npend;
-                        float lt[NP];
-#pragma unroll
-                        for (int a = 0; a < NP; ++a) lt[a] = live[j] ? s_lth[ent[j]][a] : 0.0f;
-                        set_cand<D, C>(cc, j, lt);
+                        const int e2 = (int)threadIdx.x + j * kBlock;
+                        if (e2 < npend) {
+                            const float* pr = s_lth[e2];
+                            const float Rt = ((pr[0] + pr[1]) + pr[2]) + pr[3];
+                            s_lth[e2][0] = Rt;
+                        }
                     }
-                    __syncthreads();  // all waves hold the round's points before partials overwrite them
-                    float racc[C][NA];
-                    event_pass_part<D, C>(d, s_hits, s_poff, ev, cc, nc, wave, kBlock / kWave, racc);
-#pragma unroll
-                    for (int j = 0; j < C; ++j)
-                        if (live[j]) s_lth[ent[j]][wave] = racc[j][0];
+                    ls_pairs += (uint64_t)rounds * per_round * (uint64_t)ev.n;
                 }
-                n_rpass_c1 += rounds * C;  // each round: a quarter pass over 64*C candidates per wave
                 __syncthreads();
 #pragma unroll
                 for (int j = 0; j < C; ++j) {
                     if (!pend[j]) continue;
                     ++nre[j];
-                    const float* pr = s_lth[slot[j]];
-                    const float Rt = ((pr[0] + pr[1]) + pr[2]) + pr[3];
+                    const float Rt = s_lth[slot[j]][0];
                     if (Rt >= Rc[j] + d->armijo_c1 * alpha[j] * gp[j]) {
 #pragma unroll
                         for (int a = 0; a < NP; ++a) th[j][a] = tt[j][a];
@@ -657,7 +767,7 @@ __global__ __launch_bounds__(kBlock) void k_ascent(const Desc* __restrict__ d, i
                 set_cand<D, C>(cl, j, lo);
             }
             float acc[C][NA];
-            event_pass<D, C, true, true>(d, s_hits, s_poff, ev, ch, cl, ncf, acc);
+            event_pass<D, C, true, true>(d, s_hits, s_poff, ev, ch, cl, ncf, acc, wave_work);
 #pragma unroll
             for (int j = 0; j < C; ++j) {
                 double g[NP], H[NP][NP], A[NP][NP], dl[NP];
@@ -696,12 +806,14 @@ __global__ __launch_bounds__(kBlock) void k_ascent(const Desc* __restrict__ d, i
             d->s_flags[gs] = flags[j];
             d->s_nreval[gs] = nre[j];
         }
-        if (lane == 0) {
+        if (lane == 0 && wave_work) {
             const uint64_t per_pass = (uint64_t)ev.n * kWave;
-            const uint64_t rp = per_pass * (uint64_t)n_rpass_c1 / 4;  // quarter passes
             atomicAdd((unsigned long long*)&d->cnt->exec_pairs,
-                      (unsigned long long)(per_pass * C * (uint64_t)(n_steps + d->n_polish) + rp));
-            atomicAdd((unsigned long long*)&d->cnt->exec_rpairs, (unsigned long long)rp);
+                      (unsigned long long)(per_pass * C * (uint64_t)(n_steps + d->n_polish)));
+        }
+        if (threadIdx.x == 0) {
+            atomicAdd((unsigned long long*)&d->cnt->exec_pairs, (unsigned long long)ls_pairs);
+            atomicAdd((unsigned long long*)&d->cnt->exec_rpairs, (unsigned long long)ls_pairs);
         }
         __syncthreads();
     }
