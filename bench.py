@@ -10,8 +10,12 @@ clustering and selection.  Two seedings of the same batch are timed:
            seeds on the device (lattice fallback per event), then the same
            ascent, polish and merge
 
-`value` is the learned path's events/s; the lattice figure, both track
-qualities against generator truth, and the speedup are reported beside it.
+`value` is the learned path's events/s.  The lattice baseline is the fastest
+lattice of the workload's sweep (`lattice_sweep`) that reaches >= 95% track
+efficiency; every swept size is reported, with the qualities against
+generator truth and the speedup.  The standalone response kernel
+(retina_response: R only and R + gradient + Hessian) is timed on the
+workload's shapes for the response evals/s and %FP32 peak figures.
 Inputs are resident in device memory before the timed regions; each timed
 region brackets exactly --steps calls with device synchronisation and runs
 with the library's HIP-event profiling on (eager launches), which gives the
@@ -81,19 +85,108 @@ def algorithmic_flops(P, ev_hits, ev_seeds, nreval_per_event, n_planes):
     return fl, pairs
 
 
-def cpu_baseline(cfg, n_events):
+def _sample_size(run_one, target_s, cap):
+    """Events for a CPU sample of about target_s seconds (one event timed first)."""
+    t0 = time.perf_counter()
+    run_one()
+    dt = max(time.perf_counter() - t0, 1e-3)
+    return int(max(1, min(cap, target_s / dt)))
+
+
+def cpu_baseline(cfg, P, target_s=12.0, cap=256):
     import oracle
     from paper_1709_08610_amd import events
-    b = events.make_batch(cfg, n_events)
     threads = os.cpu_count() or 1
+    n_events = _sample_size(lambda: oracle.find_tracks(events.make_batch(cfg, 1), P, n_threads=threads),
+                            target_s, cap)
+    b = events.make_batch(cfg, n_events)
     t0 = time.perf_counter()
-    oracle.find_tracks(b, cfg["params"], n_threads=threads)
+    oracle.find_tracks(b, P, n_threads=threads)
     dt = time.perf_counter() - t0
     return dict(value=n_events / dt, unit="events/s", cores=threads, kind="oracle",
                 sample="first %d of %d events of the %s workload, full method with the %dx%d lattice "
                        "(FP64, OpenMP over seeds), %.1f s"
-                       % (n_events, cfg["n_events"], cfg["name"], cfg["params"]["lattice_n"][0],
-                          cfg["params"]["lattice_n"][1], dt))
+                       % (n_events, cfg["n_events"], cfg["name"], P["lattice_n"][0], P["lattice_n"][1], dt))
+
+
+def cpu_baseline_learned(cfg, LS, model, target_s=12.0, cap=256):
+    """The oracle's own learned path on the host cores: the FP64 network forward
+    (numpy, BF16 at the device's storage points) and seed selection of
+    oracle/proposer.py on the same weights, then oracle_find_tracks on those
+    seeds."""
+    import numpy as np
+    import oracle
+    from oracle import proposer as op
+    from paper_1709_08610_amd import events
+    layers = op.unpack_params(model.retina_model_get_params())
+    lat = oracle.lattice(2, LS["params"])
+    threads = os.cpu_count() or 1
+
+    def run(b):
+        seeds, off = [], [0]
+        for e in range(b.n_events):
+            ev = b.event(e)
+            _, z = op.forward(op.bin_image(ev.x, ev.y, ev.plane, b.plane_z), layers)
+            picks = op.nms_topk(z, LS["tau"], LS["k_max"], nms=LS["nms"])
+            fb = not picks or z.max() < op.logit_threshold(LS["conf_min"])
+            s = lat if fb else op.seeds_from_pixels(picks)
+            seeds.append(s)
+            off.append(off[-1] + len(s))
+        oracle.find_tracks(b, LS["params"], np.concatenate(seeds), np.array(off, np.int64), n_threads=threads)
+
+    n_events = _sample_size(lambda: run(events.make_batch(cfg, 1)), target_s, cap)
+    b = events.make_batch(cfg, n_events)
+    t0 = time.perf_counter()
+    run(b)
+    dt = time.perf_counter() - t0
+    return dict(value=n_events / dt, unit="events/s", cores=threads, kind="oracle",
+                sample="first %d of %d events of the %s workload, oracle proposer (numpy FP64 forward) + full "
+                       "method on its seeds (FP64, OpenMP over seeds), %.1f s" % (n_events, cfg["n_events"],
+                                                                               cfg["name"], dt))
+
+
+def response_throughput(ctx, retina, cfg, b, torch, np):
+    """retina_response alone (R only, and R + gradient + Hessian) on the
+    workload's events with its lattice as the candidate lines: pair
+    evaluations per second and the algorithmic FP32 rate."""
+    P = cfg["params"]
+    D = b.meas_dim
+    n0, n1 = P["lattice_n"]
+    i0, i1 = np.meshgrid(np.arange(n0), np.arange(n1), indexing="ij")
+    v0 = (P["lattice_lo"][0] + (i0.ravel() + 0.5) * (P["lattice_hi"][0] - P["lattice_lo"][0]) / n0)
+    v1 = (P["lattice_lo"][1] + (i1.ravel() + 0.5) * (P["lattice_hi"][1] - P["lattice_lo"][1]) / n1)
+    th = np.zeros((n0 * n1, 2 * D), np.float32)
+    if D == 2:
+        th[:, 2], th[:, 3] = v0, v1
+    else:
+        th[:, 0], th[:, 1] = v1, v0
+    dev = torch.device("cuda:0")
+    E = b.n_events
+    theta = torch.from_numpy(np.tile(th, (E, 1))).to(dev)
+    toff = torch.from_numpy(np.arange(E + 1, dtype=np.int64) * len(th)).to(dev)
+    tin = lambda a: torch.from_numpy(np.ascontiguousarray(a)).to(dev)
+    hits = (tin(b.event_offsets), tin(b.x), tin(b.y) if D == 2 else None, tin(b.plane))
+    pairs = float(len(th)) * float(b.x.shape[0])
+    out = {"candidates_per_event": len(th), "events": E, "hits": int(b.x.shape[0])}
+    for name, want, fl in (("R", retina.WANT_R, FLOP_R_PAIR if D == 2 else 6),
+                           ("RGH", retina.WANT_R | retina.WANT_GRAD | retina.WANT_HESS, FLOP_RGH_PAIR if D == 2 else 10)):
+        f = lambda: ctx.retina_response(D, b.plane_z, *hits, theta, toff, sigma=P["sigma_final"], want=want)
+        f()
+        torch.cuda.synchronize()
+        ctx.retina_set_profiling(True)
+        ctx.retina_profile_reset()
+        for _ in range(3):
+            f()
+        torch.cuda.synchronize()
+        pr = ctx.retina_get_profile()
+        ctx.retina_set_profiling(False)
+        ms = pr["ms_hot"] / max(pr["calls"], 1)
+        rate = pairs / (ms * 1e-3)
+        out[name] = {"ms": ms, "pair_evals_per_s": rate, "tflops": rate * fl / 1e12,
+                     "frac_fp32_peak": rate * fl / 1e12 / PEAK_FP32_TFLOPS}
+        log("response %s: %.3f ms, %.3g pair evals/s, %.1f%% of FP32 peak" % (name, ms, rate,
+                                                                              100 * rate * fl / 1e12 / PEAK_FP32_TFLOPS))
+    return out
 
 
 def timed(ctx, step, steps):
@@ -127,7 +220,8 @@ def main():
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default="c3")
-    ap.add_argument("--cpu-events", type=int, default=8)
+    ap.add_argument("--cpu-seconds", type=float, default=12.0,
+                    help="approximate length of each CPU oracle sample")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--calib-copy-mib", type=int, default=0,
                     help="after the run, one plain device-to-device copy of this many MiB (a known-size "
@@ -168,6 +262,28 @@ def main():
     def learned_step():
         return ctx.retina_find_tracks_learned(model, b.plane_z, off_d, x_d, y_d, pl_d, PL, LS["k_max"],
                                               LS["tau"], LS["conf_min"], nms=LS["nms"])
+
+    # ---- lattice sweep: the fastest lattice reaching the efficiency bar is the baseline
+    sweep = []
+    for n in cfg.get("lattice_sweep", [P["lattice_n"][0]]):
+        Pn = dict(P, lattice_n=[n, n])
+        f = lambda: ctx.retina_find_tracks(D, b.plane_z, off_d, x_d, y_d, pl_d, Pn)
+        r = f()
+        torch.cuda.synchronize()
+        qn = quality(retina.tracks_from_device(r)["theta"][:, :2 * D], r["track_offsets"].cpu().numpy())
+        del r
+        t0 = time.perf_counter()
+        for _ in range(2):
+            f()
+        torch.cuda.synchronize()
+        tn = (time.perf_counter() - t0) / 2
+        sweep.append(dict(lattice_n=n, ms_per_step=tn * 1e3, events_per_s=E / tn,
+                          efficiency=round(qn["efficiency"], 5), fake_rate=round(qn["fake_rate"], 5)))
+        log("lattice %dx%d: %.2f ms, efficiency %.4f fake %.4f" % (n, n, tn * 1e3, qn["efficiency"], qn["fake_rate"]))
+    ok = [r for r in sweep if r["efficiency"] >= 0.95]
+    best = min(ok, key=lambda r: r["ms_per_step"]) if ok else max(sweep, key=lambda r: r["efficiency"])
+    P = dict(P, lattice_n=[best["lattice_n"], best["lattice_n"]])
+    log("lattice baseline: %dx%d" % (best["lattice_n"], best["lattice_n"]))
 
     # ---- quality + work accounting (untimed)
     log("lattice: quality + work accounting run")
@@ -214,10 +330,24 @@ def main():
     log("learned: %.2f ms/step (graph replay %.2f), proposer %.2f ms, ascent %.2f ms" % (
         dt_lrn * 1e3, g_lrn * 1e3, prof_lrn["ms_propose"], prof_lrn["ms_hot"]))
 
-    cpu = None
+    # end to end from host memory (hits H2D, tracks D2H included)
+    hb = (b.event_offsets, b.x, b.y, b.plane)
+    ctx.retina_find_tracks_learned(model, b.plane_z, *hb, PL, LS["k_max"], LS["tau"], LS["conf_min"], nms=LS["nms"])
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        ctx.retina_find_tracks_learned(model, b.plane_z, *hb, PL, LS["k_max"], LS["tau"], LS["conf_min"],
+                                       nms=LS["nms"])
+    ms_host = (time.perf_counter() - t0) / args.steps * 1e3
+    log("learned, host memory end to end: %.2f ms/step" % ms_host)
+
+    resp = response_throughput(ctx, retina, cfg, b, torch, np)
+
+    cpu = cpu_l = None
     if not args.no_cpu_baseline:
-        log("cpu baseline (oracle) on %d events" % args.cpu_events)
-        cpu = cpu_baseline(cfg, args.cpu_events)
+        log("cpu baseline (oracle, %dx%d lattice)" % tuple(P["lattice_n"]))
+        cpu = cpu_baseline(cfg, P, args.cpu_seconds)
+        log("cpu baseline (oracle, learned seeds)")
+        cpu_l = cpu_baseline_learned(cfg, LS, model, args.cpu_seconds)
 
     hot = prof_lrn["ms_hot"]
     achieved = fl_lrn / (hot * 1e-3) / 1e12
@@ -249,13 +379,16 @@ def main():
                     "kernel_ms": dict(kms(prof_lrn), proposer=prof_lrn["ms_propose"]),
                     "response_evals_per_s": pairs_lrn / (hot * 1e-3),
                     "proposer_net_tflops": net_tflops},
-        "lattice": {"events_per_s": E / dt_lat, "ms_per_step": dt_lat * 1e3, "ms_per_step_graph_replay": g_lat * 1e3,
+        "lattice": {"lattice_n": best["lattice_n"], "events_per_s": E / dt_lat, "ms_per_step": dt_lat * 1e3, "ms_per_step_graph_replay": g_lat * 1e3,
                     "quality": rq(q_lat), "kernel_ms": kms(prof_lat),
                     "response_evals_per_s": pairs_lat / (prof_lat["ms_hot"] * 1e-3),
                     "ascent_tflops": fl_lat / (prof_lat["ms_hot"] * 1e-3) / 1e12,
                     "pairs_per_launch": {"algorithmic": pairs_lat, "executed": prof_lat["exec_pairs"],
                                          "executed_line_search": prof_lat["exec_rpairs"]}},
+        "lattice_sweep": sweep,
         "speedup_vs_lattice": dt_lat / dt_lrn,
+        "end_to_end_host_ms_per_step": ms_host,
+        "response": resp,
         "response_evals_per_s": pairs_lrn / (hot * 1e-3),
         "pairs_per_launch": {"algorithmic": pairs_lrn, "executed": prof_lrn["exec_pairs"],
                              "executed_line_search": prof_lrn["exec_rpairs"]},
@@ -268,6 +401,7 @@ def main():
                               "kernel": "binning + four conv layers + seed selection (network flops only)",
                               "flops_per_launch": FLOP_NET_EVENT * E},
         "cpu_baseline": cpu,
+        "cpu_baseline_learned": cpu_l,
     }
     print(json.dumps(out))
     if args.calib_copy_mib:
