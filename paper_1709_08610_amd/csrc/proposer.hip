@@ -46,41 +46,56 @@ NetLayout net_layout()
 
 // ------------------------------------------------------------------ binning
 // One work-group per event: a 2 x 128 x 128 histogram of hit slopes (x/z,
-// y/z) in LDS (16-bit counts, two per word), channel 0 for the first half of
-// the planes, 1 for the second; written as log1p(count) in BF16.
+// y/z) in LDS, channel 0 for the first half of the planes, 1 for the second;
+// written as log1p(count) in BF16.  Events of at most 65,535 hits keep both
+// channels' counts as 16-bit halves of one word (no count can overflow);
+// larger events take one pass per channel with 32-bit counts.
+__device__ __forceinline__ int slope_bin(float x, float y, float z, float w)
+{
+    const float u = (x / z - kSlopeLo) / w;
+    const float v = (y / z - kSlopeLo) / w;
+    if (u >= 0.0f && u < (float)kImg && v >= 0.0f && v < (float)kImg) return (int)u * kImg + (int)v;
+    return -1;
+}
+
 __global__ __launch_bounds__(256) void k_bin_image(const float* __restrict__ hits,
                                                    const int32_t* __restrict__ plane_off, int P, int D,
                                                    const float* __restrict__ plane_z, int64_t E,
                                                    uint16_t* __restrict__ img)
 {
-    __shared__ uint32_t s_h[kPix];  // 2 * kPix 16-bit counts
+    __shared__ uint32_t s_h[kPix];
     const float w = (kSlopeHi - kSlopeLo) / kImg;
     for (int64_t e = blockIdx.x; e < E; e += gridDim.x) {
-        for (int i = threadIdx.x; i < kPix; i += blockDim.x) s_h[i] = 0;
-        __syncthreads();
         const int32_t* po = plane_off + e * (P + 1);
-        for (int p = 0; p < P; ++p) {
-            const float z = plane_z[p];
-            const int ch = p < P / 2 ? 0 : 1;
-            for (int k = po[p] + threadIdx.x; k < po[p + 1]; k += blockDim.x) {
-                const float x = hits[(int64_t)k * D];
-                const float y = D == 2 ? hits[(int64_t)k * D + 1] : 0.0f;
-                const float u = (x / z - kSlopeLo) / w;
-                const float v = (y / z - kSlopeLo) / w;
-                if (u >= 0.0f && u < (float)kImg && v >= 0.0f && v < (float)kImg) {
-                    const int idx = (((int)u * kImg + (int)v) << 1) | ch;
-                    atomicAdd(&s_h[idx >> 1], 1u << (16 * (idx & 1)));
+        const bool packed = po[P] - po[0] <= 0xFFFF;
+        for (int pass = 0; pass < (packed ? 1 : 2); ++pass) {
+            for (int i = threadIdx.x; i < kPix; i += blockDim.x) s_h[i] = 0;
+            __syncthreads();
+            for (int p = 0; p < P; ++p) {
+                const int ch = p < P / 2 ? 0 : 1;
+                if (!packed && ch != pass) continue;
+                const float z = plane_z[p];
+                for (int k = po[p] + threadIdx.x; k < po[p + 1]; k += blockDim.x) {
+                    const float x = hits[(int64_t)k * D];
+                    const float y = D == 2 ? hits[(int64_t)k * D + 1] : 0.0f;
+                    const int bin = slope_bin(x, y, z, w);
+                    if (bin >= 0) atomicAdd(&s_h[bin], packed ? 1u << (16 * ch) : 1u);
                 }
             }
+            __syncthreads();
+            if (packed) {
+                uint32_t* out = reinterpret_cast<uint32_t*>(img + e * kPix * 2);
+                for (int i = threadIdx.x; i < kPix; i += blockDim.x) {
+                    const uint32_t c = s_h[i];
+                    const float a = log1pf((float)(c & 0xFFFFu)), b = log1pf((float)(c >> 16));
+                    out[i] = (uint32_t)f2bf(a) | ((uint32_t)f2bf(b) << 16);
+                }
+            } else {
+                uint16_t* out = img + e * kPix * 2;
+                for (int i = threadIdx.x; i < kPix; i += blockDim.x) out[2 * i + pass] = f2bf(log1pf((float)s_h[i]));
+            }
+            __syncthreads();
         }
-        __syncthreads();
-        uint32_t* out = reinterpret_cast<uint32_t*>(img + e * kPix * 2);
-        for (int i = threadIdx.x; i < kPix; i += blockDim.x) {
-            const uint32_t c = s_h[i];
-            const float a = log1pf((float)(c & 0xFFFFu)), b = log1pf((float)(c >> 16));
-            out[i] = (uint32_t)f2bf(a) | ((uint32_t)f2bf(b) << 16);
-        }
-        __syncthreads();
     }
 }
 
