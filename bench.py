@@ -48,8 +48,8 @@ FLOP_NET_EVENT = 2 * 16384 * 9 * (2 * 64 + 64 * 128 + 128 * 96 + 96 * 1)
 # by the counter's reading for a 1 GiB device copy (FETCH_SIZE x 2.0, WRITE_SIZE
 # x 1.0).  Valid only for the kernel source they were taken with (hash of
 # csrc/hot.hip + csrc/rt_internal.h); reported as null otherwise.
-MEASURED_TRAFFIC = {("c3", "learned"): {"bytes": 83.2e6, "fetch": 75.7e6, "write": 7.3e6,
-                                         "source_sha256_16": "670bf742c546b5b0"}}
+MEASURED_TRAFFIC = {("c3", "learned"): {"bytes": 86.4e6, "fetch": 79.2e6, "write": 7.2e6,
+                                         "source_sha256_16": "d139224ccd790786"}}
 
 
 def kernel_source_hash():
@@ -341,6 +341,14 @@ def main():
     log("learned, host memory end to end: %.2f ms/step" % ms_host)
 
     resp = response_throughput(ctx, retina, cfg, b, torch, np)
+    # the other response shapes: one c2 event (4096 lattice lines x 5.6k hits,
+    # occupancy-limited) and the c1 brute-force grid (400 x 400 lines x 130
+    # hits, meas_dim 1)
+    c2 = events.load_config("c2")
+    resp_c2 = response_throughput(ctx, retina, c2, events.make_batch(c2, 1), torch, np)
+    c1 = events.load_config("c1")
+    c1g = dict(c1, params=dict(c1["params"], lattice_n=[400, 400]))
+    resp_c1 = response_throughput(ctx, retina, c1g, events.make_batch(c1, 1), torch, np)
 
     cpu = cpu_l = None
     if not args.no_cpu_baseline:
@@ -389,6 +397,8 @@ def main():
         "speedup_vs_lattice": dt_lat / dt_lrn,
         "end_to_end_host_ms_per_step": ms_host,
         "response": resp,
+        "response_c2_event": resp_c2,
+        "response_c1_grid": resp_c1,
         "response_evals_per_s": pairs_lrn / (hot * 1e-3),
         "pairs_per_launch": {"algorithmic": pairs_lrn, "executed": prof_lrn["exec_pairs"],
                              "executed_line_search": prof_lrn["exec_rpairs"]},

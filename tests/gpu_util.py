@@ -140,6 +140,11 @@ def assert_tracks_match(D, gpu_theta, gpu_R, ref_theta, ref_R, d_merge, z0, z1):
     assert rel.max() <= 1e-4, "parameter error %g" % rel.max()
     Rg = np.asarray(gpu_R, np.float64)[t2f]
     np.testing.assert_allclose(Rg, ref_R, rtol=1e-5)
+    # the FP32-vs-FP64 error of this track set (shown with pytest -s)
+    absd = np.abs(g - ref_theta).max(axis=0)
+    print("    %d tracks: max |dp|/max(|p|, s_p) %.2e, max |dp| per component %s, max |dR|/R %.2e" % (
+        len(ref_theta), rel.max(), " ".join("%.1e" % v for v in absd),
+        float(np.max(np.abs(Rg - ref_R) / np.maximum(np.abs(ref_R), 1e-30)))), flush=True)
     return rel.max(axis=1)
 
 
