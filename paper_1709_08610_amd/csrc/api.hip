@@ -28,7 +28,7 @@ enum BufId {
     B_INX, B_INY, B_INPL, B_INOFF, B_INSEEDS, B_INSOFF, B_INTH, B_INTHOFF, B_OUTTR, B_OUTTOFF,
     B_OUTEVF, B_OUTSTH, B_OUTSR, B_OUTSFL, B_OUTSNR, B_OUTR, B_OUTG, B_OUTH,
     // learned proposer workspace
-    B_IMG, B_ACT1, B_ACT2, B_ACT3, B_LOGIT, B_HEADU, B_DZ4, B_DZ3, B_DZ2, B_DZ1, B_TGT, B_TGTIN, B_TGTOFF,
+    B_IMG, B_ACT1, B_ACT2, B_ACT3, B_LOGIT, B_HEADU, B_RESPPART, B_DZ4, B_DZ3, B_DZ2, B_DZ1, B_TGT, B_TGTIN, B_TGTOFF,
     B_DWPART, B_WT, B_LOSSPART, B_LOSS, B_BPART, B_PSCORE, B_PPIX, B_PCOUNT, B_PCONF, B_PFB,
     B_PSOFF, B_PSEEDS, B_OUTIMG, B_OUTLOGIT,
     B_COUNT
@@ -272,6 +272,10 @@ int device_error(retina_ctx* c, uint32_t err)
 // find_tracks batches averaging fewer seeds per event than this run the
 // ascent with the sparse-seeding launch shape (tuning kernel 2)
 constexpr int64_t kSparseSeeds = 512;
+// retina_response hit splitting: at most this many parts, each part at least
+// this many hits of an average event
+constexpr int kRespMaxParts = 32;
+constexpr int64_t kRespMinPartHits = 128;
 
 HotConfig& tuning_slot(retina_ctx* c, int D, int kernel)
 {
@@ -577,8 +581,20 @@ int retina_response(retina_ctx* c, const retina_geometry* g, const retina_hits* 
     if ((rc = stage_inputs(c, d, g, h, n_hits))) return rc;
     const HotConfig hc = c->resp_cfg[D];
     d.seeds_per_item = hot_seeds_per_item(hc);
-    d.items_cap = n_theta / d.seeds_per_item + E + 1;
+    // few (event, theta block) items leave CUs idle: split each event's hits
+    // into parts (each part at least kRespMinPartHits hits on average), reduced
+    // in part order afterwards
+    const int64_t blocks = n_theta / d.seeds_per_item + E;
+    int parts = 1;
+    while (parts < kRespMaxParts && blocks * parts < (int64_t)hc.grid &&
+           n_hits / (E * parts * 2) >= kRespMinPartHits)
+        parts *= 2;
+    d.resp_parts = parts;
+    d.resp_ntheta = n_theta;
+    d.items_cap = (n_theta / d.seeds_per_item + E + 1) * parts;
     if ((rc = ensure_t(c, B_ITEMS, (size_t)d.items_cap, &d.items))) return rc;
+    if (parts > 1 && (rc = ensure_t(c, B_RESPPART, (size_t)parts * n_theta * (D == 2 ? 16 : 8), &d.resp_partial)))
+        return rc;
     d.want = want | RETINA_WANT_R;
     d.resp_sigma = sigma;
     // inputs
@@ -624,6 +640,8 @@ int retina_response(retina_ctx* c, const retina_geometry* g, const retina_hits* 
     launch_plan_response(c->d_desc, c->stream);
     prof_mark(c, 2);
     launch_response(c->d_desc, D, hc, (want & (RETINA_WANT_GRAD | RETINA_WANT_HESS)) != 0, c->stream);
+    if (parts > 1)
+        launch_response_reduce(c->d_desc, D, (want & (RETINA_WANT_GRAD | RETINA_WANT_HESS)) != 0, n_theta, c->stream);
     prof_mark(c, 3);
     prof_mark(c, 4);
     HIP_TRY(c, hipGetLastError());

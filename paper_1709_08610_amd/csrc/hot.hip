@@ -495,19 +495,23 @@ __device__ __forceinline__ bool wg_or(bool v, bool resident)
 }
 
 // Load the event's plane offsets (event-relative) and, if it fits, its hits.
+// With parts > 1 the view is part `part` of the event's hits (a contiguous
+// range across planes; plane segments are clipped to it).
 __device__ __forceinline__ EventView begin_event(const Desc* __restrict__ d, int e, float* s_hits,
-                                                 int* s_poff, int tile_cap)
+                                                 int* s_poff, int tile_cap, int part = 0, int parts = 1)
 {
     const int P = d->n_planes;
     const int32_t* po = d->plane_off + (int64_t)e * (P + 1);
-    const int base = po[0];
+    const int n_all = d->ev_nhits[e];
+    const int h0 = (int)((int64_t)n_all * part / parts), h1 = (int)((int64_t)n_all * (part + 1) / parts);
+    const int base = po[0] + h0;
     EventView ev;
     ev.P = P;
-    ev.n = d->ev_nhits[e];
+    ev.n = h1 - h0;
     ev.g_hits = d->hits + (int64_t)base * d->meas_dim;
     ev.tile_cap = tile_cap;
     ev.resident = ev.n <= tile_cap;
-    if ((int)threadIdx.x <= P) s_poff[threadIdx.x] = po[threadIdx.x] - base;
+    if ((int)threadIdx.x <= P) s_poff[threadIdx.x] = min(max(po[threadIdx.x] - base, 0), h1 - h0);
     if (ev.resident) {
         if (d->meas_dim == 2) {
             const float2* src = reinterpret_cast<const float2*>(ev.g_hits);
@@ -552,7 +556,8 @@ __global__ __launch_bounds__(kBlock) void k_ascent(const Desc* __restrict__ d, i
         __syncthreads();
         const int item = __builtin_amdgcn_readfirstlane(s_item);
         if (item >= n_items) break;
-        const int2 it = d->items[item];
+        const int2 it0 = d->items[item];
+        const int2 it = make_int2(it0.x, it0.y * d->seeds_per_item);  // (event, first seed)
         const int e = __builtin_amdgcn_readfirstlane(it.x);
         const EventView ev = begin_event(d, e, s_hits, s_poff, tile_cap);
         const int64_t sbase = d->seed_off[e];
@@ -843,9 +848,12 @@ __global__ __launch_bounds__(kBlock) void k_response(const Desc* __restrict__ d,
         __syncthreads();
         const int item = __builtin_amdgcn_readfirstlane(s_item);
         if (item >= n_items) break;
-        const int2 it = d->items[item];
+        const int2 it0 = d->items[item];
+        const int parts = d->resp_parts;
+        const int part = it0.y % parts;
+        const int2 it = make_int2(it0.x, (it0.y / parts) * d->seeds_per_item);  // (event, first theta)
         const int e = __builtin_amdgcn_readfirstlane(it.x);
-        const EventView ev = begin_event(d, e, s_hits, s_poff, tile_cap);
+        const EventView ev = begin_event(d, e, s_hits, s_poff, tile_cap, part, parts);
         const int64_t sbase = d->seed_off[e];
         const int ns = (int)(d->seed_off[e + 1] - sbase);
         Cands<C> c;
@@ -862,6 +870,19 @@ __global__ __launch_bounds__(kBlock) void k_response(const Desc* __restrict__ d,
         }
         float acc[C][NA];
         event_pass<D, C, DERIV, false>(d, s_hits, s_poff, ev, c, zero_c, nc, acc);
+        if (parts > 1) {
+            // partial sums of this part of the hits; k_response_reduce adds the parts
+#pragma unroll
+            for (int j = 0; j < C; ++j) {
+                if (!active[j]) continue;
+                const int64_t gj = sbase + it.y + (wave * C + j) * kWave + lane;
+                float* dst = d->resp_partial + ((int64_t)part * d->resp_ntheta + gj) * NA;
+#pragma unroll
+                for (int a = 0; a < NA; ++a) dst[a] = (DERIV || a == 0) ? acc[j][a] : 0.0f;
+            }
+            __syncthreads();
+            continue;
+        }
 #pragma unroll
         for (int j = 0; j < C; ++j) {
             if (!active[j]) continue;
@@ -884,6 +905,56 @@ __global__ __launch_bounds__(kBlock) void k_response(const Desc* __restrict__ d,
             }
         }
         __syncthreads();
+    }
+}
+
+// Sum of the parts' accumulators in part order, then the outputs as in k_response.
+template <int D, bool DERIV>
+__global__ __launch_bounds__(256) void k_response_reduce(const Desc* __restrict__ d, int64_t n_theta)
+{
+    constexpr int NP = 2 * D;
+    constexpr int NA = Acc<D>::N;
+    if (d->cnt->err) return;
+    const float sig = d->resp_sigma;
+    const int parts = d->resp_parts;
+    for (int64_t gj = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; gj < n_theta;
+         gj += (int64_t)gridDim.x * blockDim.x) {
+        float acc[NA];
+#pragma unroll
+        for (int a = 0; a < NA; ++a) acc[a] = 0.0f;
+        for (int q = 0; q < parts; ++q) {
+            const float* src = d->resp_partial + ((int64_t)q * n_theta + gj) * NA;
+#pragma unroll
+            for (int a = 0; a < NA; ++a) acc[a] += src[a];
+        }
+        d->out_R[gj] = acc[0];
+        if (DERIV) {
+            float g[NP], H[NP][NP];
+            grad_hess<D, float>(acc, sig, g, H);
+            if (d->want & RETINA_WANT_GRAD) {
+#pragma unroll
+                for (int a = 0; a < NP; ++a) d->out_grad[gj * NP + a] = g[a];
+            }
+            if (d->want & RETINA_WANT_HESS) {
+                int q = 0;
+#pragma unroll
+                for (int a = 0; a < NP; ++a)
+#pragma unroll
+                    for (int b = a; b < NP; ++b) d->out_hess[gj * (NP * (NP + 1) / 2) + q++] = H[a][b];
+            }
+        }
+    }
+}
+
+void launch_response_reduce(const Desc* d, int D, bool deriv, int64_t n_theta, hipStream_t st)
+{
+    const dim3 g((unsigned)std::min<int64_t>((n_theta + 255) / 256, 4096)), b(256);
+    if (D == 2) {
+        if (deriv) hipLaunchKernelGGL((k_response_reduce<2, true>), g, b, 0, st, d, n_theta);
+        else hipLaunchKernelGGL((k_response_reduce<2, false>), g, b, 0, st, d, n_theta);
+    } else {
+        if (deriv) hipLaunchKernelGGL((k_response_reduce<1, true>), g, b, 0, st, d, n_theta);
+        else hipLaunchKernelGGL((k_response_reduce<1, false>), g, b, 0, st, d, n_theta);
     }
 }
 

@@ -74,6 +74,9 @@ struct Desc {
     const int64_t* in_theta_off; // NULL: single event
     uint32_t want;
     float resp_sigma;
+    int32_t resp_parts;          // hit parts per (event, theta block): 1, or a split for few items
+    int64_t resp_ntheta;
+    float* resp_partial;         // resp_parts x n_theta x accumulators (parts > 1)
     float* out_R;
     float* out_grad;
     float* out_hess;
@@ -86,7 +89,7 @@ struct Desc {
     // work items
     int32_t seeds_per_item;
     int32_t* order;              // events, longest first
-    int2* items;                 // (event, first seed within event)
+    int2* items;                 // (event, block * parts + part): seeds [block * seeds_per_item, ...)
     int64_t items_cap;
     // per-seed results (pool)
     double* s_theta;             // n_seeds * 4
@@ -127,6 +130,7 @@ struct HotConfig {
 int hot_seeds_per_item(const HotConfig& c);
 void launch_ascent(const Desc* d, int meas_dim, const HotConfig& c, hipStream_t st);
 void launch_response(const Desc* d, int meas_dim, const HotConfig& c, bool deriv, hipStream_t st);
+void launch_response_reduce(const Desc* d, int meas_dim, bool deriv, int64_t n_theta, hipStream_t st);
 size_t hot_lds_bytes(int meas_dim, const HotConfig& c);
 int hot_max_blocks_per_cu(int meas_dim, const HotConfig& c, bool ascent);
 

@@ -203,6 +203,7 @@ __global__ __launch_bounds__(1024) void k_plan(const Desc* __restrict__ d, int m
     __syncthreads();
     // items in rank order
     const int spi = d->seeds_per_item;
+    const int parts = mode == 2 && d->resp_parts > 1 ? d->resp_parts : 1;
     carry = 0;
     for (int64_t r0 = 0; r0 < E; r0 += 1024) {
         const int64_t r = r0 + t;
@@ -211,14 +212,14 @@ __global__ __launch_bounds__(1024) void k_plan(const Desc* __restrict__ d, int m
         if (r < E) {
             e = d->order[r];
             const int64_t ns = d->seed_off[e + 1] - d->seed_off[e];
-            nb = (ns + spi - 1) / spi;
+            nb = (ns + spi - 1) / spi * parts;
         }
         int64_t tot;
         const int64_t ex = block_excl_scan(nb, s_tmp, tot);
         if (r < E) {
             for (int64_t b = 0; b < nb; ++b) {
                 const int64_t it = carry + ex + b;
-                if (it < d->items_cap) d->items[it] = make_int2(e, (int)(b * spi));
+                if (it < d->items_cap) d->items[it] = make_int2(e, (int)b);
             }
         }
         carry += tot;
