@@ -66,6 +66,9 @@ def _load():
         lib.oracle_polish.restype = None
         lib.oracle_lattice.argtypes = [ctypes.c_int, ctypes.POINTER(Params), P]
         lib.oracle_lattice.restype = None
+        lib.oracle_grid_search.argtypes = [ctypes.c_int, ctypes.c_int, P, I64, P, P, P, ctypes.POINTER(Params),
+                                           D, D, P, I64, P, P, P, P, ctypes.c_int]
+        lib.oracle_grid_search.restype = I64
         _lib = lib
     return _lib
 
@@ -228,6 +231,36 @@ def polish(meas_dim, plane_z, x, y, plane, theta, sigma, n_iter):
     lib.oracle_polish(D, z.shape[0], _p(z), x.shape[0], _p(x), _p(y), _p(pl), n, _p(th),
                       float(sigma), int(n_iter), _p(R), _p(st), _p(pd))
     return th, R, st, pd.astype(bool)
+
+
+def grid_search(meas_dim, plane_z, x, y, plane, grid: dict, n_threads=0, want_grid=True):
+    """Grid-search Artificial Retina on ONE event (Section 2).  grid: n, lo, hi
+    (the lattice box, as the seed lattice), sigma, R0.  Returns dict(R_grid
+    [n0, n1] or None, cell [k], theta [k, n_par], R [k], members [k]), peaks in
+    cell order."""
+    lib = _load()
+    D = int(meas_dim)
+    P = Params()
+    P.lattice_n[:] = list(grid["n"])
+    P.lattice_lo[:] = list(grid["lo"])
+    P.lattice_hi[:] = list(grid["hi"])
+    z = _c(plane_z, np.float32)
+    x = _c(x, np.float32)
+    y = _c(y, np.float32) if D == 2 else None
+    pl = _c(plane, np.int32)
+    n0, n1 = int(grid["n"][0]), int(grid["n"][1])
+    G = np.zeros((n0, n1)) if want_grid else None
+    cap = n0 * n1
+    cell = np.zeros(max(cap, 1), np.int64)
+    th = np.zeros((max(cap, 1), 2 * D))
+    R = np.zeros(max(cap, 1))
+    mem = np.zeros(max(cap, 1), np.int32)
+    k = lib.oracle_grid_search(D, z.shape[0], _p(z), x.shape[0], _p(x), _p(y), _p(pl), ctypes.byref(P),
+                               float(grid["sigma"]), float(grid["R0"]), _p(G), cap, _p(cell), _p(th), _p(R),
+                               _p(mem), int(n_threads))
+    if k < 0:
+        raise ValueError("oracle_grid_search: bad geometry")
+    return dict(R_grid=G, cell=cell[:k].copy(), theta=th[:k].copy(), R=R[:k].copy(), members=mem[:k].copy())
 
 
 from .evaluate import match_tracks, efficiency  # noqa: E402  (plain-definition evaluation)

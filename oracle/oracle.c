@@ -25,6 +25,8 @@
  *   oracle_find_tracks     Algorithm 1 end to end over a batch of events
  *   oracle_polish          Newton polish of arbitrary points (used by the
  *                          brute-force grid cross-check)
+ *   oracle_grid_search     the grid-search Artificial Retina the method is
+ *                          compared with (Section 2, its four usual steps)
  *
  * Parameter layout: meas_dim D = 2 gives theta = (x0, y0, tx, ty); D = 1
  * gives theta = (x0, tx).  n_par = 2*D.  Hessians are returned packed upper
@@ -589,4 +591,86 @@ void oracle_lattice(int D, const oracle_params* P, double* out)
 {
     const int64_t n = (int64_t)P->lattice_n[0] * P->lattice_n[1];
     for (int64_t i = 0; i < n; ++i) lattice_seed(D, P, i, out + i * 2 * D);
+}
+
+/* ------------------------------------------------------------------------- */
+/* The plain Artificial Retina that the method replaces (Section 2, the four
+ * usual steps of grid-based AR algorithms):
+ *   1. a parameter grid: the cell-centred lattice of lattice_seed over the
+ *      box of P (same FP32 cell centres, slow index first);
+ *   2. the response of Eq. (1) at every cell, at bandwidth sigma;
+ *   3. clusters of activated cells: read as the strict local maxima of the
+ *      grid response over the up to 8 neighbouring cells inside the grid,
+ *      with R >= R0 (a cell whose neighbour has an equal response is not a
+ *      maximum);
+ *   4. one estimate per cluster: read as the response-weighted mean of the
+ *      cell centres of the maximum's 3 x 3 neighbourhood (cells inside the
+ *      grid only).
+ * One event.  Outputs: R_grid[n0 * n1] (may be NULL); the peaks in cell
+ * order: peak_cell, peak_theta (n_par doubles; the parameters the grid does
+ * not span are 0), peak_R (the maximum's response), peak_members (cells of
+ * the neighbourhood with R >= R0, the maximum included).  At most max_peaks
+ * are written; the return value is the number of peaks found.              */
+int64_t oracle_grid_search(int D, int n_planes, const float* plane_z, int64_t n_hits, const float* x,
+                           const float* y, const int32_t* plane, const oracle_params* P, double sigma,
+                           double R0, double* R_grid, int64_t max_peaks, int64_t* peak_cell,
+                           double* peak_theta, double* peak_R, int32_t* peak_members, int n_threads)
+{
+    const int np = 2 * D;
+    double pz[256];
+    if (n_planes > 256 || n_planes < 1) return -1;
+    for (int p = 0; p < n_planes; ++p) pz[p] = (double)plane_z[p];
+    const int64_t n0 = P->lattice_n[0], n1 = P->lattice_n[1], nc = n0 * n1;
+    double* G = (double*)malloc(sizeof(double) * (size_t)(nc > 0 ? nc : 1));
+    double *xd, *yd;
+    widen(D, n_hits, x, y, &xd, &yd);
+#ifdef _OPENMP
+    const int nt = n_threads > 0 ? n_threads : omp_get_max_threads();
+#pragma omp parallel for schedule(dynamic, 64) num_threads(nt)
+#endif
+    for (int64_t c = 0; c < nc; ++c) {
+        double th[MAXP];
+        lattice_seed(D, P, c, th);
+        G[c] = response_only(D, pz, n_hits, xd, yd, plane, th, sigma);
+    }
+    int64_t n_peaks = 0;
+    for (int64_t c = 0; c < nc; ++c) {
+        const int64_t i0 = c / n1, i1 = c % n1;
+        const double Rc = G[c];
+        if (!(Rc >= R0)) continue;
+        int is_max = 1;
+        for (int d0 = -1; d0 <= 1 && is_max; ++d0)
+            for (int d1 = -1; d1 <= 1; ++d1) {
+                const int64_t j0 = i0 + d0, j1 = i1 + d1;
+                if ((d0 == 0 && d1 == 0) || j0 < 0 || j0 >= n0 || j1 < 0 || j1 >= n1) continue;
+                if (!(Rc > G[j0 * n1 + j1])) { is_max = 0; break; }
+            }
+        if (!is_max) continue;
+        if (n_peaks < max_peaks) {
+            double wsum = 0.0, tsum[MAXP] = {0};
+            int32_t members = 0;
+            for (int d0 = -1; d0 <= 1; ++d0)
+                for (int d1 = -1; d1 <= 1; ++d1) {
+                    const int64_t j0 = i0 + d0, j1 = i1 + d1;
+                    if (j0 < 0 || j0 >= n0 || j1 < 0 || j1 >= n1) continue;
+                    const double w = G[j0 * n1 + j1];
+                    double th[MAXP];
+                    lattice_seed(D, P, j0 * n1 + j1, th);
+                    wsum += w;
+                    for (int a = 0; a < np; ++a) tsum[a] += w * th[a];
+                    if (w >= R0) ++members;
+                }
+            double tc[MAXP];
+            lattice_seed(D, P, c, tc);
+            peak_cell[n_peaks] = c;
+            for (int a = 0; a < np; ++a) peak_theta[n_peaks * np + a] = wsum > 0.0 ? tsum[a] / wsum : tc[a];
+            peak_R[n_peaks] = Rc;
+            peak_members[n_peaks] = members;
+        }
+        ++n_peaks;
+    }
+    if (R_grid) memcpy(R_grid, G, sizeof(double) * (size_t)nc);
+    free(xd);
+    free(G);
+    return n_peaks;
 }
