@@ -259,6 +259,40 @@ int retina_find_tracks(retina_ctx* ctx, const retina_geometry* geom, const retin
                        const retina_seed_out* seeds_out);
 
 /* ------------------------------------------------------------------------
+ * Grid-search Artificial Retina: the grid-based algorithm family that the
+ * optimisation method replaces (Section 2: response at every unit of a
+ * parameter grid, clusters of activated units, one estimate per cluster).
+ * ---------------------------------------------------------------------- */
+typedef struct {
+    int32_t n[2];           /* cells per dimension (>= 1, at most 2^26 cells) */
+    float lo[2], hi[2];     /* box (finite, lo < hi); cell centres as the seed
+                               lattice: FP32(lo + (i + 1/2)(hi - lo)/n), dimension
+                               0 slow; meas_dim 2: dims (tx, ty) at x0 = y0 = 0;
+                               meas_dim 1: dims (tx, x0) */
+    float sigma;            /* bandwidth of the grid response (> 0) */
+    float R0;               /* activation threshold (> 0) */
+} retina_grid;
+
+/* For every event: R of Eq. (1) at every cell centre (FP32, as
+ * retina_response); a peak is a cell whose R reaches R0 and exceeds the R of
+ * each of its (up to 8) neighbouring cells inside the grid (an equal
+ * neighbour: no peak).  Each peak gives one retina_track: the parameters the
+ * grid spans are the R-weighted mean of the centres of the peak's 3 x 3
+ * neighbourhood (cells inside the grid, FP64 sums), the others 0; R is the
+ * peak cell's response; n_members counts the neighbourhood's cells with
+ * R >= R0; seed_index is the peak's cell index; flags 0.
+ *   R_grid         n_events * n[0] * n[1] floats (event-major, cell index
+ *                  i0 * n[1] + i1), or NULL
+ *   tracks         capacity slots; event e's peaks are
+ *                  tracks[track_offsets[e] .. track_offsets[e+1]-1] in cell order
+ *   track_offsets  n_events+1
+ * All arrays in the hits' memory space.  RETINA_ERR_CAPACITY as
+ * retina_find_tracks (only track_offsets[n_events] is written). */
+int retina_grid_search(retina_ctx* ctx, const retina_geometry* geom, const retina_hits* hits,
+                       const retina_grid* grid, float* R_grid, retina_track* tracks, int64_t capacity,
+                       int64_t* track_offsets);
+
+/* ------------------------------------------------------------------------
  * Learned seed proposer (a workload extension, not part of the paper).
  *
  * An event's hits are binned into a 128 x 128 image over slope space

@@ -28,6 +28,7 @@ enum BufId {
     B_INX, B_INY, B_INPL, B_INOFF, B_INSEEDS, B_INSOFF, B_INTH, B_INTHOFF, B_OUTTR, B_OUTTOFF,
     B_OUTEVF, B_OUTSTH, B_OUTSR, B_OUTSFL, B_OUTSNR, B_OUTR, B_OUTG, B_OUTH,
     // learned proposer workspace
+    B_GRID, B_GRIDCNT, B_GRIDBASE,
     B_IMG, B_ACT1, B_ACT2, B_ACT3, B_LOGIT, B_HEADU, B_RESPPART, B_DZ4, B_DZ3, B_DZ2, B_DZ1, B_TGT, B_TGTIN, B_TGTOFF,
     B_DWPART, B_WT, B_LOSSPART, B_LOSS, B_BPART, B_PSCORE, B_PPIX, B_PCOUNT, B_PCONF, B_PFB,
     B_PSOFF, B_PSEEDS, B_OUTIMG, B_OUTLOGIT,
@@ -656,6 +657,118 @@ int retina_response(retina_ctx* c, const retina_geometry* g, const retina_hits* 
             HIP_TRY(c, hipMemcpyAsync(hess, d.out_hess, sizeof(float) * n_theta * NH, hipMemcpyDeviceToHost, c->stream));
         HIP_TRY(c, hipStreamSynchronize(c->stream));
     }
+    return RETINA_OK;
+}
+
+int retina_grid_search(retina_ctx* c, const retina_geometry* g, const retina_hits* h, const retina_grid* grid,
+                       float* R_grid, retina_track* tracks, int64_t capacity, int64_t* track_offsets)
+{
+    if (!c) return RETINA_ERR_INVALID_ARG;
+    c->err.clear();
+    int rc;
+    if ((rc = check_geometry(c, g)) || (rc = check_hits(c, g, h))) return rc;
+    if (!grid) return fail(c, RETINA_ERR_INVALID_ARG, "grid is NULL");
+    if (grid->n[0] < 1 || grid->n[1] < 1 || (int64_t)grid->n[0] * grid->n[1] > (1 << 26))
+        return fail(c, RETINA_ERR_INVALID_ARG, "grid n must be >= 1 with at most 2^26 cells");
+    for (int i = 0; i < 2; ++i)
+        if (!isfinite(grid->lo[i]) || !isfinite(grid->hi[i]) || !(grid->lo[i] < grid->hi[i]))
+            return fail(c, RETINA_ERR_INVALID_ARG, "grid box must be finite with lo < hi");
+    if (!(grid->sigma > 0.0f) || !isfinite(grid->sigma))
+        return fail(c, RETINA_ERR_INVALID_ARG, "grid sigma must be finite and > 0");
+    if (!(grid->R0 > 0.0f) || !isfinite(grid->R0)) return fail(c, RETINA_ERR_INVALID_ARG, "grid R0 must be finite and > 0");
+    if (capacity < 0) return fail(c, RETINA_ERR_INVALID_ARG, "capacity < 0");
+    if (!track_offsets) return fail(c, RETINA_ERR_INVALID_ARG, "track_offsets is NULL");
+    if (capacity > 0 && !tracks) return fail(c, RETINA_ERR_INVALID_ARG, "tracks is NULL");
+    DeviceGuard guard(c->device);
+    const int D = g->meas_dim;
+    const int64_t E = h->n_events;
+    const bool host = h->mem == RETINA_MEM_HOST;
+    if (host && !host_offsets_ok(h->event_offsets, E))
+        return fail(c, RETINA_ERR_INVALID_ARG, "event_offsets must start at 0 and be non-decreasing");
+    if (E == 0) {
+        if (host) track_offsets[0] = 0;
+        else HIP_TRY(c, hipMemsetAsync(track_offsets, 0, sizeof(int64_t), c->stream));
+        HIP_TRY(c, hipStreamSynchronize(c->stream));
+        return RETINA_OK;
+    }
+    int64_t n_hits;
+    if ((rc = read_i64(c, h->mem, h->event_offsets, E, &n_hits))) return rc;
+    if (n_hits < 0 || n_hits > 0x7FFFFFFF) return fail(c, RETINA_ERR_INVALID_ARG, "bad total hit count");
+    const int64_t n_cells = (int64_t)grid->n[0] * grid->n[1], n_theta = E * n_cells;
+    const int64_t nch = (n_cells + kGridChunk - 1) / kGridChunk;
+    if (E * nch > 0x7FFFFFFF) return fail(c, RETINA_ERR_INVALID_ARG, "batch too large for one grid search");
+
+    Desc& d = *c->h_desc;
+    memset(&d, 0, sizeof(Desc));
+    fill_geometry(d, g);
+    d.cnt = c->d_cnt;
+    if ((rc = stage_inputs(c, d, g, h, n_hits))) return rc;
+    const HotConfig hc = c->resp_cfg[D];
+    d.seeds_per_item = hot_seeds_per_item(hc);
+    const int64_t blocks = n_theta / d.seeds_per_item + E;
+    int parts = 1;
+    while (parts < kRespMaxParts && blocks * parts < (int64_t)hc.grid && n_hits / (E * parts * 2) >= kRespMinPartHits)
+        parts *= 2;
+    d.resp_parts = parts;
+    d.resp_ntheta = n_theta;
+    d.items_cap = (n_theta / d.seeds_per_item + E + 1) * parts;
+    if ((rc = ensure_t(c, B_ITEMS, (size_t)d.items_cap, &d.items))) return rc;
+    if (parts > 1 && (rc = ensure_t(c, B_RESPPART, (size_t)parts * n_theta * (D == 2 ? 16 : 8), &d.resp_partial)))
+        return rc;
+    d.want = RETINA_WANT_R;
+    d.resp_sigma = grid->sigma;
+    d.resp_grid = 1;
+    d.lattice_n[0] = grid->n[0];
+    d.lattice_n[1] = grid->n[1];
+    for (int i = 0; i < 2; ++i) { d.lattice_lo[i] = grid->lo[i]; d.lattice_hi[i] = grid->hi[i]; }
+    d.grid_R0 = grid->R0;
+    d.grid_chunks = (int32_t)nch;
+    if (!host && R_grid) d.out_R = R_grid;
+    else if ((rc = ensure_t(c, B_GRID, (size_t)n_theta, &d.out_R))) return rc;
+    if ((rc = ensure_t(c, B_GRIDCNT, (size_t)(E * nch), &d.grid_cnt)) ||
+        (rc = ensure_t(c, B_GRIDBASE, (size_t)(E * nch), &d.grid_base)))
+        return rc;
+    const int64_t host_cap = std::min<int64_t>(capacity, n_theta);
+    if (host) {
+        if ((rc = ensure_t(c, B_OUTTR, (size_t)std::max<int64_t>(host_cap, 1), &d.out_tracks)) ||
+            (rc = ensure_t(c, B_OUTTOFF, (size_t)E + 1, &d.out_track_off)))
+            return rc;
+        d.out_capacity = host_cap;
+    } else {
+        d.out_tracks = tracks;
+        d.out_capacity = capacity;
+        d.out_track_off = track_offsets;
+    }
+    if ((rc = upload_desc(c))) return rc;
+    prof_mark(c, 0);
+    launch_reset(c->d_desc, c->stream);
+    launch_stage(c->d_desc, (int)std::min<int64_t>((E + 3) / 4, (int64_t)c->n_cu * 8), c->stream);
+    prof_mark(c, 1);
+    launch_plan_grid(c->d_desc, c->stream);
+    prof_mark(c, 2);
+    launch_response(c->d_desc, D, hc, false, c->stream);
+    if (parts > 1) launch_response_reduce(c->d_desc, D, false, n_theta, c->stream);
+    prof_mark(c, 3);
+    launch_grid_peaks(c->d_desc, D, E * nch, c->stream);
+    prof_mark(c, 4);
+    HIP_TRY(c, hipGetLastError());
+    if ((rc = download_counters(c))) return rc;
+    prof_collect(c);
+    const uint32_t err = c->h_cnt->err;
+    const int64_t total = c->h_cnt->total_tracks;
+    if (err & ~kErrCapacity) return device_error(c, err);
+    if (err & kErrCapacity || total > capacity) {
+        if (host) track_offsets[E] = total;
+        return fail(c, RETINA_ERR_CAPACITY, "%lld peaks found, capacity %lld", (long long)total, (long long)capacity);
+    }
+    if (host) {
+        if (total)
+            HIP_TRY(c, hipMemcpyAsync(tracks, d.out_tracks, sizeof(retina_track) * total, hipMemcpyDeviceToHost, c->stream));
+        HIP_TRY(c, hipMemcpyAsync(track_offsets, d.out_track_off, sizeof(int64_t) * (E + 1), hipMemcpyDeviceToHost, c->stream));
+    }
+    if (R_grid && (host || R_grid != d.out_R))
+        HIP_TRY(c, hipMemcpyAsync(R_grid, d.out_R, sizeof(float) * n_theta, host ? hipMemcpyDeviceToHost : hipMemcpyDeviceToDevice, c->stream));
+    HIP_TRY(c, hipStreamSynchronize(c->stream));
     return RETINA_OK;
 }
 

@@ -526,6 +526,19 @@ __device__ __forceinline__ EventView begin_event(const Desc* __restrict__ d, int
 }
 
 // ------------------------------------------------------------------ ascent
+// Lattice point i of an event (dimension 0 slow): D = 2 gives (0, 0, tx, ty),
+// D = 1 gives (x0, tx) with tx along dimension 0.
+template <int D>
+__device__ __forceinline__ void lattice_point(const Desc* __restrict__ d, int i, float* th)
+{
+    const int n1 = d->lattice_n[1];
+    const int i0 = i / n1, i1 = i % n1;
+    const float v0 = lattice_coord(d->lattice_lo[0], d->lattice_hi[0], d->lattice_n[0], i0);
+    const float v1 = lattice_coord(d->lattice_lo[1], d->lattice_hi[1], n1, i1);
+    if constexpr (D == 2) { th[0] = 0.0f; th[1] = 0.0f; th[2] = v0; th[3] = v1; }
+    else { th[0] = v1; th[1] = v0; }
+}
+
 template <int D, int C>
 __global__ __launch_bounds__(kBlock) void k_ascent(const Desc* __restrict__ d, int tile_cap)
 {
@@ -579,14 +592,7 @@ __global__ __launch_bounds__(kBlock) void k_ascent(const Desc* __restrict__ d, i
 #pragma unroll
                 for (int a = 0; a < NP; ++a) th[j][a] = active[j] ? (float)s[a] : 0.0f;
             } else {
-                const int n1 = d->lattice_n[1];
-                const int i0 = sjc / n1, i1 = sjc % n1;
-                const double lo0 = d->lattice_lo[0], hi0 = d->lattice_hi[0];
-                const double lo1 = d->lattice_lo[1], hi1 = d->lattice_hi[1];
-                const float v0 = (float)(lo0 + ((double)i0 + 0.5) * (hi0 - lo0) / (double)d->lattice_n[0]);
-                const float v1 = (float)(lo1 + ((double)i1 + 0.5) * (hi1 - lo1) / (double)n1);
-                if constexpr (D == 2) { th[j][0] = 0.0f; th[j][1] = 0.0f; th[j][2] = v0; th[j][3] = v1; }
-                else { th[j][0] = v1; th[j][1] = v0; }
+                lattice_point<D>(d, sjc, th[j]);
             }
         }
 
@@ -863,9 +869,13 @@ __global__ __launch_bounds__(kBlock) void k_response(const Desc* __restrict__ d,
             const int sj = it.y + (wave * C + j) * kWave + lane;
             active[j] = sj < ns;
             float th[NP];
-            const float* src = d->in_theta + (sbase + (active[j] ? sj : 0)) * NP;
+            if (d->resp_grid) {
+                lattice_point<D>(d, active[j] ? sj : 0, th);
+            } else {
+                const float* src = d->in_theta + (sbase + (active[j] ? sj : 0)) * NP;
 #pragma unroll
-            for (int a = 0; a < NP; ++a) th[a] = active[j] ? src[a] : 0.0f;
+                for (int a = 0; a < NP; ++a) th[a] = active[j] ? src[a] : 0.0f;
+            }
             set_cand<D, C>(c, j, th);
         }
         float acc[C][NA];

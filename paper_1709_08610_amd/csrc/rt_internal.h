@@ -28,6 +28,13 @@ enum : uint32_t {
     kErrCapacity = 128u   // tracks do not fit the caller's array
 };
 
+// Cell-centred lattice coordinate i of n over [lo, hi]: FP32 rounding of
+// lo + (i + 1/2)(hi - lo)/n formed in FP64 (seed lattice and search grid alike).
+__host__ __device__ __forceinline__ float lattice_coord(float lo, float hi, int n, int64_t i)
+{
+    return (float)((double)lo + ((double)i + 0.5) * ((double)hi - (double)lo) / (double)n);
+}
+
 // device-side counters (one cache line each to avoid false sharing of atomics)
 struct Counters {
     uint32_t item;          // persistent work queue cursor
@@ -80,6 +87,12 @@ struct Desc {
     float* out_R;
     float* out_grad;
     float* out_hess;
+    // grid search: k_response takes its candidates from the lattice fields
+    int32_t resp_grid;
+    float grid_R0;
+    int32_t grid_chunks;         // peak-pass chunks per event
+    int32_t* grid_cnt;           // n_events * grid_chunks peak counts
+    int64_t* grid_base;          // n_events * grid_chunks first track slot of each chunk
     // method parameters
     int32_t n_sigma;
     float sigma[kMaxSigma];
@@ -121,6 +134,7 @@ void launch_reset(const Desc* d, hipStream_t st);
 void launch_stage(const Desc* d, int grid, hipStream_t st);
 void launch_plan_tracks(const Desc* d, hipStream_t st);
 void launch_plan_response(const Desc* d, hipStream_t st);
+void launch_plan_grid(const Desc* d, hipStream_t st);
 
 struct HotConfig {
     int cand;        // candidates per lane (1, 2)
@@ -137,5 +151,8 @@ int hot_max_blocks_per_cu(int meas_dim, const HotConfig& c, bool ascent);
 void launch_merge(const Desc* d, int meas_dim, int grid, hipStream_t st);
 void launch_finalize(const Desc* d, hipStream_t st);
 void launch_emit(const Desc* d, int meas_dim, int grid, hipStream_t st);
+
+constexpr int kGridChunk = 8192;     // cells per work-group of the peak passes
+void launch_grid_peaks(const Desc* d, int meas_dim, int64_t n_chunks_total, hipStream_t st);
 
 }  // namespace rt

@@ -118,7 +118,8 @@ __global__ __launch_bounds__(kBlock) void k_stage(const Desc* __restrict__ d)
 
 // ---------------------------------------------------------------- planning
 // Work list for the persistent kernels.  seed_mode 0: lattice (same count per
-// event); 1: explicit seeds (in_seed_off); 2: response thetas (in_theta_off).
+// event); 1: explicit seeds (in_seed_off); 2: response thetas (in_theta_off);
+// 3: response on the lattice (grid search; same count per event).
 __device__ __forceinline__ int64_t block_excl_scan(int64_t v, int64_t* s_tmp, int64_t& total)
 {
     // blockDim.x == 1024
@@ -203,7 +204,7 @@ __global__ __launch_bounds__(1024) void k_plan(const Desc* __restrict__ d, int m
     __syncthreads();
     // items in rank order
     const int spi = d->seeds_per_item;
-    const int parts = mode == 2 && d->resp_parts > 1 ? d->resp_parts : 1;
+    const int parts = (mode == 2 || mode == 3) && d->resp_parts > 1 ? d->resp_parts : 1;
     carry = 0;
     for (int64_t r0 = 0; r0 < E; r0 += 1024) {
         const int64_t r = r0 + t;
@@ -250,6 +251,11 @@ void launch_plan_tracks(const Desc* d, hipStream_t st)
 void launch_plan_response(const Desc* d, hipStream_t st)
 {
     hipLaunchKernelGGL(k_plan, dim3(1), dim3(1024), 0, st, d, 2);
+}
+
+void launch_plan_grid(const Desc* d, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_plan, dim3(1), dim3(1024), 0, st, d, 3);
 }
 
 }  // namespace rt

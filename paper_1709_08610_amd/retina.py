@@ -68,6 +68,11 @@ class Proposal(ctypes.Structure):
                 ("nms", ctypes.c_int32)]
 
 
+class Grid(ctypes.Structure):
+    _fields_ = [("n", ctypes.c_int32 * 2), ("lo", ctypes.c_float * 2), ("hi", ctypes.c_float * 2),
+                ("sigma", ctypes.c_float), ("R0", ctypes.c_float)]
+
+
 class SeedOut(ctypes.Structure):
     _fields_ = [("theta", ctypes.c_void_p), ("R", ctypes.c_void_p), ("flags", ctypes.c_void_p),
                 ("n_reval", ctypes.c_void_p), ("capacity", ctypes.c_int64)]
@@ -89,7 +94,7 @@ EXPORTS = ["retina_create", "retina_destroy", "retina_last_error", "retina_set_s
            "retina_model_create", "retina_model_save", "retina_model_load", "retina_model_free",
            "retina_model_get_params", "retina_model_set_params", "retina_model_step",
            "retina_train_step", "retina_model_forward", "retina_propose_seeds",
-           "retina_find_tracks_learned"]
+           "retina_find_tracks_learned", "retina_grid_search"]
 MODEL_PARAMS = 186625
 IMG = 128
 SLOPE_LO, SLOPE_HI = -0.35, 0.35
@@ -174,6 +179,9 @@ def load(path: str = LIB_PATH):
                                        ctypes.POINTER(Params), P, ctypes.c_int64, P, P,
                                        ctypes.POINTER(SeedOut)]
     lib.retina_find_tracks.restype = ctypes.c_int
+    lib.retina_grid_search.argtypes = [V, ctypes.POINTER(Geometry), ctypes.POINTER(Hits), ctypes.POINTER(Grid),
+                                       P, P, ctypes.c_int64, P]
+    lib.retina_grid_search.restype = ctypes.c_int
     _lib = lib
     return lib
 
@@ -418,6 +426,43 @@ class Context:
                        seed_nreval=snr[:n_seeds])
         return out
 
+    def retina_grid_search(self, meas_dim, plane_z, event_offsets, x, y, plane, grid: dict,
+                           capacity=None, want_grid=False):
+        """Grid-search Artificial Retina over the batch.  grid: n, lo, hi, sigma,
+        R0.  Returns dict(tracks (structured numpy array or uint8 tensor view),
+        track_offsets, R_grid ([E, n0, n1] or None))."""
+        g, zkeep = self._geometry(meas_dim, plane_z)
+        hits, keep, mem = self._hits(meas_dim, event_offsets, x, y, plane)
+        E = hits.n_events
+        n0, n1 = int(grid["n"][0]), int(grid["n"][1])
+        G = Grid((ctypes.c_int32 * 2)(n0, n1), (ctypes.c_float * 2)(*grid["lo"]),
+                 (ctypes.c_float * 2)(*grid["hi"]), float(grid["sigma"]), float(grid["R0"]))
+        cap = E * ((n0 * n1 + 1) // 2) if capacity is None else int(capacity)
+        if mem == MEM_HOST:
+            tracks = np.zeros(max(cap, 1), TRACK_DTYPE)
+            toff = np.zeros(E + 1, np.int64)
+            Rg = np.zeros((E, n0, n1), np.float32) if want_grid else None
+        else:
+            import torch
+            dev = x.device
+            self.set_stream(torch.cuda.current_stream(dev).cuda_stream)
+            tracks = torch.zeros(max(cap, 1) * 48, dtype=torch.uint8, device=dev)
+            toff = torch.zeros(E + 1, dtype=torch.int64, device=dev)
+            Rg = torch.zeros((E, n0, n1), dtype=torch.float32, device=dev) if want_grid else None
+        rc = self.lib.retina_grid_search(self.h, ctypes.byref(g), ctypes.byref(hits), ctypes.byref(G),
+                                         _ptr(Rg), _ptr(tracks), cap, _ptr(toff))
+        if rc == ERR_CAPACITY:
+            need = int(toff[-1]) if mem == MEM_HOST else int(toff[-1].item())
+            err = RetinaError(rc, self.lib.retina_last_error(self.h).decode())
+            err.required = need
+            raise err
+        self._check(rc)
+        out = dict(track_offsets=toff, R_grid=Rg)
+        if mem == MEM_HOST:
+            out["tracks"] = tracks[:int(toff[-1])]
+        else:
+            out["tracks_bytes"] = tracks
+        return out
 
     # ------------------------------------------------ learned seed proposer
     def retina_model_create(self, init_key: int) -> Model:
