@@ -223,6 +223,8 @@ def main():
     ap.add_argument("--cpu-seconds", type=float, default=12.0,
                     help="approximate length of each CPU oracle sample")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-budget", action="store_true",
+                    help="skip the grid-search vs multi-start comparison (c7 track-count scan)")
     ap.add_argument("--calib-copy-mib", type=int, default=0,
                     help="after the run, one plain device-to-device copy of this many MiB (a known-size "
                          "reference for hardware byte counters)")
@@ -350,6 +352,13 @@ def main():
     c1g = dict(c1, params=dict(c1["params"], lattice_n=[400, 400]))
     resp_c1 = response_throughput(ctx, retina, c1g, events.make_batch(c1, 1), torch, np)
 
+    # Section 3's comparison: multi-start at 1/3 and 1/10 of the grid search's
+    # measured cost, efficiency against the number of tracks (Fig. 3)
+    alpha = None
+    if not args.no_budget:
+        from paper_1709_08610_amd import budget
+        alpha = budget.run(ctx, log=log)
+
     cpu = cpu_l = None
     if not args.no_cpu_baseline:
         log("cpu baseline (oracle, %dx%d lattice)" % tuple(P["lattice_n"]))
@@ -410,6 +419,7 @@ def main():
                               "unit": "TFLOP/s", "frac": net_tflops / PEAK_BF16_TFLOPS,
                               "kernel": "binning + four conv layers + seed selection (network flops only)",
                               "flops_per_launch": FLOP_NET_EVENT * E},
+        "alpha_budget": alpha,
         "cpu_baseline": cpu,
         "cpu_baseline_learned": cpu_l,
     }

@@ -183,6 +183,25 @@ def make_batch(cfg: dict, n_events: Optional[int] = None, start: int = 0) -> Bat
     return batch_from_events(int(cfg["meas_dim"]), zp, evs)
 
 
+def scan_batches(cfg: dict, n_tracks=None, events_per_point: Optional[int] = None) -> list:
+    """Track-count scan of a config with a ``scan`` entry: for the k-th count N,
+    events k*m .. k*m+m-1 of the config's random stream, each with exactly N
+    tracks (m events per point).  Returns [(N, Batch), ...]."""
+    sc = cfg["scan"]
+    counts = list(sc["n_tracks"])
+    m = int(events_per_point or sc["events_per_point"])
+    zp = plane_z(cfg)
+    out = []
+    for k, n in enumerate(counts):
+        if n_tracks is not None and n not in n_tracks:
+            continue
+        c = json.loads(json.dumps(cfg))
+        c["tracks"]["count"] = {"kind": "fixed", "n": int(n)}
+        evs = [make_event(c, k * int(sc["events_per_point"]) + i, zp) for i in range(m)]
+        out.append((int(n), batch_from_events(int(cfg["meas_dim"]), zp, evs)))
+    return out
+
+
 def batch_from_events(meas_dim: int, zp: np.ndarray, evs: list) -> Batch:
     off = np.zeros(len(evs) + 1, np.int64)
     off[1:] = np.cumsum([e.n_hits for e in evs])

@@ -12,6 +12,9 @@ Each true track takes at most one found track, nearest pairs first.
               / found tracks
   eff_eps     Section 3's criterion: some found track within 1e-3 of the true
               slopes (max over the slope components)
+  fake_rate_eps  found tracks whose slopes are within 1e-3 of no true track
+              / found tracks (the same criterion, for estimates that carry
+              slopes only, such as the grid search's)
 """
 from __future__ import annotations
 
@@ -30,7 +33,7 @@ def event_quality(meas_dim, found, truth, truth_nhits, tol, z0, z1, eps=1e-3):
     pt = _endpoints(truth, meas_dim, z0, z1)
     nf, nt = pf.shape[0], pt.shape[0]
     rec = np.asarray(truth_nhits) >= 2
-    out = dict(n_true_rec=int(rec.sum()), n_found=nf, n_matched=0, n_fake=nf, n_clone=0, n_eps=0)
+    out = dict(n_true_rec=int(rec.sum()), n_found=nf, n_matched=0, n_fake=nf, n_clone=0, n_eps=0, n_fake_eps=nf)
     if nf == 0 or nt == 0:
         return out
     cheb = np.abs(pf[:, None, :] - pt[None, :, :]).max(axis=2)  # Chebyshev separation
@@ -46,14 +49,16 @@ def event_quality(meas_dim, found, truth, truth_nhits, tol, z0, z1, eps=1e-3):
     near_any = close.any(axis=1)
     slopes_f = np.asarray(found, np.float64).reshape(nf, -1)[:, meas_dim:]
     slopes_t = np.asarray(truth, np.float64).reshape(nt, -1)[:, meas_dim:]
-    eps_ok = (np.abs(slopes_f[:, None, :] - slopes_t[None, :, :]).max(axis=2) <= eps).any(axis=0)
+    eps_close = np.abs(slopes_f[:, None, :] - slopes_t[None, :, :]).max(axis=2) <= eps
+    eps_ok = eps_close.any(axis=0)
     out.update(n_matched=int((used_t & rec).sum()), n_fake=int((~near_any).sum()),
-               n_clone=int((near_any & ~used_f).sum()), n_eps=int((eps_ok & rec).sum()))
+               n_clone=int((near_any & ~used_f).sum()), n_eps=int((eps_ok & rec).sum()),
+               n_fake_eps=int((~eps_close.any(axis=1)).sum()))
     return out
 
 
 def batch_quality(meas_dim, tracks_theta, track_offsets, truth_list, truth_nhits_list, tol, z0, z1):
-    tot = dict(n_true_rec=0, n_found=0, n_matched=0, n_fake=0, n_clone=0, n_eps=0)
+    tot = dict(n_true_rec=0, n_found=0, n_matched=0, n_fake=0, n_clone=0, n_eps=0, n_fake_eps=0)
     off = np.asarray(track_offsets)
     for e in range(len(truth_list)):
         q = event_quality(meas_dim, tracks_theta[off[e]:off[e + 1]], truth_list[e], truth_nhits_list[e],
@@ -63,4 +68,5 @@ def batch_quality(meas_dim, tracks_theta, track_offsets, truth_list, truth_nhits
     rec = max(tot["n_true_rec"], 1)
     nf = max(tot["n_found"], 1)
     return dict(efficiency=tot["n_matched"] / rec, fake_rate=tot["n_fake"] / nf,
-                clone_rate=tot["n_clone"] / nf, eff_eps=tot["n_eps"] / rec, **tot)
+                clone_rate=tot["n_clone"] / nf, eff_eps=tot["n_eps"] / rec, fake_rate_eps=tot["n_fake_eps"] / nf,
+                **tot)

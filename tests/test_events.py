@@ -66,3 +66,25 @@ def test_c1_toy():
     assert ev.y is None and ev.truth.shape == (10, 2)
     assert ev.n_hits == 80 + 50
     assert np.all(np.abs(ev.truth[:, 1]) <= 1.0) and np.all(np.abs(ev.truth[:, 0]) <= 0.5)
+
+
+def test_track_count_scan():
+    """The c7 scan: every event of point N carries exactly N true tracks, the
+    points use disjoint event indices of one stream, and the geometry is c2's."""
+    cfg = events.load_config("c7")
+    pts = events.scan_batches(cfg, n_tracks=[50, 350], events_per_point=3)
+    assert [n for n, _ in pts] == [50, 350]
+    for n, b in pts:
+        assert b.n_events == 3 and all(len(t) == n for t in b.truth)
+        np.testing.assert_array_equal(b.plane_z, events.plane_z(events.load_config("c2")))
+    a = events.scan_batches(cfg, n_tracks=[50], events_per_point=2)[0][1]
+    np.testing.assert_array_equal(a.x, pts[0][1].x[: a.event_offsets[-1]])
+
+
+def test_quality_eps_fake_count():
+    """A found line is an eps-fake when no true track's slopes are within 1e-3."""
+    from paper_1709_08610_amd import metrics
+    truth = np.array([[0.0, 0.0, 0.1, 0.1], [0.0, 0.0, -0.2, 0.05]])
+    found = np.array([[0.5, 0.5, 0.1004, 0.0996], [0.0, 0.0, 0.2, 0.2]])
+    q = metrics.event_quality(2, found, truth, np.array([20, 20]), 0.06, 20.0, 750.0)
+    assert q["n_eps"] == 1 and q["n_fake_eps"] == 1 and q["n_matched"] == 0 and q["n_fake"] == 2
