@@ -260,8 +260,8 @@ int retina_find_tracks(retina_ctx* ctx, const retina_geometry* geom, const retin
 
 /* ------------------------------------------------------------------------
  * Grid-search Artificial Retina: the grid-based algorithm family that the
- * optimisation method replaces (Section 2: response at every unit of a
- * parameter grid, clusters of activated units, one estimate per cluster).
+ * optimisation method replaces (Section 2: the response at every cell of a
+ * parameter grid, groups of high-response cells, one estimate per group).
  * ---------------------------------------------------------------------- */
 typedef struct {
     int32_t n[2];           /* cells per dimension (>= 1, at most 2^26 cells) */

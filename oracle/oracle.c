@@ -599,7 +599,7 @@ void oracle_lattice(int D, const oracle_params* P, double* out)
  *   1. a parameter grid: the cell-centred lattice of lattice_seed over the
  *      box of P (same FP32 cell centres, slow index first);
  *   2. the response of Eq. (1) at every cell, at bandwidth sigma;
- *   3. clusters of activated cells: read as the strict local maxima of the
+ *   3. groups of high-response cells: read as the strict local maxima of the
  *      grid response over the up to 8 neighbouring cells inside the grid,
  *      with R >= R0 (a cell whose neighbour has an equal response is not a
  *      maximum);

@@ -1,7 +1,7 @@
 // Grid-search Artificial Retina (Section 2: the steps of the grid-based AR
 // algorithms that the optimisation method replaces).  The response at every
 // cell comes from k_response on lattice candidates; this file finds the
-// clusters of activated cells and estimates one track per cluster:
+// groups of cells with a high response and estimates one track per group:
 //   peak      a cell whose response reaches R0 and exceeds that of each of its
 //             (up to 8) neighbours inside the grid; an equal neighbour means
 //             no peak

@@ -1,6 +1,6 @@
 """Pins of the grid-search Artificial Retina oracle (Section 2: the response at
-every cell of a parameter grid, clusters of activated cells, one estimate per
-cluster), through what the geometry fixes: symmetric neighbourhoods, exact
+every cell of a parameter grid, groups of high-response cells, one estimate
+per group), through what the geometry fixes: symmetric neighbourhoods, exact
 ties, the value of the grid against the independently pinned response
 function, and the continuous maxima the multi-start procedure converges to."""
 import numpy as np
