@@ -60,7 +60,8 @@ typedef struct {
     float armijo_c1;
     float step_cap_sigmas;    /* cap on the scaled step, in units of sigma */
     float small_step_sigmas;  /* scaled Newton steps at or below this (in sigma) skip the line search */
-    int32_t n_slope_steps;    /* D = 2: the first n_slope_steps steps move (tx, ty) only */
+    int32_t n_slope_steps;    /* D = 2: the first n_slope_steps steps, counted on into the
+                                 polish iterations, move (tx, ty) only */
     float conv_tol;           /* converged iff |D delta| <= conv_tol*sigma_final on the last polish */
     float R0;                 /* response threshold */
     float d_merge;            /* cluster radius (end-plane distance) */
@@ -290,11 +291,13 @@ static void make_dscale(int D, double zref, double* ds)
 }
 
 /* FP64 Newton polish at sigma_final: n_iter times, if -H is positive definite
- * theta += (-H)^-1 g.  Reports R of the last evaluation, the scaled length of
- * the last step and whether -H was positive definite there. */
+ * theta += (-H)^-1 g; the first slope_iters iterations (D = 2) solve on the
+ * slope block only, offsets held.  Reports R of the last evaluation, the
+ * scaled length of the last step and whether -H (or its slope block) was
+ * positive definite there. */
 static void polish_one(int D, const double* pz, const double* ds, int64_t n, const double* x,
                        const double* y, const int32_t* pl, double* th, double sigma, int n_iter,
-                       double* R_out, double* step_out, int* pd_out)
+                       int slope_iters, double* R_out, double* step_out, int* pd_out)
 {
     const int np = 2 * D;
     double R = 0.0, step = INFINITY;
@@ -302,8 +305,17 @@ static void polish_one(int D, const double* pz, const double* ds, int64_t n, con
     for (int it = 0; it < n_iter; ++it) {
         double g[MAXP], H[MAXP * MAXP], A[MAXP * MAXP], dl[MAXP];
         response_one(D, pz, n, x, y, pl, th, sigma, &R, g, H);
-        for (int a = 0; a < np * np; ++a) A[a] = -H[a];
-        pd = chol_solve(np, A, g, dl);
+        if (D == 2 && it < slope_iters) {
+            /* offsets held: the Newton system of the slope block */
+            const double As[4] = {-H[2 * np + 2], -H[2 * np + 3], -H[3 * np + 2], -H[3 * np + 3]};
+            const double gs[2] = {g[2], g[3]};
+            double ds2[2];
+            pd = chol_solve(2, As, gs, ds2);
+            dl[0] = 0.0; dl[1] = 0.0; dl[2] = ds2[0]; dl[3] = ds2[1];
+        } else {
+            for (int a = 0; a < np * np; ++a) A[a] = -H[a];
+            pd = chol_solve(np, A, g, dl);
+        }
         if (pd) {
             double s = 0.0;
             for (int a = 0; a < np; ++a) {
@@ -383,7 +395,10 @@ static void ascend_one(int D, const double* pz, double zref, int64_t n, const do
     }
     double R, step;
     int pd;
-    polish_one(D, pz, ds, n, x, y, pl, th, (double)P->sigma_final, P->n_polish, &R, &step, &pd);
+    /* n_slope_steps counts the steps, then the polish iterations: a count past
+     * the steps holds the offsets in that many polish iterations too */
+    const int slope_iters = P->n_slope_steps > n_steps ? P->n_slope_steps - n_steps : 0;
+    polish_one(D, pz, ds, n, x, y, pl, th, (double)P->sigma_final, P->n_polish, slope_iters, &R, &step, &pd);
     if (!pd) flags |= OR_NOT_PD;
     if (pd && step <= (double)P->conv_tol * (double)P->sigma_final) flags |= OR_CONVERGED;
     *R_out = R;
@@ -580,7 +595,7 @@ void oracle_polish(int D, int n_planes, const float* plane_z, int64_t n_hits, co
 #pragma omp parallel for schedule(dynamic, 4)
     for (int64_t i = 0; i < n_theta; ++i) {
         int pd;
-        polish_one(D, pz, ds, n_hits, xd, yd, plane, theta + i * np, sigma, n_iter, &R_out[i], &step_out[i], &pd);
+        polish_one(D, pz, ds, n_hits, xd, yd, plane, theta + i * np, sigma, n_iter, 0, &R_out[i], &step_out[i], &pd);
         pd_out[i] = pd;
     }
     free(xd);

@@ -81,6 +81,7 @@ class Batch:
     label: np.ndarray            # int32 [total_hits]
     truth: list                  # per event float64 arrays
     truth_nhits: list            # per event int32 arrays
+    index: Optional[list] = None  # event indices in the config's stream (scan batches)
 
     @property
     def n_events(self) -> int:
@@ -105,8 +106,88 @@ def _draw_param(rng, spec, n):
     raise ValueError("unknown distribution %r" % spec["kind"])
 
 
+def _make_svelo_event(cfg: dict, idx: int, zp: np.ndarray) -> Event:
+    """The simplified VELO of Section 3: disk layers perpendicular to z, tracks
+    from the origin with pseudo-rapidity eta ~ U[eta_lo, eta_hi] (polar angle
+    theta = 2 atan(exp(-eta))) and azimuth phi ~ U[0, 2 pi), direction
+    (sin theta cos phi, sin theta sin phi, cos theta); a layer records the
+    crossing with probability p_hit when it lies on the disk (r_inner <= r <=
+    r_outer), smeared by N(0, sd) in x and y.  Particles are drawn until
+    `count` of them leave at least n_min hits; the hits of the others are kept
+    as noise (label -1), as are Poisson(noise_mean) hits uniform in area on a
+    uniformly chosen layer.  Truth: (x0, y0, tx, ty) = (0, 0, tan theta cos phi,
+    tan theta sin phi) of the reconstructible tracks."""
+    rng = _rng(cfg, idx)
+    sv = cfg["svelo"]
+    z64 = zp.astype(np.float64)
+    n_planes = zp.shape[0]
+    target = int(cfg["tracks"]["count"]["n"])
+    r_in, r_out = float(sv["r_inner"]), float(sv["r_outer"])
+    sd, p_hit, n_min = float(sv["smear_sd"]), float(sv["p_hit"]), int(sv["n_min"])
+    truth, nh, hx, hy, hp, hl = [], [], [], [], [], []
+    n_rec = 0
+    while n_rec < target:
+        m = 2 * (target - n_rec) + 16   # one chunk of particles, consumed in order
+        eta = rng.uniform(sv["eta"][0], sv["eta"][1], m)
+        phi = rng.uniform(0.0, 2.0 * np.pi, m)
+        ran = rng.random((m, n_planes))
+        ex = rng.normal(0.0, sd, (m, n_planes))
+        ey = rng.normal(0.0, sd, (m, n_planes))
+        tt = np.tan(2.0 * np.arctan(np.exp(-eta)))
+        tx, ty = tt * np.cos(phi), tt * np.sin(phi)
+        r = tt[:, None] * z64[None, :]
+        hit = (r >= r_in) & (r <= r_out) & (ran < p_hit)
+        for k in range(m):
+            if n_rec == target:
+                break
+            lay = np.nonzero(hit[k])[0]
+            rec = lay.size >= n_min
+            hx.append(tx[k] * z64[lay] + ex[k, lay])
+            hy.append(ty[k] * z64[lay] + ey[k, lay])
+            hp.append(lay.astype(np.int32))
+            hl.append(np.full(lay.size, n_rec if rec else -1, np.int32))
+            if rec:
+                truth.append((0.0, 0.0, tx[k], ty[k]))
+                nh.append(lay.size)
+                n_rec += 1
+    n_noise = int(rng.poisson(float(sv["noise_mean"])))
+    nr = np.sqrt(rng.uniform(r_in * r_in, r_out * r_out, n_noise))
+    na = rng.uniform(0.0, 2.0 * np.pi, n_noise)
+    hx.append(nr * np.cos(na))
+    hy.append(nr * np.sin(na))
+    hp.append(rng.integers(0, n_planes, n_noise).astype(np.int32))
+    hl.append(np.full(n_noise, -1, np.int32))
+    x, y = np.concatenate(hx), np.concatenate(hy)
+    plane, label = np.concatenate(hp).astype(np.int32), np.concatenate(hl).astype(np.int32)
+    perm = rng.permutation(x.shape[0])
+    return Event(x=x[perm].astype(np.float32), y=y[perm].astype(np.float32), plane=plane[perm],
+                 label=label[perm], truth=np.array(truth, np.float64).reshape(-1, 4),
+                 truth_nhits=np.array(nh, np.int32))
+
+
+def prior_seeds(cfg: dict, n: int, events_idx) -> tuple:
+    """Algorithm 1's first step for the simplified VELO: n initial guesses per
+    event drawn from the track prior (eta ~ U[eta_lo, eta_hi], phi ~ U[0, 2 pi)),
+    as lines from the origin (0, 0, tan theta cos phi, tan theta sin phi).  The
+    draws of event index i come from their own Philox stream keyed by
+    (seed key, i).  Returns (seeds [len(events_idx) * n, 4] float64, offsets)."""
+    sv = cfg["svelo"]
+    out = np.zeros((len(events_idx) * n, 4))
+    for k, i in enumerate(events_idx):
+        key = np.array([int(cfg["seed_key"]), int(i)], dtype=np.uint64)
+        rng = np.random.Generator(np.random.Philox(key=key))
+        eta = rng.uniform(sv["eta"][0], sv["eta"][1], n)
+        phi = rng.uniform(0.0, 2.0 * np.pi, n)
+        tt = np.tan(2.0 * np.arctan(np.exp(-eta)))
+        out[k * n:(k + 1) * n, 2] = tt * np.cos(phi)
+        out[k * n:(k + 1) * n, 3] = tt * np.sin(phi)
+    return out, np.arange(len(events_idx) + 1, dtype=np.int64) * n
+
+
 def make_event(cfg: dict, idx: int, zp: Optional[np.ndarray] = None) -> Event:
     """Generate event ``idx`` of workload ``cfg`` (deterministic in (key, idx))."""
+    if cfg.get("kind") == "svelo":
+        return _make_svelo_event(cfg, idx, plane_z(cfg) if zp is None else zp)
     rng = _rng(cfg, idx)
     D = int(cfg["meas_dim"])
     if zp is None:
@@ -197,8 +278,10 @@ def scan_batches(cfg: dict, n_tracks=None, events_per_point: Optional[int] = Non
             continue
         c = json.loads(json.dumps(cfg))
         c["tracks"]["count"] = {"kind": "fixed", "n": int(n)}
-        evs = [make_event(c, k * int(sc["events_per_point"]) + i, zp) for i in range(m)]
-        out.append((int(n), batch_from_events(int(cfg["meas_dim"]), zp, evs)))
+        idx = [k * int(sc["events_per_point"]) + i for i in range(m)]
+        b = batch_from_events(int(cfg["meas_dim"]), zp, [make_event(c, i, zp) for i in idx])
+        b.index = idx
+        out.append((int(n), b))
     return out
 
 
