@@ -354,10 +354,12 @@ def main():
 
     # Section 3's comparison: multi-start at 1/3 and 1/10 of the grid search's
     # measured cost, efficiency against the number of tracks (Fig. 3)
-    alpha = None
+    alpha = alpha_sv = None
     if not args.no_budget:
         from paper_1709_08610_amd import budget
-        alpha = budget.run(ctx, log=log)
+        alpha = budget.run(ctx, events.load_config("c7"), log=log)
+        # the same on the paper's simplified VELO (tracks from the origin, prior-drawn seeds)
+        alpha_sv = budget.run(ctx, events.load_config("c8"), log=log)
 
     cpu = cpu_l = None
     if not args.no_cpu_baseline:
@@ -420,6 +422,7 @@ def main():
                               "kernel": "binning + four conv layers + seed selection (network flops only)",
                               "flops_per_launch": FLOP_NET_EVENT * E},
         "alpha_budget": alpha,
+        "alpha_budget_svelo": alpha_sv,
         "cpu_baseline": cpu,
         "cpu_baseline_learned": cpu_l,
     }

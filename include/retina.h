@@ -109,7 +109,10 @@ typedef struct {
     float step_cap_sigmas;      /* scaled step capped at step_cap_sigmas * sigma */
     float small_step_sigmas;    /* Newton steps (no negative curvature) with scaled length
                                    <= small_step_sigmas * sigma are taken without a search */
-    int32_t n_slope_steps;      /* meas_dim 2: the first n_slope_steps steps move only (tx, ty) */
+    int32_t n_slope_steps;      /* meas_dim 2: the first n_slope_steps steps move only (tx, ty);
+                                   the count runs on into the polish iterations, so a value
+                                   >= steps + n_polish holds the offsets at their seed values
+                                   throughout (lines through the origin) */
     float conv_tol;             /* converged iff last polish step <= conv_tol * sigma_final */
     float R0;                   /* keep clusters whose best response is >= R0 */
     float d_merge;              /* cluster radius: largest in-plane separation over the two

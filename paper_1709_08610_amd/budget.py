@@ -16,11 +16,14 @@ Both are throughput figures: each track count is a batch of hundreds of events,
 so that even the smallest seed lattice keeps the GPU busy (a few events with a
 few hundred seeds each would time the latency of one seed's twelve sequential
 steps, not the cost the formula counts).
-The seeds form a square lattice of floor(sqrt(n)) per side over the prior box.
-Workload: the c7 track-count scan (c2 geometry, 50..350 tracks per event).
-Efficiency is counted with the paper's criterion (a found track within 1e-3 of
-the true slopes, eff_eps) and, for the multi-start, also with the end-plane
-criterion of the benchmark (the grid estimates carry slopes only).
+Seeds: a square lattice of floor(sqrt(n)) per side over the prior box, or,
+for a config with "seeding": "prior", round(n) draws per event from the track
+prior (Algorithm 1's first step), passed in as explicit seeds.
+Workloads: the c7 track-count scan (c2 geometry, 50..350 tracks per event;
+efficiency by the paper's 1e-3 criterion on the slopes, eff_eps) and the c8
+scan on the simplified VELO of Section 3 (tracks from the origin; 1e-3 rad
+between directions, eff_angle).  The multi-start is also scored with the
+end-plane criterion of the benchmark (the grid estimates carry slopes only).
 """
 from __future__ import annotations
 
@@ -76,9 +79,21 @@ def run(ctx, cfg=None, counts=None, events_per_point=None, reps=3, log=print):
         E = b.n_events
         return ctx.retina_grid_search(2, b.plane_z, *d, G, capacity=E * 4096)
 
-    def ms_call(b, d, side):
-        Pn = dict(P, lattice_n=[side, side])
-        return ctx.retina_find_tracks(2, b.plane_z, *d, Pn, capacity=b.n_events * side * side)
+    prior = cfg.get("seeding") == "prior"
+    qkey = cfg.get("quality_key", "eff_eps")
+
+    def seeds_for(b, n):
+        """(find_tracks keyword arguments, seeds per event) for about n seeds per event."""
+        if prior:
+            k = max(1, int(round(n)))
+            s, o = events.prior_seeds(cfg, k, b.index)
+            return dict(params=P, seeds=tin(s), seed_offsets=tin(o)), k
+        side = max(1, int(math.floor(math.sqrt(n))))
+        return dict(params=dict(P, lattice_n=[side, side])), side * side
+
+    def ms_call(b, d, kw, k):
+        return ctx.retina_find_tracks(2, b.plane_z, *d, kw["params"], seeds=kw.get("seeds"),
+                                      seed_offsets=kw.get("seed_offsets"), capacity=b.n_events * k)
 
     def quality(b, theta, toff):
         return metrics.batch_quality(2, theta, toff, b.truth, b.truth_nhits, cfg["match_tol"], z0, z1)
@@ -89,34 +104,37 @@ def run(ctx, cfg=None, counts=None, events_per_point=None, reps=3, log=print):
     t_grid = _median_time(lambda: grid_call(b_mid, d_mid), reps)
     T0 = t_grid / (E * n_grid)
     side_ref = int(cfg.get("calibration_lattice", 48))
-    t_ref = _median_time(lambda: ms_call(b_mid, d_mid, side_ref), reps)
-    C0 = t_ref / (E * side_ref * side_ref * q) / T0
-    log("alpha budget: n_grid %d, q %d, T0 %.3g ns per cell, C0 %.2f (lattice %d at %d tracks)"
-        % (n_grid, q, T0 * 1e9, C0, side_ref, n_mid))
-    out = dict(workload=cfg["description"], events_per_point=E, grid=G, n_grid=n_grid, q=q,
-               T0_ns=T0 * 1e9, C0=C0, C0_calibration=dict(n_tracks=n_mid, lattice=side_ref),
+    kw_ref, k_ref = seeds_for(b_mid, side_ref * side_ref)
+    t_ref = _median_time(lambda: ms_call(b_mid, d_mid, kw_ref, k_ref), reps)
+    C0 = t_ref / (E * k_ref * q) / T0
+    log("alpha budget (%s): n_grid %d, q %d, T0 %.3g ns per cell, C0 %.2f (%d seeds at %d tracks)"
+        % (cfg["name"], n_grid, q, T0 * 1e9, C0, k_ref, n_mid))
+    out = dict(workload="%s: %s" % (cfg["name"], cfg["description"]), events_per_point=E, grid=G, n_grid=n_grid,
+               q=q, T0_ns=T0 * 1e9, C0=C0, C0_calibration=dict(n_tracks=n_mid, seeds=k_ref),
+               seeding="prior draws" if prior else "lattice", efficiency_criterion=qkey,
                paper=dict(C0=30, q=3), points=[])
     for n_tr, b, d in pts:
         E = b.n_events
         t_g = _median_time(lambda: grid_call(b, d), reps)
         qg = quality(b, *_tracks(grid_call(b, d), E))
         row = dict(n_tracks=n_tr, hits_per_event=float(np.mean(np.diff(b.event_offsets))),
-                   grid=dict(ms_per_event=1e3 * t_g / E, eff_eps=qg["eff_eps"], fake_rate_eps=qg["fake_rate_eps"],
+                   grid=dict(ms_per_event=1e3 * t_g / E, eff=qg[qkey], eff_eps=qg["eff_eps"],
+                             eff_angle=qg["eff_angle"], fake_rate_eps=qg["fake_rate_eps"],
                              peaks_per_event=qg["n_found"] / E))
         for a in cfg["alphas"]:
             n = a * n_grid / (C0 * q)
-            side = max(1, int(math.floor(math.sqrt(n))))
-            t_m = _median_time(lambda: ms_call(b, d, side), reps)
-            qm = quality(b, *_tracks(ms_call(b, d, side), E))
-            row["alpha_%.4g" % a] = dict(alpha=a, seeds=side * side, seeds_formula=n, lattice=side,
-                                         ms_per_event=1e3 * t_m / E, cost_ratio=t_m / t_g, eff_eps=qm["eff_eps"],
-                                         efficiency=qm["efficiency"], fake_rate=qm["fake_rate"],
-                                         fake_rate_eps=qm["fake_rate_eps"])
+            kw, k = seeds_for(b, n)
+            t_m = _median_time(lambda: ms_call(b, d, kw, k), reps)
+            qm = quality(b, *_tracks(ms_call(b, d, kw, k), E))
+            row["alpha_%.4g" % a] = dict(alpha=a, seeds=k, seeds_formula=n, ms_per_event=1e3 * t_m / E,
+                                         cost_ratio=t_m / t_g, eff=qm[qkey], eff_eps=qm["eff_eps"],
+                                         eff_angle=qm["eff_angle"], efficiency=qm["efficiency"],
+                                         fake_rate=qm["fake_rate"], fake_rate_eps=qm["fake_rate_eps"])
         out["points"].append(row)
-        log("  %3d tracks: grid eff_eps %.3f (%.3f ms/event) | %s" % (
-            n_tr, qg["eff_eps"], 1e3 * t_g / E,
-            " | ".join("alpha %.3g: %d seeds, eff_eps %.3f, eff %.3f, cost %.2f" % (
-                r["alpha"], r["seeds"], r["eff_eps"], r["efficiency"], r["cost_ratio"])
+        log("  %3d tracks: grid %s %.3f (%.3f ms/event) | %s" % (
+            n_tr, qkey, qg[qkey], 1e3 * t_g / E,
+            " | ".join("alpha %.3g: %d seeds, %s %.3f, eff %.3f, cost %.2f" % (
+                r["alpha"], r["seeds"], qkey, r["eff"], r["efficiency"], r["cost_ratio"])
                 for k, r in row.items() if k.startswith("alpha_"))))
     return out
 
@@ -126,12 +144,13 @@ def main(argv=None):
     ap.add_argument("--events", type=int, default=None, help="events per track count (default: the config's)")
     ap.add_argument("--counts", type=int, nargs="*", default=None)
     ap.add_argument("--reps", type=int, default=3)
+    ap.add_argument("--config", default="c7", help="c7 (c2 geometry) or c8 (simplified VELO)")
     a = ap.parse_args(argv)
     import torch
     if not torch.cuda.is_available():
         raise SystemExit("budget needs a GPU")
     ctx = retina.Context(0)
-    out = run(ctx, counts=a.counts, events_per_point=a.events, reps=a.reps,
+    out = run(ctx, events.load_config(a.config), counts=a.counts, events_per_point=a.events, reps=a.reps,
               log=lambda m: print(m, file=sys.stderr, flush=True))
     print(json.dumps(out))
 

@@ -765,6 +765,8 @@ __global__ __launch_bounds__(kBlock) void k_ascent(const Desc* __restrict__ d, i
         double step[C];
         bool pd[C];
         for (int it2 = 0; it2 < d->n_polish; ++it2) {
+            // n_slope_steps counts on from the steps into the polish iterations
+            const bool slope_pol = D == 2 && n_steps + it2 < d->n_slope_steps;
             Cands<C> ch, cl;
 #pragma unroll
             for (int j = 0; j < C; ++j) {
@@ -787,6 +789,20 @@ __global__ __launch_bounds__(kBlock) void k_ascent(const Desc* __restrict__ d, i
                 for (int a = 0; a < NP; ++a)
 #pragma unroll
                     for (int b = 0; b < NP; ++b) A[a][b] = -H[a][b];
+                if (slope_pol) {
+                    // offsets held: identity on the offset block and a zero offset
+                    // gradient leave the Newton system of the slope block (its
+                    // Cholesky factor is the block's own) and zero offset steps
+#pragma unroll
+                    for (int a = 0; a < NP; ++a)
+#pragma unroll
+                        for (int b = 0; b < 2; ++b) {
+                            A[a][b] = a == b ? 1.0 : 0.0;
+                            A[b][a] = a == b ? 1.0 : 0.0;
+                        }
+                    g[0] = 0.0;
+                    g[1] = 0.0;
+                }
                 pd[j] = chol_solve<NP>(A, g, dl);
                 Rfin[j] = acc[j][0];
                 if (pd[j]) {

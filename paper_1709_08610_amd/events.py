@@ -170,7 +170,8 @@ def prior_seeds(cfg: dict, n: int, events_idx) -> tuple:
     event drawn from the track prior (eta ~ U[eta_lo, eta_hi], phi ~ U[0, 2 pi)),
     as lines from the origin (0, 0, tan theta cos phi, tan theta sin phi).  The
     draws of event index i come from their own Philox stream keyed by
-    (seed key, i).  Returns (seeds [len(events_idx) * n, 4] float64, offsets)."""
+    (seed key, i); slopes are rounded to FP32, the precision the GPU path starts
+    from.  Returns (seeds [len(events_idx) * n, 4] float64, offsets)."""
     sv = cfg["svelo"]
     out = np.zeros((len(events_idx) * n, 4))
     for k, i in enumerate(events_idx):
@@ -179,8 +180,8 @@ def prior_seeds(cfg: dict, n: int, events_idx) -> tuple:
         eta = rng.uniform(sv["eta"][0], sv["eta"][1], n)
         phi = rng.uniform(0.0, 2.0 * np.pi, n)
         tt = np.tan(2.0 * np.arctan(np.exp(-eta)))
-        out[k * n:(k + 1) * n, 2] = tt * np.cos(phi)
-        out[k * n:(k + 1) * n, 3] = tt * np.sin(phi)
+        out[k * n:(k + 1) * n, 2] = (tt * np.cos(phi)).astype(np.float32)
+        out[k * n:(k + 1) * n, 3] = (tt * np.sin(phi)).astype(np.float32)
     return out, np.arange(len(events_idx) + 1, dtype=np.int64) * n
 
 
