@@ -41,7 +41,7 @@ class Params(ctypes.Structure):
                 ("conv_tol", ctypes.c_float),
                 ("R0", ctypes.c_float), ("d_merge", ctypes.c_float),
                 ("lattice_n", ctypes.c_int32 * 2), ("lattice_lo", ctypes.c_float * 2),
-                ("lattice_hi", ctypes.c_float * 2)]
+                ("lattice_hi", ctypes.c_float * 2), ("update", ctypes.c_int32)]
 
 
 def _load():
@@ -69,6 +69,8 @@ def _load():
         lib.oracle_grid_search.argtypes = [ctypes.c_int, ctypes.c_int, P, I64, P, P, P, ctypes.POINTER(Params),
                                            D, D, P, I64, P, P, P, P, ctypes.c_int]
         lib.oracle_grid_search.restype = I64
+        lib.oracle_bfgs_update.argtypes = [ctypes.c_int, P, P, P]
+        lib.oracle_bfgs_update.restype = None
         _lib = lib
     return _lib
 
@@ -79,6 +81,9 @@ def _p(a):
 
 def _c(a, dt):
     return None if a is None else np.ascontiguousarray(a, dtype=dt)
+
+
+UPDATE_RULES = {"newton": 0, "gradient": 1, "bfgs": 2}
 
 
 def make_params(p: dict):
@@ -101,6 +106,7 @@ def make_params(p: dict):
     P.lattice_n[:] = list(p["lattice_n"])
     P.lattice_lo[:] = list(p["lattice_lo"])
     P.lattice_hi[:] = list(p["lattice_hi"])
+    P.update = UPDATE_RULES[p.get("update", "newton")]
     return P, sig
 
 
@@ -231,6 +237,15 @@ def polish(meas_dim, plane_z, x, y, plane, theta, sigma, n_iter):
     lib.oracle_polish(D, z.shape[0], _p(z), x.shape[0], _p(x), _p(y), _p(pl), n, _p(th),
                       float(sigma), int(n_iter), _p(R), _p(st), _p(pd))
     return th, R, st, pd.astype(bool)
+
+
+def bfgs_update(B, s, y):
+    """The oracle's BFGS inverse-Hessian update (returns a new matrix)."""
+    lib = _load()
+    Bn = np.array(B, dtype=np.float64, copy=True)
+    n = Bn.shape[0]
+    lib.oracle_bfgs_update(n, _p(Bn), _p(np.ascontiguousarray(s, np.float64)), _p(np.ascontiguousarray(y, np.float64)))
+    return Bn
 
 
 def grid_search(meas_dim, plane_z, x, y, plane, grid: dict, n_threads=0, want_grid=True):

@@ -23,6 +23,7 @@
  *                          highest response per cluster above R0
  *                          (Algorithm 1, last two steps)
  *   oracle_find_tracks     Algorithm 1 end to end over a batch of events
+ *   oracle_bfgs_update     the quasi-Newton update of the BFGS rule
  *   oracle_polish          Newton polish of arbitrary points (used by the
  *                          brute-force grid cross-check)
  *   oracle_grid_search     the grid-search Artificial Retina the method is
@@ -68,6 +69,7 @@ typedef struct {
     int32_t lattice_n[2];
     float lattice_lo[2];
     float lattice_hi[2];
+    int32_t update;           /* 0 truncated Newton, 1 normalised gradient, 2 BFGS */
 } oracle_params;
 
 enum { OR_CONVERGED = 1, OR_STALLED = 2, OR_NOT_PD = 4, OR_NEGCURV = 8 };
@@ -332,12 +334,36 @@ static void polish_one(int D, const double* pz, const double* ds, int64_t n, con
     *pd_out = pd;
 }
 
+/* BFGS update of an inverse-Hessian model B (n x n, row-major, in place)
+ * with step s and gradient change y, s.y > 0 (Nocedal & Wright, Ch. 6):
+ * B <- (I - rho s y^T) B (I - rho y s^T) + rho s s^T,  rho = 1 / (y.s). */
+void oracle_bfgs_update(int n, double* B, const double* s, const double* y)
+{
+    double sy = 0.0;
+    for (int a = 0; a < n; ++a) sy += s[a] * y[a];
+    const double rho = 1.0 / sy;
+    double E[MAXP * MAXP], Bn[MAXP * MAXP];
+    for (int a = 0; a < n; ++a)
+        for (int c = 0; c < n; ++c) E[a * n + c] = (a == c ? 1.0 : 0.0) - rho * s[a] * y[c];
+    for (int a = 0; a < n; ++a)
+        for (int c = 0; c < n; ++c) {
+            double v = 0.0;
+            for (int k = 0; k < n; ++k)
+                for (int l = 0; l < n; ++l) v += E[a * n + k] * B[k * n + l] * E[c * n + l];
+            Bn[a * n + c] = v + rho * s[a] * s[c];
+        }
+    for (int a = 0; a < n * n; ++a) B[a] = Bn[a];
+}
+
 /* One multi-start trajectory (Algorithm 1, the loop over j for a fixed i):
  * seeds are independent, so a seed's whole trajectory can run before the
  * next seed's without changing any result.
  *   for s = 1 .. n_sigma + n_final_steps:
  *     sigma_s = sigma[s] for the continuation stages, then sigma_final
- *     (R, g, H) at theta;  p = Newton-CG direction
+ *     (R, g, H) at theta;  p = the update rule's direction: Newton-CG
+ *       (truncated Newton, Section 3's choice), the normalised gradient, or
+ *       BFGS on the scaled gradient restarted whenever sigma changes (other
+ *       methods the paper reports examining)
  *     if the scaled Newton step is small (no negative curvature and
  *       |p~| <= small_step_sigmas*sigma_s): theta += p
  *     else backtracking: first alpha in 1, 1/2, 1/4, .. (ls_trials values)
@@ -355,12 +381,48 @@ static void ascend_one(int D, const double* pz, double zref, int64_t n, const do
     make_dscale(D, zref, ds);
     const int n_steps = P->n_sigma + P->n_final_steps;
     int32_t flags = 0, n_reval = 0;
+    /* state of the quasi-Newton rule (scaled coordinates): inverse-Hessian
+     * model, gradient and accepted step of the previous update */
+    double Bm[MAXP * MAXP] = {0}, b_prev[MAXP] = {0}, s_prev[MAXP] = {0}, sig_prev = 0.0;
     for (int s = 0; s < n_steps; ++s) {
         const double sig = (double)(s < P->n_sigma ? P->sigma[s] : P->sigma_final);
         double R, g[MAXP], H[MAXP * MAXP], p[MAXP], pn;
         int neg;
         response_one(D, pz, n, x, y, pl, th, sig, &R, g, H);
-        if (D == 2 && s < P->n_slope_steps) {
+        const int slope_only = D == 2 && s < P->n_slope_steps;
+        if (P->update != 0) {
+            /* first-order and quasi-Newton rules in the scaled coordinates */
+            double b[MAXP], q[MAXP], bn = 0.0;
+            for (int a = 0; a < np; ++a) b[a] = (slope_only && a < 2) ? 0.0 : g[a] / ds[a];
+            for (int a = 0; a < np; ++a) bn += b[a] * b[a];
+            bn = sqrt(bn);
+            if (P->update == 1 || s == 0 || sig != sig_prev) {
+                /* normalised gradient step of one bandwidth; BFGS (re)starts here
+                 * with the inverse-Hessian model (sigma / |b|) I */
+                for (int a = 0; a < np * np; ++a) Bm[a] = 0.0;
+                for (int a = 0; a < np; ++a) Bm[a * np + a] = bn > 0.0 ? sig / bn : 0.0;
+            } else {
+                /* BFGS update of the inverse Hessian of f = -R with the last
+                 * step s~ and the change of grad f, y = -(b - b_prev); skipped
+                 * unless s~.y > 0 */
+                double yv[MAXP], sy = 0.0;
+                for (int a = 0; a < np; ++a) { yv[a] = -(b[a] - b_prev[a]); sy += s_prev[a] * yv[a]; }
+                if (sy > 0.0) oracle_bfgs_update(np, Bm, s_prev, yv);
+            }
+            for (int a = 0; a < np; ++a) {
+                double v = 0.0;
+                for (int c2 = 0; c2 < np; ++c2) v += Bm[a * np + c2] * b[c2];
+                q[a] = v;
+            }
+            double qn = 0.0;
+            for (int a = 0; a < np; ++a) qn += q[a] * q[a];
+            qn = sqrt(qn);
+            const double lim = (double)P->step_cap_sigmas * sig;
+            if (qn > lim) { for (int a = 0; a < np; ++a) q[a] *= lim / qn; qn = lim; }
+            for (int a = 0; a < np; ++a) { p[a] = q[a] / ds[a]; b_prev[a] = b[a]; s_prev[a] = 0.0; }
+            pn = qn;
+            neg = 0;
+        } else if (slope_only) {
             /* offsets held at their current values: Newton-CG on the slope block */
             const double gs[2] = {g[2], g[3]};
             const double Hs[4] = {H[2 * np + 2], H[2 * np + 3], H[3 * np + 2], H[3 * np + 3]};
@@ -371,9 +433,10 @@ static void ascend_one(int D, const double* pz, double zref, int64_t n, const do
         } else {
             oracle_newton_cg(np, g, H, ds, sig, (double)P->step_cap_sigmas, p, &pn, &neg);
         }
+        sig_prev = sig;
         if (neg) flags |= OR_NEGCURV;
         if (!neg && pn <= (double)P->small_step_sigmas * sig) {
-            for (int a = 0; a < np; ++a) th[a] += p[a];
+            for (int a = 0; a < np; ++a) { th[a] += p[a]; s_prev[a] = ds[a] * p[a]; }
             continue;
         }
         double gp = 0.0;
@@ -386,7 +449,7 @@ static void ascend_one(int D, const double* pz, double zref, int64_t n, const do
             const double Rt = response_only(D, pz, n, x, y, pl, tt, sig);
             ++n_reval;
             if (Rt >= R + (double)P->armijo_c1 * alpha * gp) {
-                for (int a = 0; a < np; ++a) th[a] = tt[a];
+                for (int a = 0; a < np; ++a) { th[a] = tt[a]; s_prev[a] = ds[a] * alpha * p[a]; }
                 accepted = 1;
                 break;
             }
