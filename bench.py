@@ -354,12 +354,15 @@ def main():
 
     # Section 3's comparison: multi-start at 1/3 and 1/10 of the grid search's
     # measured cost, efficiency against the number of tracks (Fig. 3)
-    alpha = alpha_sv = None
+    alpha = alpha_sv = upd = None
     if not args.no_budget:
         from paper_1709_08610_amd import budget
         alpha = budget.run(ctx, events.load_config("c7"), log=log)
         # the same on the paper's simplified VELO (tracks from the origin, prior-drawn seeds)
         alpha_sv = budget.run(ctx, events.load_config("c8"), log=log)
+        # Section 3's choice of update rule: truncated Newton against the
+        # normalised gradient and BFGS from the same seeds
+        upd = {name: budget.compare_updates(ctx, events.load_config(name), log=log) for name in ("c7", "c8")}
 
     cpu = cpu_l = None
     if not args.no_cpu_baseline:
@@ -423,6 +426,7 @@ def main():
                               "flops_per_launch": FLOP_NET_EVENT * E},
         "alpha_budget": alpha,
         "alpha_budget_svelo": alpha_sv,
+        "update_rules": upd,
         "cpu_baseline": cpu,
         "cpu_baseline_learned": cpu_l,
     }

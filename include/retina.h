@@ -64,6 +64,9 @@ typedef enum {
 enum { RETINA_MEM_HOST = 0, RETINA_MEM_DEVICE = 1 };
 enum { RETINA_WANT_R = 1, RETINA_WANT_GRAD = 2, RETINA_WANT_HESS = 4 };
 enum { RETINA_SEED_LATTICE = 0, RETINA_SEED_EXPLICIT = 1 };
+/* Update rule of Algorithm 1's inner loop (Section 3 reports trying several
+ * optimisation methods and keeping truncated Newton). */
+enum { RETINA_UPDATE_NEWTON = 0, RETINA_UPDATE_GRADIENT = 1, RETINA_UPDATE_BFGS = 2 };
 
 /* per-seed / per-track flag bits */
 enum {
@@ -125,6 +128,13 @@ typedef struct {
     const double* seeds;        /* EXPLICIT: n_par doubles per seed (rounded to FP32 for the
                                    ascent), in the hits' memory space */
     const int64_t* seed_offsets;/* EXPLICIT: n_events+1, in the hits' memory space */
+    int32_t update;             /* RETINA_UPDATE_NEWTON: truncated Newton (Newton-CG in scaled
+                                   coordinates); RETINA_UPDATE_GRADIENT: a scaled step of one
+                                   bandwidth along the scaled gradient; RETINA_UPDATE_BFGS:
+                                   quasi-Newton, the BFGS inverse-Hessian model of -R in scaled
+                                   coordinates, (sigma / |g~|) I whenever sigma changes, updated
+                                   when s~.y > 0.  Every rule keeps the line search, the step cap
+                                   and the FP64 Newton polish. */
 } retina_params;
 
 /* One reconstructed track (48 bytes). */

@@ -139,19 +139,69 @@ def run(ctx, cfg=None, counts=None, events_per_point=None, reps=3, log=print):
     return out
 
 
+def compare_updates(ctx, cfg=None, n_tracks=200, events_per_point=None, seeds=2304, reps=3, log=print):
+    """Section 3's choice among update rules: truncated Newton, the normalised
+    gradient and BFGS from the same seeds on the same events (the middle point
+    of a scan), with the same steps, line search and FP64 polish: efficiency
+    and measured time per seed and step (in units of T0, the grid-search cost
+    per cell, as C0)."""
+    import torch
+    cfg = cfg or events.load_config("c7")
+    P = dict(cfg["params"])
+    G = cfg["grid"]
+    n_grid = int(G["n"][0]) * int(G["n"][1])
+    q = len(P["sigma"]) + int(P["n_final_steps"]) + int(P["n_polish"])
+    qkey = cfg.get("quality_key", "eff_eps")
+    dev = torch.device("cuda:0")
+    tin = lambda a: torch.from_numpy(np.ascontiguousarray(a)).to(dev)
+    (_, b), = events.scan_batches(cfg, [n_tracks], events_per_point)
+    E = b.n_events
+    d = (tin(b.event_offsets), tin(b.x), tin(b.y), tin(b.plane))
+    z0, z1 = float(cfg["planes"]["z_first"]), float(cfg["planes"]["z_last"])
+    t_grid = _median_time(lambda: ctx.retina_grid_search(2, b.plane_z, *d, G, capacity=E * 4096), reps)
+    T0 = t_grid / (E * n_grid)
+    if cfg.get("seeding") == "prior":
+        s, o = events.prior_seeds(cfg, seeds, b.index)
+        kw = dict(seeds=tin(s), seed_offsets=tin(o))
+        k = seeds
+    else:
+        side = int(round(math.sqrt(seeds)))
+        P = dict(P, lattice_n=[side, side])
+        kw = {}
+        k = side * side
+    out = dict(workload="%s, %d tracks per event, %d events" % (cfg["name"], n_tracks, E), seeds=k, q=q,
+               T0_ns=T0 * 1e9, efficiency_criterion=qkey, rules={})
+    for rule in ("newton", "gradient", "bfgs"):
+        Pr = dict(P, update=rule)
+        call = lambda: ctx.retina_find_tracks(2, b.plane_z, *d, Pr, capacity=E * k, **kw)
+        t = _median_time(call, reps)
+        theta, toff = _tracks(call(), E)
+        qm = metrics.batch_quality(2, theta, toff, b.truth, b.truth_nhits, cfg["match_tol"], z0, z1)
+        out["rules"][rule] = dict(ms_per_event=1e3 * t / E, C0=t / (E * k * q) / T0, eff=qm[qkey],
+                                  efficiency=qm["efficiency"], fake_rate=qm["fake_rate"],
+                                  tracks_per_event=qm["n_found"] / E)
+        log("  update %-8s: %s %.3f, eff %.3f, C0 %.2f, %.3f ms/event" % (
+            rule, qkey, qm[qkey], qm["efficiency"], out["rules"][rule]["C0"], 1e3 * t / E))
+    return out
+
+
 def main(argv=None):
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--events", type=int, default=None, help="events per track count (default: the config's)")
     ap.add_argument("--counts", type=int, nargs="*", default=None)
     ap.add_argument("--reps", type=int, default=3)
     ap.add_argument("--config", default="c7", help="c7 (c2 geometry) or c8 (simplified VELO)")
+    ap.add_argument("--updates", action="store_true", help="compare the update rules instead of the scan")
     a = ap.parse_args(argv)
     import torch
     if not torch.cuda.is_available():
         raise SystemExit("budget needs a GPU")
     ctx = retina.Context(0)
-    out = run(ctx, events.load_config(a.config), counts=a.counts, events_per_point=a.events, reps=a.reps,
-              log=lambda m: print(m, file=sys.stderr, flush=True))
+    lg = lambda m: print(m, file=sys.stderr, flush=True)
+    if a.updates:
+        out = compare_updates(ctx, events.load_config(a.config), events_per_point=a.events, reps=a.reps, log=lg)
+    else:
+        out = run(ctx, events.load_config(a.config), counts=a.counts, events_per_point=a.events, reps=a.reps, log=lg)
     print(json.dumps(out))
 
 

@@ -62,7 +62,7 @@ struct retina_ctx {
     // (meas_dim, launch shape, profiling) serves any batch
     bool use_graphs = true;
     struct GraphEntry {
-        int D, cand, tile, grid, prof;
+        int D, cand, tile, grid, prof, update;
         hipGraphExec_t exec;
     };
     std::vector<GraphEntry> graphs;
@@ -351,7 +351,7 @@ int run_tracks(retina_ctx* c, int D, const HotConfig& hc)
         hipGraphExec_t exec = nullptr;
         for (auto& g : c->graphs)
             if (g.D == D && g.cand == hc.cand && g.tile == hc.tile_hits && g.grid == hc.grid &&
-                g.prof == (int)c->prof)
+                g.prof == (int)c->prof && g.update == hc.update)
                 exec = g.exec;
         if (!exec) {
             hipGraph_t graph = nullptr;
@@ -367,7 +367,7 @@ int run_tracks(retina_ctx* c, int D, const HotConfig& hc)
                 (void)hipGetLastError();
                 c->use_graphs = false;  // capture unsupported here: launch eagerly from now on
             } else {
-                c->graphs.push_back({D, hc.cand, hc.tile_hits, hc.grid, (int)c->prof, exec});
+                c->graphs.push_back({D, hc.cand, hc.tile_hits, hc.grid, (int)c->prof, hc.update, exec});
             }
         }
         if (exec) {
@@ -803,6 +803,8 @@ static int find_tracks_impl(retina_ctx* c, const retina_geometry* g, const retin
         return fail(c, RETINA_ERR_INVALID_ARG, "step_cap_sigmas, conv_tol must be > 0 and d_merge >= 0");
     if (P->seed_mode != RETINA_SEED_LATTICE && P->seed_mode != RETINA_SEED_EXPLICIT)
         return fail(c, RETINA_ERR_INVALID_ARG, "unknown seed_mode %d", P->seed_mode);
+    if (P->update != RETINA_UPDATE_NEWTON && P->update != RETINA_UPDATE_GRADIENT && P->update != RETINA_UPDATE_BFGS)
+        return fail(c, RETINA_ERR_INVALID_ARG, "unknown update rule %d", P->update);
     if (P->seed_mode == RETINA_SEED_LATTICE) {
         if (P->lattice_n[0] < 1 || P->lattice_n[1] < 1 || (int64_t)P->lattice_n[0] * P->lattice_n[1] > (1 << 24))
             return fail(c, RETINA_ERR_INVALID_ARG, "lattice_n must be >= 1 with at most 2^24 seeds");
@@ -851,7 +853,13 @@ static int find_tracks_impl(retina_ctx* c, const retina_geometry* g, const retin
     fill_geometry(d, g);
     d.cnt = c->d_cnt;
     if ((rc = stage_inputs(c, d, g, h, n_hits))) return rc;
-    const HotConfig hc = n_seeds < kSparseSeeds * E ? c->sparse_cfg[D] : c->ascent_cfg[D];
+    HotConfig hc = n_seeds < kSparseSeeds * E ? c->sparse_cfg[D] : c->ascent_cfg[D];
+    if (P->update != RETINA_UPDATE_NEWTON) {
+        // the alternative rules run one candidate per lane (the sparse shape)
+        hc = c->sparse_cfg[D];
+        hc.cand = 1;
+        hc.update = P->update;
+    }
     d.seeds_per_item = hot_seeds_per_item(hc);
     d.items_cap = n_seeds / d.seeds_per_item + E + 1;
     if ((rc = ensure_t(c, B_ITEMS, (size_t)d.items_cap, &d.items))) return rc;

@@ -539,7 +539,10 @@ __device__ __forceinline__ void lattice_point(const Desc* __restrict__ d, int i,
     else { th[0] = v1; th[1] = v0; }
 }
 
-template <int D, int C>
+// Update rules of the inner loop (U): 0 truncated Newton, 1 normalised
+// gradient, 2 BFGS.  The rule is a template parameter so that the default
+// Newton kernels carry no quasi-Newton state.
+template <int D, int C, int U = 0>
 __global__ __launch_bounds__(kBlock) void k_ascent(const Desc* __restrict__ d, int tile_cap)
 {
     constexpr int NP = 2 * D;
@@ -580,6 +583,11 @@ __global__ __launch_bounds__(kBlock) void k_ascent(const Desc* __restrict__ d, i
         float th[C][NP];
         bool active[C];
         int flags[C], nre[C];
+        // BFGS state per candidate (scaled coordinates): inverse-Hessian model
+        // of -R, the previous step's scaled gradient and its accepted step
+        constexpr int CQ = U == 2 ? C : 1;
+        float Bq[CQ][NP][NP], bq[CQ][NP], sq[CQ][NP];
+        float sig_prev = 0.0f;
 #pragma unroll
         for (int j = 0; j < C; ++j) {
             const int sj = it.y + (wave * C + j) * kWave + lane;
@@ -620,7 +628,80 @@ __global__ __launch_bounds__(kBlock) void k_ascent(const Desc* __restrict__ d, i
                 grad_hess<D, float>(acc[j], sig, g, H);
                 float pn;
                 bool neg;
-                if constexpr (D == 2) {
+                if constexpr (U != 0) {
+                    // scaled gradient (offset components zero while they are held)
+                    float b[NP], q[NP], bb = 0.0f;
+#pragma unroll
+                    for (int a = 0; a < NP; ++a) b[a] = (D == 2 && slope_only && a < 2) ? 0.0f : g[a] / ds[a];
+#pragma unroll
+                    for (int a = 0; a < NP; ++a) bb = __builtin_fmaf(b[a], b[a], bb);
+                    const float bn = sqrtf(bb);
+                    if constexpr (U == 1) {
+#pragma unroll
+                        for (int a = 0; a < NP; ++a) q[a] = bn > 0.0f ? sig * (b[a] / bn) : 0.0f;
+                    } else {
+                        float (&B)[NP][NP] = Bq[U == 2 ? j : 0];
+                        if (s == 0 || sig != sig_prev) {
+                            // (re)start: the normalised gradient step of one bandwidth
+#pragma unroll
+                            for (int a = 0; a < NP; ++a)
+#pragma unroll
+                                for (int c2 = 0; c2 < NP; ++c2) B[a][c2] = a == c2 ? (bn > 0.0f ? sig / bn : 0.0f) : 0.0f;
+                        } else {
+                            // BFGS with y = -(b - b_prev) (gradient change of -R) and
+                            // the accepted step, in the expanded form
+                            // B + ((s.y + y.B.y) / (s.y)^2) s s^T - (B y s^T + s y^T B) / s.y
+                            float y[NP], sy = 0.0f;
+#pragma unroll
+                            for (int a = 0; a < NP; ++a) {
+                                y[a] = bq[U == 2 ? j : 0][a] - b[a];
+                                sy = __builtin_fmaf(sq[U == 2 ? j : 0][a], y[a], sy);
+                            }
+                            if (sy > 0.0f) {
+                                float By[NP], yBy = 0.0f;
+#pragma unroll
+                                for (int a = 0; a < NP; ++a) {
+                                    float v = 0.0f;
+#pragma unroll
+                                    for (int c2 = 0; c2 < NP; ++c2) v = __builtin_fmaf(B[a][c2], y[c2], v);
+                                    By[a] = v;
+                                    yBy = __builtin_fmaf(y[a], v, yBy);
+                                }
+                                const float inv = 1.0f / sy;
+                                const float cs = (sy + yBy) * inv * inv;
+                                const float* sv = sq[U == 2 ? j : 0];
+#pragma unroll
+                                for (int a = 0; a < NP; ++a)
+#pragma unroll
+                                    for (int c2 = 0; c2 < NP; ++c2)
+                                        B[a][c2] += cs * sv[a] * sv[c2] - (By[a] * sv[c2] + sv[a] * By[c2]) * inv;
+                            }
+                        }
+#pragma unroll
+                        for (int a = 0; a < NP; ++a) {
+                            float v = 0.0f;
+#pragma unroll
+                            for (int c2 = 0; c2 < NP; ++c2) v = __builtin_fmaf(B[a][c2], b[c2], v);
+                            q[a] = v;
+                            bq[U == 2 ? j : 0][a] = b[a];
+                            sq[U == 2 ? j : 0][a] = 0.0f;
+                        }
+                    }
+                    float qq = 0.0f;
+#pragma unroll
+                    for (int a = 0; a < NP; ++a) qq = __builtin_fmaf(q[a], q[a], qq);
+                    pn = sqrtf(qq);
+                    const float lim = d->step_cap * sig;
+                    if (pn > lim) {
+                        const float sc = lim / pn;
+#pragma unroll
+                        for (int a = 0; a < NP; ++a) q[a] *= sc;
+                        pn = lim;
+                    }
+#pragma unroll
+                    for (int a = 0; a < NP; ++a) p[j][a] = q[a] / ds[a];
+                    neg = false;
+                } else if constexpr (D == 2) {
                     if (slope_only) {
                         const float gs[2] = {g[2], g[3]};
                         const float Hs[2][2] = {{H[2][2], H[2][3]}, {H[3][2], H[3][3]}};
@@ -647,11 +728,16 @@ __global__ __launch_bounds__(kBlock) void k_ascent(const Desc* __restrict__ d, i
                 } else if (!neg && pn <= d->small_step * sig) {
 #pragma unroll
                     for (int a = 0; a < NP; ++a) th[j][a] += p[j][a];
+                    if constexpr (U == 2) {
+#pragma unroll
+                        for (int a = 0; a < NP; ++a) sq[j][a] = ds[a] * p[j][a];
+                    }
                     pend[j] = false;
                 } else {
                     pend[j] = true;
                 }
             }
+            sig_prev = sig;
             // Backtracking line search.  Each round gathers the work-group's
             // pending trial points into an LDS list and evaluates R only for
             // those.  One candidate per lane and up to 64 pending points: the
@@ -742,6 +828,10 @@ __global__ __launch_bounds__(kBlock) void k_ascent(const Desc* __restrict__ d, i
                     if (Rt >= Rc[j] + d->armijo_c1 * alpha[j] * gp[j]) {
 #pragma unroll
                         for (int a = 0; a < NP; ++a) th[j][a] = tt[j][a];
+                        if constexpr (U == 2) {
+#pragma unroll
+                            for (int a = 0; a < NP; ++a) sq[j][a] = ds[a] * (alpha[j] * p[j][a]);
+                        }
                         pend[j] = false;
                     } else if (++trial[j] >= d->ls_trials) {
                         pend[j] = false;
@@ -1012,6 +1102,17 @@ void launch_ascent(const Desc* d, int D, const HotConfig& c, hipStream_t st)
 {
     const size_t lds = hot_lds_bytes(D, c);
     const dim3 g(c.grid), b(kBlock);
+    if (c.update != 0) {
+        // the alternative update rules run one candidate per lane
+        if (D == 2) {
+            if (c.update == 1) hipLaunchKernelGGL((k_ascent<2, 1, 1>), g, b, lds, st, d, c.tile_hits);
+            else hipLaunchKernelGGL((k_ascent<2, 1, 2>), g, b, lds, st, d, c.tile_hits);
+        } else {
+            if (c.update == 1) hipLaunchKernelGGL((k_ascent<1, 1, 1>), g, b, lds, st, d, c.tile_hits);
+            else hipLaunchKernelGGL((k_ascent<1, 1, 2>), g, b, lds, st, d, c.tile_hits);
+        }
+        return;
+    }
     if (D == 2) {
         if (c.cand == 2) hipLaunchKernelGGL((k_ascent<2, 2>), g, b, lds, st, d, c.tile_hits);
         else hipLaunchKernelGGL((k_ascent<2, 1>), g, b, lds, st, d, c.tile_hits);

@@ -140,6 +140,7 @@ struct HotConfig {
     int cand;        // candidates per lane (1, 2)
     int tile_hits;   // LDS capacity in hits
     int grid;        // persistent work-groups
+    int update = 0;  // ascent update rule: 0 Newton, 1 gradient, 2 BFGS (cand 1)
 };
 int hot_seeds_per_item(const HotConfig& c);
 void launch_ascent(const Desc* d, int meas_dim, const HotConfig& c, hipStream_t st);

@@ -50,7 +50,7 @@ class Params(ctypes.Structure):
                 ("conv_tol", ctypes.c_float), ("R0", ctypes.c_float), ("d_merge", ctypes.c_float),
                 ("seed_mode", ctypes.c_int32), ("lattice_n", ctypes.c_int32 * 2),
                 ("lattice_lo", ctypes.c_float * 2), ("lattice_hi", ctypes.c_float * 2),
-                ("seeds", ctypes.c_void_p), ("seed_offsets", ctypes.c_void_p)]
+                ("seeds", ctypes.c_void_p), ("seed_offsets", ctypes.c_void_p), ("update", ctypes.c_int32)]
 
 
 class Track(ctypes.Structure):
@@ -95,6 +95,7 @@ EXPORTS = ["retina_create", "retina_destroy", "retina_last_error", "retina_set_s
            "retina_model_get_params", "retina_model_set_params", "retina_model_step",
            "retina_train_step", "retina_model_forward", "retina_propose_seeds",
            "retina_find_tracks_learned", "retina_grid_search"]
+UPDATE_RULES = {"newton": 0, "gradient": 1, "bfgs": 2}   # RETINA_UPDATE_*
 MODEL_PARAMS = 186625
 IMG = 128
 SLOPE_LO, SLOPE_HI = -0.35, 0.35
@@ -308,6 +309,7 @@ class Context:
         P.lattice_n[:] = list(params["lattice_n"])
         P.lattice_lo[:] = list(params["lattice_lo"])
         P.lattice_hi[:] = list(params["lattice_hi"])
+        P.update = UPDATE_RULES[params.get("update", "newton")]
         if seeds is not None:
             P.seed_mode = SEED_EXPLICIT
             if mem == MEM_HOST:

@@ -152,3 +152,39 @@ def event_tracks(res, e, D):
     a, b = int(res["track_offsets"][e]), int(res["track_offsets"][e + 1])
     t = res["tracks"][a:b]
     return t["theta"][:, :2 * D], t["R"]
+
+
+def assert_tracks_match_up_to_convergence_flags(D, gpu, ref, e, d_merge, z0, z1, seed_tol=1e-6):
+    """Track-set parity where a track may hang on a single seed (rules that bring
+    few seeds to convergence): matched tracks as assert_tracks_match; a track on
+    one side only is accepted when every seed that supports it (converged, within
+    d_merge of it) ended at the same point on the other side (|dp| <= seed_tol
+    relative, scale floors S_P), i.e. the two sides differ only in the
+    convergence decision (last polish step against conv_tol), not in a
+    trajectory.  gpu/ref: result dicts with per-seed arrays (global seed order)
+    and their seed offsets; returns (matched, boundary-only) counts."""
+    so_g, so_r = gpu["seed_offsets"], ref["seed_offsets"]
+    sg = slice(int(so_g[e]), int(so_g[e + 1]))
+    sr = slice(int(so_r[e]), int(so_r[e + 1]))
+    th_g, th_r = np.asarray(gpu["seed_theta"][sg], np.float64), np.asarray(ref["seed_theta"][sr], np.float64)
+    assert th_g.shape == th_r.shape
+    seed_rel = (np.abs(th_g - th_r) / np.maximum(np.abs(th_r), S_P[D])).max(axis=1) if len(th_r) else np.zeros(0)
+    tg, Rg = gpu["tracks_theta"][e], gpu["tracks_R"][e]
+    tr, Rr = ref["tracks_theta"][e], ref["tracks_R"][e]
+    f2t, t2f, _ = match_tracks(D, tg, tr, d_merge, z0, z1)
+    m = t2f >= 0
+    if m.any():
+        rel = np.abs(tg[t2f[m]] - tr[m]) / np.maximum(np.abs(tr[m]), S_P[D])
+        assert rel.max() <= 1e-4, "parameter error %g" % rel.max()
+        np.testing.assert_allclose(Rg[t2f[m]], Rr[m], rtol=1e-5)
+    boundary = 0
+    for side_tracks, miss, th_side, fl_side in ((tr, np.nonzero(t2f < 0)[0], th_r, ref["seed_flags"][sr]),
+                                                (tg, np.nonzero(f2t < 0)[0], th_g, gpu["seed_flags"][sg])):
+        for k in miss:
+            dd = _dist(D, th_side, side_tracks[k][None, :], z0, z1)[:, 0]
+            sup = np.nonzero((dd <= d_merge) & ((np.asarray(fl_side) & 1) > 0))[0]
+            assert len(sup) > 0
+            assert np.all(seed_rel[sup] <= seed_tol), \
+                "track on one side only and its seeds' trajectories differ (%s)" % seed_rel[sup]
+            boundary += 1
+    return int(m.sum()), boundary
