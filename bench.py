@@ -127,7 +127,7 @@ def cpu_baseline_learned(cfg, LS, model, target_s=12.0, cap=256):
         for e in range(b.n_events):
             ev = b.event(e)
             _, z = op.forward(op.bin_image(ev.x, ev.y, ev.plane, b.plane_z), layers)
-            picks = op.nms_topk(z, LS["tau"], LS["k_max"], nms=LS["nms"])
+            picks = op.seed_bins(z, LS["tau"], LS["k_max"], nms=LS["nms"])
             fb = not picks or z.max() < op.logit_threshold(LS["conf_min"])
             s = lat if fb else op.seeds_from_pixels(picks)
             seeds.append(s)
@@ -332,6 +332,46 @@ def main():
     log("learned: %.2f ms/step (graph replay %.2f), proposer %.2f ms, ascent %.2f ms" % (
         dt_lrn * 1e3, g_lrn * 1e3, prof_lrn["ms_propose"], prof_lrn["ms_hot"]))
 
+    # ---- locality-pruned passes (prune_u = 30: each skipped term < 1e-13), both
+    # seedings: the lattice sweep again (pruning favours compact waves, so the
+    # fastest lattice reaching the bar may change) and the learned seeds
+    PU = 30.0
+    sweep_p = []
+    for n in cfg.get("lattice_sweep", [P["lattice_n"][0]]):
+        Pn = dict(P, lattice_n=[n, n], prune_u=PU)
+        f = lambda: ctx.retina_find_tracks(D, b.plane_z, off_d, x_d, y_d, pl_d, Pn)
+        r = f()
+        torch.cuda.synchronize()
+        qn = quality(retina.tracks_from_device(r)["theta"][:, :2 * D], r["track_offsets"].cpu().numpy())
+        del r
+        t0 = time.perf_counter()
+        for _ in range(2):
+            f()
+        torch.cuda.synchronize()
+        tn = (time.perf_counter() - t0) / 2
+        sweep_p.append(dict(lattice_n=n, ms_per_step=tn * 1e3, events_per_s=E / tn,
+                            efficiency=round(qn["efficiency"], 5), fake_rate=round(qn["fake_rate"], 5)))
+        log("pruned lattice %dx%d: %.2f ms, efficiency %.4f" % (n, n, tn * 1e3, qn["efficiency"]))
+    ok_p = [r for r in sweep_p if r["efficiency"] >= 0.95]
+    best_p = min(ok_p, key=lambda r: r["ms_per_step"]) if ok_p else max(sweep_p, key=lambda r: r["efficiency"])
+    PLp = dict(PL, prune_u=PU)
+
+    def learned_pruned():
+        return ctx.retina_find_tracks_learned(model, b.plane_z, off_d, x_d, y_d, pl_d, PLp, LS["k_max"],
+                                              LS["tau"], LS["conf_min"], nms=LS["nms"])
+    r = learned_pruned()
+    torch.cuda.synchronize()
+    q_lp = quality(retina.tracks_from_device(r)["theta"][:, :2 * D], r["track_offsets"].cpu().numpy())
+    del r
+    dt_lp, prof_lp, g_lp = timed(ctx, learned_pruned, args.steps)
+    log("pruned learned: %.2f ms/step, ascent %.2f ms, efficiency %.4f; pruned lattice %dx%d %.2f ms" % (
+        dt_lp * 1e3, prof_lp["ms_hot"], q_lp["efficiency"], best_p["lattice_n"], best_p["lattice_n"],
+        best_p["ms_per_step"]))
+    pruned = {"prune_u": PU, "lattice_sweep": sweep_p, "lattice_best": best_p,
+              "learned": {"events_per_s": E / dt_lp, "ms_per_step": dt_lp * 1e3, "ascent_ms": prof_lp["ms_hot"],
+                          "efficiency": round(q_lp["efficiency"], 5), "fake_rate": round(q_lp["fake_rate"], 5)},
+              "speedup_vs_lattice": best_p["ms_per_step"] / (dt_lp * 1e3)}
+
     # end to end from host memory (hits H2D, tracks D2H included)
     hb = (b.event_offsets, b.x, b.y, b.plane)
     ctx.retina_find_tracks_learned(model, b.plane_z, *hb, PL, LS["k_max"], LS["tau"], LS["conf_min"], nms=LS["nms"])
@@ -409,6 +449,7 @@ def main():
                                          "executed_line_search": prof_lat["exec_rpairs"]}},
         "lattice_sweep": sweep,
         "speedup_vs_lattice": dt_lat / dt_lrn,
+        "pruned": pruned,
         "end_to_end_host_ms_per_step": ms_host,
         "response": resp,
         "response_c2_event": resp_c2,

@@ -135,6 +135,14 @@ typedef struct {
                                    coordinates, (sigma / |g~|) I whenever sigma changes, updated
                                    when s~.y > 0.  Every rule keeps the line search, the step cap
                                    and the FP64 Newton polish. */
+    float prune_u;              /* 0: every pass sums over every hit (exact).  > 0: a pass skips
+                                   the hits of a plane whose first coordinate lies farther than
+                                   sqrt(prune_u) * sigma from that of every candidate a wavefront
+                                   holds; each skipped term is below exp(-prune_u), so R moves by
+                                   less than n_hits * exp(-prune_u) (e.g. 30: 1e-13 per hit).
+                                   Hits are then sorted by that coordinate within each plane;
+                                   events with a plane of more than 4096 hits stay exact.
+                                   Truncated-Newton rule only. */
 } retina_params;
 
 /* One reconstructed track (48 bytes). */

@@ -12,6 +12,8 @@ Plain numpy, direct definitions:
   * adam_step      Kingma & Ba's update with bias correction
   * nms_topk       bins above a threshold (optionally strict 3x3 local
                    maxima), best k
+  * seed_bins      those bins in bin order (the order seeds are handed to
+                   the ascent)
   * target_image / seeds_from_pixels   slope pair <-> bin maps
   * forward / backward of the four-layer network, optionally rounding the
     stored activations and gradients to BF16 where the device stores them
@@ -168,6 +170,12 @@ def nms_topk(z, tau, k_max, nms=True):
                 cands.append((-float(v), r * Wd + c))
     cands.sort()
     return [i for _, i in cands[:k_max]]
+
+
+def seed_bins(z, tau, k_max, nms=True):
+    """The proposal's seed bins: the set nms_topk selects, emitted in ascending
+    bin index (tx bin major), so that consecutive seeds are neighbours in tx."""
+    return sorted(nms_topk(z, tau, k_max, nms))
 
 
 def unpack_params(flat):

@@ -28,7 +28,7 @@ enum BufId {
     B_INX, B_INY, B_INPL, B_INOFF, B_INSEEDS, B_INSOFF, B_INTH, B_INTHOFF, B_OUTTR, B_OUTTOFF,
     B_OUTEVF, B_OUTSTH, B_OUTSR, B_OUTSFL, B_OUTSNR, B_OUTR, B_OUTG, B_OUTH,
     // learned proposer workspace
-    B_GRID, B_GRIDCNT, B_GRIDBASE,
+    B_GRID, B_GRIDCNT, B_GRIDBASE, B_EVSORT,
     B_IMG, B_ACT1, B_ACT2, B_ACT3, B_LOGIT, B_HEADU, B_RESPPART, B_DZ4, B_DZ3, B_DZ2, B_DZ1, B_TGT, B_TGTIN, B_TGTOFF,
     B_DWPART, B_WT, B_LOSSPART, B_LOSS, B_BPART, B_PSCORE, B_PPIX, B_PCOUNT, B_PCONF, B_PFB,
     B_PSOFF, B_PSEEDS, B_OUTIMG, B_OUTLOGIT,
@@ -62,7 +62,7 @@ struct retina_ctx {
     // (meas_dim, launch shape, profiling) serves any batch
     bool use_graphs = true;
     struct GraphEntry {
-        int D, cand, tile, grid, prof, update;
+        int D, cand, tile, grid, prof, update, prune;
         hipGraphExec_t exec;
     };
     std::vector<GraphEntry> graphs;
@@ -329,6 +329,7 @@ void tracks_sequence(retina_ctx* c, int D, const HotConfig& hc, hipStream_t st)
     mark(0);
     launch_reset(c->d_desc, st);
     launch_stage(c->d_desc, c->n_cu * 8, st);
+    if (hc.prune) launch_sort_planes(c->d_desc, c->n_cu * 8, st);
     mark(1);
     launch_plan_tracks(c->d_desc, st);
     mark(2);
@@ -351,7 +352,7 @@ int run_tracks(retina_ctx* c, int D, const HotConfig& hc)
         hipGraphExec_t exec = nullptr;
         for (auto& g : c->graphs)
             if (g.D == D && g.cand == hc.cand && g.tile == hc.tile_hits && g.grid == hc.grid &&
-                g.prof == (int)c->prof && g.update == hc.update)
+                g.prof == (int)c->prof && g.update == hc.update && g.prune == hc.prune)
                 exec = g.exec;
         if (!exec) {
             hipGraph_t graph = nullptr;
@@ -367,7 +368,7 @@ int run_tracks(retina_ctx* c, int D, const HotConfig& hc)
                 (void)hipGetLastError();
                 c->use_graphs = false;  // capture unsupported here: launch eagerly from now on
             } else {
-                c->graphs.push_back({D, hc.cand, hc.tile_hits, hc.grid, (int)c->prof, hc.update, exec});
+                c->graphs.push_back({D, hc.cand, hc.tile_hits, hc.grid, (int)c->prof, hc.update, hc.prune, exec});
             }
         }
         if (exec) {
@@ -805,6 +806,10 @@ static int find_tracks_impl(retina_ctx* c, const retina_geometry* g, const retin
         return fail(c, RETINA_ERR_INVALID_ARG, "unknown seed_mode %d", P->seed_mode);
     if (P->update != RETINA_UPDATE_NEWTON && P->update != RETINA_UPDATE_GRADIENT && P->update != RETINA_UPDATE_BFGS)
         return fail(c, RETINA_ERR_INVALID_ARG, "unknown update rule %d", P->update);
+    if (!isfinite(P->prune_u) || P->prune_u < 0.0f)
+        return fail(c, RETINA_ERR_INVALID_ARG, "prune_u must be finite and >= 0");
+    if (P->prune_u > 0.0f && P->update != RETINA_UPDATE_NEWTON)
+        return fail(c, RETINA_ERR_INVALID_ARG, "pruned passes run with the truncated-Newton rule only");
     if (P->seed_mode == RETINA_SEED_LATTICE) {
         if (P->lattice_n[0] < 1 || P->lattice_n[1] < 1 || (int64_t)P->lattice_n[0] * P->lattice_n[1] > (1 << 24))
             return fail(c, RETINA_ERR_INVALID_ARG, "lattice_n must be >= 1 with at most 2^24 seeds");
@@ -860,6 +865,7 @@ static int find_tracks_impl(retina_ctx* c, const retina_geometry* g, const retin
         hc.cand = 1;
         hc.update = P->update;
     }
+    hc.prune = P->prune_u > 0.0f;
     d.seeds_per_item = hot_seeds_per_item(hc);
     d.items_cap = n_seeds / d.seeds_per_item + E + 1;
     if ((rc = ensure_t(c, B_ITEMS, (size_t)d.items_cap, &d.items))) return rc;
@@ -880,6 +886,8 @@ static int find_tracks_impl(retina_ctx* c, const retina_geometry* g, const retin
     d.conv_tol = P->conv_tol;
     d.R0 = P->R0;
     d.d_merge = P->d_merge;
+    d.prune_u = P->prune_u;
+    if (P->prune_u > 0.0f && (rc = ensure_t(c, B_EVSORT, (size_t)E, &d.ev_sorted))) return rc;
     if (P->seed_mode == RETINA_SEED_EXPLICIT) {
         if (!seeds_dev) {
             double* s;

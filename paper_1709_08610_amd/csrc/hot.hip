@@ -154,19 +154,106 @@ struct EventView {
     int P;
     bool resident;        // all hits already in LDS
     int tile_cap;
+    bool prune;           // plane segments sorted by x: passes visit only each wave's x window
 };
+
+// ------------------------------------------------------------ pruning
+// A pass may skip the hits of a plane whose x lies farther than
+// w = sqrt(prune_u) sigma from the predicted x of every candidate the wave
+// holds: each skipped term is below exp(-prune_u), so R changes by less than
+// (hits) * exp(-prune_u) and the derivatives by the same factor times their
+// polynomial weights.  The hits of a plane are sorted by x, the window is
+// wave-uniform, and its index range comes from two rounds of 64 parallel
+// probes (segments hold at most 4096 hits).
+template <int D>
+__device__ __forceinline__ float hit_key(const float* s_hits, int i)
+{
+    if constexpr (D == 2) return reinterpret_cast<const float2*>(s_hits)[i].x;
+    else return s_hits[i];
+}
+
+// first index in [lo, hi) whose key is >= v (STRICT: > v); v wave-uniform,
+// keys ascending, hi - lo <= 4096; every lane of the wave must call it
+template <int D, bool STRICT>
+__device__ __forceinline__ int wave_bound(const float* s_hits, int lo, int hi, float v)
+{
+    const int n = hi - lo;
+    if (n <= 0) return lo;
+    const int lane = threadIdx.x & (kWave - 1);
+    const int step = (n + kWave - 1) / kWave;
+    const int i1 = lo + lane * step;
+    bool below = false;
+    if (i1 < hi) {
+        const float k = hit_key<D>(s_hits, i1);
+        below = STRICT ? (k <= v) : (k < v);
+    }
+    const int c = __popcll(__ballot(below));
+    if (c == 0) return lo;
+    const int base = lo + (c - 1) * step + 1;
+    const int end = min(hi, lo + c * step);
+    const int i2 = base + lane;
+    bool below2 = false;
+    if (lane < step - 1 && i2 < end) {
+        const float k = hit_key<D>(s_hits, i2);
+        below2 = STRICT ? (k <= v) : (k < v);
+    }
+    return __builtin_amdgcn_readfirstlane(base + __popcll(__ballot(below2)));
+}
+
+// x window [xlo, xhi] of the wave's live candidates at plane z
+template <int C>
+__device__ __forceinline__ void wave_window(const Cands<C>& c, const bool* live, float z, float w, float& xlo,
+                                            float& xhi)
+{
+    float mn = INFINITY, mx = -INFINITY;
+#pragma unroll
+    for (int j = 0; j < C; ++j) {
+        if (live && !live[j]) continue;
+        const float xc = __builtin_fmaf(c.t[j][0], z, c.o[j][0]);
+        mn = fminf(mn, xc);
+        mx = fmaxf(mx, xc);
+    }
+#pragma unroll
+    for (int off = kWave / 2; off > 0; off >>= 1) {
+        mn = fminf(mn, __shfl_xor(mn, off, kWave));
+        mx = fmaxf(mx, __shfl_xor(mx, off, kWave));
+    }
+    xlo = mn - w;
+    xhi = mx + w;
+}
+
+// the part [lo, hi) of a plane segment (tile-relative) inside the window
+template <int D, int C>
+__device__ __forceinline__ void prune_range(const float* s_hits, const Cands<C>& c, const bool* live, float z,
+                                            float w, int& lo, int& hi)
+{
+    float xlo, xhi;
+    wave_window<C>(c, live, z, w, xlo, xhi);
+    const int a = wave_bound<D, false>(s_hits, lo, hi, xlo);
+    const int b = wave_bound<D, true>(s_hits, lo, hi, xhi);
+    lo = a;
+    hi = max(a, b);
+}
+
+__device__ __forceinline__ float prune_width(const Desc* __restrict__ d, float nc)
+{
+    // nc = -log2(e) / sigma^2
+    return sqrtf(d->prune_u * (-1.44269504088896340736f / nc));
+}
 
 // One pass over all of the event's hits for the lane's C candidates.
 // Tiled events are streamed through LDS; the work-group must call this
 // uniformly then (it contains barriers).
 // `work` (wave-uniform) false: the wave holds no live candidate and only takes
 // part in the tile loads and barriers; its sums stay zero.
-template <int D, int C, bool DERIV, bool DF>
+template <int D, int C, bool DERIV, bool DF, bool PR = false>
 __device__ __forceinline__ void event_pass(const Desc* __restrict__ d, float* s_hits,
                                            const int* s_poff, const EventView& ev,
                                            const Cands<C>& c, const Cands<C>& cl, float nc,
-                                           float (&acc)[C][Acc<D>::N], bool work = true)
+                                           float (&acc)[C][Acc<D>::N], bool work = true,
+                                           const bool* live = nullptr)
 {
+    const float pw = PR && ev.prune ? prune_width(d, nc) : 0.0f;
 #pragma unroll
     for (int j = 0; j < C; ++j)
 #pragma unroll
@@ -187,10 +274,17 @@ __device__ __forceinline__ void event_pass(const Desc* __restrict__ d, float* s_
         if (!work) continue;
         for (int p = 0; p < ev.P; ++p) {
             // LDS values are the same in every lane: keep the loop bounds scalar
-            const int lo = __builtin_amdgcn_readfirstlane(max(s_poff[p], t0));
-            const int hi = __builtin_amdgcn_readfirstlane(min(s_poff[p + 1], t1));
+            int lo = __builtin_amdgcn_readfirstlane(max(s_poff[p], t0)) - t0;
+            int hi = __builtin_amdgcn_readfirstlane(min(s_poff[p + 1], t1)) - t0;
             if (lo >= hi) continue;
-            seg_accumulate<D, C, DERIV, DF>(s_hits, lo - t0, hi - t0, d->plane_z[p], c, cl, nc, acc);
+            const float z = d->plane_z[p];
+            if constexpr (PR) {
+                if (ev.prune) {
+                    prune_range<D, C>(s_hits, c, live, z, pw, lo, hi);
+                    if (lo >= hi) continue;
+                }
+            }
+            seg_accumulate<D, C, DERIV, DF>(s_hits, lo, hi, z, c, cl, nc, acc);
         }
     }
 }
@@ -200,12 +294,18 @@ __device__ __forceinline__ void event_pass(const Desc* __restrict__ d, float* s_
 // wave may hold different parts: hit reads are then per lane).  The per-pair
 // arithmetic is seg_accumulate's; per-plane sums are added in plane order.
 // Same barrier rule as event_pass.
-template <int D>
+template <int D, bool PR = false>
 __device__ __forceinline__ float event_pass_split(const Desc* __restrict__ d, float* s_hits, const int* s_poff,
                                                   const EventView& ev, const float* th, float nc, int part,
-                                                  int parts)
+                                                  int parts, bool live = true)
 {
     float R = 0.0f;
+    const float pw = PR && ev.prune ? prune_width(d, nc) : 0.0f;
+    // the window of every point the wave holds (each wave holds all of them)
+    Cands<1> wc;
+    if constexpr (D == 2) { wc.o[0][0] = th[0]; wc.t[0][0] = th[2]; }
+    else { wc.o[0][0] = th[0]; wc.t[0][0] = th[1]; }
+    const bool wl[1] = {live};
     for (int t0 = 0; t0 < ev.n; t0 += ev.tile_cap) {
         const int t1 = min(ev.n, t0 + ev.tile_cap);
         if (!ev.resident) {
@@ -220,15 +320,21 @@ __device__ __forceinline__ float event_pass_split(const Desc* __restrict__ d, fl
             __syncthreads();
         }
         for (int p = 0; p < ev.P; ++p) {
-            const int lo = __builtin_amdgcn_readfirstlane(max(s_poff[p], t0));
-            const int hi = __builtin_amdgcn_readfirstlane(min(s_poff[p + 1], t1));
+            int lo = __builtin_amdgcn_readfirstlane(max(s_poff[p], t0)) - t0;
+            int hi = __builtin_amdgcn_readfirstlane(min(s_poff[p + 1], t1)) - t0;
             if (lo >= hi) continue;
             const float z = d->plane_z[p];
+            if constexpr (PR) {
+                if (ev.prune) {
+                    prune_range<D, 1>(s_hits, wc, wl, z, pw, lo, hi);
+                    if (lo >= hi) continue;
+                }
+            }
             float pe = 0.0f;
             // two hits per iteration, the next two read while these are summed;
             // indices are clamped to the segment, so every read is in bounds
-            const int last = hi - 1 - t0;
-            int k = lo - t0 + part;
+            const int last = hi - 1;
+            int k = lo + part;
             if constexpr (D == 2) {
                 const float2* h = reinterpret_cast<const float2*>(s_hits);
                 auto term = [&](const float2 v) {
@@ -267,13 +373,14 @@ __device__ __forceinline__ float event_pass_split(const Desc* __restrict__ d, fl
 // R-only pass over part `part` of `parts` of every plane segment (the waves of a
 // work-group split the hits; their partial sums are added afterwards in a
 // fixed order).  Same barrier rule as event_pass.
-template <int D, int C>
+template <int D, int C, bool PR = false>
 __device__ __forceinline__ void event_pass_part(const Desc* __restrict__ d, float* s_hits,
                                                 const int* s_poff, const EventView& ev,
                                                 const Cands<C>& c, float nc, int part, int parts,
-                                                float (&acc)[C][Acc<D>::N])
+                                                float (&acc)[C][Acc<D>::N], const bool* live = nullptr)
 {
     const Cands<C> zero_c = {};
+    const float pw = PR && ev.prune ? prune_width(d, nc) : 0.0f;
 #pragma unroll
     for (int j = 0; j < C; ++j) acc[j][0] = 0.0f;
     for (int t0 = 0; t0 < ev.n; t0 += ev.tile_cap) {
@@ -290,14 +397,21 @@ __device__ __forceinline__ void event_pass_part(const Desc* __restrict__ d, floa
             __syncthreads();
         }
         for (int p = 0; p < ev.P; ++p) {
-            const int lo = __builtin_amdgcn_readfirstlane(max(s_poff[p], t0));
-            const int hi = __builtin_amdgcn_readfirstlane(min(s_poff[p + 1], t1));
+            int lo = __builtin_amdgcn_readfirstlane(max(s_poff[p], t0)) - t0;
+            int hi = __builtin_amdgcn_readfirstlane(min(s_poff[p + 1], t1)) - t0;
             if (lo >= hi) continue;
+            const float z = d->plane_z[p];
+            if constexpr (PR) {
+                if (ev.prune) {
+                    prune_range<D, C>(s_hits, c, live, z, pw, lo, hi);
+                    if (lo >= hi) continue;
+                }
+            }
             const int len = hi - lo;
             const int a = lo + (len * part) / parts;
             const int b = lo + (len * (part + 1)) / parts;
             if (a >= b) continue;
-            seg_accumulate<D, C, false, false>(s_hits, a - t0, b - t0, d->plane_z[p], c, zero_c, nc, acc);
+            seg_accumulate<D, C, false, false>(s_hits, a, b, z, c, zero_c, nc, acc);
         }
     }
 }
@@ -511,6 +625,7 @@ __device__ __forceinline__ EventView begin_event(const Desc* __restrict__ d, int
     ev.g_hits = d->hits + (int64_t)base * d->meas_dim;
     ev.tile_cap = tile_cap;
     ev.resident = ev.n <= tile_cap;
+    ev.prune = d->prune_u > 0.0f && parts == 1 && d->ev_sorted != nullptr && d->ev_sorted[e] != 0;
     if ((int)threadIdx.x <= P) s_poff[threadIdx.x] = min(max(po[threadIdx.x] - base, 0), h1 - h0);
     if (ev.resident) {
         if (d->meas_dim == 2) {
@@ -542,7 +657,7 @@ __device__ __forceinline__ void lattice_point(const Desc* __restrict__ d, int i,
 // Update rules of the inner loop (U): 0 truncated Newton, 1 normalised
 // gradient, 2 BFGS.  The rule is a template parameter so that the default
 // Newton kernels carry no quasi-Newton state.
-template <int D, int C, int U = 0>
+template <int D, int C, int U = 0, bool PR = false>
 __global__ __launch_bounds__(kBlock) void k_ascent(const Desc* __restrict__ d, int tile_cap)
 {
     constexpr int NP = 2 * D;
@@ -617,7 +732,7 @@ __global__ __launch_bounds__(kBlock) void k_ascent(const Desc* __restrict__ d, i
 #pragma unroll
             for (int j = 0; j < C; ++j) set_cand<D, C>(c, j, th[j]);
             float acc[C][NA];
-            event_pass<D, C, true, false>(d, s_hits, s_poff, ev, c, zero_c, nc, acc, wave_work);
+            event_pass<D, C, true, false, PR>(d, s_hits, s_poff, ev, c, zero_c, nc, acc, wave_work, active);
             float p[C][NP], Rc[C], gp[C], alpha[C];
             bool pend[C];
             int trial[C];
@@ -775,7 +890,7 @@ __global__ __launch_bounds__(kBlock) void k_ascent(const Desc* __restrict__ d, i
                     float lt[NP];
 #pragma unroll
                     for (int a = 0; a < NP; ++a) lt[a] = pt < npend ? s_lth[pt][a] : 0.0f;
-                    s_red[threadIdx.x] = event_pass_split<D>(d, s_hits, s_poff, ev, lt, nc, part, parts);
+                    s_red[threadIdx.x] = event_pass_split<D, PR>(d, s_hits, s_poff, ev, lt, nc, part, parts, pt < npend);
                     __syncthreads();  // every thread holds its point and partial
                     if (part == 0 && pt < npend) {
                         float Rt = 0.0f;
@@ -801,7 +916,7 @@ __global__ __launch_bounds__(kBlock) void k_ascent(const Desc* __restrict__ d, i
                         }
                         __syncthreads();  // all waves hold the round's points before partials overwrite them
                         float racc[C][NA];
-                        event_pass_part<D, C>(d, s_hits, s_poff, ev, cc, nc, wave, kBlock / kWave, racc);
+                        event_pass_part<D, C, PR>(d, s_hits, s_poff, ev, cc, nc, wave, kBlock / kWave, racc, live);
 #pragma unroll
                         for (int j = 0; j < C; ++j)
                             if (live[j]) s_lth[ent[j]][wave] = racc[j][0];
@@ -870,7 +985,7 @@ __global__ __launch_bounds__(kBlock) void k_ascent(const Desc* __restrict__ d, i
                 set_cand<D, C>(cl, j, lo);
             }
             float acc[C][NA];
-            event_pass<D, C, true, true>(d, s_hits, s_poff, ev, ch, cl, ncf, acc, wave_work);
+            event_pass<D, C, true, true, PR>(d, s_hits, s_poff, ev, ch, cl, ncf, acc, wave_work, active);
 #pragma unroll
             for (int j = 0; j < C; ++j) {
                 double g[NP], H[NP][NP], A[NP][NP], dl[NP];
@@ -1102,6 +1217,17 @@ void launch_ascent(const Desc* d, int D, const HotConfig& c, hipStream_t st)
 {
     const size_t lds = hot_lds_bytes(D, c);
     const dim3 g(c.grid), b(kBlock);
+    if (c.prune) {
+        // locality-pruned passes (truncated Newton)
+        if (D == 2) {
+            if (c.cand == 2) hipLaunchKernelGGL((k_ascent<2, 2, 0, true>), g, b, lds, st, d, c.tile_hits);
+            else hipLaunchKernelGGL((k_ascent<2, 1, 0, true>), g, b, lds, st, d, c.tile_hits);
+        } else {
+            if (c.cand == 2) hipLaunchKernelGGL((k_ascent<1, 2, 0, true>), g, b, lds, st, d, c.tile_hits);
+            else hipLaunchKernelGGL((k_ascent<1, 1, 0, true>), g, b, lds, st, d, c.tile_hits);
+        }
+        return;
+    }
     if (c.update != 0) {
         // the alternative update rules run one candidate per lane
         if (D == 2) {

@@ -1239,12 +1239,37 @@ __global__ __launch_bounds__(256) void k_propose_select(ProposeArgs a)
                 __syncthreads();
             }
         const int keep = min(nc, a.k_max);
+        // the kept bins are emitted in bin order (tx bin major): a wavefront's
+        // seeds then sit in a narrow slope band, which keeps pruned passes short
+        int kp2 = 1;
+        while (kp2 < keep) kp2 <<= 1;
+        for (int i = threadIdx.x; i < kp2; i += blockDim.x) {
+            uint64_t v = ~0ull;
+            if (i < keep) {
+                const uint64_t key = s_key[i];
+                v = ((uint64_t)(0xFFFFFFFFu - (uint32_t)(key & 0xFFFFFFFFull)) << 32) | (key >> 32);
+            }
+            s_key[i] = v;
+        }
+        __syncthreads();
+        for (int k = 2; k <= kp2; k <<= 1)
+            for (int j = k >> 1; j > 0; j >>= 1) {
+                for (int i = threadIdx.x; i < kp2; i += blockDim.x) {
+                    const int l = i ^ j;
+                    if (l > i) {
+                        const uint64_t x = s_key[i], y = s_key[l];
+                        const bool up = (i & k) == 0;
+                        if (up ? (x > y) : (x < y)) { s_key[i] = y; s_key[l] = x; }
+                    }
+                }
+                __syncthreads();
+            }
         for (int i = threadIdx.x; i < keep; i += blockDim.x) {
             const uint64_t key = s_key[i];
-            uint32_t b = (uint32_t)(key >> 32);
+            uint32_t b = (uint32_t)(key & 0xFFFFFFFFull);
             b = (b & 0x80000000u) ? (b & 0x7FFFFFFFu) : ~b;
             a.cand_score[e * a.k_max + i] = __uint_as_float(b);
-            a.cand_pix[e * a.k_max + i] = (int32_t)(0xFFFFFFFFu - (uint32_t)(key & 0xFFFFFFFFull));
+            a.cand_pix[e * a.k_max + i] = (int32_t)(key >> 32);
         }
         if (threadIdx.x == 0) {
             a.confidence[e] = 1.0f / (1.0f + expf(-s_best[0]));

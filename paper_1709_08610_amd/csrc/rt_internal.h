@@ -99,6 +99,8 @@ struct Desc {
     float sigma_final;
     int32_t n_final_steps, n_polish, ls_trials, n_slope_steps;
     float armijo_c1, step_cap, small_step, conv_tol, R0, d_merge;
+    float prune_u;               // > 0: skip hits farther than sqrt(prune_u) sigma in x from every candidate
+    int32_t* ev_sorted;          // n_events: 1 when every plane segment is sorted by x (pruning allowed)
     // work items
     int32_t seeds_per_item;
     int32_t* order;              // events, longest first
@@ -132,6 +134,7 @@ struct Desc {
 // launchers (one per translation unit); all asynchronous on `st`
 void launch_reset(const Desc* d, hipStream_t st);
 void launch_stage(const Desc* d, int grid, hipStream_t st);
+void launch_sort_planes(const Desc* d, int grid, hipStream_t st);
 void launch_plan_tracks(const Desc* d, hipStream_t st);
 void launch_plan_response(const Desc* d, hipStream_t st);
 void launch_plan_grid(const Desc* d, hipStream_t st);
@@ -141,6 +144,7 @@ struct HotConfig {
     int tile_hits;   // LDS capacity in hits
     int grid;        // persistent work-groups
     int update = 0;  // ascent update rule: 0 Newton, 1 gradient, 2 BFGS (cand 1)
+    int prune = 0;   // locality-pruned passes (hits sorted by x per plane first)
 };
 int hot_seeds_per_item(const HotConfig& c);
 void launch_ascent(const Desc* d, int meas_dim, const HotConfig& c, hipStream_t st);

@@ -81,7 +81,11 @@ __global__ __launch_bounds__(kBlock) void k_stage(const Desc* __restrict__ d)
         int cursor = (int)a + incl - c;  // lane p: next free slot of plane p
         int32_t* po = d->plane_off + e * (P + 1);
         if (lane < P) po[lane] = cursor;
-        if (lane == 0) { po[P] = (int)b; d->ev_nhits[e] = (int)(b - a); }
+        if (lane == 0) {
+            po[P] = (int)b;
+            d->ev_nhits[e] = (int)(b - a);
+            if (d->ev_sorted) d->ev_sorted[e] = 1;  // cleared by k_sort_planes for an unsortable plane
+        }
         for (int64_t k0 = a; k0 < b; k0 += kWave) {
             const int64_t k = k0 + lane;
             const bool live = k < b;
@@ -114,6 +118,62 @@ __global__ __launch_bounds__(kBlock) void k_stage(const Desc* __restrict__ d)
         }
     }
     if (err) atomicOr(&d->cnt->err, err);
+}
+
+// ---------------------------------------------------------------- sorting
+// Pruned passes need every plane segment of an event sorted by x (the first
+// measured coordinate).  One work-group per (event, plane) segment of at most
+// kSortCap hits: a bitonic sort in LDS, padding with +inf keys; an event with
+// a longer segment is marked unsorted and its passes stay unpruned.
+constexpr int kSortCap = 4096;
+
+__global__ __launch_bounds__(kBlock) void k_sort_planes(const Desc* __restrict__ d)
+{
+    __shared__ float2 s_h[kSortCap];
+    if (d->cnt->err) return;
+    const int P = d->n_planes;
+    const int D = d->meas_dim;
+    const int64_t n_seg = d->n_events * P;
+    for (int64_t sg = blockIdx.x; sg < n_seg; sg += gridDim.x) {
+        const int64_t e = sg / P;
+        const int p = (int)(sg % P);
+        const int32_t* po = d->plane_off + e * (P + 1);
+        const int lo = po[p], len = po[p + 1] - po[p];
+        if (len > kSortCap) {
+            if (threadIdx.x == 0) d->ev_sorted[e] = 0;
+            continue;
+        }
+        if (len <= 1) continue;
+        int n_pad = 1;
+        while (n_pad < len) n_pad <<= 1;
+        for (int i = threadIdx.x; i < n_pad; i += blockDim.x) {
+            float2 v = make_float2(INFINITY, 0.0f);
+            if (i < len) {
+                if (D == 2) v = reinterpret_cast<const float2*>(d->hits)[lo + i];
+                else v.x = d->hits[lo + i];
+            }
+            s_h[i] = v;
+        }
+        __syncthreads();
+        for (int k = 2; k <= n_pad; k <<= 1) {
+            for (int j = k >> 1; j > 0; j >>= 1) {
+                for (int i = threadIdx.x; i < n_pad; i += blockDim.x) {
+                    const int l = i ^ j;
+                    if (l > i) {
+                        const float2 a = s_h[i], b = s_h[l];
+                        const bool up = (i & k) == 0;
+                        if (up ? (a.x > b.x) : (a.x < b.x)) { s_h[i] = b; s_h[l] = a; }
+                    }
+                }
+                __syncthreads();
+            }
+        }
+        for (int i = threadIdx.x; i < len; i += blockDim.x) {
+            if (D == 2) reinterpret_cast<float2*>(d->hits)[lo + i] = s_h[i];
+            else d->hits[lo + i] = s_h[i].x;
+        }
+        __syncthreads();  // the LDS buffer is reused by the next segment
+    }
 }
 
 // ---------------------------------------------------------------- planning
@@ -239,6 +299,11 @@ void launch_reset(const Desc* d, hipStream_t st)
 void launch_stage(const Desc* d, int grid, hipStream_t st)
 {
     hipLaunchKernelGGL(k_stage, dim3(grid), dim3(kBlock), 0, st, d);
+}
+
+void launch_sort_planes(const Desc* d, int grid, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_sort_planes, dim3(grid), dim3(kBlock), 0, st, d);
 }
 
 void launch_plan_tracks(const Desc* d, hipStream_t st)

@@ -50,7 +50,8 @@ class Params(ctypes.Structure):
                 ("conv_tol", ctypes.c_float), ("R0", ctypes.c_float), ("d_merge", ctypes.c_float),
                 ("seed_mode", ctypes.c_int32), ("lattice_n", ctypes.c_int32 * 2),
                 ("lattice_lo", ctypes.c_float * 2), ("lattice_hi", ctypes.c_float * 2),
-                ("seeds", ctypes.c_void_p), ("seed_offsets", ctypes.c_void_p), ("update", ctypes.c_int32)]
+                ("seeds", ctypes.c_void_p), ("seed_offsets", ctypes.c_void_p), ("update", ctypes.c_int32),
+                ("prune_u", ctypes.c_float)]
 
 
 class Track(ctypes.Structure):
@@ -310,6 +311,7 @@ class Context:
         P.lattice_lo[:] = list(params["lattice_lo"])
         P.lattice_hi[:] = list(params["lattice_hi"])
         P.update = UPDATE_RULES[params.get("update", "newton")]
+        P.prune_u = float(params.get("prune_u", 0.0))
         if seeds is not None:
             P.seed_mode = SEED_EXPLICIT
             if mem == MEM_HOST:

@@ -121,7 +121,7 @@ def test_trained_seeds_and_tracks_match_oracle(setup):
     ref_seeds, ref_off, same = [], [0], True
     for e, img in enumerate(_oracle_images(sub)):
         _, z = op.forward(img, layers, store_bf16=True)
-        picks = op.nms_topk(z, LS["tau"], LS["k_max"], nms=LS["nms"])
+        picks = op.seed_bins(z, LS["tau"], LS["k_max"], nms=LS["nms"])
         a, c = int(res["seed_offsets"][e]), int(res["seed_offsets"][e + 1])
         s = res["seeds"][a:c]
         gpix = set((np.floor((s[:, 2] - lo) / w).astype(int) * op.IMG + np.floor((s[:, 3] - lo) / w).astype(int)))

@@ -261,7 +261,7 @@ def _oracle_seeds(b, layers, lattice_params, nms, k_max=K_MAX, tau=TAU, conf_min
     lat = oracle.lattice(2, lattice_params)
     for e, img in enumerate(_oracle_images(b)):
         _, z = op.forward(img, layers, store_bf16=True)
-        picks = op.nms_topk(z, tau, k_max, nms=nms)
+        picks = op.seed_bins(z, tau, k_max, nms=nms)
         conf.append(1.0 / (1.0 + np.exp(-z.max())))
         if not picks or z.max() < op.logit_threshold(conf_min):
             fb.append(1)

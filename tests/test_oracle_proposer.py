@@ -186,3 +186,11 @@ def test_logit_threshold():
     assert op.logit_threshold(0.0) == -np.inf and op.logit_threshold(1.0) == np.inf
     assert op.logit_threshold(0.9) == pytest.approx(np.log(9), rel=1e-7)
     assert op.logit_threshold(0.9) == float(np.float32(op.logit_threshold(0.9)))
+
+
+def test_seed_bins_are_the_selection_in_bin_order():
+    z = np.round(np.random.default_rng(9).normal(size=(16, 16)), 1)
+    for nms in (False, True):
+        sel = op.nms_topk(z, 0.3, 20, nms=nms)
+        got = op.seed_bins(z, 0.3, 20, nms=nms)
+        assert got == sorted(sel) and len(got) == len(set(got))
