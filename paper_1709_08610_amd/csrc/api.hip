@@ -62,7 +62,7 @@ struct retina_ctx {
     // (meas_dim, launch shape, profiling) serves any batch
     bool use_graphs = true;
     struct GraphEntry {
-        int D, cand, tile, grid, prof, update, prune;
+        int D, cand, tile, grid, prof, update, prune, staged;
         hipGraphExec_t exec;
     };
     std::vector<GraphEntry> graphs;
@@ -328,7 +328,7 @@ void tracks_sequence(retina_ctx* c, int D, const HotConfig& hc, hipStream_t st)
     };
     mark(0);
     launch_reset(c->d_desc, st);
-    launch_stage(c->d_desc, c->n_cu * 8, st);
+    if (!hc.staged) launch_stage(c->d_desc, c->n_cu * 8, st);
     if (hc.prune) launch_sort_planes(c->d_desc, c->n_cu * 8, st);
     mark(1);
     launch_plan_tracks(c->d_desc, st);
@@ -352,7 +352,8 @@ int run_tracks(retina_ctx* c, int D, const HotConfig& hc)
         hipGraphExec_t exec = nullptr;
         for (auto& g : c->graphs)
             if (g.D == D && g.cand == hc.cand && g.tile == hc.tile_hits && g.grid == hc.grid &&
-                g.prof == (int)c->prof && g.update == hc.update && g.prune == hc.prune)
+                g.prof == (int)c->prof && g.update == hc.update && g.prune == hc.prune &&
+                g.staged == hc.staged)
                 exec = g.exec;
         if (!exec) {
             hipGraph_t graph = nullptr;
@@ -368,7 +369,8 @@ int run_tracks(retina_ctx* c, int D, const HotConfig& hc)
                 (void)hipGetLastError();
                 c->use_graphs = false;  // capture unsupported here: launch eagerly from now on
             } else {
-                c->graphs.push_back({D, hc.cand, hc.tile_hits, hc.grid, (int)c->prof, hc.update, hc.prune, exec});
+                c->graphs.push_back({D, hc.cand, hc.tile_hits, hc.grid, (int)c->prof, hc.update, hc.prune, hc.staged,
+                                     exec});
             }
         }
         if (exec) {
@@ -778,7 +780,7 @@ int retina_grid_search(retina_ctx* c, const retina_geometry* g, const retina_hit
 static int find_tracks_impl(retina_ctx* c, const retina_geometry* g, const retina_hits* h,
                             const retina_params* P, retina_track* tracks, int64_t capacity,
                             int64_t* track_offsets, int32_t* event_flags, const retina_seed_out* so,
-                            bool seeds_dev)
+                            bool seeds_dev, bool staged = false)
 {
     if (!c) return RETINA_ERR_INVALID_ARG;
     c->err.clear();
@@ -866,6 +868,7 @@ static int find_tracks_impl(retina_ctx* c, const retina_geometry* g, const retin
         hc.update = P->update;
     }
     hc.prune = P->prune_u > 0.0f;
+    hc.staged = staged;
     d.seeds_per_item = hot_seeds_per_item(hc);
     d.items_cap = n_seeds / d.seeds_per_item + E + 1;
     if ((rc = ensure_t(c, B_ITEMS, (size_t)d.items_cap, &d.items))) return rc;
@@ -1601,7 +1604,8 @@ int retina_find_tracks_learned(retina_ctx* c, const retina_geometry* g, const re
     Q.seed_mode = RETINA_SEED_EXPLICIT;
     Q.seeds = pa.seeds;
     Q.seed_offsets = pa.seed_off;
-    rc = find_tracks_impl(c, g, h, &Q, tracks, capacity, track_offsets, event_flags, nullptr, true);
+    // the proposer staged these hits into the same buffers (and validated them)
+    rc = find_tracks_impl(c, g, h, &Q, tracks, capacity, track_offsets, event_flags, nullptr, true, true);
     if (rc) return rc;
     if (event_flags) {
         const int64_t E = h->n_events;

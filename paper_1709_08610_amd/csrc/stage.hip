@@ -14,6 +14,10 @@ namespace rt {
 
 __global__ void k_reset(const Desc* __restrict__ d)
 {
+    // pruning: every event starts sortable; k_sort_planes clears the flag of an
+    // event with a plane too long to sort
+    if (d->ev_sorted)
+        for (int64_t e = threadIdx.x; e < d->n_events; e += blockDim.x) d->ev_sorted[e] = 1;
     if (threadIdx.x == 0) {
         Counters* c = d->cnt;
         c->item = 0;
@@ -84,7 +88,6 @@ __global__ __launch_bounds__(kBlock) void k_stage(const Desc* __restrict__ d)
         if (lane == 0) {
             po[P] = (int)b;
             d->ev_nhits[e] = (int)(b - a);
-            if (d->ev_sorted) d->ev_sorted[e] = 1;  // cleared by k_sort_planes for an unsortable plane
         }
         for (int64_t k0 = a; k0 < b; k0 += kWave) {
             const int64_t k = k0 + lane;
