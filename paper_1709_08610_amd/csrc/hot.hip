@@ -883,19 +883,22 @@ __global__ __launch_bounds__(kBlock) void k_ascent(const Desc* __restrict__ d, i
                 const int npend = __builtin_amdgcn_readfirstlane(s_npend);
                 if (npend == 0) break;
                 if (C == 1 && npend <= kWave) {
-                    int per = 1;  // points: a power of two, <= 64
-                    while (per < npend) per <<= 1;
+                    // npend points, parts = 256 / npend threads on each (the last
+                    // 256 - parts * npend threads duplicate a part and are not read)
+                    const int per = npend;
                     const int parts = kBlock / per;
-                    const int pt = threadIdx.x & (per - 1), part = threadIdx.x / per;
+                    const int used = parts * per;
+                    const bool in = (int)threadIdx.x < used;
+                    const int pt = in ? (int)threadIdx.x % per : 0, part = in ? (int)threadIdx.x / per : 0;
                     float lt[NP];
 #pragma unroll
-                    for (int a = 0; a < NP; ++a) lt[a] = pt < npend ? s_lth[pt][a] : 0.0f;
-                    s_red[threadIdx.x] = event_pass_split<D, PR>(d, s_hits, s_poff, ev, lt, nc, part, parts, pt < npend);
+                    for (int a = 0; a < NP; ++a) lt[a] = s_lth[pt][a];
+                    s_red[threadIdx.x] = event_pass_split<D, PR>(d, s_hits, s_poff, ev, lt, nc, part, parts, in);
                     __syncthreads();  // every thread holds its point and partial
-                    if (part == 0 && pt < npend) {
+                    if ((int)threadIdx.x < per) {
                         float Rt = 0.0f;
-                        for (int q = 0; q < parts; ++q) Rt += s_red[q * per + pt];
-                        s_lth[pt][0] = Rt;
+                        for (int q = 0; q < parts; ++q) Rt += s_red[q * per + threadIdx.x];
+                        s_lth[threadIdx.x][0] = Rt;
                     }
                     ls_pairs += (uint64_t)per * (uint64_t)ev.n;
                 } else {
