@@ -22,6 +22,7 @@ Each true track takes at most one found track, nearest pairs first.
 from __future__ import annotations
 
 import numpy as np
+from scipy.spatial import cKDTree
 
 
 def _endpoints(theta: np.ndarray, meas_dim: int, z0: float, z1: float) -> np.ndarray:
@@ -31,14 +32,18 @@ def _endpoints(theta: np.ndarray, meas_dim: int, z0: float, z1: float) -> np.nda
     return np.concatenate([off + slope * z0, off + slope * z1], axis=1)
 
 
-def _direction_angle(sf, st):
-    """Angle between the directions (tx, ty, 1) of every found / true pair."""
-    u = np.concatenate([sf, np.ones((sf.shape[0], 1))], axis=1)
-    v = np.concatenate([st, np.ones((st.shape[0], 1))], axis=1)
-    u /= np.linalg.norm(u, axis=1, keepdims=True)
-    v /= np.linalg.norm(v, axis=1, keepdims=True)
-    chord = np.linalg.norm(u[:, None, :] - v[None, :, :], axis=2)
-    return 2.0 * np.arcsin(np.minimum(chord / 2.0, 1.0))
+def _close_pairs(a, b, r, p):
+    """Pairs (i, j) with |a[i] - b[j]| <= r in the p-norm (KD-trees), with the
+    distances."""
+    if a.shape[0] == 0 or b.shape[0] == 0:
+        return np.zeros(0, np.int64), np.zeros(0, np.int64), np.zeros(0)
+    m = cKDTree(a).sparse_distance_matrix(cKDTree(b), r, p=p, output_type="ndarray")
+    return m["i"].astype(np.int64), m["j"].astype(np.int64), m["v"]
+
+
+def _unit_directions(slopes):
+    u = np.concatenate([slopes, np.ones((slopes.shape[0], 1))], axis=1)
+    return u / np.linalg.norm(u, axis=1, keepdims=True)
 
 
 def event_quality(meas_dim, found, truth, truth_nhits, tol, z0, z1, eps=1e-3):
@@ -50,26 +55,36 @@ def event_quality(meas_dim, found, truth, truth_nhits, tol, z0, z1, eps=1e-3):
                n_ang=0, n_fake_ang=nf)
     if nf == 0 or nt == 0:
         return out
-    cheb = np.abs(pf[:, None, :] - pt[None, :, :]).max(axis=2)  # Chebyshev separation
-    close = cheb <= tol
-    fi, ti = np.nonzero(close)
-    order = np.argsort(cheb[fi, ti], kind="stable")
+    # end-plane separation (Chebyshev) within tol; greedy, nearest pairs first,
+    # ties in (found, true) index order
+    fi, ti, cheb = _close_pairs(pf, pt, tol, np.inf)
     used_f = np.zeros(nf, bool)
     used_t = np.zeros(nt, bool)
-    for k in order:
+    for k in np.lexsort((ti, fi, cheb)):
         f, t = fi[k], ti[k]
         if not used_f[f] and not used_t[t]:
             used_f[f] = used_t[t] = True
-    near_any = close.any(axis=1)
+    near_any = np.zeros(nf, bool)
+    near_any[fi] = True
     slopes_f = np.asarray(found, np.float64).reshape(nf, -1)[:, meas_dim:]
     slopes_t = np.asarray(truth, np.float64).reshape(nt, -1)[:, meas_dim:]
-    eps_close = np.abs(slopes_f[:, None, :] - slopes_t[None, :, :]).max(axis=2) <= eps
-    eps_ok = eps_close.any(axis=0)
-    ang_close = _direction_angle(slopes_f, slopes_t) <= eps if meas_dim == 2 else eps_close
+    ef, et, _ = _close_pairs(slopes_f, slopes_t, eps, np.inf)
+    eps_t = np.zeros(nt, bool)
+    eps_t[et] = True
+    eps_f = np.zeros(nf, bool)
+    eps_f[ef] = True
+    if meas_dim == 2:
+        # angle between directions <= eps  <=>  chord between unit vectors <= 2 sin(eps / 2)
+        af, at, _ = _close_pairs(_unit_directions(slopes_f), _unit_directions(slopes_t), 2.0 * np.sin(eps / 2.0), 2)
+        ang_t = np.zeros(nt, bool)
+        ang_t[at] = True
+        ang_f = np.zeros(nf, bool)
+        ang_f[af] = True
+    else:
+        ang_t, ang_f = eps_t, eps_f
     out.update(n_matched=int((used_t & rec).sum()), n_fake=int((~near_any).sum()),
-               n_clone=int((near_any & ~used_f).sum()), n_eps=int((eps_ok & rec).sum()),
-               n_fake_eps=int((~eps_close.any(axis=1)).sum()), n_ang=int((ang_close.any(axis=0) & rec).sum()),
-               n_fake_ang=int((~ang_close.any(axis=1)).sum()))
+               n_clone=int((near_any & ~used_f).sum()), n_eps=int((eps_t & rec).sum()),
+               n_fake_eps=int((~eps_f).sum()), n_ang=int((ang_t & rec).sum()), n_fake_ang=int((~ang_f).sum()))
     return out
 
 
