@@ -6,8 +6,8 @@
 //   * a work-group (4 waves) owns one event's hits in LDS and 4*64*C
 //     candidate lines (C per lane, each wave its own 64*C);
 //   * every lane walks the same hit (an LDS broadcast read), so the hit loop
-//     is wave-uniform and the per-pair work is pure VALU: two fused residuals,
-//     one exp2 and six running sums;
+//     is wave-uniform and the per-pair work is pure VALU: two residuals of two
+//     subtractions each, one exp2 and six running sums;
 //   * hits are grouped by plane, where z is constant, so the per-pair sums are
 //     P_e, P_x, P_y, P_xx, P_yy, P_xy and the z-moments are folded once per
 //     plane into 16 accumulators (8 for meas_dim 1);
@@ -15,10 +15,17 @@
 //   * the kernels are persistent: work-groups pull (event, seed block) items
 //     from an atomic cursor over a longest-first list.
 //
-// Residuals are formed as fma(-t, z, x) - x0 so the product t*z is never
-// rounded on its own: x reaches ~260 mm where one FP32 ulp is already
-// ~1.5e-5 mm, too coarse next to a 0.03 mm bandwidth.  The FP64 polish
-// evaluates at an FP64 theta split into two floats (hi + lo) so that the
+// Residuals: x reaches ~260 mm, where one FP32 ulp is already ~1.5e-5 mm,
+// too coarse next to a 0.03 mm bandwidth, so the predicted position
+// x0 + t z of a line on a plane is never rounded to one float.  Once per
+// (line, plane) it is split exactly into s + l (s the rounded value, l its
+// error, from the exact product error of an fma and the exact error of one
+// addition); every hit of the plane then costs (x - s) - l, where x - s is
+// exact whenever x lies within a factor 2 of s (every hit near the line), so
+// the residual carries one rounding of its own size.  Both subtractions take
+// VGPR operands only, which gfx950 issues at twice the rate of an fma with
+// the plane's z in a scalar register.  The FP64 polish evaluates at an FP64
+// theta split into two floats (hi + lo); the low words join l, so the
 // gradient it solves with belongs to the FP64 point.
 #include "rt_internal.h"
 
@@ -41,6 +48,25 @@ struct Cands {
     float t[C][2];
 };
 
+// s + l = o + t z up to ~2^-48 relative (s = fl(o + t z)); with the polish's
+// low words (ol, tl) added to l.
+__device__ __forceinline__ void line_split(float o, float t, float z, float& s, float& l)
+{
+#pragma clang fp contract(off)  // s must be fl(p + o) for the error terms to be exact
+    const float p = t * z;
+    const float pe = __builtin_fmaf(t, z, -p);  // t z - p, exact
+    s = p + o;
+    const float bb = s - p;
+    const float se = (p - (s - bb)) + (o - bb);  // p + o - s, exact
+    l = pe + se;
+}
+
+__device__ __forceinline__ void line_split(float o, float t, float ol, float tl, float z, float& s, float& l)
+{
+    line_split(o, t, z, s, l);
+    l += __builtin_fmaf(tl, z, ol);
+}
+
 // One plane segment [lo, hi) of LDS hits at plane position z.
 template <int D, int C, bool DERIV, bool DF>
 __device__ __forceinline__ void seg_accumulate(const float* __restrict__ s_hits, int lo, int hi,
@@ -48,25 +74,23 @@ __device__ __forceinline__ void seg_accumulate(const float* __restrict__ s_hits,
                                                float nc, float (&acc)[C][Acc<D>::N])
 {
     float pe[C], px[C], py[C], pxx[C], pyy[C], pxy[C];
+    float sp[C][2], lp[C][2];  // the lines' positions on this plane, s + l
 #pragma unroll
-    for (int j = 0; j < C; ++j) { pe[j] = px[j] = py[j] = pxx[j] = pyy[j] = pxy[j] = 0.0f; }
+    for (int j = 0; j < C; ++j) {
+        pe[j] = px[j] = py[j] = pxx[j] = pyy[j] = pxy[j] = 0.0f;
+#pragma unroll
+        for (int m = 0; m < D; ++m) {
+            if (DF) line_split(c.o[j][m], c.t[j][m], cl.o[j][m], cl.t[j][m], z, sp[j][m], lp[j][m]);
+            else line_split(c.o[j][m], c.t[j][m], z, sp[j][m], lp[j][m]);
+        }
+    }
     if constexpr (D == 2) {
         const float2* h = reinterpret_cast<const float2*>(s_hits);
         auto pair = [&](const float2 v) {
 #pragma unroll
             for (int j = 0; j < C; ++j) {
-                float rx = __builtin_fmaf(-c.t[j][0], z, v.x);
-                float ry = __builtin_fmaf(-c.t[j][1], z, v.y);
-                if (DF) {
-                    rx = __builtin_fmaf(-cl.t[j][0], z, rx);
-                    ry = __builtin_fmaf(-cl.t[j][1], z, ry);
-                }
-                rx -= c.o[j][0];
-                ry -= c.o[j][1];
-                if (DF) {
-                    rx -= cl.o[j][0];
-                    ry -= cl.o[j][1];
-                }
+                const float rx = (v.x - sp[j][0]) - lp[j][0];
+                const float ry = (v.y - sp[j][1]) - lp[j][1];
                 const float d2 = __builtin_fmaf(ry, ry, rx * rx);
                 const float e = __builtin_amdgcn_exp2f(d2 * nc);
                 pe[j] += e;
@@ -100,10 +124,7 @@ __device__ __forceinline__ void seg_accumulate(const float* __restrict__ s_hits,
             const float v = s_hits[k];
 #pragma unroll
             for (int j = 0; j < C; ++j) {
-                float r = __builtin_fmaf(-c.t[j][0], z, v);
-                if (DF) r = __builtin_fmaf(-cl.t[j][0], z, r);
-                r -= c.o[j][0];
-                if (DF) r -= cl.o[j][0];
+                const float r = (v - sp[j][0]) - lp[j][0];
                 const float e = __builtin_amdgcn_exp2f((r * r) * nc);
                 pe[j] += e;
                 if (DERIV) {
@@ -337,9 +358,12 @@ __device__ __forceinline__ float event_pass_split(const Desc* __restrict__ d, fl
             int k = lo + part;
             if constexpr (D == 2) {
                 const float2* h = reinterpret_cast<const float2*>(s_hits);
+                float sx, lx, sy, ly;
+                line_split(th[0], th[2], z, sx, lx);
+                line_split(th[1], th[3], z, sy, ly);
                 auto term = [&](const float2 v) {
-                    const float rx = __builtin_fmaf(-th[2], z, v.x) - th[0];
-                    const float ry = __builtin_fmaf(-th[3], z, v.y) - th[1];
+                    const float rx = (v.x - sx) - lx;
+                    const float ry = (v.y - sy) - ly;
                     return __builtin_amdgcn_exp2f(__builtin_fmaf(ry, ry, rx * rx) * nc);
                 };
                 float2 a = h[min(k, last)], b = h[min(k + parts, last)];
@@ -351,8 +375,10 @@ __device__ __forceinline__ float event_pass_split(const Desc* __restrict__ d, fl
                     b = nb;
                 }
             } else {
+                float sx, lx;
+                line_split(th[0], th[1], z, sx, lx);
                 auto term = [&](const float v) {
-                    const float r = __builtin_fmaf(-th[1], z, v) - th[0];
+                    const float r = (v - sx) - lx;
                     return __builtin_amdgcn_exp2f((r * r) * nc);
                 };
                 float a = s_hits[min(k, last)], b = s_hits[min(k + parts, last)];

@@ -16,8 +16,11 @@ def fp32_error_model(D, plane_z, x, y, plane, theta, sigma, chunk=2048):
 
     For every theta returns (E, S): E = (E_R, E_G, E_H) bounds the sum over hits of
     each term's absolute error and S = (S_R, S_G, S_H) sums the terms' absolute
-    values.  A residual formed as fma(-t, z, x) - x0 carries an absolute error
-    eps_r <= u(|x - t z| + |r|); exp(-r^2/sigma^2) then carries a relative error
+    values.  The kernels form a residual as (x - s) - l, with s + l = x0 + t z
+    split exactly once per plane: x - s is exact when x is within a factor 2 of
+    s and otherwise rounds by u|x - s|, the subtraction of l rounds by u|r|, and
+    l itself is rounded at u|l| <= 2u^2(|t z| + |x0|), so
+    eps_r <= u(2|r| + 4u(|x| + |t z| + |x0|)); exp(-r^2/sigma^2) then carries a relative error
     2|r| eps_r / sigma^2 plus the rounding of its argument (~4u(1 + r^2/sigma^2));
     gradient and Hessian terms also carry eps_r through their residual factors.
     Summation adds ~sqrt(N) u of S (applied by assert_response_bounded)."""
@@ -37,21 +40,21 @@ def fp32_error_model(D, plane_z, x, y, plane, theta, sigma, chunk=2048):
     for i0 in range(0, n, chunk):
         th = theta[i0:i0 + chunk]
         if D == 2:
-            ux = x[None, :] - th[:, 2:3] * z[None, :]
-            uy = y[None, :] - th[:, 3:4] * z[None, :]
-            rx = ux - th[:, 0:1]
-            ry = uy - th[:, 1:2]
-            ex = U32 * (np.abs(ux) + np.abs(rx))
-            ey = U32 * (np.abs(uy) + np.abs(ry))
+            tzx = th[:, 2:3] * z[None, :]
+            tzy = th[:, 3:4] * z[None, :]
+            rx = x[None, :] - tzx - th[:, 0:1]
+            ry = y[None, :] - tzy - th[:, 1:2]
+            ex = U32 * (2 * np.abs(rx) + 4 * U32 * (np.abs(x)[None, :] + np.abs(tzx) + np.abs(th[:, 0:1])))
+            ey = U32 * (2 * np.abs(ry) + 4 * U32 * (np.abs(y)[None, :] + np.abs(tzy) + np.abs(th[:, 1:2])))
             a = (rx ** 2 + ry ** 2) / s2
             rel = 2 * (np.abs(rx) * ex + np.abs(ry) * ey) / s2 + 4 * U32 * (1 + a)
             comps = [np.abs(rx), np.abs(ry), np.abs(rx) * z, np.abs(ry) * z]
             errs = [ex, ey, ex * z, ey * z]
             phi = [(1.0, 0.0), (0.0, 1.0), (z, 0.0), (0.0, z)]
         else:
-            u = x[None, :] - th[:, 1:2] * z[None, :]
-            r = u - th[:, 0:1]
-            e_r = U32 * (np.abs(u) + np.abs(r))
+            tz = th[:, 1:2] * z[None, :]
+            r = x[None, :] - tz - th[:, 0:1]
+            e_r = U32 * (2 * np.abs(r) + 4 * U32 * (np.abs(x)[None, :] + np.abs(tz) + np.abs(th[:, 0:1])))
             a = r ** 2 / s2
             rel = 2 * np.abs(r) * e_r / s2 + 4 * U32 * (1 + a)
             comps = [np.abs(r), np.abs(r) * z]
