@@ -32,6 +32,9 @@
 namespace rt {
 
 constexpr float kLog2e = 1.44269504088896340736f;
+// spare hit entries after the LDS tile: the meas_dim-2 hit loop reads two
+// entries ahead of the segment it walks, up to index tile_hits + 1
+constexpr int kTilePad = 2;
 
 template <int D>
 struct Acc;  // number of accumulators
@@ -106,12 +109,13 @@ __device__ __forceinline__ void seg_accumulate(const float* __restrict__ s_hits,
             }
         };
         // two hits per iteration; the next two are read from LDS while these
-        // are processed (indices clamped to the segment: every read is in bounds)
-        const int last = hi - 1;
-        float2 a = h[lo], b = h[min(lo + 1, last)];
+        // are processed.  The reads run up to 2 entries past the segment: the
+        // LDS tile carries kTilePad spare entries, so they stay inside it, and
+        // their values are never used.
+        float2 a = h[lo], b = h[lo + 1];
         int k = lo;
         for (; k + 1 < hi; k += 2) {
-            const float2 na = h[min(k + 2, last)], nb = h[min(k + 3, last)];
+            const float2 na = h[k + 2], nb = h[k + 3];
             pair(a);
             pair(b);
             a = na;
@@ -1221,7 +1225,7 @@ void launch_response_reduce(const Desc* d, int D, bool deriv, int64_t n_theta, h
 // ------------------------------------------------------------------ launch
 int hot_seeds_per_item(const HotConfig& c) { return (kBlock / kWave) * kWave * c.cand; }
 
-size_t hot_lds_bytes(int meas_dim, const HotConfig& c) { return (size_t)c.tile_hits * meas_dim * sizeof(float); }
+size_t hot_lds_bytes(int meas_dim, const HotConfig& c) { return (size_t)(c.tile_hits + kTilePad) * meas_dim * sizeof(float); }
 
 template <typename K>
 static int occupancy(K kern, size_t lds)
