@@ -32,9 +32,9 @@
 namespace rt {
 
 constexpr float kLog2e = 1.44269504088896340736f;
-// spare hit entries after the LDS tile: the meas_dim-2 hit loop reads two
-// entries ahead of the segment it walks, up to index tile_hits + 1
-constexpr int kTilePad = 2;
+// spare hit entries after the LDS tile: the meas_dim-2 hit loops read ahead
+// of the segment they walk, up to index tile_hits + 3 (half-split lanes)
+constexpr int kTilePad = 4;
 
 template <int D>
 struct Acc;  // number of accumulators
@@ -70,8 +70,10 @@ __device__ __forceinline__ void line_split(float o, float t, float ol, float tl,
     l += __builtin_fmaf(tl, z, ol);
 }
 
-// One plane segment [lo, hi) of LDS hits at plane position z.
-template <int D, int C, bool DERIV, bool DF>
+// One plane segment [lo, hi) of LDS hits at plane position z.  HS (half
+// split): the two 32-lane halves of the wave hold the same candidates and walk
+// alternate hits (lanes 32-63 start one later); event_pass adds the halves.
+template <int D, int C, bool DERIV, bool DF, bool HS = false>
 __device__ __forceinline__ void seg_accumulate(const float* __restrict__ s_hits, int lo, int hi,
                                                float z, const Cands<C>& c, const Cands<C>& cl,
                                                float nc, float (&acc)[C][Acc<D>::N])
@@ -109,22 +111,37 @@ __device__ __forceinline__ void seg_accumulate(const float* __restrict__ s_hits,
             }
         };
         // two hits per iteration; the next two are read from LDS while these
-        // are processed.  The reads run up to 2 entries past the segment: the
-        // LDS tile carries kTilePad spare entries, so they stay inside it, and
-        // their values are never used.
-        float2 a = h[lo], b = h[lo + 1];
-        int k = lo;
-        for (; k + 1 < hi; k += 2) {
-            const float2 na = h[k + 2], nb = h[k + 3];
-            pair(a);
-            pair(b);
-            a = na;
-            b = nb;
+        // are processed.  The reads run up to 2 entries (HS: 3) past the
+        // segment: the LDS tile carries kTilePad spare entries, so they stay
+        // inside it, and their values are never used.
+        if constexpr (HS) {
+            const int k0 = lo + (int)(__lane_id() >> 5);
+            float2 a = h[k0], b = h[k0 + 2];
+            int k = k0;
+            for (; k + 2 < hi; k += 4) {
+                const float2 na = h[k + 4], nb = h[k + 6];
+                pair(a);
+                pair(b);
+                a = na;
+                b = nb;
+            }
+            if (k < hi) pair(a);
+        } else {
+            float2 a = h[lo], b = h[lo + 1];
+            int k = lo;
+            for (; k + 1 < hi; k += 2) {
+                const float2 na = h[k + 2], nb = h[k + 3];
+                pair(a);
+                pair(b);
+                a = na;
+                b = nb;
+            }
+            if (k < hi) pair(a);
         }
-        if (k < hi) pair(a);
     } else {
+        const int k0 = HS ? lo + (int)(__lane_id() >> 5) : lo;
 #pragma unroll 4
-        for (int k = lo; k < hi; ++k) {
+        for (int k = k0; k < hi; k += HS ? 2 : 1) {
             const float v = s_hits[k];
 #pragma unroll
             for (int j = 0; j < C; ++j) {
@@ -271,7 +288,7 @@ __device__ __forceinline__ float prune_width(const Desc* __restrict__ d, float n
 // uniformly then (it contains barriers).
 // `work` (wave-uniform) false: the wave holds no live candidate and only takes
 // part in the tile loads and barriers; its sums stay zero.
-template <int D, int C, bool DERIV, bool DF, bool PR = false>
+template <int D, int C, bool DERIV, bool DF, bool PR = false, bool HS = false>
 __device__ __forceinline__ void event_pass(const Desc* __restrict__ d, float* s_hits,
                                            const int* s_poff, const EventView& ev,
                                            const Cands<C>& c, const Cands<C>& cl, float nc,
@@ -309,8 +326,15 @@ __device__ __forceinline__ void event_pass(const Desc* __restrict__ d, float* s_
                     if (lo >= hi) continue;
                 }
             }
-            seg_accumulate<D, C, DERIV, DF>(s_hits, lo, hi, z, c, cl, nc, acc);
+            seg_accumulate<D, C, DERIV, DF, HS>(s_hits, lo, hi, z, c, cl, nc, acc);
         }
+    }
+    if constexpr (HS) {
+        // the halves' sums: a + b in one half and b + a in the other, equal bit for bit
+#pragma unroll
+        for (int j = 0; j < C; ++j)
+#pragma unroll
+            for (int a = 0; a < Acc<D>::N; ++a) acc[j][a] += __shfl_xor(acc[j][a], kWave / 2);
     }
 }
 
@@ -687,11 +711,17 @@ __device__ __forceinline__ void lattice_point(const Desc* __restrict__ d, int i,
 // Update rules of the inner loop (U): 0 truncated Newton, 1 normalised
 // gradient, 2 BFGS.  The rule is a template parameter so that the default
 // Newton kernels carry no quasi-Newton state.
-template <int D, int C, int U = 0, bool PR = false>
+// HS (half split, one candidate per lane, Newton): both 32-lane halves of a
+// wave hold the same 32 seeds and share every pass's hits, so a work item of
+// 128 seeds keeps all four waves busy; the halves' results are identical bit
+// for bit, the lower half alone queues line-search points and writes results.
+template <int D, int C, int U = 0, bool PR = false, bool HS = false>
 __global__ __launch_bounds__(kBlock) void k_ascent(const Desc* __restrict__ d, int tile_cap)
 {
+    static_assert(!HS || (C == 1 && U == 0), "half split: one candidate per lane, Newton steps");
     constexpr int NP = 2 * D;
     constexpr int NA = Acc<D>::N;
+    constexpr int SL = HS ? kWave / 2 : kWave;  // seeds per wave and candidate slot
     // dynamic LDS follows the static arrays: declared float4 so it starts 16-byte
     // aligned (the (x, y) hit pairs are read with 8-byte LDS loads)
     extern __shared__ float4 s_dyn[];
@@ -704,6 +734,8 @@ __global__ __launch_bounds__(kBlock) void k_ascent(const Desc* __restrict__ d, i
     if (d->cnt->err) return;
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);  // scalar: same in every lane
     const int lane = threadIdx.x & (kWave - 1);
+    const int slane = lane & (SL - 1);   // the lane's seed within the wave's slot
+    const bool owner = !HS || lane < SL;  // queues line-search points, writes the results
     const int64_t n_items = d->cnt->n_items;
     const int n_steps = d->n_sigma + d->n_final_steps;
     const float zr = d->z_ref;
@@ -735,7 +767,7 @@ __global__ __launch_bounds__(kBlock) void k_ascent(const Desc* __restrict__ d, i
         float sig_prev = 0.0f;
 #pragma unroll
         for (int j = 0; j < C; ++j) {
-            const int sj = it.y + (wave * C + j) * kWave + lane;
+            const int sj = it.y + (wave * C + j) * SL + slane;
             active[j] = sj < ns;
             flags[j] = 0;
             nre[j] = 0;
@@ -762,7 +794,7 @@ __global__ __launch_bounds__(kBlock) void k_ascent(const Desc* __restrict__ d, i
 #pragma unroll
             for (int j = 0; j < C; ++j) set_cand<D, C>(c, j, th[j]);
             float acc[C][NA];
-            event_pass<D, C, true, false, PR>(d, s_hits, s_poff, ev, c, zero_c, nc, acc, wave_work, active);
+            event_pass<D, C, true, false, PR, HS>(d, s_hits, s_poff, ev, c, zero_c, nc, acc, wave_work, active);
             float p[C][NP], Rc[C], gp[C], alpha[C];
             bool pend[C];
             int trial[C];
@@ -905,9 +937,15 @@ __global__ __launch_bounds__(kBlock) void k_ascent(const Desc* __restrict__ d, i
                     if (!pend[j]) continue;
 #pragma unroll
                     for (int a = 0; a < NP; ++a) tt[j][a] = __builtin_fmaf(alpha[j], p[j][a], th[j][a]);
+                    if (!owner) continue;
                     slot[j] = atomicAdd(&s_npend, 1);
 #pragma unroll
                     for (int a = 0; a < NP; ++a) s_lth[slot[j]][a] = tt[j][a];
+                }
+                if constexpr (HS) {
+                    // the upper half reads its twin's point
+#pragma unroll
+                    for (int j = 0; j < C; ++j) slot[j] = __shfl(slot[j], slane);
                 }
                 __syncthreads();
                 const int npend = __builtin_amdgcn_readfirstlane(s_npend);
@@ -1018,7 +1056,7 @@ __global__ __launch_bounds__(kBlock) void k_ascent(const Desc* __restrict__ d, i
                 set_cand<D, C>(cl, j, lo);
             }
             float acc[C][NA];
-            event_pass<D, C, true, true, PR>(d, s_hits, s_poff, ev, ch, cl, ncf, acc, wave_work, active);
+            event_pass<D, C, true, true, PR, HS>(d, s_hits, s_poff, ev, ch, cl, ncf, acc, wave_work, active);
 #pragma unroll
             for (int j = 0; j < C; ++j) {
                 double g[NP], H[NP][NP], A[NP][NP], dl[NP];
@@ -1061,8 +1099,8 @@ __global__ __launch_bounds__(kBlock) void k_ascent(const Desc* __restrict__ d, i
         for (int j = 0; j < C; ++j) {
             if (!pd[j]) flags[j] |= RETINA_NOT_PD;
             else if (step[j] <= (double)d->conv_tol * (double)sf) flags[j] |= RETINA_CONVERGED;
-            if (!active[j]) continue;
-            const int sj = it.y + (wave * C + j) * kWave + lane;
+            if (!active[j] || !owner) continue;
+            const int sj = it.y + (wave * C + j) * SL + slane;
             const int64_t gs = sbase + sj;
             double* o = d->s_theta + gs * 4;
 #pragma unroll
@@ -1072,7 +1110,7 @@ __global__ __launch_bounds__(kBlock) void k_ascent(const Desc* __restrict__ d, i
             d->s_nreval[gs] = nre[j];
         }
         if (lane == 0 && wave_work) {
-            const uint64_t per_pass = (uint64_t)ev.n * kWave;
+            const uint64_t per_pass = (uint64_t)ev.n * SL;
             atomicAdd((unsigned long long*)&d->cnt->exec_pairs,
                       (unsigned long long)(per_pass * C * (uint64_t)(n_steps + d->n_polish)));
         }
@@ -1223,7 +1261,7 @@ void launch_response_reduce(const Desc* d, int D, bool deriv, int64_t n_theta, h
 }
 
 // ------------------------------------------------------------------ launch
-int hot_seeds_per_item(const HotConfig& c) { return (kBlock / kWave) * kWave * c.cand; }
+int hot_seeds_per_item(const HotConfig& c) { return (kBlock / kWave) * kWave * c.cand / (c.half ? 2 : 1); }
 
 size_t hot_lds_bytes(int meas_dim, const HotConfig& c) { return (size_t)(c.tile_hits + kTilePad) * meas_dim * sizeof(float); }
 
@@ -1239,6 +1277,7 @@ int hot_max_blocks_per_cu(int D, const HotConfig& c, bool ascent)
 {
     const size_t lds = hot_lds_bytes(D, c);
     if (ascent) {
+        if (c.half) return D == 2 ? occupancy(k_ascent<2, 1, 0, false, true>, lds) : occupancy(k_ascent<1, 1, 0, false, true>, lds);
         if (D == 2) return c.cand == 2 ? occupancy(k_ascent<2, 2>, lds) : occupancy(k_ascent<2, 1>, lds);
         return c.cand == 2 ? occupancy(k_ascent<1, 2>, lds) : occupancy(k_ascent<1, 1>, lds);
     }
@@ -1250,6 +1289,17 @@ void launch_ascent(const Desc* d, int D, const HotConfig& c, hipStream_t st)
 {
     const size_t lds = hot_lds_bytes(D, c);
     const dim3 g(c.grid), b(kBlock);
+    if (c.half && c.cand == 1 && c.update == 0) {
+        // two lanes per seed (one candidate per lane, Newton steps)
+        if (D == 2) {
+            if (c.prune) hipLaunchKernelGGL((k_ascent<2, 1, 0, true, true>), g, b, lds, st, d, c.tile_hits);
+            else hipLaunchKernelGGL((k_ascent<2, 1, 0, false, true>), g, b, lds, st, d, c.tile_hits);
+        } else {
+            if (c.prune) hipLaunchKernelGGL((k_ascent<1, 1, 0, true, true>), g, b, lds, st, d, c.tile_hits);
+            else hipLaunchKernelGGL((k_ascent<1, 1, 0, false, true>), g, b, lds, st, d, c.tile_hits);
+        }
+        return;
+    }
     if (c.prune) {
         // locality-pruned passes (truncated Newton)
         if (D == 2) {
