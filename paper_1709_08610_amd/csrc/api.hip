@@ -62,7 +62,7 @@ struct retina_ctx {
     // (meas_dim, launch shape, profiling) serves any batch
     bool use_graphs = true;
     struct GraphEntry {
-        int D, cand, tile, grid, prof, update, prune, staged, half;
+        int D, cand, tile, grid, prof, update, prune, staged, split;
         hipGraphExec_t exec;
     };
     std::vector<GraphEntry> graphs;
@@ -273,9 +273,10 @@ int device_error(retina_ctx* c, uint32_t err)
 // find_tracks batches averaging fewer seeds per event than this run the
 // ascent with the sparse-seeding launch shape (tuning kernel 2)
 constexpr int64_t kSparseSeeds = 512;
-// one candidate per lane with Newton steps runs two lanes per seed (each over
-// half of every plane's hits): an event's ~100-250 seeds then fill 4 waves
-constexpr bool kHalfSplit = true;
+// one candidate per lane with Newton steps runs several lanes per seed (each
+// over a share of every plane's hits): an event's ~100-250 seeds then fill
+// the work-groups' waves
+constexpr bool kSplitSeeds = true;
 // retina_response hit splitting: at most this many parts, each part at least
 // this many hits of an average event
 constexpr int kRespMaxParts = 32;
@@ -356,7 +357,7 @@ int run_tracks(retina_ctx* c, int D, const HotConfig& hc)
         for (auto& g : c->graphs)
             if (g.D == D && g.cand == hc.cand && g.tile == hc.tile_hits && g.grid == hc.grid &&
                 g.prof == (int)c->prof && g.update == hc.update && g.prune == hc.prune &&
-                g.staged == hc.staged && g.half == hc.half)
+                g.staged == hc.staged && g.split == hc.split)
                 exec = g.exec;
         if (!exec) {
             hipGraph_t graph = nullptr;
@@ -373,7 +374,7 @@ int run_tracks(retina_ctx* c, int D, const HotConfig& hc)
                 c->use_graphs = false;  // capture unsupported here: launch eagerly from now on
             } else {
                 c->graphs.push_back({D, hc.cand, hc.tile_hits, hc.grid, (int)c->prof, hc.update, hc.prune, hc.staged,
-                                     hc.half, exec});
+                                     hc.split, exec});
             }
         }
         if (exec) {
@@ -872,8 +873,8 @@ static int find_tracks_impl(retina_ctx* c, const retina_geometry* g, const retin
     }
     hc.prune = P->prune_u > 0.0f;
     hc.staged = staged;
-    if (kHalfSplit && hc.cand == 1 && hc.update == RETINA_UPDATE_NEWTON) {
-        hc.half = 1;
+    if (kSplitSeeds && hc.cand == 1 && hc.update == RETINA_UPDATE_NEWTON) {
+        hc.split = 1;
         hc.grid = c->n_cu * hot_max_blocks_per_cu(D, hc, true);
     }
     d.seeds_per_item = hot_seeds_per_item(hc);

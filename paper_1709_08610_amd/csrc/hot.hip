@@ -32,9 +32,12 @@
 namespace rt {
 
 constexpr float kLog2e = 1.44269504088896340736f;
+// Lanes per seed of the split ascent (one candidate per lane, Newton steps):
+// each of a seed's lanes walks every kSplitLanes-th hit of a plane segment.
+constexpr int kSplitLanes = 4;
 // spare hit entries after the LDS tile: the meas_dim-2 hit loops read ahead
-// of the segment they walk, up to index tile_hits + 3 (half-split lanes)
-constexpr int kTilePad = 4;
+// of the segment they walk, up to index tile_hits + 2 * lanes per seed - 1
+constexpr int kTilePad = 2 * kSplitLanes;
 
 template <int D>
 struct Acc;  // number of accumulators
@@ -70,10 +73,10 @@ __device__ __forceinline__ void line_split(float o, float t, float ol, float tl,
     l += __builtin_fmaf(tl, z, ol);
 }
 
-// One plane segment [lo, hi) of LDS hits at plane position z.  HS (half
-// split): the two 32-lane halves of the wave hold the same candidates and walk
-// alternate hits (lanes 32-63 start one later); event_pass adds the halves.
-template <int D, int C, bool DERIV, bool DF, bool HS = false>
+// One plane segment [lo, hi) of LDS hits at plane position z.  QS > 1 (split):
+// the wave's QS groups of 64 / QS lanes hold the same candidates and group g
+// walks hits lo + g, lo + g + QS, ...; event_pass adds the groups' sums.
+template <int D, int C, bool DERIV, bool DF, int QS = 1>
 __device__ __forceinline__ void seg_accumulate(const float* __restrict__ s_hits, int lo, int hi,
                                                float z, const Cands<C>& c, const Cands<C>& cl,
                                                float nc, float (&acc)[C][Acc<D>::N])
@@ -111,22 +114,10 @@ __device__ __forceinline__ void seg_accumulate(const float* __restrict__ s_hits,
             }
         };
         // two hits per iteration; the next two are read from LDS while these
-        // are processed.  The reads run up to 2 entries (HS: 3) past the
+        // are processed.  The reads run up to 2 QS - 1 entries past the
         // segment: the LDS tile carries kTilePad spare entries, so they stay
         // inside it, and their values are never used.
-        if constexpr (HS) {
-            const int k0 = lo + (int)(__lane_id() >> 5);
-            float2 a = h[k0], b = h[k0 + 2];
-            int k = k0;
-            for (; k + 2 < hi; k += 4) {
-                const float2 na = h[k + 4], nb = h[k + 6];
-                pair(a);
-                pair(b);
-                a = na;
-                b = nb;
-            }
-            if (k < hi) pair(a);
-        } else {
+        if constexpr (QS == 1) {
             float2 a = h[lo], b = h[lo + 1];
             int k = lo;
             for (; k + 1 < hi; k += 2) {
@@ -137,11 +128,23 @@ __device__ __forceinline__ void seg_accumulate(const float* __restrict__ s_hits,
                 b = nb;
             }
             if (k < hi) pair(a);
+        } else {
+            const int k0 = lo + (int)(__lane_id() / (kWave / QS));
+            float2 a = h[k0], b = h[k0 + QS];
+            int k = k0;
+            for (; k + QS < hi; k += 2 * QS) {
+                const float2 na = h[k + 2 * QS], nb = h[k + 3 * QS];
+                pair(a);
+                pair(b);
+                a = na;
+                b = nb;
+            }
+            if (k < hi) pair(a);
         }
     } else {
-        const int k0 = HS ? lo + (int)(__lane_id() >> 5) : lo;
+        const int k0 = QS == 1 ? lo : lo + (int)(__lane_id() / (kWave / QS));
 #pragma unroll 4
-        for (int k = k0; k < hi; k += HS ? 2 : 1) {
+        for (int k = k0; k < hi; k += QS) {
             const float v = s_hits[k];
 #pragma unroll
             for (int j = 0; j < C; ++j) {
@@ -288,7 +291,7 @@ __device__ __forceinline__ float prune_width(const Desc* __restrict__ d, float n
 // uniformly then (it contains barriers).
 // `work` (wave-uniform) false: the wave holds no live candidate and only takes
 // part in the tile loads and barriers; its sums stay zero.
-template <int D, int C, bool DERIV, bool DF, bool PR = false, bool HS = false>
+template <int D, int C, bool DERIV, bool DF, bool PR = false, int QS = 1>
 __device__ __forceinline__ void event_pass(const Desc* __restrict__ d, float* s_hits,
                                            const int* s_poff, const EventView& ev,
                                            const Cands<C>& c, const Cands<C>& cl, float nc,
@@ -326,15 +329,18 @@ __device__ __forceinline__ void event_pass(const Desc* __restrict__ d, float* s_
                     if (lo >= hi) continue;
                 }
             }
-            seg_accumulate<D, C, DERIV, DF, HS>(s_hits, lo, hi, z, c, cl, nc, acc);
+            seg_accumulate<D, C, DERIV, DF, QS>(s_hits, lo, hi, z, c, cl, nc, acc);
         }
     }
-    if constexpr (HS) {
-        // the halves' sums: a + b in one half and b + a in the other, equal bit for bit
+    if constexpr (QS > 1) {
+        // butterfly over the groups: at each level one lane adds a + b and its
+        // partner b + a, so every lane of a seed ends with the same bits
 #pragma unroll
-        for (int j = 0; j < C; ++j)
+        for (int m = kWave / 2; m >= kWave / QS; m >>= 1)
 #pragma unroll
-            for (int a = 0; a < Acc<D>::N; ++a) acc[j][a] += __shfl_xor(acc[j][a], kWave / 2);
+            for (int j = 0; j < C; ++j)
+#pragma unroll
+                for (int a = 0; a < Acc<D>::N; ++a) acc[j][a] += __shfl_xor(acc[j][a], m);
     }
 }
 
@@ -711,31 +717,33 @@ __device__ __forceinline__ void lattice_point(const Desc* __restrict__ d, int i,
 // Update rules of the inner loop (U): 0 truncated Newton, 1 normalised
 // gradient, 2 BFGS.  The rule is a template parameter so that the default
 // Newton kernels carry no quasi-Newton state.
-// HS (half split, one candidate per lane, Newton): both 32-lane halves of a
-// wave hold the same 32 seeds and share every pass's hits, so a work item of
-// 128 seeds keeps all four waves busy; the halves' results are identical bit
-// for bit, the lower half alone queues line-search points and writes results.
-template <int D, int C, int U = 0, bool PR = false, bool HS = false>
+// QS > 1 (split, one candidate per lane, Newton): QS lane groups of a wave
+// hold the same 64 / QS seeds and share every pass's hits, so a work item of
+// 256 / QS seeds keeps all four waves busy with an event of few seeds; the
+// groups' results are identical bit for bit, and the first group alone
+// queues line-search points and writes results.
+template <int D, int C, int U = 0, bool PR = false, int QS = 1>
 __global__ __launch_bounds__(kBlock) void k_ascent(const Desc* __restrict__ d, int tile_cap)
 {
-    static_assert(!HS || (C == 1 && U == 0), "half split: one candidate per lane, Newton steps");
+    static_assert(QS == 1 || (C == 1 && U == 0), "split: one candidate per lane, Newton steps");
     constexpr int NP = 2 * D;
     constexpr int NA = Acc<D>::N;
-    constexpr int SL = HS ? kWave / 2 : kWave;  // seeds per wave and candidate slot
+    constexpr int SL = kWave / QS;  // seeds per wave and candidate slot
     // dynamic LDS follows the static arrays: declared float4 so it starts 16-byte
     // aligned (the (x, y) hit pairs are read with 8-byte LDS loads)
     extern __shared__ float4 s_dyn[];
     float* s_hits = reinterpret_cast<float*>(s_dyn);
     __shared__ int s_poff[kMaxPlanes + 1];
     __shared__ int s_item;
-    __shared__ int s_npend;                 // line-search list: pending trial points,
-    __shared__ float s_lth[kBlock * C][4];  // then their responses (slot 0)
+    constexpr int kNW = kBlock / kWave;
+    __shared__ int s_wcnt[C * kNW];         // line-search list: pending points per (slot j, wave),
+    __shared__ float s_lth[kBlock * C][4];  // the points, then their responses (slot 0)
     __shared__ float s_red[kBlock];         // partial responses of a line-search round
     if (d->cnt->err) return;
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);  // scalar: same in every lane
     const int lane = threadIdx.x & (kWave - 1);
     const int slane = lane & (SL - 1);   // the lane's seed within the wave's slot
-    const bool owner = !HS || lane < SL;  // queues line-search points, writes the results
+    const bool owner = lane < SL;  // queues line-search points, writes the results
     const int64_t n_items = d->cnt->n_items;
     const int n_steps = d->n_sigma + d->n_final_steps;
     const float zr = d->z_ref;
@@ -794,7 +802,7 @@ __global__ __launch_bounds__(kBlock) void k_ascent(const Desc* __restrict__ d, i
 #pragma unroll
             for (int j = 0; j < C; ++j) set_cand<D, C>(c, j, th[j]);
             float acc[C][NA];
-            event_pass<D, C, true, false, PR, HS>(d, s_hits, s_poff, ev, c, zero_c, nc, acc, wave_work, active);
+            event_pass<D, C, true, false, PR, QS>(d, s_hits, s_poff, ev, c, zero_c, nc, acc, wave_work, active);
             float p[C][NP], Rc[C], gp[C], alpha[C];
             bool pend[C];
             int trial[C];
@@ -924,31 +932,52 @@ __global__ __launch_bounds__(kBlock) void k_ascent(const Desc* __restrict__ d, i
             // 64 * C points per wave, every wave over its quarter of each plane
             // segment (C candidates per lane share each hit read; measured
             // faster for C = 2 even when few points are pending).  Partial sums
-            // are added in a fixed order.
+            // are added in a fixed order.  The list is in (slot j, wave, lane)
+            // order, so which points share a wave (and, with pruning, its hit
+            // window) is the same on every run.
             for (;;) {
-                __syncthreads();
-                if (threadIdx.x == 0) s_npend = 0;
-                __syncthreads();
                 float tt[C][NP];
-                int slot[C];
+                int slot[C], rank[C];
+                uint64_t bal[C];
 #pragma unroll
                 for (int j = 0; j < C; ++j) {
-                    slot[j] = -1;
-                    if (!pend[j]) continue;
+                    if (pend[j]) {
 #pragma unroll
-                    for (int a = 0; a < NP; ++a) tt[j][a] = __builtin_fmaf(alpha[j], p[j][a], th[j][a]);
-                    if (!owner) continue;
-                    slot[j] = atomicAdd(&s_npend, 1);
-#pragma unroll
-                    for (int a = 0; a < NP; ++a) s_lth[slot[j]][a] = tt[j][a];
+                        for (int a = 0; a < NP; ++a) tt[j][a] = __builtin_fmaf(alpha[j], p[j][a], th[j][a]);
+                    }
+                    bal[j] = __ballot(pend[j] && owner);
+                    rank[j] = __popcll(bal[j] & ((1ull << lane) - 1ull));
                 }
-                if constexpr (HS) {
-                    // the upper half reads its twin's point
+                __syncthreads();  // the previous round is done with the list
+                if (lane == 0) {
+#pragma unroll
+                    for (int j = 0; j < C; ++j) s_wcnt[j * kNW + wave] = __popcll(bal[j]);
+                }
+                __syncthreads();
+                int npend = 0, base[C];
+#pragma unroll
+                for (int j = 0; j < C; ++j) {
+                    base[j] = 0;
+                    for (int w = 0; w < kNW; ++w) {
+                        if (w == wave) base[j] = npend;
+                        npend += s_wcnt[j * kNW + w];
+                    }
+                }
+#pragma unroll
+                for (int j = 0; j < C; ++j) {
+                    slot[j] = pend[j] && owner ? base[j] + rank[j] : -1;
+                    if (slot[j] >= 0) {
+#pragma unroll
+                        for (int a = 0; a < NP; ++a) s_lth[slot[j]][a] = tt[j][a];
+                    }
+                }
+                if constexpr (QS > 1) {
+                    // the other lanes of a seed read its point
 #pragma unroll
                     for (int j = 0; j < C; ++j) slot[j] = __shfl(slot[j], slane);
                 }
                 __syncthreads();
-                const int npend = __builtin_amdgcn_readfirstlane(s_npend);
+                npend = __builtin_amdgcn_readfirstlane(npend);
                 if (npend == 0) break;
                 if (C == 1 && npend <= kWave) {
                     // npend points, parts = 256 / npend threads on each (the last
@@ -1056,7 +1085,7 @@ __global__ __launch_bounds__(kBlock) void k_ascent(const Desc* __restrict__ d, i
                 set_cand<D, C>(cl, j, lo);
             }
             float acc[C][NA];
-            event_pass<D, C, true, true, PR, HS>(d, s_hits, s_poff, ev, ch, cl, ncf, acc, wave_work, active);
+            event_pass<D, C, true, true, PR, QS>(d, s_hits, s_poff, ev, ch, cl, ncf, acc, wave_work, active);
 #pragma unroll
             for (int j = 0; j < C; ++j) {
                 double g[NP], H[NP][NP], A[NP][NP], dl[NP];
@@ -1261,7 +1290,7 @@ void launch_response_reduce(const Desc* d, int D, bool deriv, int64_t n_theta, h
 }
 
 // ------------------------------------------------------------------ launch
-int hot_seeds_per_item(const HotConfig& c) { return (kBlock / kWave) * kWave * c.cand / (c.half ? 2 : 1); }
+int hot_seeds_per_item(const HotConfig& c) { return (kBlock / kWave) * kWave * c.cand / (c.split ? kSplitLanes : 1); }
 
 size_t hot_lds_bytes(int meas_dim, const HotConfig& c) { return (size_t)(c.tile_hits + kTilePad) * meas_dim * sizeof(float); }
 
@@ -1277,7 +1306,7 @@ int hot_max_blocks_per_cu(int D, const HotConfig& c, bool ascent)
 {
     const size_t lds = hot_lds_bytes(D, c);
     if (ascent) {
-        if (c.half) return D == 2 ? occupancy(k_ascent<2, 1, 0, false, true>, lds) : occupancy(k_ascent<1, 1, 0, false, true>, lds);
+        if (c.split) return D == 2 ? occupancy(k_ascent<2, 1, 0, false, kSplitLanes>, lds) : occupancy(k_ascent<1, 1, 0, false, kSplitLanes>, lds);
         if (D == 2) return c.cand == 2 ? occupancy(k_ascent<2, 2>, lds) : occupancy(k_ascent<2, 1>, lds);
         return c.cand == 2 ? occupancy(k_ascent<1, 2>, lds) : occupancy(k_ascent<1, 1>, lds);
     }
@@ -1289,14 +1318,14 @@ void launch_ascent(const Desc* d, int D, const HotConfig& c, hipStream_t st)
 {
     const size_t lds = hot_lds_bytes(D, c);
     const dim3 g(c.grid), b(kBlock);
-    if (c.half && c.cand == 1 && c.update == 0) {
-        // two lanes per seed (one candidate per lane, Newton steps)
+    if (c.split && c.cand == 1 && c.update == 0) {
+        // kSplitLanes lanes per seed (one candidate per lane, Newton steps)
         if (D == 2) {
-            if (c.prune) hipLaunchKernelGGL((k_ascent<2, 1, 0, true, true>), g, b, lds, st, d, c.tile_hits);
-            else hipLaunchKernelGGL((k_ascent<2, 1, 0, false, true>), g, b, lds, st, d, c.tile_hits);
+            if (c.prune) hipLaunchKernelGGL((k_ascent<2, 1, 0, true, kSplitLanes>), g, b, lds, st, d, c.tile_hits);
+            else hipLaunchKernelGGL((k_ascent<2, 1, 0, false, kSplitLanes>), g, b, lds, st, d, c.tile_hits);
         } else {
-            if (c.prune) hipLaunchKernelGGL((k_ascent<1, 1, 0, true, true>), g, b, lds, st, d, c.tile_hits);
-            else hipLaunchKernelGGL((k_ascent<1, 1, 0, false, true>), g, b, lds, st, d, c.tile_hits);
+            if (c.prune) hipLaunchKernelGGL((k_ascent<1, 1, 0, true, kSplitLanes>), g, b, lds, st, d, c.tile_hits);
+            else hipLaunchKernelGGL((k_ascent<1, 1, 0, false, kSplitLanes>), g, b, lds, st, d, c.tile_hits);
         }
         return;
     }

@@ -146,7 +146,7 @@ struct HotConfig {
     int update = 0;  // ascent update rule: 0 Newton, 1 gradient, 2 BFGS (cand 1)
     int prune = 0;   // locality-pruned passes (hits sorted by x per plane first)
     int staged = 0;  // hits already staged by the caller's previous launch (learned seeding)
-    int half = 0;    // ascent: two lanes per seed (cand 1, Newton), 128-seed work items
+    int split = 0;   // ascent: several lanes per seed (cand 1, Newton), smaller work items
 };
 int hot_seeds_per_item(const HotConfig& c);
 void launch_ascent(const Desc* d, int meas_dim, const HotConfig& c, hipStream_t st);

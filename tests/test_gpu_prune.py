@@ -102,6 +102,44 @@ def test_prune_tiled_events(ctx):
         ctx.retina_set_tuning(2, 0, old["cand"], old["tile_hits"])
 
 
+def test_prune_runs_are_bit_identical(ctx):
+    """The pruned passes visit the hit window of the points a wave holds, so
+    the line search must put its pending points into waves in the same order on
+    every run: repeated calls (lattice through a 1024-hit tile, one candidate
+    per lane with several lanes per seed; and the learned-seeding shape on c3
+    events) give the same bits."""
+    _say("pruned: repeated calls are bit-identical")
+    cfg = events.load_config("c2")
+    b = events.make_batch(cfg)
+    P = dict(cfg["params"], lattice_n=[32, 32], prune_u=U)
+    old = ctx.retina_get_tuning(2, 0)
+    try:
+        ctx.retina_set_tuning(2, 0, 1, 1024)
+        runs = [_find(ctx, b, P, want_seeds=True) for _ in range(3)]
+    finally:
+        ctx.retina_set_tuning(2, 0, old["cand"], old["tile_hits"])
+    for r in runs[1:]:
+        for k in ("seed_theta", "seed_R", "seed_flags", "seed_nreval", "track_offsets"):
+            assert r[k].tobytes() == runs[0][k].tobytes(), k
+        assert r["tracks"].tobytes() == runs[0]["tracks"].tobytes()
+    c3 = events.load_config("c3")
+    b3 = events.make_batch(c3, 4)
+    rng = np.random.default_rng(5)
+    seeds, offs = [], [0]
+    for e in range(4):
+        t = b3.truth[e]
+        s = np.zeros((len(t), 4))
+        s[:, 2:] = t[:, 2:] + rng.normal(0, 0.002, (len(t), 2))
+        seeds.append(s.astype(np.float32).astype(np.float64))
+        offs.append(offs[-1] + len(s))
+    S, O = np.concatenate(seeds), np.array(offs, np.int64)
+    runs = [_find(ctx, b3, dict(c3["params"], prune_u=U), seeds=S, seed_offsets=O, want_seeds=True)
+            for _ in range(3)]
+    for r in runs[1:]:
+        assert r["seed_theta"].tobytes() == runs[0]["seed_theta"].tobytes()
+        assert r["tracks"].tobytes() == runs[0]["tracks"].tobytes()
+
+
 def test_prune_long_plane_stays_exact(ctx):
     """A plane with more than 4096 hits cannot be sorted in LDS: that event runs
     unpruned (same results as prune_u = 0 within rounding) while the others of
