@@ -201,6 +201,41 @@ def test_find_tracks_explicit_seeds(ctx):
         assert_tracks_match(2, th, R, ref["theta"][a:c], ref["R"][a:c], P["d_merge"], 20.0, 750.0)
 
 
+@pytest.mark.parametrize("cfg_name", ["c1", "c2"])
+def test_find_tracks_split_lanes_item_edges(ctx, cfg_name):
+    """Few seeds per event run one candidate per lane with four lanes per seed
+    (16 seeds per wave, 64 per work item): seed counts on both sides of the
+    wave and item boundaries, meas_dim 1 (c1) and 2 (c3 events), seeds near the
+    true tracks, against the oracle."""
+    _say("find_tracks split lanes: %s" % cfg_name)
+    counts = [1, 15, 16, 17, 63, 64, 65] + ([128, 129] if cfg_name == "c2" else [])
+    cfg = events.load_config("c1" if cfg_name == "c1" else "c3")
+    P = cfg["params"]
+    D = 1 if cfg_name == "c1" else 2
+    b = events.make_batch(cfg, len(counts), start=20)
+    rng = np.random.default_rng(7)
+    seeds, offs = [], [0]
+    for e, n in enumerate(counts):
+        t = b.truth[e][np.arange(n) % len(b.truth[e])]
+        if D == 1:
+            s = t + rng.normal(0, 1, t.shape) * [0.002, 0.002]
+        else:
+            s = np.zeros((n, 4))
+            s[:, 2:] = t[:, 2:] + rng.normal(0, 0.002, (n, 2))
+        seeds.append(s.astype(np.float32).astype(np.float64))
+        offs.append(offs[-1] + n)
+    seeds = np.concatenate(seeds)
+    offs = np.array(offs, np.int64)
+    res = _find(ctx, b, P, seeds=seeds, seed_offsets=offs)
+    ref = oracle.find_tracks(b, P, seeds=seeds, seed_offsets=offs)
+    z0, z1 = (1.0, 8.0) if D == 1 else (20.0, 750.0)
+    for e in range(len(counts)):
+        th, R = event_tracks(res, e, D)
+        a, c = ref["track_offsets"][e], ref["track_offsets"][e + 1]
+        assert_tracks_match(D, th, R, ref["theta"][a:c], ref["R"][a:c], P["d_merge"], z0, z1)
+        _say("  %d seeds: %d tracks" % (counts[e], len(R)))
+
+
 def test_find_tracks_tiled_ascent_matches(ctx):
     """Events streamed through a small LDS tile give the same track set."""
     _say("find_tracks tiled")
