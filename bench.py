@@ -229,8 +229,9 @@ def main():
                          "reference for hardware byte counters)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print("bench.py measures one GPU only: this build has no multi-GPU path "
-              "(events shard across GPUs with no exchange; see DESIGN.md). Use --gpus 1.")
+        print("bench.py measures one GPU only: the library runs on one device per context and "
+              "has no multi-GPU launcher (events would shard across GPUs with no exchange). "
+              "Use --gpus 1.")
         sys.exit(2)
 
     import numpy as np

@@ -8,8 +8,8 @@ The detector follows the paper's simplified VELO model (Section 3): planes
 perpendicular to the beam axis z, straight tracks, Gaussian smearing of the
 in-plane coordinates and uniformly distributed noise hits.  The concrete
 workloads (plane positions, track counts, slope ranges, inefficiency, noise
-fractions) are the JSON files in ``configs/``; readings where the workload text
-leaves a choice open are listed in the design doc.
+fractions) are the JSON files in ``configs/``; each field there is a stated
+choice where the paper leaves the workload open.
 
 Random streams: every event uses its own ``numpy.random.Philox`` keyed by
 ``(config key, event index)``, so any event can be regenerated alone and in any
