@@ -100,12 +100,12 @@ def cpu_baseline(cfg, P, target_s=12.0, cap=256):
                             target_s, cap)
     b = events.make_batch(cfg, n_events)
     t0 = time.perf_counter()
-    oracle.find_tracks(b, P, n_threads=threads)
+    ref = oracle.find_tracks(b, P, n_threads=threads)
     dt = time.perf_counter() - t0
     return dict(value=n_events / dt, unit="events/s", cores=threads, kind="oracle",
                 sample="first %d of %d events of the %s workload, full method with the %dx%d lattice "
                        "(FP64, OpenMP over seeds), %.1f s"
-                       % (n_events, cfg["n_events"], cfg["name"], P["lattice_n"][0], P["lattice_n"][1], dt))
+                       % (n_events, cfg["n_events"], cfg["name"], P["lattice_n"][0], P["lattice_n"][1], dt)), ref
 
 
 def cpu_baseline_learned(cfg, LS, model, target_s=12.0, cap=256):
@@ -131,17 +131,47 @@ def cpu_baseline_learned(cfg, LS, model, target_s=12.0, cap=256):
             s = lat if fb else op.seeds_from_pixels(picks)
             seeds.append(s)
             off.append(off[-1] + len(s))
-        oracle.find_tracks(b, LS["params"], np.concatenate(seeds), np.array(off, np.int64), n_threads=threads)
+        return oracle.find_tracks(b, LS["params"], np.concatenate(seeds), np.array(off, np.int64),
+                                  n_threads=threads)
 
     n_events = _sample_size(lambda: run(events.make_batch(cfg, 1)), target_s, cap)
     b = events.make_batch(cfg, n_events)
     t0 = time.perf_counter()
-    run(b)
+    ref = run(b)
     dt = time.perf_counter() - t0
     return dict(value=n_events / dt, unit="events/s", cores=threads, kind="oracle",
                 sample="first %d of %d events of the %s workload, oracle proposer (numpy FP64 forward) + full "
                        "method on its seeds (FP64, OpenMP over seeds), %.1f s" % (n_events, cfg["n_events"],
-                                                                               cfg["name"], dt))
+                                                                               cfg["name"], dt)), ref
+
+
+def fp32_vs_fp64(D, gpu_theta, gpu_R, gpu_toff, ref, d_merge, z0, z1):
+    """The GPU's FP32 track sets against the FP64 oracle's on the oracle's
+    sample events: tracks matched within d_merge, the largest parameter error
+    |dp| / max(|p|, s_p) (s_p = 0.05 mm for offsets, 0.01 for slopes) and the
+    largest |dR| / R over the matched tracks, and the tracks on one side only."""
+    import numpy as np
+    from oracle.evaluate import match_tracks
+    s_p = np.array([0.05, 0.05, 0.01, 0.01]) if D == 2 else np.array([0.01, 0.01])
+    rto = ref["track_offsets"]
+    n_ev = len(rto) - 1
+    matched = only_gpu = only_ref = 0
+    dth = dR = 0.0
+    for e in range(n_ev):
+        g = np.asarray(gpu_theta[gpu_toff[e]:gpu_toff[e + 1]], np.float64)[:, :2 * D]
+        gR = np.asarray(gpu_R[gpu_toff[e]:gpu_toff[e + 1]], np.float64)
+        r = np.asarray(ref["theta"][rto[e]:rto[e + 1]], np.float64)
+        rR = np.asarray(ref["R"][rto[e]:rto[e + 1]], np.float64)
+        f2t, t2f, _ = match_tracks(D, g, r, d_merge, z0, z1)
+        m = t2f >= 0
+        matched += int(m.sum())
+        only_ref += int((~m).sum())
+        only_gpu += int((f2t < 0).sum())
+        if m.any():
+            dth = max(dth, float((np.abs(g[t2f[m]] - r[m]) / np.maximum(np.abs(r[m]), s_p)).max()))
+            dR = max(dR, float((np.abs(gR[t2f[m]] - rR[m]) / np.abs(rR[m])).max()))
+    return dict(events=n_ev, matched_tracks=matched, gpu_only=only_gpu, oracle_only=only_ref,
+                max_rel_dtheta=dth, max_rel_dR=dR)
 
 
 def response_throughput(ctx, retina, cfg, b, torch, np):
@@ -292,7 +322,8 @@ def main():
     res = lattice_step(want_seeds=True)
     torch.cuda.synchronize()
     tl = retina.tracks_from_device(res)
-    q_lat = quality(tl["theta"][:, :2 * D], res["track_offsets"].cpu().numpy())
+    toff_lat = res["track_offsets"].cpu().numpy()
+    q_lat = quality(tl["theta"][:, :2 * D], toff_lat)
     ns = P["lattice_n"][0] * P["lattice_n"][1]
     nre = res["seed_nreval"].cpu().numpy().astype(np.int64).reshape(E, ns).sum(axis=1)
     fl_lat, pairs_lat = algorithmic_flops(P, ev_hits, [ns] * E, nre, len(b.plane_z))
@@ -315,7 +346,8 @@ def main():
     res2 = learned_step()
     torch.cuda.synchronize()
     tr = retina.tracks_from_device(res2)
-    q_lrn = quality(tr["theta"][:, :2 * D], res2["track_offsets"].cpu().numpy())
+    toff_lrn = res2["track_offsets"].cpu().numpy()
+    q_lrn = quality(tr["theta"][:, :2 * D], toff_lrn)
     fb_rate = float(((res2["event_flags"] >> 4) & 1).float().mean().item())
     assert np.array_equal(res["track_offsets"].cpu().numpy(), res2["track_offsets"].cpu().numpy())
     del res, res2, prop
@@ -404,12 +436,16 @@ def main():
         # normalised gradient and BFGS from the same seeds
         upd = {name: budget.compare_updates(ctx, events.load_config(name), log=log) for name in ("c7", "c8")}
 
-    cpu = cpu_l = None
+    cpu = cpu_l = prec = None
     if not args.no_cpu_baseline:
         log("cpu baseline (oracle, %dx%d lattice)" % tuple(P["lattice_n"]))
-        cpu = cpu_baseline(cfg, P, args.cpu_seconds)
+        cpu, ref_lat = cpu_baseline(cfg, P, args.cpu_seconds)
         log("cpu baseline (oracle, learned seeds)")
-        cpu_l = cpu_baseline_learned(cfg, LS, model, args.cpu_seconds)
+        cpu_l, ref_lrn = cpu_baseline_learned(cfg, LS, model, args.cpu_seconds)
+        # FP32 GPU against the FP64 oracle on the baseline's sample events
+        prec = {"lattice": fp32_vs_fp64(D, tl["theta"], tl["R"], toff_lat, ref_lat, P["d_merge"], z0, z1),
+                "learned": fp32_vs_fp64(D, tr["theta"], tr["R"], toff_lrn, ref_lrn, PL["d_merge"], z0, z1)}
+        log("fp32 vs fp64 (oracle sample): %s" % prec)
 
     hot = prof_lrn["ms_hot"]
     achieved = fl_lrn / (hot * 1e-3) / 1e12
@@ -470,6 +506,7 @@ def main():
         "update_rules": upd,
         "cpu_baseline": cpu,
         "cpu_baseline_learned": cpu_l,
+        "fp32_vs_fp64": prec,
     }
     print(json.dumps(out))
     if args.calib_copy_mib:
