@@ -62,7 +62,7 @@ struct retina_ctx {
     // (meas_dim, launch shape, profiling) serves any batch
     bool use_graphs = true;
     struct GraphEntry {
-        int D, cand, tile, grid, prof, update, prune, staged, split;
+        int D, cand, tile, grid, prof, update, prune, staged, split, small_merge;
         hipGraphExec_t exec;
     };
     std::vector<GraphEntry> graphs;
@@ -339,7 +339,7 @@ void tracks_sequence(retina_ctx* c, int D, const HotConfig& hc, hipStream_t st)
     mark(2);
     launch_ascent(c->d_desc, D, hc, st);
     mark(3);
-    launch_merge(c->d_desc, D, c->n_cu, st);
+    launch_merge(c->d_desc, D, c->n_cu, hc.small_merge != 0, st);
     launch_finalize(c->d_desc, st);
     launch_emit(c->d_desc, D, c->n_cu * 4, st);
     mark(4);
@@ -357,7 +357,7 @@ int run_tracks(retina_ctx* c, int D, const HotConfig& hc)
         for (auto& g : c->graphs)
             if (g.D == D && g.cand == hc.cand && g.tile == hc.tile_hits && g.grid == hc.grid &&
                 g.prof == (int)c->prof && g.update == hc.update && g.prune == hc.prune &&
-                g.staged == hc.staged && g.split == hc.split)
+                g.staged == hc.staged && g.split == hc.split && g.small_merge == hc.small_merge)
                 exec = g.exec;
         if (!exec) {
             hipGraph_t graph = nullptr;
@@ -374,7 +374,7 @@ int run_tracks(retina_ctx* c, int D, const HotConfig& hc)
                 c->use_graphs = false;  // capture unsupported here: launch eagerly from now on
             } else {
                 c->graphs.push_back({D, hc.cand, hc.tile_hits, hc.grid, (int)c->prof, hc.update, hc.prune, hc.staged,
-                                     hc.split, exec});
+                                     hc.split, hc.small_merge, exec});
             }
         }
         if (exec) {
@@ -877,6 +877,7 @@ static int find_tracks_impl(retina_ctx* c, const retina_geometry* g, const retin
         hc.split = 1;
         hc.grid = c->n_cu * hot_max_blocks_per_cu(D, hc, true);
     }
+    hc.small_merge = n_seeds <= (int64_t)kMergeSmallKeys * E;
     d.seeds_per_item = hot_seeds_per_item(hc);
     d.items_cap = n_seeds / d.seeds_per_item + E + 1;
     if ((rc = ensure_t(c, B_ITEMS, (size_t)d.items_cap, &d.items))) return rc;

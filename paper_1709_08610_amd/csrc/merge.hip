@@ -34,12 +34,15 @@ __device__ __forceinline__ double line_dist(const double* a, const double* b, do
     return d;
 }
 
-template <int D>
-__global__ __launch_bounds__(kBlock) void k_merge(const Desc* __restrict__ d)
+// KC / LC: candidates sorted in LDS and leaders cached in LDS (larger events
+// use the global scratch for the rest); WPS: waves per SIMD the kernel must
+// leave room for (the small-capacity shape runs several events per CU).
+template <int D, int KC = kMergeKeyCap, int LC = kMergeLeaderCap, int WPS = 1>
+__global__ __launch_bounds__(kBlock, WPS) void k_merge(const Desc* __restrict__ d)
 {
     constexpr int NP = 2 * D;
-    __shared__ uint64_t s_keys[kMergeKeyCap];
-    __shared__ double s_lth[kMergeLeaderCap][NP];
+    __shared__ uint64_t s_keys[KC];
+    __shared__ double s_lth[LC][NP];
     __shared__ int s_join[kBlock];
     __shared__ int s_wcnt[kBlock / kWave];
     __shared__ int s_n;
@@ -55,7 +58,7 @@ __global__ __launch_bounds__(kBlock) void k_merge(const Desc* __restrict__ d)
         if (t == 0) { s_n = 0; s_nl = 0; s_flag = 0; }
         __syncthreads();
         // keys: LDS when they fit, else the event's slice of a 2x-seeds scratch (pow2 padding)
-        uint64_t* keys = ns <= kMergeKeyCap ? s_keys : d->m_keys + 2 * s0;
+        uint64_t* keys = ns <= KC ? s_keys : d->m_keys + 2 * s0;
         int* lead = d->m_leader + s0;    // leader seed index (event-local)
         int* memb = d->m_members + s0;
         // 1. collect (order-preserving compaction)
@@ -116,7 +119,7 @@ __global__ __launch_bounds__(kBlock) void k_merge(const Desc* __restrict__ d)
                 int join = -1;
                 for (int l = 0; l < nl_old; ++l) {
                     double lt[NP];
-                    if (l < kMergeLeaderCap) {
+                    if (l < LC) {
 #pragma unroll
                         for (int a = 0; a < NP; ++a) lt[a] = s_lth[l][a];
                     } else {
@@ -149,7 +152,7 @@ __global__ __launch_bounds__(kBlock) void k_merge(const Desc* __restrict__ d)
                         bool hit = false;
                         if (l < nl) {
                             double lt[NP];
-                            if (l < kMergeLeaderCap) {
+                            if (l < LC) {
 #pragma unroll
                                 for (int a = 0; a < NP; ++a) lt[a] = s_lth[l][a];
                             } else {
@@ -166,7 +169,7 @@ __global__ __launch_bounds__(kBlock) void k_merge(const Desc* __restrict__ d)
                         if (lane == 0) s_join[u] = found;
                     } else {
                         if (lane == 0) {
-                            if (nl < kMergeLeaderCap) {
+                            if (nl < LC) {
 #pragma unroll
                                 for (int a = 0; a < NP; ++a) s_lth[nl][a] = tu[a];
                             }
@@ -267,8 +270,14 @@ __global__ __launch_bounds__(kBlock) void k_emit(const Desc* __restrict__ d)
     }
 }
 
-void launch_merge(const Desc* d, int D, int grid, hipStream_t st)
+void launch_merge(const Desc* d, int D, int grid, bool small, hipStream_t st)
 {
+    // few seeds per event: small LDS caches and 4 work-groups per CU
+    if (small) {
+        if (D == 2) hipLaunchKernelGGL((k_merge<2, kMergeSmallKeys, kMergeSmallLeaders, 4>), dim3(grid * 4), dim3(kBlock), 0, st, d);
+        else hipLaunchKernelGGL((k_merge<1, kMergeSmallKeys, kMergeSmallLeaders, 4>), dim3(grid * 4), dim3(kBlock), 0, st, d);
+        return;
+    }
     if (D == 2) hipLaunchKernelGGL(k_merge<2>, dim3(grid), dim3(kBlock), 0, st, d);
     else hipLaunchKernelGGL(k_merge<1>, dim3(grid), dim3(kBlock), 0, st, d);
 }

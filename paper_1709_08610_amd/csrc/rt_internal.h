@@ -14,6 +14,8 @@ constexpr int kBlock = 256;          // threads per work-group of the hot kernel
 constexpr int kWave = 64;            // CDNA wavefront
 constexpr int kMergeKeyCap = 8192;   // candidates sorted in LDS by the merge kernel
 constexpr int kMergeLeaderCap = 1024;// leader parameters cached in LDS by the merge kernel
+constexpr int kMergeSmallKeys = 1024;   // the same for sparse seeding (several events per CU)
+constexpr int kMergeSmallLeaders = 256;
 constexpr int kPlanSortCap = 8192;   // events ordered longest-first in LDS (larger: batch order)
 
 // error bits raised by device-side validation
@@ -147,6 +149,7 @@ struct HotConfig {
     int prune = 0;   // locality-pruned passes (hits sorted by x per plane first)
     int staged = 0;  // hits already staged by the caller's previous launch (learned seeding)
     int split = 0;   // ascent: several lanes per seed (cand 1, Newton), smaller work items
+    int small_merge = 0;  // merge with small LDS caches, several events per CU
 };
 int hot_seeds_per_item(const HotConfig& c);
 void launch_ascent(const Desc* d, int meas_dim, const HotConfig& c, hipStream_t st);
@@ -155,7 +158,7 @@ void launch_response_reduce(const Desc* d, int meas_dim, bool deriv, int64_t n_t
 size_t hot_lds_bytes(int meas_dim, const HotConfig& c);
 int hot_max_blocks_per_cu(int meas_dim, const HotConfig& c, bool ascent);
 
-void launch_merge(const Desc* d, int meas_dim, int grid, hipStream_t st);
+void launch_merge(const Desc* d, int meas_dim, int grid, bool small, hipStream_t st);
 void launch_finalize(const Desc* d, hipStream_t st);
 void launch_emit(const Desc* d, int meas_dim, int grid, hipStream_t st);
 
