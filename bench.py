@@ -17,10 +17,13 @@ generator truth and the speedup.  The standalone response kernel
 (retina_response: R only and R + gradient + Hessian) is timed on the
 workload's shapes for the response evals/s and %FP32 peak figures.
 Inputs are resident in device memory before the timed regions; each timed
-region brackets exactly --steps calls with device synchronisation and runs
-with the library's HIP-event profiling on (eager launches), which gives the
-dominant kernel's (the ascent's) average duration on the library's stream.
-The same steps replayed through the captured hipGraph are timed as well.
+region brackets exactly --steps calls with device synchronisation.  `value`
+and `ms_per_step` come from the library's default mode, each call replaying
+its captured hipGraph.  A second timed region runs the same steps with the
+library's HIP-event profiling on (eager launches: events cannot sit inside a
+graph), which gives the per-kernel times on the library's stream and the
+dominant kernel's (the ascent's) average duration for the roofline
+(`ms_per_step_profiled`).
 The FP64 CPU oracle is timed on a bounded sample of the same workload.
 """
 import argparse
@@ -359,10 +362,10 @@ def main():
         learned_step()
         log("warmup %d done" % (i + 1))
     dt_lat, prof_lat, g_lat = timed(ctx, lattice_step, args.steps)
-    log("lattice: %.2f ms/step (graph replay %.2f), ascent %.2f ms" % (dt_lat * 1e3, g_lat * 1e3, prof_lat["ms_hot"]))
+    log("lattice: %.2f ms/step (profiled, eager: %.2f), ascent %.2f ms" % (g_lat * 1e3, dt_lat * 1e3, prof_lat["ms_hot"]))
     dt_lrn, prof_lrn, g_lrn = timed(ctx, learned_step, args.steps)
-    log("learned: %.2f ms/step (graph replay %.2f), proposer %.2f ms, ascent %.2f ms" % (
-        dt_lrn * 1e3, g_lrn * 1e3, prof_lrn["ms_propose"], prof_lrn["ms_hot"]))
+    log("learned: %.2f ms/step (profiled, eager: %.2f), proposer %.2f ms, ascent %.2f ms" % (
+        g_lrn * 1e3, dt_lrn * 1e3, prof_lrn["ms_propose"], prof_lrn["ms_hot"]))
 
     # ---- locality-pruned passes (prune_u = 30: each skipped term < 1e-13), both
     # seedings: the lattice sweep again (pruning favours compact waves, so the
@@ -397,12 +400,12 @@ def main():
     del r
     dt_lp, prof_lp, g_lp = timed(ctx, learned_pruned, args.steps)
     log("pruned learned: %.2f ms/step, ascent %.2f ms, efficiency %.4f; pruned lattice %dx%d %.2f ms" % (
-        dt_lp * 1e3, prof_lp["ms_hot"], q_lp["efficiency"], best_p["lattice_n"], best_p["lattice_n"],
+        g_lp * 1e3, prof_lp["ms_hot"], q_lp["efficiency"], best_p["lattice_n"], best_p["lattice_n"],
         best_p["ms_per_step"]))
     pruned = {"prune_u": PU, "lattice_sweep": sweep_p, "lattice_best": best_p,
-              "learned": {"events_per_s": E / dt_lp, "ms_per_step": dt_lp * 1e3, "ascent_ms": prof_lp["ms_hot"],
+              "learned": {"events_per_s": E / g_lp, "ms_per_step": g_lp * 1e3, "ms_per_step_profiled": dt_lp * 1e3, "ascent_ms": prof_lp["ms_hot"],
                           "efficiency": round(q_lp["efficiency"], 5), "fake_rate": round(q_lp["fake_rate"], 5)},
-              "speedup_vs_lattice": best_p["ms_per_step"] / (dt_lp * 1e3)}
+              "speedup_vs_lattice": best_p["ms_per_step"] / (g_lp * 1e3)}
 
     # end to end from host memory (hits H2D, tracks D2H included)
     hb = (b.event_offsets, b.x, b.y, b.plane)
@@ -454,13 +457,13 @@ def main():
     kms = lambda p: {"stage": p["ms_stage"], "plan": p["ms_plan"], "ascent": p["ms_hot"], "merge": p["ms_merge"]}
     out = {
         "metric": "events/sec at >=95% track eff (learned vs lattice seeds); response evals/s, %FP32 peak",
-        "value": E / dt_lrn,
+        "value": E / g_lrn,
         "unit": "events/s",
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
-        "ms_per_step": dt_lrn * 1e3,
-        "ms_per_step_graph_replay": g_lrn * 1e3,
+        "ms_per_step": g_lrn * 1e3,
+        "ms_per_step_profiled": dt_lrn * 1e3,
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
@@ -477,14 +480,14 @@ def main():
                     "kernel_ms": dict(kms(prof_lrn), proposer=prof_lrn["ms_propose"]),
                     "response_evals_per_s": pairs_lrn / (hot * 1e-3),
                     "proposer_net_tflops": net_tflops},
-        "lattice": {"lattice_n": best["lattice_n"], "events_per_s": E / dt_lat, "ms_per_step": dt_lat * 1e3, "ms_per_step_graph_replay": g_lat * 1e3,
+        "lattice": {"lattice_n": best["lattice_n"], "events_per_s": E / g_lat, "ms_per_step": g_lat * 1e3, "ms_per_step_profiled": dt_lat * 1e3,
                     "quality": rq(q_lat), "kernel_ms": kms(prof_lat),
                     "response_evals_per_s": pairs_lat / (prof_lat["ms_hot"] * 1e-3),
                     "ascent_tflops": fl_lat / (prof_lat["ms_hot"] * 1e-3) / 1e12,
                     "pairs_per_launch": {"algorithmic": pairs_lat, "executed": prof_lat["exec_pairs"],
                                          "executed_line_search": prof_lat["exec_rpairs"]}},
         "lattice_sweep": sweep,
-        "speedup_vs_lattice": dt_lat / dt_lrn,
+        "speedup_vs_lattice": g_lat / g_lrn,
         "pruned": pruned,
         "end_to_end_host_ms_per_step": ms_host,
         "response": resp,
