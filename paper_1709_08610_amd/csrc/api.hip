@@ -1616,7 +1616,12 @@ int retina_find_tracks_learned(retina_ctx* c, const retina_geometry* g, const re
     // the proposer staged these hits into the same buffers (and validated them)
     rc = find_tracks_impl(c, g, h, &Q, tracks, capacity, track_offsets, event_flags, nullptr, true, true);
     if (rc) return rc;
-    if (event_flags) {
+    if (event_flags && h->mem == RETINA_MEM_DEVICE) {
+        // the fallback bit is set on the device, in stream order
+        launch_flag_fallback(event_flags, pa.fallback, h->n_events, c->stream);
+        HIP_TRY(c, hipGetLastError());
+        HIP_TRY(c, hipStreamSynchronize(c->stream));
+    } else if (event_flags) {
         const int64_t E = h->n_events;
         std::vector<int32_t> fb(E), ef(E);
         HIP_TRY(c, hipMemcpyAsync(fb.data(), pa.fallback, 4 * E, hipMemcpyDeviceToHost, c->stream));

@@ -89,5 +89,6 @@ struct ProposeArgs {
 void launch_propose_select(const ProposeArgs& a, hipStream_t st);
 void launch_propose_offsets(const ProposeArgs& a, hipStream_t st);
 void launch_propose_write(const ProposeArgs& a, hipStream_t st);
+void launch_flag_fallback(int32_t* ev_flags, const int32_t* fallback, int64_t n_events, hipStream_t st);
 
 }  // namespace rt

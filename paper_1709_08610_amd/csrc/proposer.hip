@@ -1349,4 +1349,20 @@ void launch_propose_write(const ProposeArgs& a, hipStream_t st)
     hipLaunchKernelGGL(k_propose_write, dim3(grid), dim3(256), 0, st, a);
 }
 
+// event_flags[e] |= 16 where the event's seeds came from the lattice fallback
+__global__ __launch_bounds__(256) void k_flag_fallback(int32_t* __restrict__ ev_flags,
+                                                       const int32_t* __restrict__ fallback, int64_t n_events)
+{
+    for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < n_events;
+         e += (int64_t)gridDim.x * blockDim.x)
+        if (fallback[e]) ev_flags[e] |= 16;
+}
+
+void launch_flag_fallback(int32_t* ev_flags, const int32_t* fallback, int64_t n_events, hipStream_t st)
+{
+    if (n_events <= 0) return;
+    const int grid = (int)std::min<int64_t>((n_events + 255) / 256, 1024);
+    hipLaunchKernelGGL(k_flag_fallback, dim3(grid), dim3(256), 0, st, ev_flags, fallback, n_events);
+}
+
 }  // namespace rt
