@@ -7,7 +7,9 @@
 //     candidate lines (C per lane, each wave its own 64*C);
 //   * every lane walks the same hit (an LDS broadcast read), so the hit loop
 //     is wave-uniform and the per-pair work is pure VALU: two residuals of two
-//     subtractions each, one exp2 and six running sums;
+//     subtractions each, one exp2 and six running sums; with few seeds per
+//     event the ascent instead gives each seed 4 lanes, each over every 4th
+//     hit (4 broadcast reads per wave), and adds their sums after each pass;
 //   * hits are grouped by plane, where z is constant, so the per-pair sums are
 //     P_e, P_x, P_y, P_xx, P_yy, P_xy and the z-moments are folded once per
 //     plane into 16 accumulators (8 for meas_dim 1);
