@@ -402,7 +402,7 @@ class Context:
             import torch
             dev = x.device
             self.set_stream(torch.cuda.current_stream(dev).cuda_stream)
-            tracks = torch.zeros(max(cap, 1) * 48, dtype=torch.uint8, device=dev)
+            tracks = torch.empty(max(cap, 1) * 48, dtype=torch.uint8, device=dev)  # records [0, offsets[-1]) written
             toff = torch.zeros(E + 1, dtype=torch.int64, device=dev)
             evf = torch.zeros(max(E, 1), dtype=torch.int32, device=dev)
             if want_seeds:
@@ -450,7 +450,7 @@ class Context:
             import torch
             dev = x.device
             self.set_stream(torch.cuda.current_stream(dev).cuda_stream)
-            tracks = torch.zeros(max(cap, 1) * 48, dtype=torch.uint8, device=dev)
+            tracks = torch.empty(max(cap, 1) * 48, dtype=torch.uint8, device=dev)  # records [0, offsets[-1]) written
             toff = torch.zeros(E + 1, dtype=torch.int64, device=dev)
             Rg = torch.zeros((E, n0, n1), dtype=torch.float32, device=dev) if want_grid else None
         rc = self.lib.retina_grid_search(self.h, ctypes.byref(g), ctypes.byref(hits), ctypes.byref(G),
@@ -568,7 +568,7 @@ class Context:
         else:
             import torch
             dev = x.device
-            tracks = torch.zeros(max(cap, 1) * 48, dtype=torch.uint8, device=dev)
+            tracks = torch.empty(max(cap, 1) * 48, dtype=torch.uint8, device=dev)  # records [0, offsets[-1]) written
             toff = torch.zeros(E + 1, dtype=torch.int64, device=dev)
             evf = torch.zeros(max(E, 1), dtype=torch.int32, device=dev)
         pr = Proposal(int(k_max), float(tau), float(conf_min), int(bool(nms)))
