@@ -39,6 +39,9 @@ __device__ __forceinline__ uint64_t lanemask_lt()
 // One wavefront per event.  Pass 1: histogram of planes (LDS atomics) and
 // validation.  Exclusive scan over planes.  Pass 2: stable scatter, ranks
 // from wave ballots per distinct plane in the chunk.
+constexpr int kPlaneBits = 6;  // plane numbers < RETINA_MAX_PLANES = 64
+static_assert(kMaxPlanes <= (1 << kPlaneBits) && kMaxPlanes <= kWave, "one lane per plane, 6-bit plane numbers");
+
 __global__ __launch_bounds__(kBlock) void k_stage(const Desc* __restrict__ d)
 {
     __shared__ int s_cnt[kBlock / kWave][kMaxPlanes];
@@ -89,25 +92,34 @@ __global__ __launch_bounds__(kBlock) void k_stage(const Desc* __restrict__ d)
             po[P] = (int)b;
             d->ev_nhits[e] = (int)(b - a);
         }
+        // per 64-hit chunk: the lanes holding the same plane are those whose
+        // plane numbers agree bit by bit (one ballot per bit), a hit's slot is
+        // its plane's cursor plus the number of earlier lanes of that plane
+        // (stable), and the last lane of each plane hands the chunk's count
+        // to the lane that keeps the plane's cursor
+        const uint64_t gt = lane == kWave - 1 ? 0ull : (~0ull << (lane + 1));
         for (int64_t k0 = a; k0 < b; k0 += kWave) {
             const int64_t k = k0 + lane;
             const bool live = k < b;
-            const int p = live ? d->in_plane[k] : -1;
-            bool pending = live;
-            int pos = 0;
-            while (true) {
-                const uint64_t pm = __ballot(pending);
-                if (pm == 0) break;
-                const int leader = __ffsll((unsigned long long)pm) - 1;
-                const int q = __shfl(p, leader, kWave);
-                const uint64_t m = __ballot(pending && p == q);
-                const int base = __shfl(cursor, q, kWave);
-                if (pending && p == q) {
-                    pos = base + __popcll(m & lanemask_lt());
-                    pending = false;
-                }
-                if (lane == q) cursor += __popcll(m);
+            const int p = live ? d->in_plane[k] : 0;
+            uint64_t same = __ballot(live);
+#pragma unroll
+            for (int bit = 0; bit < kPlaneBits; ++bit) {
+                const bool on = live && ((p >> bit) & 1);
+                const uint64_t m = __ballot(on);
+                same &= on ? m : ~m;
             }
+            const int base = __shfl(cursor, p, kWave);
+            const int pos = base + __popcll(same & lanemask_lt());
+            if (lane < P) cnt[lane] = 0;
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+            __builtin_amdgcn_wave_barrier();
+            if (live && (same & gt) == 0) cnt[p] = __popcll(same);
+            __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
+            __builtin_amdgcn_wave_barrier();
+            if (lane < P) cursor += cnt[lane];
+            __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
+            __builtin_amdgcn_wave_barrier();
             if (live) {
                 if (D == 2) {
                     float2 v;
