@@ -11,20 +11,34 @@ clustering and selection.  Two seedings of the same batch are timed:
            ascent, polish and merge
 
 `value` is the learned path's events/s.  The lattice baseline is the fastest
-lattice of the workload's sweep (`lattice_sweep`) that reaches >= 95% track
-efficiency; every swept size is reported, with the qualities against
-generator truth and the speedup.  The standalone response kernel
-(retina_response: R only and R + gradient + Hessian) is timed on the
-workload's shapes for the response evals/s and %FP32 peak figures.
-Inputs are resident in device memory before the timed regions; each timed
-region brackets exactly --steps calls with device synchronisation.  `value`
-and `ms_per_step` come from the library's default mode, each call replaying
-its captured hipGraph.  A second timed region runs the same steps with the
-library's HIP-event profiling on (eager launches: events cannot sit inside a
-graph), which gives the per-kernel times on the library's stream and the
-dominant kernel's (the ascent's) average duration for the roofline
-(`ms_per_step_profiled`).
-The FP64 CPU oracle is timed on a bounded sample of the same workload.
+lattice of the workload's sweep that reaches >= 95% track efficiency.
+
+Timing.  Inputs are resident in device memory before any timed region.  After
+--warmup untimed steps, exactly --steps calls are timed in the library's
+default mode (each call replays its captured hipGraph): the wall clock
+brackets the K calls with device synchronisation on both sides
+(`ms_per_step`, `value`), and HIP events recorded on the library's stream
+around each call give the per-step device time (`ms_per_step_events_median`,
+the median of the K steps).  A further profiled run (eager launches with the
+library's per-kernel HIP events on its stream) gives the dominant kernel's
+(the ascent's) average duration for the roofline.
+
+Cost model of Section 3, measured: T0 = time of R at one line over an event's
+hits (the standalone response kernel, R only, the workload's batch and
+lattice lines), C = time of R + gradient + Hessian / T0, and C0 = time of
+one optimisation step per seed / T0, where a seed's steps are its sigma
+stages, final steps and FP64 polish iterations (lattice ascent).
+
+The FP64 CPU oracle is timed on a bounded sample of the same workload
+(`cpu_baseline`, the learned path; `cpu_baseline_lattice`), and the GPU's
+FP32 track sets are compared with the oracle's on that sample
+(`fp32_vs_fp64`).
+
+Output: the LAST stdout line is one compact JSON object (the headline).  The
+full report (lattice sweep, per-kernel times, response shapes, optional
+studies) goes to stderr as one line starting with "[bench] detail " and, with
+--detail-out PATH, to that file.  --studies adds the locality-pruned
+comparison, Section 3's alpha-budget scans and the update-rule comparison.
 """
 import argparse
 import json
@@ -38,10 +52,12 @@ sys.path.insert(0, ROOT)
 PEAK_FP32_TFLOPS = 157.3       # MI355X FP32 vector peak: 256 CU x 4 SIMD x 32 lanes x 2.4 GHz x 2 (FMA)
 PEAK_BF16_TFLOPS = 2500.0      # MI355X dense BF16 MFMA
 # algorithmic FP32 flops (FMA = 2, exp2 not counted) per hit-candidate pair,
-# meas_dim 2, per-plane factored sums
+# meas_dim 2, per-plane factored sums.  The polish evaluates the same
+# R + gradient + Hessian sums (its two-float residual is implementation work,
+# not counted).
 FLOP_RGH_PAIR = 21
 FLOP_R_PAIR = 11
-FLOP_POLISH_PAIR = 25          # RGH pair with the two-float residual (4 more)
+FLOP_POLISH_PAIR = FLOP_RGH_PAIR
 FLOP_FOLD = 26                 # per (candidate, plane) per derivative pass
 # proposer network: 2 x 16384 pixels x (9 x (2x64 + 64x128 + 128x96 + 96x1)) per event
 FLOP_NET_EVENT = 2 * 16384 * 9 * (2 * 64 + 64 * 128 + 128 * 96 + 96 * 1)
@@ -76,6 +92,10 @@ def log(msg):
 
 
 def algorithmic_flops(P, ev_hits, ev_seeds, nreval_per_event, n_planes):
+    """FP32 flops of one ascent launch by the method's own work: per seed and
+    event hit, one R + gradient + Hessian pair per step and per polish
+    iteration, one R pair per line-search evaluation, and one fold per
+    (seed, plane) of every derivative pass."""
     n_steps = len(P["sigma"]) + P["n_final_steps"]
     fl = 0.0
     pairs = 0.0
@@ -106,8 +126,7 @@ def cpu_baseline(cfg, P, target_s=12.0, cap=256):
     ref = oracle.find_tracks(b, P, n_threads=threads)
     dt = time.perf_counter() - t0
     return dict(value=n_events / dt, unit="events/s", cores=threads, kind="oracle",
-                sample="first %d of %d events of the %s workload, full method with the %dx%d lattice "
-                       "(FP64, OpenMP over seeds), %.1f s"
+                sample="first %d of %d %s events, FP64 oracle, %dx%d lattice, %.1f s"
                        % (n_events, cfg["n_events"], cfg["name"], P["lattice_n"][0], P["lattice_n"][1], dt)), ref
 
 
@@ -143,9 +162,8 @@ def cpu_baseline_learned(cfg, LS, model, target_s=12.0, cap=256):
     ref = run(b)
     dt = time.perf_counter() - t0
     return dict(value=n_events / dt, unit="events/s", cores=threads, kind="oracle",
-                sample="first %d of %d events of the %s workload, oracle proposer (numpy FP64 forward) + full "
-                       "method on its seeds (FP64, OpenMP over seeds), %.1f s" % (n_events, cfg["n_events"],
-                                                                               cfg["name"], dt)), ref
+                sample="first %d of %d %s events, FP64 oracle proposer (numpy) + FP64 method on its "
+                       "seeds, %.1f s" % (n_events, cfg["n_events"], cfg["name"], dt)), ref
 
 
 def fp32_vs_fp64(D, gpu_theta, gpu_R, gpu_toff, ref, d_merge, z0, z1):
@@ -177,10 +195,11 @@ def fp32_vs_fp64(D, gpu_theta, gpu_R, gpu_toff, ref, d_merge, z0, z1):
                 max_rel_dtheta=dth, max_rel_dR=dR)
 
 
-def response_throughput(ctx, retina, cfg, b, torch, np):
+def response_throughput(ctx, retina, cfg, b, torch, np, reps=3):
     """retina_response alone (R only, and R + gradient + Hessian) on the
     workload's events with its lattice as the candidate lines: pair
-    evaluations per second and the algorithmic FP32 rate."""
+    evaluations per second, the algorithmic FP32 rate, and the kernel time
+    per candidate line (T0 for R only)."""
     P = cfg["params"]
     D = b.meas_dim
     n0, n1 = P["lattice_n"]
@@ -207,56 +226,102 @@ def response_throughput(ctx, retina, cfg, b, torch, np):
         torch.cuda.synchronize()
         ctx.retina_set_profiling(True)
         ctx.retina_profile_reset()
-        for _ in range(3):
+        for _ in range(reps):
             f()
         torch.cuda.synchronize()
         pr = ctx.retina_get_profile()
         ctx.retina_set_profiling(False)
         ms = pr["ms_hot"] / max(pr["calls"], 1)
         rate = pairs / (ms * 1e-3)
-        out[name] = {"ms": ms, "pair_evals_per_s": rate, "tflops": rate * fl / 1e12,
-                     "frac_fp32_peak": rate * fl / 1e12 / PEAK_FP32_TFLOPS}
-        log("response %s: %.3f ms, %.3g pair evals/s, %.1f%% of FP32 peak" % (name, ms, rate,
-                                                                              100 * rate * fl / 1e12 / PEAK_FP32_TFLOPS))
+        out[name] = {"ms": ms, "ns_per_candidate": ms * 1e6 / (len(th) * E), "pair_evals_per_s": rate,
+                     "tflops": rate * fl / 1e12, "frac_fp32_peak": rate * fl / 1e12 / PEAK_FP32_TFLOPS}
+        log("response %s (%s): %.3f ms, %.3g pair evals/s, %.1f%% of FP32 peak" % (
+            name, cfg["name"], ms, rate, 100 * rate * fl / 1e12 / PEAK_FP32_TFLOPS))
     return out
 
 
-def timed(ctx, step, steps):
-    """Run `steps` calls with HIP-event profiling on; then the same through the
-    graph path without events.  Returns (s per step, profile per call, graph s per step)."""
+def timed_graph(step, steps):
+    """`steps` calls in the library's default mode (graph replay): wall-clock
+    mean over the bracketed region and the median of per-call HIP-event
+    times on the library's stream (the binding runs the library on torch's
+    current stream)."""
+    import numpy as np
+    import torch
+    st = torch.cuda.current_stream()
+    evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(steps)]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for a, b in evs:
+        a.record(st)
+        step()
+        b.record(st)
+    torch.cuda.synchronize()
+    wall = (time.perf_counter() - t0) / steps
+    ev_ms = [a.elapsed_time(b) for a, b in evs]
+    return wall, float(np.median(ev_ms)), ev_ms
+
+
+def profiled(ctx, step, steps):
+    """`steps` eager calls with the library's per-kernel HIP events on its
+    stream; returns the per-call average of each profile field."""
     import torch
     ctx.retina_set_profiling(True)
     ctx.retina_profile_reset()
     torch.cuda.synchronize()
-    t0 = time.perf_counter()
     for _ in range(steps):
         step()
     torch.cuda.synchronize()
-    dt = (time.perf_counter() - t0) / steps
     prof = ctx.retina_get_profile()
     ctx.retina_set_profiling(False)
     n = max(prof["calls"], 1)
-    prof = {k: (v / n if k != "calls" else v) for k, v in prof.items()}
-    step()
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for _ in range(steps):
-        step()
-    torch.cuda.synchronize()
-    return dt, prof, (time.perf_counter() - t0) / steps
+    return {k: (v / n if k != "calls" else v) for k, v in prof.items()}
+
+
+def lattice_sweep(ctx, retina, b, dev_hits, P, sizes, quality, reps=2, prune_u=0.0):
+    import torch
+    D = b.meas_dim
+    E = b.n_events
+    rows = []
+    for n in sizes:
+        Pn = dict(P, lattice_n=[n, n], prune_u=prune_u)
+        f = lambda: ctx.retina_find_tracks(D, b.plane_z, *dev_hits, Pn)
+        r = f()
+        torch.cuda.synchronize()
+        qn = quality(retina.tracks_from_device(r)["theta"][:, :2 * D], r["track_offsets"].cpu().numpy())
+        del r
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            f()
+        torch.cuda.synchronize()
+        tn = (time.perf_counter() - t0) / reps
+        rows.append(dict(lattice_n=n, ms_per_step=tn * 1e3, events_per_s=E / tn,
+                         efficiency=round(qn["efficiency"], 5), fake_rate=round(qn["fake_rate"], 5)))
+        log("%slattice %dx%d: %.2f ms, efficiency %.4f fake %.4f" % (
+            "pruned " if prune_u else "", n, n, tn * 1e3, qn["efficiency"], qn["fake_rate"]))
+    ok = [r for r in rows if r["efficiency"] >= 0.95]
+    best = min(ok, key=lambda r: r["ms_per_step"]) if ok else max(rows, key=lambda r: r["efficiency"])
+    return rows, best
+
+
+def r5(v):
+    return None if v is None else float("%.5g" % v)
 
 
 def main():
-    ap = argparse.ArgumentParser(description=__doc__)
+    ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=5)
-    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--workload", default="c3")
+    ap.add_argument("--lattice-sweep", type=int, nargs="*", default=None,
+                    help="lattice sides to sweep for the baseline (default: the workload's list)")
     ap.add_argument("--cpu-seconds", type=float, default=12.0,
                     help="approximate length of each CPU oracle sample")
+    ap.add_argument("--cpu-max-events", type=int, default=256)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--no-budget", action="store_true",
-                    help="skip the grid-search vs multi-start comparison (c7 track-count scan)")
+    ap.add_argument("--studies", action="store_true",
+                    help="also run the pruned comparison, the alpha-budget scans and the update rules")
+    ap.add_argument("--detail-out", default=None, help="write the full report (JSON) to this file")
     ap.add_argument("--calib-copy-mib", type=int, default=0,
                     help="after the run, one plain device-to-device copy of this many MiB (a known-size "
                          "reference for hardware byte counters)")
@@ -281,7 +346,7 @@ def main():
     E = b.n_events
     dev = torch.device("cuda:0")
     tin = lambda a: torch.from_numpy(np.ascontiguousarray(a)).to(dev)
-    off_d, x_d, y_d, pl_d = tin(b.event_offsets), tin(b.x), tin(b.y), tin(b.plane)
+    dev_hits = (tin(b.event_offsets), tin(b.x), tin(b.y), tin(b.plane))
     ctx = retina.Context(0)
     model = ctx.retina_model_load(LS["model"])
     torch.cuda.synchronize()
@@ -291,37 +356,20 @@ def main():
     def quality(tracks_theta, toff):
         return metrics.batch_quality(D, tracks_theta, toff, b.truth, b.truth_nhits, cfg["match_tol"], z0, z1)
 
-    def lattice_step(want_seeds=False):
-        return ctx.retina_find_tracks(D, b.plane_z, off_d, x_d, y_d, pl_d, P, want_seeds=want_seeds)
-
-    def learned_step():
-        return ctx.retina_find_tracks_learned(model, b.plane_z, off_d, x_d, y_d, pl_d, PL, LS["k_max"],
-                                              LS["tau"], LS["conf_min"], nms=LS["nms"])
-
     # ---- lattice sweep: the fastest lattice reaching the efficiency bar is the baseline
-    sweep = []
-    for n in cfg.get("lattice_sweep", [P["lattice_n"][0]]):
-        Pn = dict(P, lattice_n=[n, n])
-        f = lambda: ctx.retina_find_tracks(D, b.plane_z, off_d, x_d, y_d, pl_d, Pn)
-        r = f()
-        torch.cuda.synchronize()
-        qn = quality(retina.tracks_from_device(r)["theta"][:, :2 * D], r["track_offsets"].cpu().numpy())
-        del r
-        t0 = time.perf_counter()
-        for _ in range(2):
-            f()
-        torch.cuda.synchronize()
-        tn = (time.perf_counter() - t0) / 2
-        sweep.append(dict(lattice_n=n, ms_per_step=tn * 1e3, events_per_s=E / tn,
-                          efficiency=round(qn["efficiency"], 5), fake_rate=round(qn["fake_rate"], 5)))
-        log("lattice %dx%d: %.2f ms, efficiency %.4f fake %.4f" % (n, n, tn * 1e3, qn["efficiency"], qn["fake_rate"]))
-    ok = [r for r in sweep if r["efficiency"] >= 0.95]
-    best = min(ok, key=lambda r: r["ms_per_step"]) if ok else max(sweep, key=lambda r: r["efficiency"])
+    sizes = args.lattice_sweep or cfg.get("lattice_sweep", [P["lattice_n"][0]])
+    sweep, best = lattice_sweep(ctx, retina, b, dev_hits, P, sizes, quality)
     P = dict(P, lattice_n=[best["lattice_n"], best["lattice_n"]])
     log("lattice baseline: %dx%d" % (best["lattice_n"], best["lattice_n"]))
 
+    def lattice_step(want_seeds=False):
+        return ctx.retina_find_tracks(D, b.plane_z, *dev_hits, P, want_seeds=want_seeds)
+
+    def learned_step():
+        return ctx.retina_find_tracks_learned(model, b.plane_z, *dev_hits, PL, LS["k_max"],
+                                              LS["tau"], LS["conf_min"], nms=LS["nms"])
+
     # ---- quality + work accounting (untimed)
-    log("lattice: quality + work accounting run")
     res = lattice_step(want_seeds=True)
     torch.cuda.synchronize()
     tl = retina.tracks_from_device(res)
@@ -333,11 +381,10 @@ def main():
     del res
     log("lattice efficiency %.4f fake %.4f" % (q_lat["efficiency"], q_lat["fake_rate"]))
 
-    log("learned: quality + work accounting run (proposer seeds -> explicit-seed ascent)")
-    prop = ctx.retina_propose_seeds(model, b.plane_z, off_d, x_d, y_d, pl_d, LS["k_max"], LS["tau"],
+    prop = ctx.retina_propose_seeds(model, b.plane_z, *dev_hits, LS["k_max"], LS["tau"],
                                     LS["conf_min"], PL, nms=LS["nms"])
     so = prop["seed_offsets"]
-    res = ctx.retina_find_tracks(D, b.plane_z, off_d, x_d, y_d, pl_d, PL, seeds=prop["seeds"].contiguous(),
+    res = ctx.retina_find_tracks(D, b.plane_z, *dev_hits, PL, seeds=prop["seeds"].contiguous(),
                                  seed_offsets=so, want_seeds=True)
     torch.cuda.synchronize()
     so_h = so.cpu().numpy()
@@ -352,100 +399,69 @@ def main():
     toff_lrn = res2["track_offsets"].cpu().numpy()
     q_lrn = quality(tr["theta"][:, :2 * D], toff_lrn)
     fb_rate = float(((res2["event_flags"] >> 4) & 1).float().mean().item())
-    assert np.array_equal(res["track_offsets"].cpu().numpy(), res2["track_offsets"].cpu().numpy())
+    assert np.array_equal(res["track_offsets"].cpu().numpy(), toff_lrn)
     del res, res2, prop
     log("learned efficiency %.4f fake %.4f, %.1f seeds/event, fallback %.3f" % (
         q_lrn["efficiency"], q_lrn["fake_rate"], seeds_ev.mean(), fb_rate))
 
+    # ---- timed regions
     for i in range(args.warmup):
         lattice_step()
         learned_step()
-        log("warmup %d done" % (i + 1))
-    dt_lat, prof_lat, g_lat = timed(ctx, lattice_step, args.steps)
-    log("lattice: %.2f ms/step (profiled, eager: %.2f), ascent %.2f ms" % (g_lat * 1e3, dt_lat * 1e3, prof_lat["ms_hot"]))
-    dt_lrn, prof_lrn, g_lrn = timed(ctx, learned_step, args.steps)
-    log("learned: %.2f ms/step (profiled, eager: %.2f), proposer %.2f ms, ascent %.2f ms" % (
-        g_lrn * 1e3, dt_lrn * 1e3, prof_lrn["ms_propose"], prof_lrn["ms_hot"]))
-
-    # ---- locality-pruned passes (prune_u = 30: each skipped term < 1e-13), both
-    # seedings: the lattice sweep again (pruning favours compact waves, so the
-    # fastest lattice reaching the bar may change) and the learned seeds
-    PU = 30.0
-    sweep_p = []
-    for n in cfg.get("lattice_sweep", [P["lattice_n"][0]]):
-        Pn = dict(P, lattice_n=[n, n], prune_u=PU)
-        f = lambda: ctx.retina_find_tracks(D, b.plane_z, off_d, x_d, y_d, pl_d, Pn)
-        r = f()
-        torch.cuda.synchronize()
-        qn = quality(retina.tracks_from_device(r)["theta"][:, :2 * D], r["track_offsets"].cpu().numpy())
-        del r
-        t0 = time.perf_counter()
-        for _ in range(2):
-            f()
-        torch.cuda.synchronize()
-        tn = (time.perf_counter() - t0) / 2
-        sweep_p.append(dict(lattice_n=n, ms_per_step=tn * 1e3, events_per_s=E / tn,
-                            efficiency=round(qn["efficiency"], 5), fake_rate=round(qn["fake_rate"], 5)))
-        log("pruned lattice %dx%d: %.2f ms, efficiency %.4f" % (n, n, tn * 1e3, qn["efficiency"]))
-    ok_p = [r for r in sweep_p if r["efficiency"] >= 0.95]
-    best_p = min(ok_p, key=lambda r: r["ms_per_step"]) if ok_p else max(sweep_p, key=lambda r: r["efficiency"])
-    PLp = dict(PL, prune_u=PU)
-
-    def learned_pruned():
-        return ctx.retina_find_tracks_learned(model, b.plane_z, off_d, x_d, y_d, pl_d, PLp, LS["k_max"],
-                                              LS["tau"], LS["conf_min"], nms=LS["nms"])
-    r = learned_pruned()
-    torch.cuda.synchronize()
-    q_lp = quality(retina.tracks_from_device(r)["theta"][:, :2 * D], r["track_offsets"].cpu().numpy())
-    del r
-    dt_lp, prof_lp, g_lp = timed(ctx, learned_pruned, args.steps)
-    log("pruned learned: %.2f ms/step, ascent %.2f ms, efficiency %.4f; pruned lattice %dx%d %.2f ms" % (
-        g_lp * 1e3, prof_lp["ms_hot"], q_lp["efficiency"], best_p["lattice_n"], best_p["lattice_n"],
-        best_p["ms_per_step"]))
-    pruned = {"prune_u": PU, "lattice_sweep": sweep_p, "lattice_best": best_p,
-              "learned": {"events_per_s": E / g_lp, "ms_per_step": g_lp * 1e3, "ms_per_step_profiled": dt_lp * 1e3, "ascent_ms": prof_lp["ms_hot"],
-                          "efficiency": round(q_lp["efficiency"], 5), "fake_rate": round(q_lp["fake_rate"], 5)},
-              "speedup_vs_lattice": best_p["ms_per_step"] / (g_lp * 1e3)}
+    log("%d warmup steps done" % args.warmup)
+    wall_lrn, med_lrn, evs_lrn = timed_graph(learned_step, args.steps)
+    log("learned: %.3f ms/step (wall mean), %.3f ms (HIP-event median)" % (wall_lrn * 1e3, med_lrn))
+    wall_lat, med_lat, evs_lat = timed_graph(lattice_step, args.steps)
+    log("lattice %dx%d: %.3f ms/step (wall mean), %.3f ms (HIP-event median)" % (
+        P["lattice_n"][0], P["lattice_n"][1], wall_lat * 1e3, med_lat))
+    nprof = max(1, min(args.steps, 5))
+    prof_lrn = profiled(ctx, learned_step, nprof)
+    prof_lat = profiled(ctx, lattice_step, nprof)
+    log("profiled: learned proposer %.3f ms, ascent %.3f ms, merge %.3f ms; lattice ascent %.3f ms" % (
+        prof_lrn["ms_propose"], prof_lrn["ms_hot"], prof_lrn["ms_merge"], prof_lat["ms_hot"]))
 
     # end to end from host memory (hits H2D, tracks D2H included)
     hb = (b.event_offsets, b.x, b.y, b.plane)
     ctx.retina_find_tracks_learned(model, b.plane_z, *hb, PL, LS["k_max"], LS["tau"], LS["conf_min"], nms=LS["nms"])
+    nh = max(1, min(args.steps, 5))
     t0 = time.perf_counter()
-    for _ in range(args.steps):
+    for _ in range(nh):
         ctx.retina_find_tracks_learned(model, b.plane_z, *hb, PL, LS["k_max"], LS["tau"], LS["conf_min"],
                                        nms=LS["nms"])
-    ms_host = (time.perf_counter() - t0) / args.steps * 1e3
+    ms_host = (time.perf_counter() - t0) / nh * 1e3
     log("learned, host memory end to end: %.2f ms/step" % ms_host)
 
+    # ---- standalone response kernel; the cost model's T0, C and C0
     resp = response_throughput(ctx, retina, cfg, b, torch, np)
-    # the other response shapes: one c2 event (4096 lattice lines x 5.6k hits,
-    # occupancy-limited) and the c1 brute-force grid (400 x 400 lines x 130
-    # hits, meas_dim 1)
-    c2 = events.load_config("c2")
-    resp_c2 = response_throughput(ctx, retina, c2, events.make_batch(c2, 1), torch, np)
-    c1 = events.load_config("c1")
-    c1g = dict(c1, params=dict(c1["params"], lattice_n=[400, 400]))
-    resp_c1 = response_throughput(ctx, retina, c1g, events.make_batch(c1, 1), torch, np)
+    resp_c2 = resp_c1 = None
+    if args.workload == "c3":
+        c2 = events.load_config("c2")
+        resp_c2 = response_throughput(ctx, retina, c2, events.make_batch(c2, 1), torch, np)
+        c1 = events.load_config("c1")
+        c1g = dict(c1, params=dict(c1["params"], lattice_n=[400, 400]))
+        resp_c1 = response_throughput(ctx, retina, c1g, events.make_batch(c1, 1), torch, np)
+    T0_ns = resp["R"]["ns_per_candidate"]
+    C = resp["RGH"]["ms"] / resp["R"]["ms"]
+    q_steps = len(P["sigma"]) + P["n_final_steps"] + P["n_polish"]
+    step_ns = prof_lat["ms_hot"] * 1e6 / (E * ns * q_steps)
+    C0 = step_ns / T0_ns
+    q_steps_l = len(PL["sigma"]) + PL["n_final_steps"] + PL["n_polish"]
+    C0_learned = prof_lrn["ms_hot"] * 1e6 / (float(seeds_ev.sum()) * q_steps_l) / T0_ns
+    log("cost model: T0 %.3f ns per line, C = %.3f (paper: 3), C0 = %.2f lattice, %.2f learned (paper: ~30)" % (
+        T0_ns, C, C0, C0_learned))
 
-    # Section 3's comparison: multi-start at 1/3 and 1/10 of the grid search's
-    # measured cost, efficiency against the number of tracks (Fig. 3)
-    alpha = alpha_sv = upd = None
-    if not args.no_budget:
-        from paper_1709_08610_amd import budget
-        alpha = budget.run(ctx, events.load_config("c7"), log=log)
-        # the same on the paper's simplified VELO (tracks from the origin, prior-drawn seeds)
-        alpha_sv = budget.run(ctx, events.load_config("c8"), log=log)
-        # Section 3's choice of update rule: truncated Newton against the
-        # normalised gradient and BFGS from the same seeds
-        upd = {name: budget.compare_updates(ctx, events.load_config(name), log=log) for name in ("c7", "c8")}
+    studies = {}
+    if args.studies:
+        studies = run_studies(ctx, retina, events, cfg, b, dev_hits, P, PL, LS, model, sizes, quality, args)
 
     cpu = cpu_l = prec = None
     if not args.no_cpu_baseline:
-        log("cpu baseline (oracle, %dx%d lattice)" % tuple(P["lattice_n"]))
-        cpu, ref_lat = cpu_baseline(cfg, P, args.cpu_seconds)
         log("cpu baseline (oracle, learned seeds)")
-        cpu_l, ref_lrn = cpu_baseline_learned(cfg, LS, model, args.cpu_seconds)
-        # FP32 GPU against the FP64 oracle on the baseline's sample events
+        cpu_l, ref_lrn = cpu_baseline_learned(cfg, LS, model, args.cpu_seconds, args.cpu_max_events)
+        log("cpu baseline: %s" % cpu_l)
+        log("cpu baseline (oracle, %dx%d lattice)" % tuple(P["lattice_n"]))
+        cpu, ref_lat = cpu_baseline(cfg, P, args.cpu_seconds, args.cpu_max_events)
+        log("cpu baseline lattice: %s" % cpu)
         prec = {"lattice": fp32_vs_fp64(D, tl["theta"], tl["R"], toff_lat, ref_lat, P["d_merge"], z0, z1),
                 "learned": fp32_vs_fp64(D, tr["theta"], tr["R"], toff_lrn, ref_lrn, PL["d_merge"], z0, z1)}
         log("fp32 vs fp64 (oracle sample): %s" % prec)
@@ -455,63 +471,78 @@ def main():
     net_tflops = FLOP_NET_EVENT * E / (prof_lrn["ms_propose"] * 1e-3) / 1e12
     rq = lambda q: {k: (round(v, 5) if isinstance(v, float) else v) for k, v in q.items()}
     kms = lambda p: {"stage": p["ms_stage"], "plan": p["ms_plan"], "ascent": p["ms_hot"], "merge": p["ms_merge"]}
-    out = {
+    value = E / wall_lrn
+    roofline = {"bound": "alu", "achieved": r5(achieved), "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s",
+                "frac": r5(achieved / PEAK_FP32_TFLOPS), "traffic": measured_traffic(cfg["name"]),
+                "kernel": "k_ascent (learned seeds)", "ms": r5(hot), "flops_per_launch": r5(fl_lrn)}
+    prec_short = None
+    if prec is not None:
+        prec_short = {k: {"events": v["events"], "tracks": v["matched_tracks"], "gpu_only": v["gpu_only"],
+                          "oracle_only": v["oracle_only"], "max_rel_dtheta": r5(v["max_rel_dtheta"]),
+                          "max_rel_dR": r5(v["max_rel_dR"])} for k, v in prec.items()}
+    headline = {
         "metric": "events/sec at >=95% track eff (learned vs lattice seeds); response evals/s, %FP32 peak",
-        "value": E / g_lrn,
+        "value": r5(value),
         "unit": "events/s",
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
-        "ms_per_step": g_lrn * 1e3,
-        "ms_per_step_profiled": dt_lrn * 1e3,
+        "ms_per_step": r5(wall_lrn * 1e3),
+        "ms_per_step_events_median": r5(med_lrn),
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
         "dtype": "f32",
         "data": "synthetic",
-        "config": {"workload": "%s: %s" % (cfg["name"], cfg["description"]), "events": E,
-                   "hits": int(b.x.shape[0]),
-                   "seeds": "learned: %s, k_max %d, tau %g, conf_min %g, nms %d; lattice %dx%d fallback"
-                            % (os.path.basename(LS["model"]), LS["k_max"], LS["tau"], LS["conf_min"],
-                               int(LS["nms"]), P["lattice_n"][0], P["lattice_n"][1]),
+        "config": {"workload": "%s: %d events, %d hits, learned seeds (lattice %dx%d fallback)"
+                               % (cfg["name"], E, int(b.x.shape[0]), P["lattice_n"][0], P["lattice_n"][1]),
                    "parallelism": "single GPU"},
-        "quality": rq(q_lrn),
-        "learned": {"seeds_per_event": float(seeds_ev.mean()), "fallback_rate": fb_rate,
-                    "kernel_ms": dict(kms(prof_lrn), proposer=prof_lrn["ms_propose"]),
-                    "response_evals_per_s": pairs_lrn / (hot * 1e-3),
-                    "proposer_net_tflops": net_tflops},
-        "lattice": {"lattice_n": best["lattice_n"], "events_per_s": E / g_lat, "ms_per_step": g_lat * 1e3, "ms_per_step_profiled": dt_lat * 1e3,
-                    "quality": rq(q_lat), "kernel_ms": kms(prof_lat),
-                    "response_evals_per_s": pairs_lat / (prof_lat["ms_hot"] * 1e-3),
-                    "ascent_tflops": fl_lat / (prof_lat["ms_hot"] * 1e-3) / 1e12,
-                    "pairs_per_launch": {"algorithmic": pairs_lat, "executed": prof_lat["exec_pairs"],
-                                         "executed_line_search": prof_lat["exec_rpairs"]}},
-        "lattice_sweep": sweep,
-        "speedup_vs_lattice": g_lat / g_lrn,
-        "pruned": pruned,
-        "end_to_end_host_ms_per_step": ms_host,
-        "response": resp,
-        "response_c2_event": resp_c2,
-        "response_c1_grid": resp_c1,
-        "response_evals_per_s": pairs_lrn / (hot * 1e-3),
-        "pairs_per_launch": {"algorithmic": pairs_lrn, "executed": prof_lrn["exec_pairs"],
-                             "executed_line_search": prof_lrn["exec_rpairs"]},
-        "roofline": {"bound": "alu", "achieved": achieved, "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s",
-                     "frac": achieved / PEAK_FP32_TFLOPS,
-                     "traffic": measured_traffic(cfg["name"]), "traffic_unit": "bytes per launch", "kernel": "k_ascent (persistent truncated-Newton ascent, learned seeds)",
-                     "flops_per_launch": fl_lrn},
+        "quality": {"efficiency": round(q_lrn["efficiency"], 5), "fake_rate": round(q_lrn["fake_rate"], 5),
+                    "seeds_per_event": r5(float(seeds_ev.mean())), "fallback_rate": r5(fb_rate)},
+        "lattice": {"n": best["lattice_n"], "events_per_s": r5(E / wall_lat), "ms_per_step": r5(wall_lat * 1e3),
+                    "efficiency": round(q_lat["efficiency"], 5), "fake_rate": round(q_lat["fake_rate"], 5)},
+        "speedup_vs_lattice": r5(wall_lat / wall_lrn),
+        "roofline": roofline,
+        "response": {"RGH_pair_evals_per_s": r5(resp["RGH"]["pair_evals_per_s"]),
+                     "RGH_frac_fp32_peak": r5(resp["RGH"]["frac_fp32_peak"]),
+                     "R_pair_evals_per_s": r5(resp["R"]["pair_evals_per_s"]),
+                     "R_frac_fp32_peak": r5(resp["R"]["frac_fp32_peak"])},
+        "cost_model": {"T0_ns": r5(T0_ns), "C": r5(C), "C_paper": 3, "C0": r5(C0),
+                       "C0_learned": r5(C0_learned), "C0_paper": 30, "q": q_steps},
+        "cpu_baseline": (dict(cpu_l, value=r5(cpu_l["value"])) if cpu_l else None),
+        "cpu_baseline_lattice": ({"value": r5(cpu["value"]), "cores": cpu["cores"]} if cpu else None),
+        "fp32_vs_fp64": prec_short,
+    }
+    detail = dict(headline)
+    detail.update({
+        "ms_per_step_events": evs_lrn,
+        "lattice_detail": {"ms_per_step_events": evs_lat, "ms_per_step_events_median": med_lat,
+                           "kernel_ms": kms(prof_lat), "response_evals_per_s": pairs_lat / (prof_lat["ms_hot"] * 1e-3),
+                           "ascent_tflops": fl_lat / (prof_lat["ms_hot"] * 1e-3) / 1e12,
+                           "quality": rq(q_lat),
+                           "pairs_per_launch": {"algorithmic": pairs_lat, "executed": prof_lat["exec_pairs"],
+                                                "executed_line_search": prof_lat["exec_rpairs"]}},
+        "learned_detail": {"kernel_ms": dict(kms(prof_lrn), proposer=prof_lrn["ms_propose"]),
+                           "response_evals_per_s": pairs_lrn / (hot * 1e-3), "quality": rq(q_lrn),
+                           "pairs_per_launch": {"algorithmic": pairs_lrn, "executed": prof_lrn["exec_pairs"],
+                                                "executed_line_search": prof_lrn["exec_rpairs"]}},
         "roofline_proposer": {"bound": "mfma", "achieved": net_tflops, "peak": PEAK_BF16_TFLOPS,
                               "unit": "TFLOP/s", "frac": net_tflops / PEAK_BF16_TFLOPS,
                               "kernel": "binning + four conv layers + seed selection (network flops only)",
                               "flops_per_launch": FLOP_NET_EVENT * E},
-        "alpha_budget": alpha,
-        "alpha_budget_svelo": alpha_sv,
-        "update_rules": upd,
-        "cpu_baseline": cpu,
-        "cpu_baseline_learned": cpu_l,
-        "fp32_vs_fp64": prec,
-    }
-    print(json.dumps(out))
+        "lattice_sweep": sweep,
+        "end_to_end_host_ms_per_step": ms_host,
+        "response_detail": resp, "response_c2_event": resp_c2, "response_c1_grid": resp_c1,
+        "cpu_baseline_lattice_detail": cpu,
+        "fp32_vs_fp64_detail": prec,
+        "studies": studies,
+    })
+    dj = json.dumps(detail)
+    sys.stderr.write("[bench] detail %s\n" % dj)
+    sys.stderr.flush()
+    if args.detail_out:
+        with open(args.detail_out, "w") as fh:
+            fh.write(dj + "\n")
     if args.calib_copy_mib:
         n = args.calib_copy_mib * (1 << 20) // 4
         src = torch.ones(n, dtype=torch.float32, device=dev)
@@ -520,6 +551,42 @@ def main():
         dst.copy_(src)
         torch.cuda.synchronize()
         log("calibration copy: %d MiB read + %d MiB written" % (args.calib_copy_mib, args.calib_copy_mib))
+    line = json.dumps(headline, separators=(",", ":"))
+    sys.stdout.write(line + "\n")
+    sys.stdout.flush()
+
+
+def run_studies(ctx, retina, events, cfg, b, dev_hits, P, PL, LS, model, sizes, quality, args):
+    """Locality-pruned passes on both seedings, Section 3's alpha-budget scans
+    (c7, c8) and the update-rule comparison."""
+    import torch
+    D = b.meas_dim
+    E = b.n_events
+    PU = 30.0
+    sweep_p, best_p = lattice_sweep(ctx, retina, b, dev_hits, P, sizes, quality, prune_u=PU)
+    PLp = dict(PL, prune_u=PU)
+
+    def learned_pruned():
+        return ctx.retina_find_tracks_learned(model, b.plane_z, *dev_hits, PLp, LS["k_max"],
+                                              LS["tau"], LS["conf_min"], nms=LS["nms"])
+    r = learned_pruned()
+    torch.cuda.synchronize()
+    q_lp = quality(retina.tracks_from_device(r)["theta"][:, :2 * D], r["track_offsets"].cpu().numpy())
+    del r
+    learned_pruned()
+    wall, med, _ = timed_graph(learned_pruned, args.steps)
+    log("pruned learned: %.2f ms/step, efficiency %.4f; pruned lattice %dx%d %.2f ms" % (
+        wall * 1e3, q_lp["efficiency"], best_p["lattice_n"], best_p["lattice_n"], best_p["ms_per_step"]))
+    out = {"pruned": {"prune_u": PU, "lattice_sweep": sweep_p, "lattice_best": best_p,
+                      "learned": {"events_per_s": E / wall, "ms_per_step": wall * 1e3, "ms_events_median": med,
+                                  "efficiency": round(q_lp["efficiency"], 5), "fake_rate": round(q_lp["fake_rate"], 5)},
+                      "speedup_vs_lattice": best_p["ms_per_step"] / (wall * 1e3)}}
+    from paper_1709_08610_amd import budget
+    out["alpha_budget"] = budget.run(ctx, events.load_config("c7"), log=log)
+    out["alpha_budget_svelo"] = budget.run(ctx, events.load_config("c8"), log=log)
+    out["update_rules"] = {name: budget.compare_updates(ctx, events.load_config(name), log=log)
+                           for name in ("c7", "c8")}
+    return out
 
 
 if __name__ == "__main__":
