@@ -85,6 +85,7 @@ typedef struct {
 
 #define RETINA_MAX_PLANES 64
 #define RETINA_MAX_SIGMA 16
+#define RETINA_MAX_LATTICE_SIDE 8192   /* cells per dimension of a seed lattice or search grid */
 
 typedef struct {
     int32_t mem;                   /* RETINA_MEM_HOST or RETINA_MEM_DEVICE */
@@ -122,11 +123,15 @@ typedef struct {
                                    end planes of the detector */
     int32_t seed_mode;          /* RETINA_SEED_LATTICE or RETINA_SEED_EXPLICIT */
     int32_t lattice_n[2];       /* lattice: dims (tx, ty) for meas_dim 2 (x0 = y0 = 0),
-                                   (tx, x0) for meas_dim 1; dim 0 is the slow index */
+                                   (tx, x0) for meas_dim 1; dim 0 is the slow index;
+                                   each 1 .. RETINA_MAX_LATTICE_SIDE, at most 2^24 seeds */
     float lattice_lo[2];
     float lattice_hi[2];        /* cell centres: FP32(lo + (j + 1/2)(hi - lo)/n) formed in FP64 */
     const double* seeds;        /* EXPLICIT: n_par doubles per seed (rounded to FP32 for the
-                                   ascent), in the hits' memory space */
+                                   ascent), in the hits' memory space; a seed that is not
+                                   finite after that rounding gives RETINA_ERR_INVALID_ARG
+                                   (host memory: before any device work; device memory:
+                                   found by the ascent, no output written) */
     const int64_t* seed_offsets;/* EXPLICIT: n_events+1, in the hits' memory space */
     int32_t update;             /* RETINA_UPDATE_NEWTON: truncated Newton (Newton-CG in scaled
                                    coordinates); RETINA_UPDATE_GRADIENT: a scaled step of one
@@ -256,8 +261,11 @@ int retina_autotune(retina_ctx* ctx, const retina_geometry* geom, const retina_h
  *                dR/dtheta in theta's component order
  *   hess         n_theta * n_par(n_par+1)/2 floats (NULL unless WANT_HESS):
  *                upper triangle row-major (00,01,..,11,12,..)
- * FP32 arithmetic; residuals formed with one fused multiply-add so that no
- * large intermediate is rounded. */
+ * FP32 arithmetic.  Residuals are never formed from a rounded line position:
+ * once per (line, plane) the position o + t z is split exactly into a
+ * rounded value s and its error l (the product error of one fma plus the
+ * error of one addition), and each hit's residual is (x - s) - l, two
+ * subtractions whose first is exact for hits near the line. */
 int retina_response(retina_ctx* ctx, const retina_geometry* geom, const retina_hits* hits,
                     const float* theta, int64_t n_theta, const int64_t* theta_offsets,
                     float sigma, uint32_t want, float* R, float* grad, float* hess);
@@ -285,7 +293,7 @@ int retina_find_tracks(retina_ctx* ctx, const retina_geometry* geom, const retin
  * parameter grid, groups of high-response cells, one estimate per group).
  * ---------------------------------------------------------------------- */
 typedef struct {
-    int32_t n[2];           /* cells per dimension (>= 1, at most 2^26 cells) */
+    int32_t n[2];           /* cells per dimension, 1 .. RETINA_MAX_LATTICE_SIDE */
     float lo[2], hi[2];     /* box (finite, lo < hi); cell centres as the seed
                                lattice: FP32(lo + (i + 1/2)(hi - lo)/n), dimension
                                0 slow; meas_dim 2: dims (tx, ty) at x0 = y0 = 0;

@@ -2,6 +2,7 @@
 // sequence and the C-ABI entry points declared in include/retina.h.
 #include <math.h>
 #include <stdarg.h>
+#include <stddef.h>
 #include <stdio.h>
 #include <string.h>
 
@@ -216,6 +217,30 @@ void fill_geometry(Desc& d, const retina_geometry* g)
     d.z_ref = (float)sqrt(s2 / g->n_planes);
 }
 
+// clear the descriptor's fixed part (the lattice table is written by set_lattice)
+void reset_desc(Desc& d)
+{
+    memset(&d, 0, offsetof(Desc, lat_coord));
+}
+
+// cell-centred lattice (seed lattice or search grid) into the descriptor: the
+// FP32 rounding of lo + (i + 1/2)(hi - lo)/n, formed in FP64 on the host
+int set_lattice(retina_ctx* c, Desc& d, const int32_t* n, const float* lo, const float* hi)
+{
+    for (int k = 0; k < 2; ++k)
+        if (n[k] < 1 || n[k] > kMaxLatticeSide)
+            return fail(c, RETINA_ERR_INVALID_ARG, "lattice / grid side %d must be in [1, %d]", n[k], kMaxLatticeSide);
+    int o = 0;
+    for (int k = 0; k < 2; ++k) {
+        d.lattice_n[k] = n[k];
+        d.lattice_lo[k] = lo[k];
+        d.lattice_hi[k] = hi[k];
+        for (int i = 0; i < n[k]; ++i)
+            d.lat_coord[o++] = (float)((double)lo[k] + ((double)i + 0.5) * ((double)hi[k] - (double)lo[k]) / (double)n[k]);
+    }
+    return RETINA_OK;
+}
+
 // stage caller hits (copying host arrays into the pool when needed)
 int stage_inputs(retina_ctx* c, Desc& d, const retina_geometry* g, const retina_hits* h, int64_t n_hits)
 {
@@ -389,7 +414,11 @@ int run_tracks(retina_ctx* c, int D, const HotConfig& hc)
 
 int upload_desc(retina_ctx* c)
 {
-    HIP_TRY(c, hipMemcpyAsync(c->d_desc, c->h_desc, sizeof(Desc), hipMemcpyHostToDevice, c->stream));
+    // the fixed part and the used entries of the lattice table
+    const Desc& d = *c->h_desc;
+    const size_t n_lat = (size_t)std::max(d.lattice_n[0], 0) + (size_t)std::max(d.lattice_n[1], 0);
+    const size_t bytes = offsetof(Desc, lat_coord) + sizeof(float) * std::min<size_t>(n_lat, 2 * kMaxLatticeSide);
+    HIP_TRY(c, hipMemcpyAsync(c->d_desc, c->h_desc, bytes, hipMemcpyHostToDevice, c->stream));
     return RETINA_OK;
 }
 
@@ -583,7 +612,7 @@ int retina_response(retina_ctx* c, const retina_geometry* g, const retina_hits* 
     if (n_hits < 0 || n_hits > 0x7FFFFFFF) return fail(c, RETINA_ERR_INVALID_ARG, "bad total hit count");
 
     Desc& d = *c->h_desc;
-    memset(&d, 0, sizeof(Desc));
+    reset_desc(d);
     fill_geometry(d, g);
     d.cnt = c->d_cnt;
     if ((rc = stage_inputs(c, d, g, h, n_hits))) return rc;
@@ -675,8 +704,8 @@ int retina_grid_search(retina_ctx* c, const retina_geometry* g, const retina_hit
     int rc;
     if ((rc = check_geometry(c, g)) || (rc = check_hits(c, g, h))) return rc;
     if (!grid) return fail(c, RETINA_ERR_INVALID_ARG, "grid is NULL");
-    if (grid->n[0] < 1 || grid->n[1] < 1 || (int64_t)grid->n[0] * grid->n[1] > (1 << 26))
-        return fail(c, RETINA_ERR_INVALID_ARG, "grid n must be >= 1 with at most 2^26 cells");
+    if (grid->n[0] < 1 || grid->n[1] < 1 || grid->n[0] > kMaxLatticeSide || grid->n[1] > kMaxLatticeSide)
+        return fail(c, RETINA_ERR_INVALID_ARG, "grid n must be in [1, %d] per dimension", kMaxLatticeSide);
     for (int i = 0; i < 2; ++i)
         if (!isfinite(grid->lo[i]) || !isfinite(grid->hi[i]) || !(grid->lo[i] < grid->hi[i]))
             return fail(c, RETINA_ERR_INVALID_ARG, "grid box must be finite with lo < hi");
@@ -706,7 +735,7 @@ int retina_grid_search(retina_ctx* c, const retina_geometry* g, const retina_hit
     if (E * nch > 0x7FFFFFFF) return fail(c, RETINA_ERR_INVALID_ARG, "batch too large for one grid search");
 
     Desc& d = *c->h_desc;
-    memset(&d, 0, sizeof(Desc));
+    reset_desc(d);
     fill_geometry(d, g);
     d.cnt = c->d_cnt;
     if ((rc = stage_inputs(c, d, g, h, n_hits))) return rc;
@@ -725,9 +754,7 @@ int retina_grid_search(retina_ctx* c, const retina_geometry* g, const retina_hit
     d.want = RETINA_WANT_R;
     d.resp_sigma = grid->sigma;
     d.resp_grid = 1;
-    d.lattice_n[0] = grid->n[0];
-    d.lattice_n[1] = grid->n[1];
-    for (int i = 0; i < 2; ++i) { d.lattice_lo[i] = grid->lo[i]; d.lattice_hi[i] = grid->hi[i]; }
+    if ((rc = set_lattice(c, d, grid->n, grid->lo, grid->hi))) return rc;
     d.grid_R0 = grid->R0;
     d.grid_chunks = (int32_t)nch;
     if (!host && R_grid) d.out_R = R_grid;
@@ -817,8 +844,10 @@ static int find_tracks_impl(retina_ctx* c, const retina_geometry* g, const retin
     if (P->prune_u > 0.0f && P->update != RETINA_UPDATE_NEWTON)
         return fail(c, RETINA_ERR_INVALID_ARG, "pruned passes run with the truncated-Newton rule only");
     if (P->seed_mode == RETINA_SEED_LATTICE) {
-        if (P->lattice_n[0] < 1 || P->lattice_n[1] < 1 || (int64_t)P->lattice_n[0] * P->lattice_n[1] > (1 << 24))
-            return fail(c, RETINA_ERR_INVALID_ARG, "lattice_n must be >= 1 with at most 2^24 seeds");
+        if (P->lattice_n[0] < 1 || P->lattice_n[1] < 1 || P->lattice_n[0] > kMaxLatticeSide ||
+            P->lattice_n[1] > kMaxLatticeSide || (int64_t)P->lattice_n[0] * P->lattice_n[1] > (1 << 24))
+            return fail(c, RETINA_ERR_INVALID_ARG, "lattice_n must be in [1, %d] with at most 2^24 seeds",
+                        kMaxLatticeSide);
         for (int i = 0; i < 2; ++i)
             if (!isfinite(P->lattice_lo[i]) || !isfinite(P->lattice_hi[i]))
                 return fail(c, RETINA_ERR_INVALID_ARG, "lattice box must be finite");
@@ -850,7 +879,8 @@ static int find_tracks_impl(retina_ctx* c, const retina_geometry* g, const retin
         if (n_seeds < 0 || n_seeds > 0x7FFFFFFF) return fail(c, RETINA_ERR_INVALID_ARG, "bad total seed count");
         if (!seeds_dev)
             for (int64_t i = 0; i < n_seeds * NP; ++i)
-                if (!isfinite(P->seeds[i])) return fail(c, RETINA_ERR_INVALID_ARG, "an explicit seed is NaN or infinite");
+                if (!isfinite((float)P->seeds[i]))
+                    return fail(c, RETINA_ERR_INVALID_ARG, "an explicit seed is NaN or infinite in FP32");
     } else {
         n_seeds = E * (int64_t)P->lattice_n[0] * P->lattice_n[1];
         if (n_seeds > 0x7FFFFFFF) return fail(c, RETINA_ERR_INVALID_ARG, "too many seeds in the batch");
@@ -860,7 +890,7 @@ static int find_tracks_impl(retina_ctx* c, const retina_geometry* g, const retin
                     (long long)so->capacity, (long long)n_seeds);
 
     Desc& d = *c->h_desc;
-    memset(&d, 0, sizeof(Desc));
+    reset_desc(d);
     fill_geometry(d, g);
     d.cnt = c->d_cnt;
     if ((rc = stage_inputs(c, d, g, h, n_hits))) return rc;
@@ -882,9 +912,8 @@ static int find_tracks_impl(retina_ctx* c, const retina_geometry* g, const retin
     d.items_cap = n_seeds / d.seeds_per_item + E + 1;
     if ((rc = ensure_t(c, B_ITEMS, (size_t)d.items_cap, &d.items))) return rc;
     d.seed_mode = P->seed_mode;
-    d.lattice_n[0] = P->lattice_n[0];
-    d.lattice_n[1] = P->lattice_n[1];
-    for (int i = 0; i < 2; ++i) { d.lattice_lo[i] = P->lattice_lo[i]; d.lattice_hi[i] = P->lattice_hi[i]; }
+    if (P->seed_mode == RETINA_SEED_LATTICE && (rc = set_lattice(c, d, P->lattice_n, P->lattice_lo, P->lattice_hi)))
+        return rc;
     d.n_sigma = P->n_sigma;
     for (int i = 0; i < P->n_sigma; ++i) d.sigma[i] = P->sigma[i];
     d.sigma_final = P->sigma_final;
@@ -1173,7 +1202,8 @@ uint64_t fnv1a(const void* p, size_t n, uint64_t h = 1469598103934665603ull)
 
 // validate + stage hits (per-plane order, plane offsets) for the proposer;
 // fills c->h_desc and leaves the staged arrays in the pool
-int proposer_stage(retina_ctx* c, const retina_geometry* g, const retina_hits* h)
+int proposer_stage(retina_ctx* c, const retina_geometry* g, const retina_hits* h,
+                   const retina_params* fallback = nullptr)
 {
     int rc;
     if ((rc = check_geometry(c, g)) || (rc = check_hits(c, g, h))) return rc;
@@ -1185,10 +1215,12 @@ int proposer_stage(retina_ctx* c, const retina_geometry* g, const retina_hits* h
     if ((rc = read_i64(c, h->mem, h->event_offsets, E, &n_hits))) return rc;
     if (n_hits < 0 || n_hits > 0x7FFFFFFF) return fail(c, RETINA_ERR_INVALID_ARG, "bad total hit count");
     Desc& d = *c->h_desc;
-    memset(&d, 0, sizeof(Desc));
+    reset_desc(d);
     fill_geometry(d, g);
     d.cnt = c->d_cnt;
     if ((rc = stage_inputs(c, d, g, h, n_hits))) return rc;
+    if (fallback && (rc = set_lattice(c, d, fallback->lattice_n, fallback->lattice_lo, fallback->lattice_hi)))
+        return rc;
     if ((rc = upload_desc(c))) return rc;
     launch_reset(c->d_desc, c->stream);
     launch_stage(c->d_desc, c->n_cu * 8, c->stream);
@@ -1510,9 +1542,11 @@ int propose_device(retina_ctx* c, const retina_geometry* g, const retina_hits* h
     if (!(tau > 0.0f && tau < 1.0f) || !(conf_min >= 0.0f && conf_min <= 1.0f))
         return fail(c, RETINA_ERR_INVALID_ARG, "tau must be in (0, 1) and conf_min in [0, 1]");
     if (pr->nms != 0 && pr->nms != 1) return fail(c, RETINA_ERR_INVALID_ARG, "nms must be 0 or 1");
-    if (P->lattice_n[0] < 1 || P->lattice_n[1] < 1 || (int64_t)P->lattice_n[0] * P->lattice_n[1] > (1 << 24))
-        return fail(c, RETINA_ERR_INVALID_ARG, "fallback lattice_n must be >= 1 with at most 2^24 seeds");
-    if ((rc = proposer_stage(c, g, h))) return rc;
+    if (P->lattice_n[0] < 1 || P->lattice_n[1] < 1 || P->lattice_n[0] > kMaxLatticeSide ||
+        P->lattice_n[1] > kMaxLatticeSide || (int64_t)P->lattice_n[0] * P->lattice_n[1] > (1 << 24))
+        return fail(c, RETINA_ERR_INVALID_ARG, "fallback lattice_n must be in [1, %d] with at most 2^24 seeds",
+                    kMaxLatticeSide);
+    if ((rc = proposer_stage(c, g, h, P))) return rc;
     const int64_t E = h->n_events;
     Acts A;
     if ((rc = ensure_acts(c, E, A, false))) return rc;
@@ -1529,10 +1563,11 @@ int propose_device(retina_ctx* c, const retina_geometry* g, const retina_hits* h
     pa.lconf = conf_min <= 0.0f ? -INFINITY
              : conf_min >= 1.0f ? INFINITY : (float)log((double)conf_min / (1.0 - (double)conf_min));
     pa.nms = pr->nms;
-    for (int i = 0; i < 2; ++i) {
-        pa.lattice_n[i] = P->lattice_n[i];
-        pa.lattice_lo[i] = P->lattice_lo[i];
-        pa.lattice_hi[i] = P->lattice_hi[i];
+    for (int i = 0; i < 2; ++i) pa.lattice_n[i] = P->lattice_n[i];
+    pa.lat_coord = c->d_desc->lat_coord;  // device address: proposer_stage uploaded the table
+    {
+        const double w = ((double)kSlopeHi - (double)kSlopeLo) / kImg;
+        for (int i = 0; i < kImg; ++i) pa.bin_centre[i] = (float)((double)kSlopeLo + ((double)i + 0.5) * w);
     }
     if ((rc = ensure_t(c, B_PSCORE, (size_t)E * k_max, &pa.cand_score)) ||
         (rc = ensure_t(c, B_PPIX, (size_t)E * k_max, &pa.cand_pix)) || (rc = ensure_t(c, B_PCOUNT, (size_t)E, &pa.count)) ||

@@ -142,20 +142,20 @@ __global__ __launch_bounds__(kGridThreads) void k_grid_emit(const Desc* __restri
             for (int a = -1; a <= 1; ++a) {
                 const int j0 = i0 + a;
                 if (j0 < 0 || j0 >= n0) continue;
-                const double v0 = lattice_coord(d->lattice_lo[0], d->lattice_hi[0], n0, j0);
+                const double v0 = d->lat_coord[j0];
                 for (int b = -1; b <= 1; ++b) {
                     const int j1 = i1 + b;
                     if (j1 < 0 || j1 >= n1) continue;
                     const float g = G[(int64_t)j0 * n1 + j1];
-                    const double v1 = lattice_coord(d->lattice_lo[1], d->lattice_hi[1], n1, j1);
+                    const double v1 = d->lat_coord[n0 + j1];
                     w += (double)g;
                     m0 += (double)g * v0;
                     m1 += (double)g * v1;
                     members += g >= R0;
                 }
             }
-            double t0 = lattice_coord(d->lattice_lo[0], d->lattice_hi[0], n0, i0);
-            double t1 = lattice_coord(d->lattice_lo[1], d->lattice_hi[1], n1, i1);
+            double t0 = d->lat_coord[i0];
+            double t1 = d->lat_coord[n0 + i1];
             if (w > 0.0) { t0 = m0 / w; t1 = m1 / w; }
             retina_track tr;
             if constexpr (D == 2) { tr.theta[0] = 0.0; tr.theta[1] = 0.0; tr.theta[2] = t0; tr.theta[3] = t1; }

@@ -704,14 +704,15 @@ __device__ __forceinline__ EventView begin_event(const Desc* __restrict__ d, int
 
 // ------------------------------------------------------------------ ascent
 // Lattice point i of an event (dimension 0 slow): D = 2 gives (0, 0, tx, ty),
-// D = 1 gives (x0, tx) with tx along dimension 0.
+// D = 1 gives (x0, tx) with tx along dimension 0.  The coordinates come from
+// the descriptor's table (formed on the host).
 template <int D>
 __device__ __forceinline__ void lattice_point(const Desc* __restrict__ d, int i, float* th)
 {
     const int n1 = d->lattice_n[1];
     const int i0 = i / n1, i1 = i % n1;
-    const float v0 = lattice_coord(d->lattice_lo[0], d->lattice_hi[0], d->lattice_n[0], i0);
-    const float v1 = lattice_coord(d->lattice_lo[1], d->lattice_hi[1], n1, i1);
+    const float v0 = d->lat_coord[i0];
+    const float v1 = d->lat_coord[d->lattice_n[0] + i1];
     if constexpr (D == 2) { th[0] = 0.0f; th[1] = 0.0f; th[2] = v0; th[3] = v1; }
     else { th[0] = v1; th[1] = v0; }
 }
@@ -784,8 +785,20 @@ __global__ __launch_bounds__(kBlock) void k_ascent(const Desc* __restrict__ d, i
             const int sjc = active[j] ? sj : 0;
             if (d->seed_mode == RETINA_SEED_EXPLICIT) {
                 const double* s = d->in_seeds + (sbase + sjc) * NP;
+                bool finite = true;
 #pragma unroll
-                for (int a = 0; a < NP; ++a) th[j][a] = active[j] ? (float)s[a] : 0.0f;
+                for (int a = 0; a < NP; ++a) {
+                    th[j][a] = active[j] ? (float)s[a] : 0.0f;
+                    finite = finite && isfinite(th[j][a]);
+                }
+                if (!finite) {
+                    // device-memory seeds are validated here: the call fails
+                    // (no output is written) and the seed stays out of the passes
+                    atomicOr(&d->cnt->err, kErrSeedVal);
+                    active[j] = false;
+#pragma unroll
+                    for (int a = 0; a < NP; ++a) th[j][a] = 0.0f;
+                }
             } else {
                 lattice_point<D>(d, sjc, th[j]);
             }

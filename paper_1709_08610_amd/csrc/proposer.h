@@ -77,7 +77,8 @@ struct ProposeArgs {
     float lconf;               // logit(conf_min): events whose best logit is below fall back
     int nms;                   // 1: strict 3x3 local maxima only
     int lattice_n[2];
-    float lattice_lo[2], lattice_hi[2];
+    const float* lat_coord;    // fallback lattice cell centres (device; dimension 0 then 1)
+    float bin_centre[kImg];    // slope at the centre of each image bin, formed on the host
     float* cand_score;         // scratch (E, k_max)
     int32_t* cand_pix;         // scratch (E, k_max)
     int32_t* count;            // (E) seeds of the event

@@ -1306,27 +1306,27 @@ __global__ __launch_bounds__(1024) void k_propose_offsets(ProposeArgs a)
 
 __global__ __launch_bounds__(256) void k_propose_write(ProposeArgs a)
 {
-    const double w = ((double)kSlopeHi - (double)kSlopeLo) / kImg;
+    // coordinates come from host-formed tables: the bin centres (FP32 rounding
+    // of lo + (i + 1/2) w formed in FP64) and the fallback lattice's centres
     for (int64_t e = blockIdx.x; e < a.n_events; e += gridDim.x) {
         double* out = a.seeds + a.seed_off[e] * 4;
         const int n = a.count[e];
         if (a.fallback[e]) {
-            const int n1 = a.lattice_n[1];
-            const double lo0 = a.lattice_lo[0], hi0 = a.lattice_hi[0], lo1 = a.lattice_lo[1], hi1 = a.lattice_hi[1];
+            const int n0 = a.lattice_n[0], n1 = a.lattice_n[1];
             for (int i = threadIdx.x; i < n; i += blockDim.x) {
                 const int i0 = i / n1, i1 = i % n1;
                 out[4 * i + 0] = 0.0;
                 out[4 * i + 1] = 0.0;
-                out[4 * i + 2] = (double)(float)(lo0 + ((double)i0 + 0.5) * (hi0 - lo0) / (double)a.lattice_n[0]);
-                out[4 * i + 3] = (double)(float)(lo1 + ((double)i1 + 0.5) * (hi1 - lo1) / (double)n1);
+                out[4 * i + 2] = (double)a.lat_coord[i0];
+                out[4 * i + 3] = (double)a.lat_coord[n0 + i1];
             }
         } else {
             for (int i = threadIdx.x; i < n; i += blockDim.x) {
                 const int pix = a.cand_pix[e * a.k_max + i];
                 out[4 * i + 0] = 0.0;
                 out[4 * i + 1] = 0.0;
-                out[4 * i + 2] = (double)(float)(kSlopeLo + ((pix / kImg) + 0.5) * w);
-                out[4 * i + 3] = (double)(float)(kSlopeLo + ((pix % kImg) + 0.5) * w);
+                out[4 * i + 2] = (double)a.bin_centre[pix / kImg];
+                out[4 * i + 3] = (double)a.bin_centre[pix % kImg];
             }
         }
     }

@@ -30,12 +30,9 @@ enum : uint32_t {
     kErrCapacity = 128u   // tracks do not fit the caller's array
 };
 
-// Cell-centred lattice coordinate i of n over [lo, hi]: FP32 rounding of
-// lo + (i + 1/2)(hi - lo)/n formed in FP64 (seed lattice and search grid alike).
-__host__ __device__ __forceinline__ float lattice_coord(float lo, float hi, int n, int64_t i)
-{
-    return (float)((double)lo + ((double)i + 0.5) * ((double)hi - (double)lo) / (double)n);
-}
+// Largest side of a seed lattice or search grid: the cell-centre coordinates
+// of both dimensions travel in the descriptor (Desc::lat_coord).
+constexpr int kMaxLatticeSide = RETINA_MAX_LATTICE_SIDE;
 
 // device-side counters (one cache line each to avoid false sharing of atomics)
 struct Counters {
@@ -131,6 +128,12 @@ struct Desc {
     int32_t* out_s_nreval;
     // device counters
     Counters* cnt;
+    // Cell-centre coordinates of the seed lattice / search grid, formed on the
+    // host: dimension 0 in [0, lattice_n[0]), dimension 1 in [lattice_n[0],
+    // lattice_n[0] + lattice_n[1]); each the FP32 rounding of
+    // lo + (i + 1/2)(hi - lo)/n formed in FP64.  Only the used entries are
+    // uploaded; must stay the last member.
+    float lat_coord[2 * kMaxLatticeSide];
 };
 
 // launchers (one per translation unit); all asynchronous on `st`
