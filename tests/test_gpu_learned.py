@@ -106,8 +106,9 @@ def test_trained_seeds_and_tracks_match_oracle(setup):
     """On a few events: the oracle runs the trained weights in FP64 (BF16 at the
     device's storage points), selects its own seeds and runs Algorithm 1 on
     them; the device's seeds must be the same bins (up to bins whose logit is
-    within the forward error bound of the threshold) and, where they are, the
-    tracks must match."""
+    within the forward error bound of the threshold); the device's ascent on
+    the oracle's seeds must match the oracle's tracks, and when the seed sets
+    are identical, so must the whole learned entry point."""
     _say("trained proposer: seeds and tracks vs the oracle")
     cfg, b, (off, x, y, pl), ctx, LS, model = setup
     ev = list(range(6))
@@ -137,14 +138,20 @@ def test_trained_seeds_and_tracks_match_oracle(setup):
         ref_seeds.append(op.seeds_from_pixels(picks))
         ref_off.append(ref_off[-1] + len(picks))
         _say("  event %d: %d seeds, %d differing (marginal) bins" % (e, len(picks), len(diff)))
-    if not same:
-        pytest.skip("marginal seed bins differ; track parity needs identical seeds")
-    ref = oracle.find_tracks(sub, LS["params"], np.concatenate(ref_seeds), np.array(ref_off, np.int64))
-    got = ctx.retina_find_tracks_learned(model, sub.plane_z, sub.event_offsets, sub.x, sub.y, sub.plane,
-                                         LS["params"], LS["k_max"], LS["tau"], LS["conf_min"], nms=LS["nms"])
+    seeds, soff = np.concatenate(ref_seeds), np.array(ref_off, np.int64)
+    ref = oracle.find_tracks(sub, LS["params"], seeds, soff)
+    # the ascent on the oracle's seeds always; the whole learned entry point
+    # too when the two seed sets are identical (no marginal bin)
+    runs = [("explicit oracle seeds", ctx.retina_find_tracks(2, sub.plane_z, sub.event_offsets, sub.x, sub.y,
+                                                             sub.plane, LS["params"], seeds=seeds, seed_offsets=soff))]
+    if same:
+        runs.append(("learned entry point", ctx.retina_find_tracks_learned(
+            model, sub.plane_z, sub.event_offsets, sub.x, sub.y, sub.plane, LS["params"], LS["k_max"], LS["tau"],
+            LS["conf_min"], nms=LS["nms"])))
     z0, z1 = float(sub.plane_z[0]), float(sub.plane_z[-1])
-    for e in range(sub.n_events):
-        a, c = int(ref["track_offsets"][e]), int(ref["track_offsets"][e + 1])
-        gt, gR = event_tracks(got, e, 2)
-        assert_tracks_match(2, gt, gR, ref["theta"][a:c], ref["R"][a:c], LS["params"]["d_merge"], z0, z1)
-    _say("  %d tracks match" % int(ref["track_offsets"][-1]))
+    for name, got in runs:
+        for e in range(sub.n_events):
+            a, c = int(ref["track_offsets"][e]), int(ref["track_offsets"][e + 1])
+            gt, gR = event_tracks(got, e, 2)
+            assert_tracks_match(2, gt, gR, ref["theta"][a:c], ref["R"][a:c], LS["params"]["d_merge"], z0, z1)
+        _say("  %s: %d tracks match" % (name, int(ref["track_offsets"][-1])))

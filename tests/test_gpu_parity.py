@@ -306,3 +306,35 @@ def test_find_tracks_rejects_invalid_hits(ctx, defect):
     with pytest.raises(retina.RetinaError) as ei:
         ctx.retina_find_tracks(2, b.plane_z, off, x, b.y, pl, cfg["params"])
     assert ei.value.code == retina.ERR_INVALID_ARG
+
+
+@pytest.mark.parametrize("mem", ["host", "device"])
+@pytest.mark.parametrize("value", [np.nan, np.inf, 1e300])
+def test_find_tracks_rejects_non_finite_seeds(ctx, mem, value):
+    """An explicit seed that is not finite in FP32 (NaN, inf, or a double
+    beyond the FP32 range) gives RETINA_ERR_INVALID_ARG: host seeds are
+    checked before any device work, device seeds by the ascent; no track is
+    written either way, and the next call on the context works."""
+    import torch
+    _say("non-finite explicit seed (%s, %s)" % (mem, value))
+    cfg = events.load_config("c2")
+    b = events.make_batch(cfg, 2)
+    P = cfg["params"]
+    seeds = np.concatenate([b.truth[0], b.truth[1]])
+    soff = np.array([0, len(b.truth[0]), len(seeds)], np.int64)
+    bad = seeds.copy()
+    bad[len(b.truth[0]) + 3, 2] = value
+    if mem == "host":
+        args = (b.event_offsets, b.x, b.y, b.plane)
+        s, so = bad, soff
+    else:
+        dev = torch.device("cuda:0")
+        tin = lambda a: torch.from_numpy(np.ascontiguousarray(a)).to(dev)
+        args = (tin(b.event_offsets), tin(b.x), tin(b.y), tin(b.plane))
+        s, so = tin(bad), tin(soff)
+    with pytest.raises(retina.RetinaError) as ei:
+        ctx.retina_find_tracks(2, b.plane_z, *args, P, seeds=s, seed_offsets=so)
+    assert ei.value.code == retina.ERR_INVALID_ARG and "seed" in str(ei.value)
+    good = ctx.retina_find_tracks(2, b.plane_z, b.event_offsets, b.x, b.y, b.plane, P, seeds=seeds,
+                                  seed_offsets=soff)
+    assert good["track_offsets"][-1] > 100
