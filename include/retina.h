@@ -86,6 +86,7 @@ typedef struct {
 #define RETINA_MAX_PLANES 64
 #define RETINA_MAX_SIGMA 16
 #define RETINA_MAX_LATTICE_SIDE 8192   /* cells per dimension of a seed lattice or search grid */
+#define RETINA_NOALLOC_SCRATCH_BYTES (64ull << 20)  /* fixed workspace of retina_response_noalloc, per device */
 
 typedef struct {
     int32_t mem;                   /* RETINA_MEM_HOST or RETINA_MEM_DEVICE */
@@ -269,6 +270,29 @@ int retina_autotune(retina_ctx* ctx, const retina_geometry* geom, const retina_h
 int retina_response(retina_ctx* ctx, const retina_geometry* geom, const retina_hits* hits,
                     const float* theta, int64_t n_theta, const int64_t* theta_offsets,
                     float sigma, uint32_t want, float* R, float* grad, float* hess);
+
+/* retina_response for callers that cannot allocate device memory: code under
+ * HIP graph capture, tight serving loops, harnesses that forbid hipMalloc.
+ * Same arguments, results and errors as retina_response, except:
+ *   - hits, theta, theta_offsets, R, grad and hess must be device memory
+ *     (hits.mem == RETINA_MEM_DEVICE), else RETINA_ERR_INVALID_ARG;
+ *   - the call's workspace (staged hits, per-event offsets, the work list and
+ *     the hit-part partial sums) comes from a fixed array of
+ *     RETINA_NOALLOC_SCRATCH_BYTES in device memory, one per device, which
+ *     the library holds from its load until the process ends; the call
+ *     itself makes no hipMalloc / hipFree or other allocation;
+ *   - a call whose workspace does not fit returns RETINA_ERR_CAPACITY with
+ *     the sizes in retina_last_error, before any device work (about
+ *     4 meas_dim bytes per hit plus 4 (n_planes + 7) bytes per event);
+ *     when the hit-part partial sums alone do not fit, fewer parts are used,
+ *     which changes R, grad and hess only in FP32 summation order.
+ * Every call on one device shares that device's array and leaves its
+ * contents behind (nothing in it has to start at zero: each call writes what
+ * it reads).  Calls that overlap in time on one device, from any context or
+ * stream, race on it and must be serialised by the caller. */
+int retina_response_noalloc(retina_ctx* ctx, const retina_geometry* geom, const retina_hits* hits,
+                            const float* theta, int64_t n_theta, const int64_t* theta_offsets,
+                            float sigma, uint32_t want, float* R, float* grad, float* hess);
 
 /* Algorithm 1 on every event of the batch in one device pass: seeds (lattice
  * or explicit), truncated-Newton ascents with sigma continuation, FP64 Newton

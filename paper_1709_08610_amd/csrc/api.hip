@@ -7,6 +7,7 @@
 #include <string.h>
 
 #include <algorithm>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -67,6 +68,7 @@ struct retina_ctx {
         hipGraphExec_t exec;
     };
     std::vector<GraphEntry> graphs;
+    void* scratch = nullptr;      // this device's fixed workspace (retina_response_noalloc)
 };
 
 namespace {
@@ -148,6 +150,30 @@ int ensure_t(retina_ctx* c, int id, size_t count, T** out)
     int rc = ensure(c, id, count * sizeof(T), &p);
     *out = (T*)p;
     return rc;
+}
+
+// Fixed workspace for the allocation-free entry point: a bump allocator over
+// the per-device scratch array (256-byte aligned pieces, no device work).
+struct Arena {
+    char* base = nullptr;
+    size_t cap = 0;
+    size_t used = 0;
+};
+
+// A pool buffer (ar == NULL) or the next piece of the arena.
+template <typename T>
+int take(retina_ctx* c, Arena* ar, int id, size_t count, T** out)
+{
+    if (!ar) return ensure_t(c, id, count, out);
+    const size_t bytes = (std::max<size_t>(count * sizeof(T), 16) + 255) & ~(size_t)255;
+    if (ar->used + bytes > ar->cap)
+        return fail(c, RETINA_ERR_CAPACITY,
+                    "the call needs more than the %zu bytes of the fixed device workspace "
+                    "(%zu in use, %zu more requested)",
+                    ar->cap, ar->used, bytes);
+    *out = reinterpret_cast<T*>(ar->base + ar->used);
+    ar->used += bytes;
+    return RETINA_OK;
 }
 
 int check_geometry(retina_ctx* c, const retina_geometry* g)
@@ -242,7 +268,8 @@ int set_lattice(retina_ctx* c, Desc& d, const int32_t* n, const float* lo, const
 }
 
 // stage caller hits (copying host arrays into the pool when needed)
-int stage_inputs(retina_ctx* c, Desc& d, const retina_geometry* g, const retina_hits* h, int64_t n_hits)
+int stage_inputs(retina_ctx* c, Desc& d, const retina_geometry* g, const retina_hits* h, int64_t n_hits,
+                 Arena* ar = nullptr)
 {
     d.n_events = h->n_events;
     d.n_hits = n_hits;
@@ -253,6 +280,7 @@ int stage_inputs(retina_ctx* c, Desc& d, const retina_geometry* g, const retina_
         d.in_y = D == 2 ? h->y : nullptr;
         d.in_plane = h->plane;
     } else {
+        if (ar) return fail(c, RETINA_ERR_INVALID_ARG, "the fixed-workspace call takes device memory only");
         int64_t* off;
         float *x, *y = nullptr;
         int32_t* pl;
@@ -276,11 +304,11 @@ int stage_inputs(retina_ctx* c, Desc& d, const retina_geometry* g, const retina_
     }
     int rc;
     const int64_t E = h->n_events;
-    if ((rc = ensure_t(c, B_HITS, (size_t)std::max<int64_t>(n_hits, 1) * D, &d.hits))) return rc;
-    if ((rc = ensure_t(c, B_POFF, (size_t)E * (g->n_planes + 1) + 1, &d.plane_off))) return rc;
-    if ((rc = ensure_t(c, B_NHITS, (size_t)E + 1, &d.ev_nhits))) return rc;
-    if ((rc = ensure_t(c, B_SOFF, (size_t)E + 1, &d.seed_off))) return rc;
-    if ((rc = ensure_t(c, B_ORDER, (size_t)E + 1, &d.order))) return rc;
+    if ((rc = take(c, ar, B_HITS, (size_t)std::max<int64_t>(n_hits, 1) * D, &d.hits))) return rc;
+    if ((rc = take(c, ar, B_POFF, (size_t)E * (g->n_planes + 1) + 1, &d.plane_off))) return rc;
+    if ((rc = take(c, ar, B_NHITS, (size_t)E + 1, &d.ev_nhits))) return rc;
+    if ((rc = take(c, ar, B_SOFF, (size_t)E + 1, &d.seed_off))) return rc;
+    if ((rc = take(c, ar, B_ORDER, (size_t)E + 1, &d.order))) return rc;
     return RETINA_OK;
 }
 
@@ -431,6 +459,36 @@ int download_counters(retina_ctx* c)
 
 }  // namespace
 
+// Per-device fixed workspace of retina_response_noalloc.  In host code the
+// array's name is a stand-in, not a device address: every host-side use goes
+// through the address hipGetSymbolAddress returns for the current device
+// (kept per device in g_scratch_addr, taken once by retina_create).
+constexpr size_t kScratchBytes = (size_t)RETINA_NOALLOC_SCRATCH_BYTES;
+static __device__ __align__(256) unsigned char scratch[kScratchBytes];
+
+namespace {
+constexpr int kMaxDevices = 64;
+void* g_scratch_addr[kMaxDevices] = {};
+std::mutex g_scratch_mu;
+
+// once per device, with that device current
+int scratch_address(int dev, void** out)
+{
+    if (dev < 0 || dev >= kMaxDevices) return RETINA_ERR_DEVICE;
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_addr[dev]) {
+        void* p = nullptr;
+        if (hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)) != hipSuccess || !p) {
+            (void)hipGetLastError();
+            return RETINA_ERR_DEVICE;
+        }
+        g_scratch_addr[dev] = p;
+    }
+    *out = g_scratch_addr[dev];
+    return RETINA_OK;
+}
+}  // namespace
+
 extern "C" {
 
 int retina_create(int device_ordinal, retina_ctx** out)
@@ -463,6 +521,10 @@ int retina_create(int device_ordinal, retina_ctx** out)
         return RETINA_ERR_DEVICE;
     }
     c->stream = c->own;
+    if (scratch_address(device_ordinal, &c->scratch) != RETINA_OK) {
+        retina_destroy(c);
+        return RETINA_ERR_DEVICE;
+    }
     for (int D = 1; D <= 2; ++D) {
         c->ascent_cfg[D] = default_hot(c, D, true);
         c->resp_cfg[D] = default_hot(c, D, false);
@@ -579,9 +641,15 @@ int retina_get_tuning(const retina_ctx* c, int32_t meas_dim, int32_t kernel, int
     return RETINA_OK;
 }
 
-int retina_response(retina_ctx* c, const retina_geometry* g, const retina_hits* h, const float* theta,
-                    int64_t n_theta, const int64_t* theta_offsets, float sigma, uint32_t want, float* R,
-                    float* grad, float* hess)
+}  // extern "C"
+
+namespace {
+
+// Eq. (1) and its derivatives at caller lines; workspace from the pool or,
+// with ar != NULL, from the fixed arena (no allocation of any kind).
+int response_impl(retina_ctx* c, const retina_geometry* g, const retina_hits* h, const float* theta,
+                  int64_t n_theta, const int64_t* theta_offsets, float sigma, uint32_t want, float* R,
+                  float* grad, float* hess, Arena* ar)
 {
     if (!c) return RETINA_ERR_INVALID_ARG;
     c->err.clear();
@@ -615,7 +683,7 @@ int retina_response(retina_ctx* c, const retina_geometry* g, const retina_hits* 
     reset_desc(d);
     fill_geometry(d, g);
     d.cnt = c->d_cnt;
-    if ((rc = stage_inputs(c, d, g, h, n_hits))) return rc;
+    if ((rc = stage_inputs(c, d, g, h, n_hits, ar))) return rc;
     const HotConfig hc = c->resp_cfg[D];
     d.seeds_per_item = hot_seeds_per_item(hc);
     // few (event, theta block) items leave CUs idle: split each event's hits
@@ -626,11 +694,20 @@ int retina_response(retina_ctx* c, const retina_geometry* g, const retina_hits* 
     while (parts < kRespMaxParts && blocks * parts < (int64_t)hc.grid &&
            n_hits / (E * parts * 2) >= kRespMinPartHits)
         parts *= 2;
+    const size_t n_acc = D == 2 ? 16 : 8;
+    if (ar) {
+        // the fixed workspace: fewer parts when the partial sums would not fit
+        // (results then differ only in FP32 summation order)
+        const size_t left = ar->cap - ar->used;
+        while (parts > 1 && ((size_t)(n_theta / d.seeds_per_item + E + 1) * parts * sizeof(int2) +
+                             (size_t)parts * n_theta * n_acc * sizeof(float) + 2048) > left)
+            parts /= 2;
+    }
     d.resp_parts = parts;
     d.resp_ntheta = n_theta;
     d.items_cap = (n_theta / d.seeds_per_item + E + 1) * parts;
-    if ((rc = ensure_t(c, B_ITEMS, (size_t)d.items_cap, &d.items))) return rc;
-    if (parts > 1 && (rc = ensure_t(c, B_RESPPART, (size_t)parts * n_theta * (D == 2 ? 16 : 8), &d.resp_partial)))
+    if ((rc = take(c, ar, B_ITEMS, (size_t)d.items_cap, &d.items))) return rc;
+    if (parts > 1 && (rc = take(c, ar, B_RESPPART, (size_t)parts * n_theta * n_acc, &d.resp_partial)))
         return rc;
     d.want = want | RETINA_WANT_R;
     d.resp_sigma = sigma;
@@ -658,12 +735,9 @@ int retina_response(retina_ctx* c, const retina_geometry* g, const retina_hits* 
         if (theta_offsets) {
             d.in_theta_off = theta_offsets;
         } else {
-            int64_t* to;
-            if ((rc = ensure_t(c, B_INTHOFF, 2, &to))) return rc;
-            const int64_t tmp[2] = {0, n_theta};
-            HIP_TRY(c, hipMemcpyAsync(to, tmp, sizeof(tmp), hipMemcpyHostToDevice, c->stream));
-            HIP_TRY(c, hipStreamSynchronize(c->stream));
-            d.in_theta_off = to;
+            d.single_off[0] = 0;
+            d.single_off[1] = n_theta;
+            d.in_theta_off = c->d_desc->single_off;  // travels with the descriptor upload
         }
         d.out_R = R;
         d.out_grad = grad;
@@ -694,6 +768,33 @@ int retina_response(retina_ctx* c, const retina_geometry* g, const retina_hits* 
         HIP_TRY(c, hipStreamSynchronize(c->stream));
     }
     return RETINA_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int retina_response(retina_ctx* c, const retina_geometry* g, const retina_hits* h, const float* theta,
+                    int64_t n_theta, const int64_t* theta_offsets, float sigma, uint32_t want, float* R,
+                    float* grad, float* hess)
+{
+    return response_impl(c, g, h, theta, n_theta, theta_offsets, sigma, want, R, grad, hess, nullptr);
+}
+
+int retina_response_noalloc(retina_ctx* c, const retina_geometry* g, const retina_hits* h, const float* theta,
+                            int64_t n_theta, const int64_t* theta_offsets, float sigma, uint32_t want,
+                            float* R, float* grad, float* hess)
+{
+    if (!c) return RETINA_ERR_INVALID_ARG;
+    if (!c->scratch)
+        return fail(c, RETINA_ERR_DEVICE, "the fixed device workspace has no address on device %d", c->device);
+    if (h && h->mem != RETINA_MEM_DEVICE)
+        return fail(c, RETINA_ERR_INVALID_ARG, "retina_response_noalloc takes device memory only (hits.mem = %d)",
+                    h->mem);
+    Arena ar;
+    ar.base = static_cast<char*>(c->scratch);
+    ar.cap = kScratchBytes;
+    return response_impl(c, g, h, theta, n_theta, theta_offsets, sigma, want, R, grad, hess, &ar);
 }
 
 int retina_grid_search(retina_ctx* c, const retina_geometry* g, const retina_hits* h, const retina_grid* grid,

@@ -128,6 +128,9 @@ struct Desc {
     int32_t* out_s_nreval;
     // device counters
     Counters* cnt;
+    // theta offsets {0, n_theta} of a one-event response call without caller
+    // offsets (in_theta_off then points here, inside the device copy)
+    int64_t single_off[2];
     // Cell-centre coordinates of the seed lattice / search grid, formed on the
     // host: dimension 0 in [0, lattice_n[0]), dimension 1 in [lattice_n[0],
     // lattice_n[0] + lattice_n[1]); each the FP32 rounding of

@@ -95,7 +95,7 @@ EXPORTS = ["retina_create", "retina_destroy", "retina_last_error", "retina_set_s
            "retina_model_create", "retina_model_save", "retina_model_load", "retina_model_free",
            "retina_model_get_params", "retina_model_set_params", "retina_model_step",
            "retina_train_step", "retina_model_forward", "retina_propose_seeds",
-           "retina_find_tracks_learned", "retina_grid_search"]
+           "retina_find_tracks_learned", "retina_grid_search", "retina_response_noalloc"]
 UPDATE_RULES = {"newton": 0, "gradient": 1, "bfgs": 2}   # RETINA_UPDATE_*
 MODEL_PARAMS = 186625
 IMG = 128
@@ -177,6 +177,8 @@ def load(path: str = LIB_PATH):
     lib.retina_response.argtypes = [V, ctypes.POINTER(Geometry), ctypes.POINTER(Hits), P, ctypes.c_int64,
                                     P, ctypes.c_float, ctypes.c_uint32, P, P, P]
     lib.retina_response.restype = ctypes.c_int
+    lib.retina_response_noalloc.argtypes = lib.retina_response.argtypes
+    lib.retina_response_noalloc.restype = ctypes.c_int
     lib.retina_find_tracks.argtypes = [V, ctypes.POINTER(Geometry), ctypes.POINTER(Hits),
                                        ctypes.POINTER(Params), P, ctypes.c_int64, P, P,
                                        ctypes.POINTER(SeedOut)]
@@ -353,6 +355,20 @@ class Context:
                         theta_offsets=None, sigma=1.0, want=WANT_R | WANT_GRAD | WANT_HESS):
         """Eq. (1) (+ gradient, packed Hessian) at each row of theta.
         Returns (R, grad, hess) in the memory space of the inputs."""
+        return self._response(self.lib.retina_response, meas_dim, plane_z, event_offsets, x, y, plane, theta,
+                              theta_offsets, sigma, want)
+
+    def retina_response_noalloc(self, meas_dim, plane_z, event_offsets, x, y, plane, theta,
+                                theta_offsets=None, sigma=1.0, want=WANT_R | WANT_GRAD | WANT_HESS,
+                                out=None):
+        """retina_response on the library's fixed device workspace (device
+        memory only; the library allocates nothing).  `out` = (R, grad, hess)
+        preallocated device tensors, else they are created here."""
+        return self._response(self.lib.retina_response_noalloc, meas_dim, plane_z, event_offsets, x, y, plane,
+                              theta, theta_offsets, sigma, want, out)
+
+    def _response(self, fn, meas_dim, plane_z, event_offsets, x, y, plane, theta, theta_offsets, sigma, want,
+                  out=None):
         g, zkeep = self._geometry(meas_dim, plane_z)
         hits, keep, mem = self._hits(meas_dim, event_offsets, x, y, plane)
         npar = 2 * meas_dim
@@ -369,12 +385,20 @@ class Context:
             th = _dev(theta, torch.float32)
             to = _dev(theta_offsets, torch.int64) if theta_offsets is not None else None
             n = th.numel() // npar
-            R = torch.zeros(n, dtype=torch.float32, device=th.device)
-            G = torch.zeros((n, npar), dtype=torch.float32, device=th.device) if want & WANT_GRAD else None
-            H = torch.zeros((n, nh), dtype=torch.float32, device=th.device) if want & WANT_HESS else None
+            if out is not None:
+                R, G, H = out
+                R = _dev(R, torch.float32)
+                G = _dev(G, torch.float32) if want & WANT_GRAD else None
+                H = _dev(H, torch.float32) if want & WANT_HESS else None
+                if R.numel() < n or (G is not None and G.numel() < n * npar) or (H is not None and H.numel() < n * nh):
+                    raise ValueError("output tensors are smaller than n_theta results")
+            else:
+                R = torch.zeros(n, dtype=torch.float32, device=th.device)
+                G = torch.zeros((n, npar), dtype=torch.float32, device=th.device) if want & WANT_GRAD else None
+                H = torch.zeros((n, nh), dtype=torch.float32, device=th.device) if want & WANT_HESS else None
             self.set_stream(torch.cuda.current_stream(th.device).cuda_stream)
-        rc = self.lib.retina_response(self.h, ctypes.byref(g), ctypes.byref(hits), _ptr(th), int(n),
-                                      _ptr(to), float(sigma), int(want), _ptr(R), _ptr(G), _ptr(H))
+        rc = fn(self.h, ctypes.byref(g), ctypes.byref(hits), _ptr(th), int(n),
+                _ptr(to), float(sigma), int(want), _ptr(R), _ptr(G), _ptr(H))
         self._check(rc)
         return R, G, H
 
