@@ -108,7 +108,10 @@ def algorithmic_flops(P, ev_hits, ev_seeds, nreval_per_event, n_planes):
 
 
 def _sample_size(run_one, target_s, cap):
-    """Events for a CPU sample of about target_s seconds (one event timed first)."""
+    """Events for a CPU sample of about target_s seconds (one event timed
+    first); a negative target_s fixes the sample at -target_s events."""
+    if target_s < 0:
+        return int(-target_s)
     t0 = time.perf_counter()
     run_one()
     dt = max(time.perf_counter() - t0, 1e-3)
@@ -315,9 +318,11 @@ def main():
     ap.add_argument("--workload", default="c3")
     ap.add_argument("--lattice-sweep", type=int, nargs="*", default=None,
                     help="lattice sides to sweep for the baseline (default: the workload's list)")
-    ap.add_argument("--cpu-seconds", type=float, default=12.0,
+    ap.add_argument("--cpu-seconds", type=float, default=15.0,
                     help="approximate length of each CPU oracle sample")
     ap.add_argument("--cpu-max-events", type=int, default=256)
+    ap.add_argument("--cpu-events", type=int, default=0,
+                    help="fixed CPU oracle sample (first N events) instead of one sized by --cpu-seconds")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--studies", action="store_true",
                     help="also run the pruned comparison, the alpha-budget scans and the update rules")
@@ -457,10 +462,11 @@ def main():
     cpu = cpu_l = prec = None
     if not args.no_cpu_baseline:
         log("cpu baseline (oracle, learned seeds)")
-        cpu_l, ref_lrn = cpu_baseline_learned(cfg, LS, model, args.cpu_seconds, args.cpu_max_events)
+        cpu_target = -float(args.cpu_events) if args.cpu_events > 0 else args.cpu_seconds
+        cpu_l, ref_lrn = cpu_baseline_learned(cfg, LS, model, cpu_target, args.cpu_max_events)
         log("cpu baseline: %s" % cpu_l)
         log("cpu baseline (oracle, %dx%d lattice)" % tuple(P["lattice_n"]))
-        cpu, ref_lat = cpu_baseline(cfg, P, args.cpu_seconds, args.cpu_max_events)
+        cpu, ref_lat = cpu_baseline(cfg, P, cpu_target, args.cpu_max_events)
         log("cpu baseline lattice: %s" % cpu)
         prec = {"lattice": fp32_vs_fp64(D, tl["theta"], tl["R"], toff_lat, ref_lat, P["d_merge"], z0, z1),
                 "learned": fp32_vs_fp64(D, tr["theta"], tr["R"], toff_lrn, ref_lrn, PL["d_merge"], z0, z1)}

@@ -16,6 +16,8 @@ import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _LIB_PATH = os.path.join(_HERE, "liboracle.so")
+# a sanitizer build of the same source (build_sanitized) may stand in
+_LIB_OVERRIDE = os.environ.get("ORACLE_LIB")
 _lib = None
 
 CONVERGED, STALLED, NOT_PD, NEGCURV = 1, 2, 4, 8
@@ -44,12 +46,23 @@ class Params(ctypes.Structure):
                 ("lattice_hi", ctypes.c_float * 2), ("update", ctypes.c_int32)]
 
 
+def build_sanitized(path: str) -> str:
+    """oracle.c with AddressSanitizer and UndefinedBehaviorSanitizer (a CPU
+    check of the checker; load it by setting ORACLE_LIB=path with the ASan
+    runtime preloaded)."""
+    src = os.path.join(_HERE, "oracle.c")
+    subprocess.check_call(["gcc", "-O1", "-g", "-std=c99", "-fPIC", "-shared", "-fopenmp", "-ffp-contract=off",
+                           "-fsanitize=address,undefined", "-fno-sanitize-recover=undefined",
+                           "-fno-omit-frame-pointer", "-Wall", "-o", path, src, "-lm"])
+    return path
+
+
 def _load():
     global _lib
     if _lib is None:
         if not os.path.exists(_LIB_PATH):
             build(force=False)
-        lib = ctypes.CDLL(_LIB_PATH)
+        lib = ctypes.CDLL(_LIB_OVERRIDE or _LIB_PATH)
         P, I64, I32, D = ctypes.c_void_p, ctypes.c_int64, ctypes.c_int32, ctypes.c_double
         lib.oracle_response.argtypes = [ctypes.c_int, ctypes.c_int, P, I64, P, P, P, I64, P, D, P, P, P]
         lib.oracle_response.restype = None

@@ -13,6 +13,7 @@
 
 #include "proposer.h"
 #include "rt_internal.h"
+#include "validate.h"
 
 using namespace rt;
 
@@ -165,45 +166,24 @@ template <typename T>
 int take(retina_ctx* c, Arena* ar, int id, size_t count, T** out)
 {
     if (!ar) return ensure_t(c, id, count, out);
-    const size_t bytes = (std::max<size_t>(count * sizeof(T), 16) + 255) & ~(size_t)255;
-    if (ar->used + bytes > ar->cap)
-        return fail(c, RETINA_ERR_CAPACITY,
-                    "the call needs more than the %zu bytes of the fixed device workspace "
-                    "(%zu in use, %zu more requested)",
-                    ar->cap, ar->used, bytes);
-    *out = reinterpret_cast<T*>(ar->base + ar->used);
-    ar->used += bytes;
+    rtv::Check k;
+    size_t off = 0;
+    if (count > SIZE_MAX / sizeof(T)) return fail(c, RETINA_ERR_CAPACITY, "workspace request overflows");
+    if (rtv::arena_take(k, ar->cap, ar->used, count * sizeof(T), &off)) return fail(c, k.code, "%s", k.msg);
+    *out = reinterpret_cast<T*>(ar->base + off);
     return RETINA_OK;
 }
 
 int check_geometry(retina_ctx* c, const retina_geometry* g)
 {
-    if (!g) return fail(c, RETINA_ERR_INVALID_ARG, "geometry is NULL");
-    if (g->meas_dim != 1 && g->meas_dim != 2)
-        return fail(c, RETINA_ERR_INVALID_ARG, "meas_dim must be 1 or 2 (got %d)", g->meas_dim);
-    if (g->n_planes < 1 || g->n_planes > kMaxPlanes)
-        return fail(c, RETINA_ERR_INVALID_ARG, "n_planes must be in [1, %d] (got %d)", kMaxPlanes,
-                    g->n_planes);
-    if (!g->plane_z) return fail(c, RETINA_ERR_INVALID_ARG, "plane_z is NULL");
-    for (int p = 0; p < g->n_planes; ++p)
-        if (!isfinite(g->plane_z[p]))
-            return fail(c, RETINA_ERR_INVALID_ARG, "plane_z[%d] is not finite", p);
-    return RETINA_OK;
+    rtv::Check k;
+    return rtv::geometry(k, g) ? fail(c, k.code, "%s", k.msg) : RETINA_OK;
 }
 
 int check_hits(retina_ctx* c, const retina_geometry* g, const retina_hits* h)
 {
-    if (!h) return fail(c, RETINA_ERR_INVALID_ARG, "hits is NULL");
-    if (h->mem != RETINA_MEM_HOST && h->mem != RETINA_MEM_DEVICE)
-        return fail(c, RETINA_ERR_INVALID_ARG, "hits.mem must be RETINA_MEM_HOST or RETINA_MEM_DEVICE");
-    if (h->n_events < 0) return fail(c, RETINA_ERR_INVALID_ARG, "n_events < 0");
-    if (h->n_events > 0x7FFFFFFF) return fail(c, RETINA_ERR_INVALID_ARG, "n_events too large");
-    if (!h->event_offsets) return fail(c, RETINA_ERR_INVALID_ARG, "event_offsets is NULL");
-    if (h->n_events > 0 && (!h->x || !h->plane))
-        return fail(c, RETINA_ERR_INVALID_ARG, "hit arrays x / plane are NULL");
-    if (h->n_events > 0 && g->meas_dim == 2 && !h->y)
-        return fail(c, RETINA_ERR_INVALID_ARG, "hit array y is NULL with meas_dim 2");
-    return RETINA_OK;
+    rtv::Check k;
+    return rtv::hits(k, g, h) ? fail(c, k.code, "%s", k.msg) : RETINA_OK;
 }
 
 // read one int64 of a caller array in either memory space
@@ -218,13 +198,7 @@ int read_i64(retina_ctx* c, int mem, const int64_t* p, int64_t idx, int64_t* out
     return RETINA_OK;
 }
 
-int host_offsets_ok(const int64_t* off, int64_t n)
-{
-    if (off[0] != 0) return 0;
-    for (int64_t i = 0; i < n; ++i)
-        if (off[i + 1] < off[i]) return 0;
-    return 1;
-}
+int host_offsets_ok(const int64_t* off, int64_t n) { return rtv::offsets_ok(off, n); }
 
 void fill_geometry(Desc& d, const retina_geometry* g)
 {
@@ -253,9 +227,8 @@ void reset_desc(Desc& d)
 // FP32 rounding of lo + (i + 1/2)(hi - lo)/n, formed in FP64 on the host
 int set_lattice(retina_ctx* c, Desc& d, const int32_t* n, const float* lo, const float* hi)
 {
-    for (int k = 0; k < 2; ++k)
-        if (n[k] < 1 || n[k] > kMaxLatticeSide)
-            return fail(c, RETINA_ERR_INVALID_ARG, "lattice / grid side %d must be in [1, %d]", n[k], kMaxLatticeSide);
+    rtv::Check chk;
+    if (rtv::lattice_sides(chk, n)) return fail(c, chk.code, "%s", chk.msg);
     int o = 0;
     for (int k = 0; k < 2; ++k) {
         d.lattice_n[k] = n[k];
@@ -655,15 +628,11 @@ int response_impl(retina_ctx* c, const retina_geometry* g, const retina_hits* h,
     c->err.clear();
     int rc;
     if ((rc = check_geometry(c, g)) || (rc = check_hits(c, g, h))) return rc;
-    if (!(sigma > 0.0f) || !isfinite(sigma)) return fail(c, RETINA_ERR_INVALID_ARG, "sigma must be finite and > 0");
-    if (n_theta < 0) return fail(c, RETINA_ERR_INVALID_ARG, "n_theta < 0");
-    if (want & ~(uint32_t)(RETINA_WANT_R | RETINA_WANT_GRAD | RETINA_WANT_HESS))
-        return fail(c, RETINA_ERR_INVALID_ARG, "unknown want bits 0x%x", want);
-    if (!theta_offsets && h->n_events != 1)
-        return fail(c, RETINA_ERR_INVALID_ARG, "theta_offsets may be NULL only with one event");
-    if (n_theta > 0 && (!theta || !R)) return fail(c, RETINA_ERR_INVALID_ARG, "theta / R is NULL");
-    if (n_theta > 0 && (want & RETINA_WANT_GRAD) && !grad) return fail(c, RETINA_ERR_INVALID_ARG, "grad is NULL");
-    if (n_theta > 0 && (want & RETINA_WANT_HESS) && !hess) return fail(c, RETINA_ERR_INVALID_ARG, "hess is NULL");
+    {
+        rtv::Check k;
+        if (rtv::response_args(k, h, theta, n_theta, theta_offsets, sigma, want, R, grad, hess))
+            return fail(c, k.code, "%s", k.msg);
+    }
     if (h->n_events == 0 || n_theta == 0) return RETINA_OK;
     DeviceGuard guard(c->device);
     const int D = g->meas_dim, NP = 2 * D, NH = NP * (NP + 1) / 2;
@@ -918,46 +887,10 @@ static int find_tracks_impl(retina_ctx* c, const retina_geometry* g, const retin
     c->err.clear();
     int rc;
     if ((rc = check_geometry(c, g)) || (rc = check_hits(c, g, h))) return rc;
-    if (!P) return fail(c, RETINA_ERR_INVALID_ARG, "params is NULL");
-    if (P->n_sigma < 0 || P->n_sigma > kMaxSigma)
-        return fail(c, RETINA_ERR_INVALID_ARG, "n_sigma must be in [0, %d]", kMaxSigma);
-    if (P->n_sigma > 0 && !P->sigma) return fail(c, RETINA_ERR_INVALID_ARG, "sigma is NULL");
-    for (int i = 0; i < P->n_sigma; ++i)
-        if (!(P->sigma[i] > 0.0f) || !isfinite(P->sigma[i]))
-            return fail(c, RETINA_ERR_INVALID_ARG, "sigma[%d] must be finite and > 0", i);
-    if (!(P->sigma_final > 0.0f) || !isfinite(P->sigma_final))
-        return fail(c, RETINA_ERR_INVALID_ARG, "sigma_final must be finite and > 0");
-    if (P->n_final_steps < 0 || P->n_polish < 1 || P->ls_trials < 1 || P->n_slope_steps < 0)
-        return fail(c, RETINA_ERR_INVALID_ARG, "step counts: n_final_steps >= 0, n_polish >= 1, ls_trials >= 1");
-    if (P->n_sigma + P->n_final_steps > 64 || P->n_polish > 16 || P->ls_trials > 16)
-        return fail(c, RETINA_ERR_INVALID_ARG, "step counts too large");
-    const float fp[] = {P->armijo_c1, P->step_cap_sigmas, P->small_step_sigmas, P->conv_tol, P->R0, P->d_merge};
-    for (float v : fp)
-        if (!isfinite(v)) return fail(c, RETINA_ERR_INVALID_ARG, "method constants must be finite");
-    if (!(P->step_cap_sigmas > 0.0f) || !(P->d_merge >= 0.0f) || !(P->conv_tol > 0.0f))
-        return fail(c, RETINA_ERR_INVALID_ARG, "step_cap_sigmas, conv_tol must be > 0 and d_merge >= 0");
-    if (P->seed_mode != RETINA_SEED_LATTICE && P->seed_mode != RETINA_SEED_EXPLICIT)
-        return fail(c, RETINA_ERR_INVALID_ARG, "unknown seed_mode %d", P->seed_mode);
-    if (P->update != RETINA_UPDATE_NEWTON && P->update != RETINA_UPDATE_GRADIENT && P->update != RETINA_UPDATE_BFGS)
-        return fail(c, RETINA_ERR_INVALID_ARG, "unknown update rule %d", P->update);
-    if (!isfinite(P->prune_u) || P->prune_u < 0.0f)
-        return fail(c, RETINA_ERR_INVALID_ARG, "prune_u must be finite and >= 0");
-    if (P->prune_u > 0.0f && P->update != RETINA_UPDATE_NEWTON)
-        return fail(c, RETINA_ERR_INVALID_ARG, "pruned passes run with the truncated-Newton rule only");
-    if (P->seed_mode == RETINA_SEED_LATTICE) {
-        if (P->lattice_n[0] < 1 || P->lattice_n[1] < 1 || P->lattice_n[0] > kMaxLatticeSide ||
-            P->lattice_n[1] > kMaxLatticeSide || (int64_t)P->lattice_n[0] * P->lattice_n[1] > (1 << 24))
-            return fail(c, RETINA_ERR_INVALID_ARG, "lattice_n must be in [1, %d] with at most 2^24 seeds",
-                        kMaxLatticeSide);
-        for (int i = 0; i < 2; ++i)
-            if (!isfinite(P->lattice_lo[i]) || !isfinite(P->lattice_hi[i]))
-                return fail(c, RETINA_ERR_INVALID_ARG, "lattice box must be finite");
-    } else if (!P->seeds || !P->seed_offsets) {
-        return fail(c, RETINA_ERR_INVALID_ARG, "explicit seeds / seed_offsets are NULL");
+    {
+        rtv::Check k;
+        if (rtv::method_params(k, P, capacity, tracks, track_offsets)) return fail(c, k.code, "%s", k.msg);
     }
-    if (capacity < 0) return fail(c, RETINA_ERR_INVALID_ARG, "capacity < 0");
-    if (!track_offsets) return fail(c, RETINA_ERR_INVALID_ARG, "track_offsets is NULL");
-    if (capacity > 0 && !tracks) return fail(c, RETINA_ERR_INVALID_ARG, "tracks is NULL");
     DeviceGuard guard(c->device);
     const int D = g->meas_dim, NP = 2 * D;
     const int64_t E = h->n_events;
@@ -978,10 +911,8 @@ static int find_tracks_impl(retina_ctx* c, const retina_geometry* g, const retin
     if (P->seed_mode == RETINA_SEED_EXPLICIT) {
         if ((rc = read_i64(c, seeds_dev ? RETINA_MEM_DEVICE : RETINA_MEM_HOST, P->seed_offsets, E, &n_seeds))) return rc;
         if (n_seeds < 0 || n_seeds > 0x7FFFFFFF) return fail(c, RETINA_ERR_INVALID_ARG, "bad total seed count");
-        if (!seeds_dev)
-            for (int64_t i = 0; i < n_seeds * NP; ++i)
-                if (!isfinite((float)P->seeds[i]))
-                    return fail(c, RETINA_ERR_INVALID_ARG, "an explicit seed is NaN or infinite in FP32");
+        rtv::Check k;
+        if (!seeds_dev && rtv::host_seeds(k, P->seeds, n_seeds * NP)) return fail(c, k.code, "%s", k.msg);
     } else {
         n_seeds = E * (int64_t)P->lattice_n[0] * P->lattice_n[1];
         if (n_seeds > 0x7FFFFFFF) return fail(c, RETINA_ERR_INVALID_ARG, "too many seeds in the batch");
