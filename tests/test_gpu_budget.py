@@ -15,9 +15,11 @@ def test_multistart_at_a_third_of_the_grid_cost():
     print("alpha budget: c7 scan, 50 and 350 tracks, 256 events each", flush=True)
     sys.stdout.flush()
     ctx = retina.Context(0)
-    out = budget.run(ctx, events.load_config("c7"), counts=[50, 350], events_per_point=256, reps=2,
+    cfg = events.load_config("c7")
+    out = budget.run(ctx, cfg, counts=[50, 350], events_per_point=256, reps=2,
                      log=lambda m: print(m, flush=True))
-    assert out["q"] == 12 and out["C0"] > 0
+    P = cfg["params"]
+    assert out["q"] == len(P["sigma"]) + P["n_final_steps"] + P["n_polish"] and out["C0"] > 0
     for row in out["points"]:
         g, a3, a10 = row["grid"], row["alpha_0.3333"], row["alpha_0.1"]
         assert g["eff_eps"] >= 0.9
