@@ -702,6 +702,141 @@ __device__ __forceinline__ EventView begin_event(const Desc* __restrict__ d, int
     return ev;
 }
 
+// R only at one line over the contiguous range [a0, a1) of a resident event's
+// plane-sorted hits (the range may cross plane boundaries; each lane holds its
+// own range and line).  One flat loop over the hits, so every lane of a wave
+// runs the same trip count ((a1 - a0) differs by at most one between lanes);
+// the line's position is split anew at each plane boundary.  Per-plane sums
+// are added in plane order.  Reads run one hit past a1 (the tile's spare
+// entries cover it).
+template <int D>
+__device__ __forceinline__ float range_response(const float* __restrict__ s_hits, const int* s_poff,
+                                                const float* s_pz, int P, int a0, int a1, const float* th,
+                                                float nc)
+{
+    if (a0 >= a1) return 0.0f;
+    // plane of hit a0: the first p with s_poff[p + 1] > a0
+    int lo = 0, hi = P - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi) >> 1;
+        if (s_poff[mid + 1] <= a0) lo = mid + 1;
+        else hi = mid;
+    }
+    int pl = lo;
+    int next = s_poff[pl + 1];
+    float sx, lx, sy = 0.0f, ly = 0.0f;
+    auto split = [&](int q) {
+        const float z = s_pz[q];
+        if constexpr (D == 2) {
+            line_split(th[0], th[2], z, sx, lx);
+            line_split(th[1], th[3], z, sy, ly);
+        } else {
+            line_split(th[0], th[1], z, sx, lx);
+        }
+    };
+    split(pl);
+    float R = 0.0f, pe = 0.0f;
+    if constexpr (D == 2) {
+        const float2* h = reinterpret_cast<const float2*>(s_hits);
+        float2 v = h[a0];
+        for (int k = a0; k < a1; ++k) {
+            const float2 nv = h[k + 1];
+            if (k >= next) {
+                R += pe;
+                pe = 0.0f;
+                do { ++pl; next = s_poff[pl + 1]; } while (next <= k);
+                split(pl);
+            }
+            const float rx = (v.x - sx) - lx;
+            const float ry = (v.y - sy) - ly;
+            pe += __builtin_amdgcn_exp2f(__builtin_fmaf(ry, ry, rx * rx) * nc);
+            v = nv;
+        }
+    } else {
+        float v = s_hits[a0];
+        for (int k = a0; k < a1; ++k) {
+            const float nv = s_hits[k + 1];
+            if (k >= next) {
+                R += pe;
+                pe = 0.0f;
+                do { ++pl; next = s_poff[pl + 1]; } while (next <= k);
+                split(pl);
+            }
+            const float r = (v - sx) - lx;
+            pe += __builtin_amdgcn_exp2f((r * r) * nc);
+            v = nv;
+        }
+    }
+    return R + pe;
+}
+
+// Backtracking line search of one wave's seeds, wave-local (no work-group
+// barrier), for the split ascent on a resident event.  The QS lanes of a seed
+// hold identical state.  Each round takes the wave's m pending seeds (by their
+// owner lanes), gives each trial point L = 64 / m lanes (rounded down to a
+// power of two), lane `sub` of a point summing R over the sub-th of L
+// contiguous, equal ranges of the event's hits; a butterfly inside the group
+// of L lanes adds the parts in a fixed order.  Every seed either accepts,
+// halves its step or stalls in a round, so at most ls_trials rounds run.
+// Returns the pair evaluations of the wave (counted once, in lane 0).
+template <int D, int QS>
+__device__ __forceinline__ uint64_t wave_line_search(const Desc* __restrict__ d, const float* s_hits,
+                                                     const int* s_poff, const float* s_pz, const EventView& ev,
+                                                     float (&th)[2 * D], const float (&p)[2 * D], float Rc,
+                                                     float gp, bool& pend, int& nre, int& flags, float nc)
+{
+    constexpr int NP = 2 * D;
+    constexpr int SL = kWave / QS;
+    const int lane = (int)__lane_id();
+    const int slane = lane & (SL - 1);
+    const bool owner = lane < SL;
+    float alpha = 1.0f;
+    int trial = 0;
+    uint64_t pairs = 0;
+    for (;;) {
+        const uint64_t bal = __ballot(pend && owner);
+        const int m = __popcll(bal);
+        if (m == 0) break;
+        int L = kWave;
+        while (L * m > kWave) L >>= 1;
+        const int q = lane / L, sub = lane & (L - 1);
+        const bool qlive = q < m;
+        // owner lane of point q: the q-th set bit of bal
+        uint64_t b = bal;
+        for (int i = 0; i < q && i < 16; ++i) b &= b - 1;
+        const int src = qlive ? __builtin_ctzll(b) : 0;
+        float tt[NP], tq[NP];
+#pragma unroll
+        for (int a = 0; a < NP; ++a) {
+            tt[a] = __builtin_fmaf(alpha, p[a], th[a]);
+            tq[a] = __shfl(tt[a], src);
+        }
+        const int a0 = (int)((int64_t)ev.n * sub / L), a1 = (int)((int64_t)ev.n * (sub + 1) / L);
+        float part = qlive ? range_response<D>(s_hits, s_poff, s_pz, ev.P, a0, a1, tq, nc) : 0.0f;
+#pragma unroll
+        for (int w = kWave / 2; w >= 1; w >>= 1)
+            if (w < L) part += __shfl_xor(part, w);
+        // the seed's lanes read the sum of its point (group of rank r, lane r * L)
+        const int rank = __popcll(bal & ((1ull << slane) - 1ull));
+        const float Rt = __shfl(part, (rank * L) & (kWave - 1));
+        pairs += (uint64_t)m * (uint64_t)ev.n;
+        if (pend) {
+            ++nre;
+            if (Rt >= Rc + d->armijo_c1 * alpha * gp) {
+#pragma unroll
+                for (int a = 0; a < NP; ++a) th[a] = tt[a];
+                pend = false;
+            } else if (++trial >= d->ls_trials) {
+                pend = false;
+                flags |= RETINA_STALLED;
+            } else {
+                alpha *= 0.5f;
+            }
+        }
+    }
+    return pairs;
+}
+
 // ------------------------------------------------------------------ ascent
 // Lattice point i of an event (dimension 0 slow): D = 2 gives (0, 0, tx, ty),
 // D = 1 gives (x0, tx) with tx along dimension 0.  The coordinates come from
@@ -742,7 +877,9 @@ __global__ __launch_bounds__(kBlock) void k_ascent(const Desc* __restrict__ d, i
     __shared__ int s_wcnt[C * kNW];         // line-search list: pending points per (slot j, wave),
     __shared__ float s_lth[kBlock * C][4];  // the points, then their responses (slot 0)
     __shared__ float s_red[kBlock];         // partial responses of a line-search round
+    __shared__ float s_pz[kMaxPlanes];      // plane positions (per-lane plane lookups)
     if (d->cnt->err) return;
+    if ((int)threadIdx.x < kMaxPlanes) s_pz[threadIdx.x] = d->plane_z[threadIdx.x];
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);  // scalar: same in every lane
     const int lane = threadIdx.x & (kWave - 1);
     const int slane = lane & (SL - 1);   // the lane's seed within the wave's slot
@@ -810,6 +947,7 @@ __global__ __launch_bounds__(kBlock) void k_ascent(const Desc* __restrict__ d, i
         for (int j = 0; j < C; ++j) any_active = any_active || active[j];
         const bool wave_work = __builtin_amdgcn_readfirstlane((int)(__any(any_active) != 0)) != 0;
         uint64_t ls_pairs = 0;  // executed line-search pair evaluations (same in every thread)
+        uint64_t wls_pairs = 0; // ... of the wave-local searches (this wave's, in every lane)
         for (int s = 0; s < n_steps; ++s) {
             const float sig = s < d->n_sigma ? d->sigma[s] : d->sigma_final;
             const float nc = -kLog2e / (sig * sig);
@@ -938,6 +1076,14 @@ __global__ __launch_bounds__(kBlock) void k_ascent(const Desc* __restrict__ d, i
                 }
             }
             sig_prev = sig;
+            if constexpr (QS > 1 && !PR) {
+                if (ev.resident) {
+                    // every hit in LDS: each wave searches for its own seeds
+                    wls_pairs += wave_line_search<D, QS>(d, s_hits, s_poff, s_pz, ev, th[0], p[0], Rc[0], gp[0],
+                                                         pend[0], nre[0], flags[0], nc);
+                    continue;
+                }
+            }
             // Backtracking line search.  Each round gathers the work-group's
             // pending trial points into an LDS list and evaluates R only for
             // those.  One candidate per lane and up to 64 pending points: the
@@ -1161,6 +1307,10 @@ __global__ __launch_bounds__(kBlock) void k_ascent(const Desc* __restrict__ d, i
         if (threadIdx.x == 0) {
             atomicAdd((unsigned long long*)&d->cnt->exec_pairs, (unsigned long long)ls_pairs);
             atomicAdd((unsigned long long*)&d->cnt->exec_rpairs, (unsigned long long)ls_pairs);
+        }
+        if (lane == 0 && wls_pairs) {
+            atomicAdd((unsigned long long*)&d->cnt->exec_pairs, (unsigned long long)wls_pairs);
+            atomicAdd((unsigned long long*)&d->cnt->exec_rpairs, (unsigned long long)wls_pairs);
         }
         __syncthreads();
     }
