@@ -17,6 +17,9 @@
 namespace rt {
 
 typedef short v4s __attribute__((ext_vector_type(4)));
+// 16-byte staging registers: a native vector (HIP's uint4 struct is copied
+// through memory, which keeps staged values out of registers)
+typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
 typedef float v4f __attribute__((ext_vector_type(4)));
 
 __device__ __forceinline__ uint16_t f2bf(float f)
@@ -419,7 +422,7 @@ __global__ __launch_bounds__(kCvThreads) void k_conv_mid(const uint16_t* __restr
 #pragma unroll
             for (int r = 0; r < 16; ++r) acc[i][j][r] = 0.0f;
 
-    uint4 wreg[WPT];
+    u32x4 wreg[WPT];
     for (int c = 0; c < NCH; ++c) {
         __syncthreads();
         for (int u = t; u < IU; u += kCvThreads) {
@@ -437,7 +440,7 @@ __global__ __launch_bounds__(kCvThreads) void k_conv_mid(const uint16_t* __restr
                 for (int i = 0; i < WPT; ++i) {
                     const int u = t + i * kCvThreads;
                     if (u < WU)
-                        wreg[i] = *reinterpret_cast<const uint4*>(w + (int64_t)(u >> 3) * KP + (tap + 1) * CIN +
+                        wreg[i] = *reinterpret_cast<const u32x4*>(w + (int64_t)(u >> 3) * KP + (tap + 1) * CIN +
                                                                   c * kCvChunk + (u & 7) * 8);
                 }
             }
@@ -468,7 +471,7 @@ __global__ __launch_bounds__(kCvThreads) void k_conv_mid(const uint16_t* __restr
 #pragma unroll
                 for (int i = 0; i < WPT; ++i) {
                     const int u = t + i * kCvThreads;
-                    if (u < WU) *reinterpret_cast<uint4*>(wn + (u >> 3) * kCvPitch + (u & 7) * 8) = wreg[i];
+                    if (u < WU) *reinterpret_cast<u32x4*>(wn + (u >> 3) * kCvPitch + (u & 7) * 8) = wreg[i];
                 }
             }
             __syncthreads();
@@ -552,13 +555,12 @@ __global__ __launch_bounds__(256) void k_conv_head(const uint16_t* __restrict__ 
 // Inference needs only the logits, so two fusions keep activations on chip:
 //   k_conv12  layer 1 computed into the LDS input tile of layer 2 (act1 never
 //             reaches HBM); layer 1 runs on MFMA with K = 18 padded to 32;
-//   k_conv3   layer 3 with its 128 input channels streamed in 32-channel
-//             chunks, the next chunk's rows loaded while this one computes;
-//             for inference its epilogue multiplies the BF16 act3 tile by the
-//             head's weights on MFMA (U[q][tap], 9 floats per pixel) instead
-//             of storing act3, and k_head_sum adds the nine shifted U values.
-// Training keeps every activation (k_conv_in, k_conv_mid<64, 128>,
-// k_conv3<0>, k_conv_head).
+//   k_conv3i  layer 3 (persistent, pipelined; below), whose epilogue
+//             multiplies the BF16 act3 tile by the head's weights on MFMA
+//             (U[q][tap], 9 floats per pixel) instead of storing act3;
+//             k_head_sum adds the nine shifted U values.
+// Training keeps every activation (k_conv_in, k_conv_mid<64, 128>, k_conv3,
+// k_conv_head).
 constexpr int kC12ImgRows = kCvRows + 4;          // image rows staged (halo 2)
 constexpr int kC12ImgCols = kImg + 4;             // image columns staged
 constexpr int kC12A1 = (kCvRows + 2) * kCvCols;   // act1 positions of the tile (780)
@@ -603,26 +605,26 @@ __device__ __forceinline__ void stage_act(uint16_t* s_out, const v16f (&acc)[NB]
 }
 
 // layer 2's weight slice (tap) of all 128 output channels: 1024 16-byte units, two per thread
-__device__ __forceinline__ void c12_load_w(const uint16_t* __restrict__ w2, int tap, int t, uint4 (&r)[2])
+__device__ __forceinline__ void c12_load_w(const uint16_t* __restrict__ w2, int tap, int t, u32x4 (&r)[2])
 {
 #pragma unroll
     for (int i = 0; i < 2; ++i) {
         const int u = t + i * kCvThreads;
-        r[i] = *reinterpret_cast<const uint4*>(w2 + (int64_t)(u >> 3) * 576 + tap * 64 + (u & 7) * 8);
+        r[i] = *reinterpret_cast<const u32x4*>(w2 + (int64_t)(u >> 3) * 576 + tap * 64 + (u & 7) * 8);
     }
 }
 
-__device__ __forceinline__ void c12_store_w(uint16_t* dst, int t, const uint4 (&r)[2])
+__device__ __forceinline__ void c12_store_w(uint16_t* dst, int t, const u32x4 (&r)[2])
 {
 #pragma unroll
     for (int i = 0; i < 2; ++i) {
         const int u = t + i * kCvThreads;
-        *reinterpret_cast<uint4*>(dst + (u >> 3) * kCvPitch + (u & 7) * 8) = r[i];
+        *reinterpret_cast<u32x4*>(dst + (u >> 3) * kCvPitch + (u & 7) * 8) = r[i];
     }
 }
 
 // act2 for inference is stored channel-chunked, [E][4][128][128][32], so that
-// k_conv3 reads whole 64-byte runs per pixel and chunk
+// layer 3 reads whole runs per pixel and stage
 __device__ __forceinline__ int64_t chunked_off(int64_t e, int chunk, int r, int col)
 {
     return (((e * 4 + chunk) * kImg + r) * kImg + col) * 32;
@@ -653,7 +655,7 @@ __global__ __launch_bounds__(kCvThreads) void k_conv12(const uint16_t* __restric
             v = *reinterpret_cast<const uint32_t*>(img + ((e * kImg + r) * kImg + col) * 2);
         s_img[u] = v;
     }
-    uint4 wreg[2];
+    u32x4 wreg[2];
     c12_load_w(w2, 0, t, wreg);
     __syncthreads();
 
@@ -721,21 +723,30 @@ __global__ __launch_bounds__(kCvThreads) void k_conv12(const uint16_t* __restric
         const int dr = tap / 3 - 1, dc = tap % 3 - 1;
         const uint16_t* xrow = s_in + ((orow + 1 + dr) * kCvCols + (ocol0 + 1 + dc)) * kCvPitch;
         const uint16_t* wb = s_w + (tap & 1) * COUT * kCvPitch;
-#pragma unroll
-        for (int kk = 0; kk < 4; ++kk) {
+        // fragments of k-step kk + 1 are read while the products of kk run: the
+        // scheduling barriers keep each read above the products it runs under
+        v8bf xf[2][2], wf[2][NB];
+        auto frags = [&](int kk, int set) __attribute__((always_inline)) {
             const int ko = kk * 16 + 8 * (lane >> 5);
-            v8bf xf[2], wf[NB];
 #pragma unroll
             for (int mb = 0; mb < 2; ++mb)
-                xf[mb] = *reinterpret_cast<const v8bf*>(xrow + (mb * 32 + (lane & 31)) * kCvPitch + ko);
+                xf[set][mb] = *reinterpret_cast<const v8bf*>(xrow + (mb * 32 + (lane & 31)) * kCvPitch + ko);
 #pragma unroll
             for (int nb = 0; nb < NB; ++nb)
-                wf[nb] = *reinterpret_cast<const v8bf*>(wb + (nb * 32 + (lane & 31)) * kCvPitch + ko);
+                wf[set][nb] = *reinterpret_cast<const v8bf*>(wb + (nb * 32 + (lane & 31)) * kCvPitch + ko);
+        };
+        frags(0, 0);
+#pragma unroll
+        for (int kk = 0; kk < 4; ++kk) {
+            if (kk < 3) frags(kk + 1, (kk + 1) & 1);
+            __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
             for (int nb = 0; nb < NB; ++nb)
 #pragma unroll
                 for (int mb = 0; mb < 2; ++mb)
-                    acc[nb][mb] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(wf[nb], xf[mb], acc[nb][mb], 0, 0, 0);
+                    acc[nb][mb] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(wf[kk & 1][nb], xf[kk & 1][mb], acc[nb][mb],
+                                                                         0, 0, 0);
+            __builtin_amdgcn_sched_barrier(0);
         }
         if (tap < 8) c12_store_w(s_w + ((tap + 1) & 1) * COUT * kCvPitch, t, wreg);
         __syncthreads();
@@ -764,14 +775,11 @@ constexpr size_t conv3_lds()
     return main > out ? main : out;
 }
 
-// MODE 0 (training): act2 NHWC in, act3 NHWC out.  MODE 1 (inference): act2
-// channel-chunked in, U[pixel][tap] = sum_c W4[tap][c] act3[pixel][c] out.
-template <int MODE>
+// Layer 3 for training: act2 NHWC in, act3 NHWC out (inference runs k_conv3i).
 __global__ __launch_bounds__(kCvThreads) void k_conv3(const uint16_t* __restrict__ x,
                                                       const uint16_t* __restrict__ w,
                                                       const float* __restrict__ bias,
-                                                      const uint16_t* __restrict__ w4,
-                                                      uint16_t* __restrict__ y, float* __restrict__ u_out)
+                                                      uint16_t* __restrict__ y)
 {
     constexpr int CIN = 128, COUT = 96, NB = 3, NCH = CIN / kC3Chunk, KP = 9 * CIN;
     constexpr int WU = COUT * (kC3Chunk / 8);  // 384 units per weight slice
@@ -794,8 +802,7 @@ __global__ __launch_bounds__(kCvThreads) void k_conv3(const uint16_t* __restrict
                 const int q = u & 3, pc = (u >> 2) % kCvCols, pr = (u >> 2) / kCvCols;
                 const int r = r0 - 1 + pr, col = pc - 1;
                 if (r >= 0 && r < kImg && col >= 0 && col < kImg) {
-                    const int64_t off = MODE == 0 ? ((e * kImg + r) * kImg + col) * CIN + c * kC3Chunk + q * 8
-                                                  : chunked_off(e, c, r, col) + q * 8;
+                    const int64_t off = ((e * kImg + r) * kImg + col) * CIN + c * kC3Chunk + q * 8;
                     v = *reinterpret_cast<const uint4*>(x + off);
                 }
             }
@@ -871,42 +878,209 @@ __global__ __launch_bounds__(kCvThreads) void k_conv3(const uint16_t* __restrict
     stage_act<NB, COUT>(s_out, acc, bias, lane);
     __syncthreads();
     const int64_t pix0 = (e * kImg + r0 + orow) * kImg + ocol0;
-    if (MODE == 0) {
-        uint16_t* dst = y + pix0 * COUT;
-        for (int u = lane; u < 64 * COUT / 8; u += 64) {
-            const int px = u / (COUT / 8), q = u % (COUT / 8);
-            *reinterpret_cast<uint4*>(dst + px * COUT + q * 8) =
-                *reinterpret_cast<const uint4*>(s_out + px * (COUT + 8) + q * 8);
-        }
-    } else {
-        // U^T = W4 (9 taps padded to 32 rows, 96) x act3^T (96 x this wave's 64 pixels):
-        // lane < 32 holds taps 0-3 and 8 (rows 0-3, 16), lane >= 32 taps 4-7, of pixel lane % 32
-        v8bf wu[COUT / 16];
-        const int n = lane & 31;
+    uint16_t* dst = y + pix0 * COUT;
+    for (int u = lane; u < 64 * COUT / 8; u += 64) {
+        const int px = u / (COUT / 8), q = u % (COUT / 8);
+        *reinterpret_cast<uint4*>(dst + px * COUT + q * 8) = *reinterpret_cast<const uint4*>(s_out + px * (COUT + 8) + q * 8);
+    }
+}
+
+// ---------------------------------------------- layer 3, inference, pipelined
+// Layer 3 (128 -> 96) and the head product U[q][tap] = sum_c W4[tap][c]
+// act3[q][c] for bands of kCvRows output rows, persistent: work-group w takes
+// bands w, w + G, w + 2G, ... of the batch, so a band's input halo rows come
+// from the neighbouring bands that the other work-groups of its XCD process
+// at the same time (work-groups are dealt to the XCDs round-robin, and the
+// band order below gives each XCD a contiguous range of bands).  The 128
+// input channels stream through LDS in stages of 16: the stage's input rows
+// and all nine taps' weights (double-buffered, one barrier per stage), the
+// next stage (or the next band's first stage) loaded from global memory while
+// this one's products run, and each tap's fragments read from LDS one tap
+// ahead of its products.  The epilogue takes the head product straight from
+// the accumulators: a lane's 16 results are four runs of four channels of one
+// pixel, so with the contraction index ordered the same way in W4's fragment,
+// each 8-value half of a run pair is already a B fragment of the product.
+constexpr int kL3Stage = 16;                                       // input channels per stage
+constexpr int kL3Pitch = kL3Stage + 8;                             // LDS elements per pixel / weight row (48 B)
+constexpr int kL3Rows = kCvRows + 2;                               // staged input rows (halo 1)
+constexpr int kL3InUnits = kL3Rows * kCvCols * (kL3Stage / 8);     // 16-byte units of a stage's input (1560)
+constexpr int kL3WUnits = 9 * 96 * (kL3Stage / 8);                 // ... of its weights (1728)
+constexpr int kL3InPT = (kL3InUnits + kCvThreads - 1) / kCvThreads;
+constexpr int kL3WPT = (kL3WUnits + kCvThreads - 1) / kCvThreads;
+constexpr int kL3InElems = kL3Rows * kCvCols * kL3Pitch;           // one input buffer
+constexpr int kL3WElems = 9 * 96 * kL3Pitch;                       // one weight buffer
+
+constexpr size_t conv3i_lds() { return (size_t)2 * (kL3InElems + kL3WElems) * 2; }
+
+// band processed by work-group `wg` in round `i` (G work-groups): the
+// work-groups of XCD x (wg % 8 == x) take a contiguous run of bands
+__device__ __forceinline__ int l3_band(int wg, int i, int G)
+{
+    if (G % 8 != 0) return i * G + wg;
+    const int per = G / 8;
+    return i * G + (wg % 8) * per + wg / 8;
+}
+
+__global__ __launch_bounds__(kCvThreads) void k_conv3i(const uint16_t* __restrict__ x, const uint16_t* __restrict__ w,
+                                                       const float* __restrict__ bias,
+                                                       const uint16_t* __restrict__ w4, float* __restrict__ u_out,
+                                                       int n_bands)
+{
+    constexpr int CIN = 128, COUT = 96, NB = 3, NST = CIN / kL3Stage, KP = 9 * CIN;
+    constexpr int BPE = kImg / kCvRows;  // bands per event
+    static_assert(NST % 2 == 0, "a band's first stage must land in buffer 0");
+    extern __shared__ float4 s_dyn[];
+    uint16_t* s_in = reinterpret_cast<uint16_t*>(s_dyn);
+    uint16_t* s_w = s_in + 2 * kL3InElems;
+    const int t = threadIdx.x, lane = t & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(t >> 6);
+    const int orow = wave >> 1, ocol0 = (wave & 1) * 64;
+    const int G = gridDim.x;
+
+    // a stage is moved in two halves (units i = 2 k, 2 k + 1 of each thread's
+    // input and weight units), so that at most half of it sits in registers
+    static_assert(kL3InPT == 4 && kL3WPT == 4, "two halves of two units each");
+    u32x4 pin[2], pw[2];
+    auto load_half = [&](int band, int c, int k) {
+        const int64_t e = band / BPE;
+        const int r0 = (band % BPE) * kCvRows;
 #pragma unroll
-        for (int kk = 0; kk < COUT / 16; ++kk) {
-            const int k0 = kk * 16 + 8 * (lane >> 5);
-            if (n < 9) {
-                wu[kk] = *reinterpret_cast<const v8bf*>(w4 + n * COUT + k0);
-            } else {
-#pragma unroll
-                for (int j = 0; j < 8; ++j) wu[kk][j] = bits_bf(0);
+        for (int i = 0; i < 2; ++i) {
+            const int u = t + (2 * k + i) * kCvThreads;
+            u32x4 v = {0u, 0u, 0u, 0u};
+            if (u < kL3InUnits) {
+                const int q = u & 1, pix = u >> 1;
+                const int r = r0 - 1 + pix / kCvCols, col = pix % kCvCols - 1;
+                if (r >= 0 && r < kImg && col >= 0 && col < kImg)
+                    v = *reinterpret_cast<const u32x4*>(x + chunked_off(e, c >> 1, r, col) + (c & 1) * kL3Stage + q * 8);
             }
+            pin[i] = v;
         }
+#pragma unroll
+        for (int i = 0; i < 2; ++i) {
+            const int u = t + (2 * k + i) * kCvThreads;
+            u32x4 v = {0u, 0u, 0u, 0u};
+            if (u < kL3WUnits) {
+                const int q = u & 1, row = u >> 1;  // row = tap * COUT + co
+                const int tap = row / COUT, co = row % COUT;
+                v = *reinterpret_cast<const u32x4*>(w + (int64_t)co * KP + tap * CIN + c * kL3Stage + q * 8);
+            }
+            pw[i] = v;
+        }
+    };
+    auto store_half = [&](int buf, int k) {
+#pragma unroll
+        for (int i = 0; i < 2; ++i) {
+            const int u = t + (2 * k + i) * kCvThreads;
+            if (u < kL3InUnits)
+                *reinterpret_cast<u32x4*>(s_in + buf * kL3InElems + (u >> 1) * kL3Pitch + (u & 1) * 8) = pin[i];
+        }
+#pragma unroll
+        for (int i = 0; i < 2; ++i) {
+            const int u = t + (2 * k + i) * kCvThreads;
+            if (u < kL3WUnits)
+                *reinterpret_cast<u32x4*>(s_w + buf * kL3WElems + (u >> 1) * kL3Pitch + (u & 1) * 8) = pw[i];
+        }
+    };
+
+    int band = l3_band(blockIdx.x, 0, G);
+    if (band >= n_bands) return;
+    load_half(band, 0, 0);
+    store_half(0, 0);
+    load_half(band, 0, 1);
+    store_half(0, 1);
+    __syncthreads();
+    for (int round = 0; band < n_bands; band = l3_band(blockIdx.x, ++round, G)) {
+        v16f acc[NB][2];
+#pragma unroll
+        for (int i = 0; i < NB; ++i)
+#pragma unroll
+            for (int j = 0; j < 2; ++j)
+#pragma unroll
+                for (int r = 0; r < 16; ++r) acc[i][j][r] = 0.0f;
+        for (int c = 0; c < NST; ++c) {
+            // the next stage: this band's next channels, or the next band's first
+            const int nband = c + 1 < NST ? band : l3_band(blockIdx.x, round + 1, G);
+            const bool more = nband < n_bands;
+            const int ncs = c + 1 < NST ? c + 1 : 0;
+            if (more) load_half(nband, ncs, 0);
+            __builtin_amdgcn_sched_barrier(0);  // the next stage's loads go out first
+            const uint16_t* ti = s_in + (c & 1) * kL3InElems;
+            const uint16_t* tw = s_w + (c & 1) * kL3WElems;
+            v8bf xf[2][2], wf[2][NB];
+            auto frags = [&](int tap, int set) {
+                const int dr = tap / 3 - 1, dc = tap % 3 - 1;
+                const uint16_t* xrow = ti + ((orow + 1 + dr) * kCvCols + (ocol0 + 1 + dc)) * kL3Pitch + 8 * (lane >> 5);
+#pragma unroll
+                for (int mb = 0; mb < 2; ++mb)
+                    xf[set][mb] = *reinterpret_cast<const v8bf*>(xrow + (mb * 32 + (lane & 31)) * kL3Pitch);
+#pragma unroll
+                for (int nb = 0; nb < NB; ++nb)
+                    wf[set][nb] = *reinterpret_cast<const v8bf*>(tw + (tap * COUT + nb * 32 + (lane & 31)) * kL3Pitch +
+                                                                 8 * (lane >> 5));
+            };
+            frags(0, 0);
+#pragma unroll
+            for (int tap = 0; tap < 9; ++tap) {
+                if (tap == 4 && more) {
+                    // first half of the next stage in (its buffer is not read in
+                    // this stage), second half requested
+                    store_half((c + 1) & 1, 0);
+                    load_half(nband, ncs, 1);
+                }
+                if (tap < 8) frags(tap + 1, (tap + 1) & 1);
+                // keep the next tap's reads above this tap's products (the
+                // scheduler would otherwise sink each read to its first use)
+                __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+                for (int nb = 0; nb < NB; ++nb)
+#pragma unroll
+                    for (int mb = 0; mb < 2; ++mb)
+                        acc[nb][mb] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(wf[tap & 1][nb], xf[tap & 1][mb],
+                                                                             acc[nb][mb], 0, 0, 0);
+                __builtin_amdgcn_sched_barrier(0);
+            }
+            // the buffer being filled was last read in the previous stage, before the barrier below it
+            if (more) store_half((c + 1) & 1, 1);
+            __syncthreads();
+        }
+
+        // epilogue (registers and global memory only): act3 = BF16(ReLU(acc + b3)),
+        // U^T (9 taps padded to 32 rows x 32 pixels) = W4 x act3^T per pixel block
+        const int64_t e = band / BPE;
+        const int r0 = (band % BPE) * kCvRows;
+        const int64_t pix0 = (e * kImg + r0 + orow) * kImg + ocol0;
+        const int h = lane >> 5, n = lane & 31;
 #pragma unroll
         for (int mb = 0; mb < 2; ++mb) {
             v16f au;
 #pragma unroll
             for (int r = 0; r < 16; ++r) au[r] = 0.0f;
 #pragma unroll
-            for (int kk = 0; kk < COUT / 16; ++kk) {
-                const v8bf xa = *reinterpret_cast<const v8bf*>(s_out + (mb * 32 + (lane & 31)) * (COUT + 8) +
-                                                               kk * 16 + 8 * (lane >> 5));
-                au = __builtin_amdgcn_mfma_f32_32x32x16_bf16(wu[kk], xa, au, 0, 0, 0);
+            for (int nb = 0; nb < NB; ++nb) {
+#pragma unroll
+                for (int ks = 0; ks < 2; ++ks) {
+                    // k position j of this lane's half = result r = 8 ks + j: channel
+                    // nb 32 + 8 (r / 4) + 4 h + r % 4 (the same order in W4's fragment)
+                    v8bf xa, wa;
+#pragma unroll
+                    for (int g = 0; g < 2; ++g) {
+                        const int ch = nb * 32 + 8 * (2 * ks + g) + 4 * h;
+                        const float4 bb = *reinterpret_cast<const float4*>(bias + ch);
+                        const float bv[4] = {bb.x, bb.y, bb.z, bb.w};
+#pragma unroll
+                        for (int q = 0; q < 4; ++q) {
+                            xa[4 * g + q] = bits_bf(f2bf(fmaxf(acc[nb][mb][8 * ks + 4 * g + q] + bv[q], 0.0f)));
+                            wa[4 * g + q] = n < 9 ? bits_bf(w4[n * COUT + ch + q]) : bits_bf(0);
+                        }
+                    }
+                    au = __builtin_amdgcn_mfma_f32_32x32x16_bf16(wa, xa, au, 0, 0, 0);
+                }
             }
-            float* dst = u_out + (pix0 + mb * 32 + (lane & 31)) * kUPitch;
-            *reinterpret_cast<float4*>(dst + 4 * (lane >> 5)) = make_float4(au[0], au[1], au[2], au[3]);
-            if (lane < 32) dst[8] = au[4];
+            // lane < 32 holds taps 0-3 and 8 of pixel n, lane >= 32 taps 4-7
+            float* dst = u_out + (pix0 + mb * 32 + n) * kUPitch;
+            *reinterpret_cast<float4*>(dst + 4 * h) = make_float4(au[0], au[1], au[2], au[3]);
+            if (h == 0) dst[8] = au[4];
         }
     }
 }
@@ -933,17 +1107,21 @@ void launch_forward(const uint16_t* img, const uint16_t* wbf, const float* w32, 
                     uint16_t* act1, uint16_t* act2, uint16_t* act3, float* u, float* logits, bool train,
                     hipStream_t st)
 {
-    constexpr size_t l1 = conv_mid_lds<64, 128>(), l12 = conv12_lds(), l3 = conv3_lds();
+    constexpr size_t l1 = conv_mid_lds<64, 128>(), l12 = conv12_lds(), l3 = conv3_lds(), l3i = conv3i_lds();
     static bool attr = false;
+    static int n_cu = 0;
     if (!attr) {
+        int dev = 0;
+        if (hipGetDevice(&dev) != hipSuccess || hipDeviceGetAttribute(&n_cu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || n_cu < 1)
+            n_cu = 256;
+        (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&k_conv3i), hipFuncAttributeMaxDynamicSharedMemorySize,
+                                  (int)l3i);
         const void* f1 = reinterpret_cast<const void*>(&k_conv_mid<64, 128>);
         const void* f12 = reinterpret_cast<const void*>(&k_conv12);
-        const void* f30 = reinterpret_cast<const void*>(&k_conv3<0>);
-        const void* f31 = reinterpret_cast<const void*>(&k_conv3<1>);
+        const void* f30 = reinterpret_cast<const void*>(&k_conv3);
         (void)hipFuncSetAttribute(f1, hipFuncAttributeMaxDynamicSharedMemorySize, (int)l1);
         (void)hipFuncSetAttribute(f12, hipFuncAttributeMaxDynamicSharedMemorySize, (int)l12);
         (void)hipFuncSetAttribute(f30, hipFuncAttributeMaxDynamicSharedMemorySize, (int)l3);
-        (void)hipFuncSetAttribute(f31, hipFuncAttributeMaxDynamicSharedMemorySize, (int)l3);
         attr = true;
     }
     const int64_t npix = E * kPix;
@@ -953,15 +1131,16 @@ void launch_forward(const uint16_t* img, const uint16_t* wbf, const float* w32, 
         hipLaunchKernelGGL(k_conv_in, dim3(g0), dim3(256), 0, st, img, wbf + L.w_off[0], w32 + L.b_off[0], act1, npix);
         hipLaunchKernelGGL((k_conv_mid<64, 128>), dim3(gm), dim3(kCvThreads), l1, st, act1, wbf + L.w_off[1],
                            w32 + L.b_off[1], act2);
-        hipLaunchKernelGGL(k_conv3<0>, dim3(gm), dim3(kCvThreads), l3, st, act2, wbf + L.w_off[2], w32 + L.b_off[2],
-                           wbf + L.w_off[3], act3, (float*)nullptr);
+        hipLaunchKernelGGL(k_conv3, dim3(gm), dim3(kCvThreads), l3, st, act2, wbf + L.w_off[2], w32 + L.b_off[2], act3);
         hipLaunchKernelGGL(k_conv_head, dim3((unsigned)(E * (kImg / kHeadRows))), dim3(256), 0, st, act3,
                            wbf + L.w_off[3], w32 + L.b_off[3], logits);
     } else {
         hipLaunchKernelGGL(k_conv12, dim3(gm), dim3(kCvThreads), l12, st, img, wbf + L.w_off[0], w32 + L.b_off[0],
                            wbf + L.w_off[1], w32 + L.b_off[1], act2);
-        hipLaunchKernelGGL(k_conv3<1>, dim3(gm), dim3(kCvThreads), l3, st, act2, wbf + L.w_off[2], w32 + L.b_off[2],
-                           wbf + L.w_off[3], (uint16_t*)nullptr, u);
+        const int n_bands = (int)gm;
+        const unsigned g3 = (unsigned)std::min<int64_t>(n_bands, (int64_t)n_cu);
+        hipLaunchKernelGGL(k_conv3i, dim3(g3), dim3(kCvThreads), l3i, st, act2, wbf + L.w_off[2], w32 + L.b_off[2],
+                           wbf + L.w_off[3], u, n_bands);
         const int gh = (int)std::min<int64_t>((npix + 255) / 256, 65536);
         hipLaunchKernelGGL(k_head_sum, dim3(gh), dim3(256), 0, st, u, w32 + L.b_off[3], npix, logits);
     }
