@@ -69,6 +69,10 @@ struct retina_ctx {
         hipGraphExec_t exec;
     };
     std::vector<GraphEntry> graphs;
+    // the learned step (proposer, ascent, merge) captured as one graph, with
+    // the by-value launch arguments it was captured with
+    hipGraphExec_t learned_exec = nullptr;
+    std::vector<unsigned char> learned_key;
     void* scratch = nullptr;      // this device's fixed workspace (retina_response_noalloc)
 };
 
@@ -526,6 +530,7 @@ void retina_destroy(retina_ctx* c)
     if (c->d_cnt) (void)hipFree(c->d_cnt);
     if (c->h_cnt) (void)hipHostFree(c->h_cnt);
     for (auto& g : c->graphs) (void)hipGraphExecDestroy(g.exec);
+    if (c->learned_exec) (void)hipGraphExecDestroy(c->learned_exec);
     for (int i = 0; i < 7; ++i)
         if (c->ev[i]) (void)hipEventDestroy(c->ev[i]);
     if (c->own) (void)hipStreamDestroy(c->own);
@@ -1289,7 +1294,7 @@ int ensure_acts(retina_ctx* c, int64_t E, Acts& A, bool train)
 void forward_net(retina_ctx* c, const retina_model* md, int64_t E, const Acts& A, bool train)
 {
     const Desc& d = *c->h_desc;
-    launch_bin_image(d.hits, d.plane_off, d.n_planes, 2, c->d_desc->plane_z, E, A.act[0], c->stream);
+    launch_bin_image(d.hits, d.plane_off, d.n_planes, 2, c->d_desc->plane_z, E, A.act[0], &c->d_cnt->err, c->stream);
     launch_forward(A.act[0], md->wbf, md->w32, md->L, E, A.act[1], A.act[2], A.act[3], A.u, A.logits, train,
                    c->stream);
 }
@@ -1624,6 +1629,244 @@ int propose_device(retina_ctx* c, const retina_geometry* g, const retina_hits* h
     return RETINA_OK;
 }
 
+// Algorithm 1 from the proposer's seeds in one device pass: staging, binning,
+// network, seed selection (lattice fallback), work plan, ascent, merge and
+// output, sized by the proposal bound E x max(k_max, lattice) so that no count
+// returns to the host between the proposer and the ascent.  The sequence is
+// replayed from one captured graph while its launch arguments stay the same.
+// The launch shape follows the bound: the sparse-seeding ascent when k_max is
+// below kSparseSeeds, the small-cache merge when k_max <= kMergeSmallKeys.
+int learned_impl(retina_ctx* c, const retina_geometry* g, const retina_hits* h, const retina_params* P,
+                 const retina_model* md, const retina_proposal* pr, retina_track* tracks, int64_t capacity,
+                 int64_t* track_offsets, int32_t* event_flags)
+{
+    int rc;
+    if ((rc = check_geometry(c, g)) || (rc = check_hits(c, g, h))) return rc;
+    if (g->meas_dim != 2) return fail(c, RETINA_ERR_INVALID_ARG, "the proposer needs meas_dim 2");
+    if (!P || !pr) return fail(c, RETINA_ERR_INVALID_ARG, "params or proposal is NULL");
+    {
+        retina_params L = *P;
+        L.seed_mode = RETINA_SEED_LATTICE;  // params carry the fallback lattice
+        rtv::Check k;
+        if (rtv::method_params(k, &L, capacity, tracks, track_offsets)) return fail(c, k.code, "%s", k.msg);
+    }
+    const int32_t k_max = pr->k_max;
+    if (k_max < 1 || k_max > 4096) return fail(c, RETINA_ERR_INVALID_ARG, "k_max must be in [1, 4096]");
+    if (!(pr->tau > 0.0f && pr->tau < 1.0f) || !(pr->conf_min >= 0.0f && pr->conf_min <= 1.0f))
+        return fail(c, RETINA_ERR_INVALID_ARG, "tau must be in (0, 1) and conf_min in [0, 1]");
+    if (pr->nms != 0 && pr->nms != 1) return fail(c, RETINA_ERR_INVALID_ARG, "nms must be 0 or 1");
+    const int D = 2;
+    const int64_t E = h->n_events;
+    const bool host = h->mem == RETINA_MEM_HOST;
+    if (host && !host_offsets_ok(h->event_offsets, E))
+        return fail(c, RETINA_ERR_INVALID_ARG, "event_offsets must start at 0 and be non-decreasing");
+    int64_t n_hits;
+    if ((rc = read_i64(c, h->mem, h->event_offsets, E, &n_hits))) return rc;
+    if (n_hits < 0 || n_hits > 0x7FFFFFFF) return fail(c, RETINA_ERR_INVALID_ARG, "bad total hit count");
+    const int64_t lat = (int64_t)P->lattice_n[0] * P->lattice_n[1];
+    const int64_t cap = E * std::max<int64_t>(k_max, lat);  // seeds of the batch, at most
+    if (cap > 0x7FFFFFFF) return fail(c, RETINA_ERR_INVALID_ARG, "too many seeds in the batch (proposal bound)");
+
+    Desc& d = *c->h_desc;
+    reset_desc(d);
+    fill_geometry(d, g);
+    d.cnt = c->d_cnt;
+    if ((rc = stage_inputs(c, d, g, h, n_hits))) return rc;
+    if ((rc = set_lattice(c, d, P->lattice_n, P->lattice_lo, P->lattice_hi))) return rc;
+    // proposer
+    Acts A;
+    if ((rc = ensure_acts(c, E, A, false))) return rc;
+    ProposeArgs pa = ProposeArgs{};
+    pa.logits = A.logits;
+    pa.n_events = E;
+    pa.k_max = k_max;
+    pa.ltau = (float)log((double)pr->tau / (1.0 - (double)pr->tau));
+    pa.lconf = pr->conf_min <= 0.0f ? -INFINITY
+             : pr->conf_min >= 1.0f ? INFINITY : (float)log((double)pr->conf_min / (1.0 - (double)pr->conf_min));
+    pa.nms = pr->nms;
+    for (int i = 0; i < 2; ++i) pa.lattice_n[i] = P->lattice_n[i];
+    pa.lat_coord = c->d_desc->lat_coord;
+    {
+        const double w = ((double)kSlopeHi - (double)kSlopeLo) / kImg;
+        for (int i = 0; i < kImg; ++i) pa.bin_centre[i] = (float)((double)kSlopeLo + ((double)i + 0.5) * w);
+    }
+    if ((rc = ensure_t(c, B_PSCORE, (size_t)E * k_max, &pa.cand_score)) ||
+        (rc = ensure_t(c, B_PPIX, (size_t)E * k_max, &pa.cand_pix)) || (rc = ensure_t(c, B_PCOUNT, (size_t)E, &pa.count)) ||
+        (rc = ensure_t(c, B_PCONF, (size_t)E, &pa.confidence)) || (rc = ensure_t(c, B_PFB, (size_t)E, &pa.fallback)) ||
+        (rc = ensure_t(c, B_PSOFF, (size_t)E + 1, &pa.seed_off)) ||
+        (rc = ensure_t(c, B_PSEEDS, (size_t)std::max<int64_t>(cap, 1) * 4, &pa.seeds)))
+        return rc;
+    // ascent and merge, sized by the bound
+    HotConfig hc = k_max < kSparseSeeds ? c->sparse_cfg[D] : c->ascent_cfg[D];
+    hc.prune = P->prune_u > 0.0f;
+    hc.staged = 1;  // the sequence stages the hits before the proposer
+    if (P->update != RETINA_UPDATE_NEWTON) {
+        hc = c->sparse_cfg[D];
+        hc.cand = 1;
+        hc.update = P->update;
+        hc.prune = 0;
+        hc.staged = 1;
+    }
+    if (kSplitSeeds && hc.cand == 1 && hc.update == RETINA_UPDATE_NEWTON) {
+        hc.split = 1;
+        hc.grid = c->n_cu * hot_max_blocks_per_cu(D, hc, true);
+    }
+    hc.small_merge = k_max <= kMergeSmallKeys;
+    d.seeds_per_item = hot_seeds_per_item(hc);
+    d.items_cap = cap / d.seeds_per_item + E + 1;
+    if ((rc = ensure_t(c, B_ITEMS, (size_t)d.items_cap, &d.items))) return rc;
+    d.seed_mode = RETINA_SEED_EXPLICIT;
+    d.in_seeds = pa.seeds;
+    d.in_seed_off = pa.seed_off;
+    d.n_sigma = P->n_sigma;
+    for (int i = 0; i < P->n_sigma; ++i) d.sigma[i] = P->sigma[i];
+    d.sigma_final = P->sigma_final;
+    d.n_final_steps = P->n_final_steps;
+    d.n_polish = P->n_polish;
+    d.ls_trials = P->ls_trials;
+    d.n_slope_steps = P->n_slope_steps;
+    d.armijo_c1 = P->armijo_c1;
+    d.step_cap = P->step_cap_sigmas;
+    d.small_step = P->small_step_sigmas;
+    d.conv_tol = P->conv_tol;
+    d.R0 = P->R0;
+    d.d_merge = P->d_merge;
+    d.prune_u = hc.prune ? P->prune_u : 0.0f;
+    if (hc.prune && (rc = ensure_t(c, B_EVSORT, (size_t)E, &d.ev_sorted))) return rc;
+    const size_t ns1 = (size_t)std::max<int64_t>(cap, 1);
+    if ((rc = ensure_t(c, B_STH, ns1 * 4, &d.s_theta)) || (rc = ensure_t(c, B_SR, ns1, &d.s_R)) ||
+        (rc = ensure_t(c, B_SFL, ns1, &d.s_flags)) || (rc = ensure_t(c, B_SNR, ns1, &d.s_nreval)) ||
+        (rc = ensure_t(c, B_MLEAD, ns1, &d.m_leader)) || (rc = ensure_t(c, B_MMEM, ns1, &d.m_members)) ||
+        (rc = ensure_t(c, B_MKEYS, ns1 * 2, &d.m_keys)) || (rc = ensure_t(c, B_EVNT, (size_t)E, &d.ev_ntracks)) ||
+        (rc = ensure_t(c, B_EVFL, (size_t)E, &d.ev_flags)) || (rc = ensure_t(c, B_EVTOFF, (size_t)E + 1, &d.ev_toff)))
+        return rc;
+    if (host) {
+        const int64_t host_cap = std::min<int64_t>(capacity, cap);
+        if ((rc = ensure_t(c, B_OUTTR, (size_t)std::max<int64_t>(host_cap, 1), &d.out_tracks)) ||
+            (rc = ensure_t(c, B_OUTTOFF, (size_t)E + 1, &d.out_track_off)))
+            return rc;
+        d.out_capacity = host_cap;
+        if (event_flags && (rc = ensure_t(c, B_OUTEVF, (size_t)E, &d.out_ev_flags))) return rc;
+    } else {
+        d.out_tracks = tracks;
+        d.out_capacity = capacity;
+        d.out_track_off = track_offsets;
+        d.out_ev_flags = event_flags;
+    }
+    if ((rc = upload_desc(c))) return rc;
+    prepare_forward();  // kernel attributes are set outside any capture
+
+    const retina_model* mdl = md;
+    auto sequence = [&](hipStream_t st) {
+        auto mark = [&](int i) {
+            if (c->prof) (void)hipEventRecord(c->ev[i], st);
+        };
+        mark(5);
+        launch_reset(c->d_desc, st);
+        launch_stage(c->d_desc, c->n_cu * 8, st);
+        launch_bin_image(d.hits, d.plane_off, d.n_planes, 2, c->d_desc->plane_z, E, A.act[0], &c->d_cnt->err, st);
+        launch_forward(A.act[0], mdl->wbf, mdl->w32, mdl->L, E, A.act[1], A.act[2], A.act[3], A.u, A.logits, false, st);
+        launch_propose_select(pa, st);
+        launch_propose_offsets(pa, st);
+        launch_propose_write(pa, st);
+        mark(6);
+        mark(0);
+        if (hc.prune) launch_sort_planes(c->d_desc, c->n_cu * 8, st);
+        mark(1);
+        launch_plan_tracks(c->d_desc, st);
+        mark(2);
+        launch_ascent(c->d_desc, D, hc, st);
+        mark(3);
+        launch_merge(c->d_desc, D, c->n_cu, hc.small_merge != 0, st);
+        launch_finalize(c->d_desc, st);
+        launch_emit(c->d_desc, D, c->n_cu * 4, st);
+        launch_flag_fallback_desc(c->d_desc, pa.fallback, E, st);
+        mark(4);
+    };
+    // every by-value launch argument of the sequence (pool and model addresses,
+    // sizes, thresholds, launch shape) keys the captured graph
+    struct Key {
+        int64_t E;
+        ProposeArgs pa;
+        Acts A;
+        const void* wbf;
+        const void* w32;
+        const void* hits;
+        const void* plane_off;
+        HotConfig hc;
+        int n_planes, n_cu;
+    } key;
+    memset(&key, 0, sizeof(key));
+    key.E = E;
+    key.pa = pa;
+    key.A = A;
+    key.wbf = md->wbf;
+    key.w32 = md->w32;
+    key.hits = d.hits;
+    key.plane_off = d.plane_off;
+    key.hc = hc;
+    key.n_planes = d.n_planes;
+    key.n_cu = c->n_cu;
+    bool launched = false;
+    if (c->use_graphs && !c->prof) {
+        const unsigned char* kb = reinterpret_cast<const unsigned char*>(&key);
+        if (!c->learned_exec || c->learned_key.size() != sizeof(key) ||
+            memcmp(c->learned_key.data(), kb, sizeof(key)) != 0) {
+            if (c->learned_exec) (void)hipGraphExecDestroy(c->learned_exec);
+            c->learned_exec = nullptr;
+            c->learned_key.clear();
+            hipGraph_t graph = nullptr;
+            HIP_TRY(c, hipStreamSynchronize(c->stream));
+            bool ok = hipStreamBeginCapture(c->own, hipStreamCaptureModeThreadLocal) == hipSuccess;
+            if (ok) {
+                sequence(c->own);
+                ok = hipStreamEndCapture(c->own, &graph) == hipSuccess && graph;
+            }
+            hipGraphExec_t exec = nullptr;
+            if (ok) ok = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0) == hipSuccess;
+            if (graph) (void)hipGraphDestroy(graph);
+            if (ok) {
+                c->learned_exec = exec;
+                c->learned_key.assign(kb, kb + sizeof(key));
+            } else {
+                (void)hipGetLastError();
+                c->use_graphs = false;  // capture unsupported here: launch eagerly from now on
+            }
+        }
+        if (c->learned_exec) {
+            HIP_TRY(c, hipGraphLaunch(c->learned_exec, c->stream));
+            launched = true;
+        }
+    }
+    if (!launched) sequence(c->stream);
+    HIP_TRY(c, hipGetLastError());
+    if ((rc = download_counters(c))) return rc;
+    if (c->prof) {
+        float t = 0.0f;
+        if (hipEventElapsedTime(&t, c->ev[5], c->ev[6]) != hipSuccess) t = 0.0f;
+        (void)hipGetLastError();
+        c->prof_acc.ms_propose += t;
+    }
+    prof_collect(c);
+    const uint32_t err = c->h_cnt->err;
+    const int64_t total = c->h_cnt->total_tracks;
+    if (err & ~kErrCapacity) return device_error(c, err);
+    if (err & kErrCapacity || total > capacity) {
+        if (host) track_offsets[E] = total;
+        return fail(c, RETINA_ERR_CAPACITY, "%lld tracks found, capacity %lld", (long long)total,
+                    (long long)capacity);
+    }
+    if (host) {
+        if (total)
+            HIP_TRY(c, hipMemcpyAsync(tracks, d.out_tracks, sizeof(retina_track) * total, hipMemcpyDeviceToHost, c->stream));
+        HIP_TRY(c, hipMemcpyAsync(track_offsets, d.out_track_off, sizeof(int64_t) * (E + 1), hipMemcpyDeviceToHost, c->stream));
+        if (event_flags)
+            HIP_TRY(c, hipMemcpyAsync(event_flags, d.out_ev_flags, sizeof(int32_t) * E, hipMemcpyDeviceToHost, c->stream));
+        HIP_TRY(c, hipStreamSynchronize(c->stream));
+    }
+    return RETINA_OK;
+}
+
 }  // namespace
 
 extern "C" {
@@ -1670,37 +1913,9 @@ int retina_find_tracks_learned(retina_ctx* c, const retina_geometry* g, const re
     if (!c || !md) return RETINA_ERR_INVALID_ARG;
     c->err.clear();
     DeviceGuard guard(c->device);
-    int rc;
     if (h && h->n_events == 0)
         return retina_find_tracks(c, g, h, P, tracks, capacity, track_offsets, event_flags, nullptr);
-    ProposeArgs pa;
-    int64_t n;
-    if ((rc = propose_device(c, g, h, md, pr, P, pa, &n))) return rc;
-    retina_params Q = *P;
-    Q.seed_mode = RETINA_SEED_EXPLICIT;
-    Q.seeds = pa.seeds;
-    Q.seed_offsets = pa.seed_off;
-    // the proposer staged these hits into the same buffers (and validated them)
-    rc = find_tracks_impl(c, g, h, &Q, tracks, capacity, track_offsets, event_flags, nullptr, true, true);
-    if (rc) return rc;
-    if (event_flags && h->mem == RETINA_MEM_DEVICE) {
-        // the fallback bit is set on the device, in stream order
-        launch_flag_fallback(event_flags, pa.fallback, h->n_events, c->stream);
-        HIP_TRY(c, hipGetLastError());
-        HIP_TRY(c, hipStreamSynchronize(c->stream));
-    } else if (event_flags) {
-        const int64_t E = h->n_events;
-        std::vector<int32_t> fb(E), ef(E);
-        HIP_TRY(c, hipMemcpyAsync(fb.data(), pa.fallback, 4 * E, hipMemcpyDeviceToHost, c->stream));
-        const hipMemcpyKind k = h->mem == RETINA_MEM_HOST ? hipMemcpyHostToHost : hipMemcpyDeviceToHost;
-        HIP_TRY(c, hipMemcpyAsync(ef.data(), event_flags, 4 * E, k, c->stream));
-        HIP_TRY(c, hipStreamSynchronize(c->stream));
-        for (int64_t e = 0; e < E; ++e) ef[e] |= fb[e] ? 16 : 0;
-        const hipMemcpyKind k2 = h->mem == RETINA_MEM_HOST ? hipMemcpyHostToHost : hipMemcpyHostToDevice;
-        HIP_TRY(c, hipMemcpyAsync(event_flags, ef.data(), 4 * E, k2, c->stream));
-        HIP_TRY(c, hipStreamSynchronize(c->stream));
-    }
-    return RETINA_OK;
+    return learned_impl(c, g, h, P, md, pr, tracks, capacity, track_offsets, event_flags);
 }
 
 }  // extern "C"

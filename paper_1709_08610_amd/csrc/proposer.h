@@ -6,6 +6,8 @@
 
 namespace rt {
 
+struct Desc;
+
 constexpr int kImg = 128;                 // slope-image side (bins)
 constexpr int kPix = kImg * kImg;
 constexpr int kLayers = 4;
@@ -48,12 +50,13 @@ void launch_gemm(const GemmArgs& a, hipStream_t st);
 // forward pass of the four layers (direct convolutions; see proposer.hip).
 // train: store act1..act3 for the backward pass; otherwise only act2 and the
 // head's per-tap partial sums u (E * kPix * 12 floats, 9 used) pass through HBM.
+int prepare_forward();
 void launch_forward(const uint16_t* img, const uint16_t* wbf, const float* w32, const NetLayout& L, int64_t E,
                     uint16_t* act1, uint16_t* act2, uint16_t* act3, float* u, float* logits, bool train,
                     hipStream_t st);
 
 void launch_bin_image(const float* hits, const int32_t* plane_off, int n_planes, int meas_dim,
-                      const float* plane_z, int64_t n_events, uint16_t* img, hipStream_t st);
+                      const float* plane_z, int64_t n_events, uint16_t* img, const uint32_t* err, hipStream_t st);
 void launch_target_image(const double* targets, const int64_t* target_off, int64_t n_events,
                          uint8_t* tgt, hipStream_t st);
 void launch_bce(const float* logits, const uint8_t* tgt, int64_t n, float pos_weight, float* loss_part,
@@ -91,5 +94,6 @@ void launch_propose_select(const ProposeArgs& a, hipStream_t st);
 void launch_propose_offsets(const ProposeArgs& a, hipStream_t st);
 void launch_propose_write(const ProposeArgs& a, hipStream_t st);
 void launch_flag_fallback(int32_t* ev_flags, const int32_t* fallback, int64_t n_events, hipStream_t st);
+void launch_flag_fallback_desc(const Desc* d, const int32_t* fallback, int64_t n_events, hipStream_t st);
 
 }  // namespace rt

@@ -61,12 +61,15 @@ __device__ __forceinline__ int slope_bin(float x, float y, float z, float w)
     return -1;
 }
 
+// err (may be NULL): validation bits of the staging that produced plane_off;
+// non-zero leaves the image unwritten (the offsets may then be stale)
 __global__ __launch_bounds__(256) void k_bin_image(const float* __restrict__ hits,
                                                    const int32_t* __restrict__ plane_off, int P, int D,
                                                    const float* __restrict__ plane_z, int64_t E,
-                                                   uint16_t* __restrict__ img)
+                                                   uint16_t* __restrict__ img, const uint32_t* __restrict__ err)
 {
     __shared__ uint32_t s_h[kPix];
+    if (err && *err) return;
     const float w = (kSlopeHi - kSlopeLo) / kImg;
     for (int64_t e = blockIdx.x; e < E; e += gridDim.x) {
         const int32_t* po = plane_off + e * (P + 1);
@@ -103,10 +106,10 @@ __global__ __launch_bounds__(256) void k_bin_image(const float* __restrict__ hit
 }
 
 void launch_bin_image(const float* hits, const int32_t* plane_off, int P, int D, const float* plane_z,
-                      int64_t E, uint16_t* img, hipStream_t st)
+                      int64_t E, uint16_t* img, const uint32_t* err, hipStream_t st)
 {
     const int grid = (int)std::min<int64_t>(E, 2048);
-    hipLaunchKernelGGL(k_bin_image, dim3(grid), dim3(256), 0, st, hits, plane_off, P, D, plane_z, E, img);
+    hipLaunchKernelGGL(k_bin_image, dim3(grid), dim3(256), 0, st, hits, plane_off, P, D, plane_z, E, img, err);
 }
 
 // Target heatmap: 1 at the bin of every target slope pair, else 0.
@@ -1103,27 +1106,37 @@ __global__ __launch_bounds__(256) void k_head_sum(const float* __restrict__ u, c
     }
 }
 
+// One-time set-up of the forward kernels (dynamic LDS limits) and the CU
+// count; idempotent, and called before any stream capture of the forward.
+int prepare_forward()
+{
+    // a function-local static: initialised once, thread-safe
+    static const int n_cu = [] {
+        constexpr size_t l1 = conv_mid_lds<64, 128>(), l12 = conv12_lds(), l3 = conv3_lds(), l3i = conv3i_lds();
+        int dev = 0, n = 0;
+        if (hipGetDevice(&dev) != hipSuccess ||
+            hipDeviceGetAttribute(&n, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || n < 1)
+            n = 256;
+        (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&k_conv3i), hipFuncAttributeMaxDynamicSharedMemorySize,
+                                  (int)l3i);
+        (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&k_conv_mid<64, 128>),
+                                  hipFuncAttributeMaxDynamicSharedMemorySize, (int)l1);
+        (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&k_conv12), hipFuncAttributeMaxDynamicSharedMemorySize,
+                                  (int)l12);
+        (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&k_conv3), hipFuncAttributeMaxDynamicSharedMemorySize,
+                                  (int)l3);
+        (void)hipGetLastError();
+        return n;
+    }();
+    return n_cu;
+}
+
 void launch_forward(const uint16_t* img, const uint16_t* wbf, const float* w32, const NetLayout& L, int64_t E,
                     uint16_t* act1, uint16_t* act2, uint16_t* act3, float* u, float* logits, bool train,
                     hipStream_t st)
 {
     constexpr size_t l1 = conv_mid_lds<64, 128>(), l12 = conv12_lds(), l3 = conv3_lds(), l3i = conv3i_lds();
-    static bool attr = false;
-    static int n_cu = 0;
-    if (!attr) {
-        int dev = 0;
-        if (hipGetDevice(&dev) != hipSuccess || hipDeviceGetAttribute(&n_cu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || n_cu < 1)
-            n_cu = 256;
-        (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&k_conv3i), hipFuncAttributeMaxDynamicSharedMemorySize,
-                                  (int)l3i);
-        const void* f1 = reinterpret_cast<const void*>(&k_conv_mid<64, 128>);
-        const void* f12 = reinterpret_cast<const void*>(&k_conv12);
-        const void* f30 = reinterpret_cast<const void*>(&k_conv3);
-        (void)hipFuncSetAttribute(f1, hipFuncAttributeMaxDynamicSharedMemorySize, (int)l1);
-        (void)hipFuncSetAttribute(f12, hipFuncAttributeMaxDynamicSharedMemorySize, (int)l12);
-        (void)hipFuncSetAttribute(f30, hipFuncAttributeMaxDynamicSharedMemorySize, (int)l3);
-        attr = true;
-    }
+    const int n_cu = prepare_forward();
     const int64_t npix = E * kPix;
     const unsigned gm = (unsigned)(E * (kImg / kCvRows));
     if (train) {
@@ -1542,6 +1555,26 @@ void launch_flag_fallback(int32_t* ev_flags, const int32_t* fallback, int64_t n_
     if (n_events <= 0) return;
     const int grid = (int)std::min<int64_t>((n_events + 255) / 256, 1024);
     hipLaunchKernelGGL(k_flag_fallback, dim3(grid), dim3(256), 0, st, ev_flags, fallback, n_events);
+}
+
+// the same, with the event-flag array taken from the descriptor (out_ev_flags,
+// may be NULL) so that a captured launch serves any caller array; skipped
+// after a validation error (the outputs are not written then)
+__global__ __launch_bounds__(256) void k_flag_fallback_desc(const Desc* __restrict__ d,
+                                                            const int32_t* __restrict__ fallback)
+{
+    int32_t* ev_flags = d->out_ev_flags;
+    if (!ev_flags || d->cnt->err) return;
+    for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < d->n_events;
+         e += (int64_t)gridDim.x * blockDim.x)
+        if (fallback[e]) ev_flags[e] |= 16;
+}
+
+void launch_flag_fallback_desc(const Desc* d, const int32_t* fallback, int64_t n_events, hipStream_t st)
+{
+    if (n_events <= 0) return;
+    const int grid = (int)std::min<int64_t>((n_events + 255) / 256, 1024);
+    hipLaunchKernelGGL(k_flag_fallback_desc, dim3(grid), dim3(256), 0, st, d, fallback);
 }
 
 }  // namespace rt

@@ -121,3 +121,50 @@ def test_sparse_seeding_has_its_own_tuned_shape(ctx, tmp_path):
         th, R = event_tracks(res, e, 2)
         a, c = ref["track_offsets"][e], ref["track_offsets"][e + 1]
         assert_tracks_match(2, th, R, ref["theta"][a:c], ref["R"][a:c], P["d_merge"], 20.0, 750.0)
+
+
+def test_learned_step_graph_equals_eager_and_explicit_seeds(ctx):
+    """The learned entry point runs proposer, ascent and merge as one device
+    sequence (one captured graph).  Its replays, across batches of different
+    shapes (each a new capture) and with eager library work in between, equal
+    its eager launches bit for bit and equal the two-call path: the proposer's
+    seeds read back and passed to retina_find_tracks as explicit seeds."""
+    import torch
+    from paper_1709_08610_amd import learned
+    cfg = events.load_config("c3")
+    LS = learned.settings(cfg)
+    PL = LS["params"]
+    model = ctx.retina_model_load(LS["model"])
+    dev = torch.device("cuda:0")
+    tin = lambda a: torch.from_numpy(np.ascontiguousarray(a)).to(dev)
+    batches = [events.make_batch(cfg, n, start=s) for n, s in ((6, 0), (17, 30), (6, 0))]
+
+    def learned_call(b):
+        d = (tin(b.event_offsets), tin(b.x), tin(b.y), tin(b.plane))
+        r = ctx.retina_find_tracks_learned(model, b.plane_z, *d, PL, LS["k_max"], LS["tau"], LS["conf_min"],
+                                           nms=LS["nms"])
+        torch.cuda.synchronize()
+        return (retina.tracks_from_device(r), r["track_offsets"].cpu().numpy(), r["event_flags"].cpu().numpy())
+
+    ctx.retina_set_graphs(False)
+    eager = [learned_call(b) for b in batches]
+    ctx.retina_set_graphs(True)
+    for rep in range(3):
+        _say("learned graph round %d" % rep)
+        for b, (tr, toff, fl) in zip(batches, eager):
+            gtr, gtoff, gfl = learned_call(b)
+            np.testing.assert_array_equal(gtoff, toff)
+            np.testing.assert_array_equal(gtr, tr)
+            np.testing.assert_array_equal(gfl, fl)
+            ctx.retina_response(2, b.plane_z, b.event_offsets[:2], b.x[:b.event_offsets[1]],
+                                b.y[:b.event_offsets[1]], b.plane[:b.event_offsets[1]],
+                                np.zeros((3, 4), np.float32), sigma=1.0)
+    # the two-call path on the same seeds
+    for b, (tr, toff, fl) in zip(batches[:2], eager[:2]):
+        prop = ctx.retina_propose_seeds(model, b.plane_z, b.event_offsets, b.x, b.y, b.plane, LS["k_max"], LS["tau"],
+                                        LS["conf_min"], PL, nms=LS["nms"])
+        res = ctx.retina_find_tracks(2, b.plane_z, b.event_offsets, b.x, b.y, b.plane, PL, seeds=prop["seeds"],
+                                     seed_offsets=prop["seed_offsets"])
+        np.testing.assert_array_equal(res["track_offsets"], toff)
+        np.testing.assert_array_equal(res["tracks"], tr)
+        np.testing.assert_array_equal(fl & 16, np.where(prop["fallback"] != 0, 16, 0))
