@@ -418,10 +418,18 @@ int retina_propose_seeds(retina_ctx* ctx, const retina_geometry* geom, const ret
                          const retina_params* params, double* seeds, int64_t capacity,
                          int64_t* seed_offsets, float* confidence, int32_t* fallback);
 
-/* Algorithm 1 with learned seeds: retina_propose_seeds followed by
- * retina_find_tracks on those seeds, on the device without a host round
- * trip.  params gives the method's constants and the fallback lattice;
- * event_flags bit 4 (value 16) marks events that fell back to the lattice. */
+/* Algorithm 1 with learned seeds: the results of retina_propose_seeds
+ * followed by retina_find_tracks on those seeds (explicit seeds), computed in
+ * one device pass: staging, network, seed selection, ascent and merge are
+ * replayed from one captured HIP graph (graphs enabled), with the work
+ * buffers sized by the proposal bound n_events * max(k_max, lattice cells),
+ * so no count returns to the host between the proposer and the ascent (the
+ * hit total is read at the start and the counters at the end).  The ascent's
+ * launch shape follows the bound: the sparse-seeding shape (retina_set_tuning
+ * kernel 2) when k_max < 512, the small-cache merge when k_max <= 1024.
+ * params gives the method's constants and the fallback lattice; event_flags
+ * bit 4 (value 16) marks events that fell back to the lattice.  Outputs and
+ * errors as retina_find_tracks. */
 int retina_find_tracks_learned(retina_ctx* ctx, const retina_geometry* geom,
                                const retina_hits* hits, const retina_params* params,
                                const retina_model* model, const retina_proposal* proposal,
