@@ -892,11 +892,26 @@ __global__ __launch_bounds__(kBlock) void k_ascent(const Desc* __restrict__ d, i
     else { ds[0] = 1.0f; ds[1] = zr; }
     const Cands<C> zero_c = {};
 
+    // this work-group's XCD queue first, then the others (work stealing at the end)
+    const int xq = (int)(blockIdx.x % kXcds);
+    (void)n_items;
     for (;;) {
-        if (threadIdx.x == 0) s_item = (int)atomicAdd(&d->cnt->item, 1u);
+        if (threadIdx.x == 0) {
+            int found = -1;
+            for (int k = 0; k < kXcds && found < 0; ++k) {
+                const int q = (xq + k) % kXcds;
+                const int64_t q0 = d->cnt->xq_start[q], nq = d->cnt->xq_start[q + 1] - q0;
+                if (nq <= 0 || (int64_t)__hip_atomic_load(&d->cnt->xq_cursor[q][0], __ATOMIC_RELAXED,
+                                                          __HIP_MEMORY_SCOPE_AGENT) >= nq)
+                    continue;
+                const uint32_t cidx = atomicAdd(&d->cnt->xq_cursor[q][0], 1u);
+                if ((int64_t)cidx < nq) found = (int)(q0 + cidx);
+            }
+            s_item = found;
+        }
         __syncthreads();
         const int item = __builtin_amdgcn_readfirstlane(s_item);
-        if (item >= n_items) break;
+        if (item < 0) break;
         const int2 it0 = d->items[item];
         const int2 it = make_int2(it0.x, it0.y * d->seeds_per_item);  // (event, first seed)
         const int e = __builtin_amdgcn_readfirstlane(it.x);

@@ -34,6 +34,11 @@ enum : uint32_t {
 // of both dimensions travel in the descriptor (Desc::lat_coord).
 constexpr int kMaxLatticeSide = RETINA_MAX_LATTICE_SIDE;
 
+// Work-groups of a launch are dealt to the XCDs round-robin by index; the
+// ascent keeps one work queue per XCD so that an event's work items share the
+// XCD's L2 (the event's hits are then read from HBM once).
+constexpr int kXcds = 8;
+
 // device-side counters (one cache line each to avoid false sharing of atomics)
 struct Counters {
     uint32_t item;          // persistent work queue cursor
@@ -46,6 +51,8 @@ struct Counters {
     uint64_t exec_pairs;    // hit-candidate pairs the hot kernel executed (all lanes)
     uint64_t exec_rpairs;   // ... of which in R-only line-search passes
     int64_t pad2[3];
+    uint32_t xq_cursor[kXcds][16];  // per-XCD queue cursors of the ascent (one line each)
+    int64_t xq_start[kXcds + 1];    // queue x holds items [xq_start[x], xq_start[x + 1])
 };
 
 // Everything a launch needs; lives in device memory and is refreshed by one

@@ -28,6 +28,8 @@ __global__ void k_reset(const Desc* __restrict__ d)
         c->exec_pairs = 0;
         c->exec_rpairs = 0;
     }
+    if (threadIdx.x < kXcds) d->cnt->xq_cursor[threadIdx.x][0] = 0;
+    if (threadIdx.x <= kXcds) d->cnt->xq_start[threadIdx.x] = 0;
 }
 
 __device__ __forceinline__ uint64_t lanemask_lt()
@@ -277,8 +279,63 @@ __global__ __launch_bounds__(1024) void k_plan(const Desc* __restrict__ d, int m
         for (int64_t r = t; r < E; r += 1024) d->order[r] = (int32_t)r;
     }
     __syncthreads();
-    // items in rank order
     const int spi = d->seeds_per_item;
+    if (mode == 0 || mode == 1) {
+        // track finding: the events of rank r (longest first) go to XCD queue
+        // r % kXcds, each queue in rank order; position of an event's items =
+        // its queue's start + the items of the queue's earlier events
+        __shared__ int64_t s_qcarry[kXcds], s_qstart[kXcds + 1];
+        for (int pass = 0; pass < 2; ++pass) {
+            if (t < kXcds) s_qcarry[t] = 0;
+            __syncthreads();
+            for (int64_t r0 = 0; r0 < E; r0 += 1024) {
+                const int64_t r = r0 + t;  // r % kXcds == t % kXcds (1024 is a multiple of kXcds)
+                int64_t nb = 0;
+                int e = 0;
+                if (r < E) {
+                    e = d->order[r];
+                    const int64_t ns = d->seed_off[e + 1] - d->seed_off[e];
+                    nb = (ns + spi - 1) / spi;
+                }
+                // inclusive prefix over this chunk's ranks of the same queue
+                s_tmp[t] = nb;
+                __syncthreads();
+                for (int off = kXcds; off < 1024; off <<= 1) {
+                    const int64_t add = t >= off ? s_tmp[t - off] : 0;
+                    __syncthreads();
+                    s_tmp[t] += add;
+                    __syncthreads();
+                }
+                const int q = t % kXcds;
+                const int64_t ex = s_tmp[t] - nb + s_qcarry[q];
+                if (pass == 1 && r < E) {
+                    for (int64_t b = 0; b < nb; ++b) {
+                        const int64_t it = s_qstart[q] + ex + b;
+                        if (it < d->items_cap) d->items[it] = make_int2(e, (int)b);
+                    }
+                }
+                __syncthreads();
+                if (t < kXcds) s_qcarry[t] += s_tmp[1024 - kXcds + t];  // the chunk's last rank of queue t
+                __syncthreads();
+            }
+            if (pass == 0 && t == 0) {
+                int64_t acc = 0;
+                for (int q = 0; q < kXcds; ++q) {
+                    s_qstart[q] = acc;
+                    acc += s_qcarry[q];
+                }
+                s_qstart[kXcds] = acc;
+            }
+            __syncthreads();
+        }
+        if (t <= kXcds) d->cnt->xq_start[t] = s_qstart[t];
+        if (t == 0) {
+            if (s_qstart[kXcds] > d->items_cap) atomicOr(&d->cnt->err, kErrSeedOff);
+            d->cnt->n_items = s_qstart[kXcds];
+        }
+        return;
+    }
+    // items in rank order
     const int parts = (mode == 2 || mode == 3) && d->resp_parts > 1 ? d->resp_parts : 1;
     carry = 0;
     for (int64_t r0 = 0; r0 < E; r0 += 1024) {
