@@ -702,81 +702,77 @@ __device__ __forceinline__ EventView begin_event(const Desc* __restrict__ d, int
     return ev;
 }
 
-// R only at one line over the contiguous range [a0, a1) of a resident event's
-// plane-sorted hits (the range may cross plane boundaries; each lane holds its
-// own range and line).  One flat loop over the hits, so every lane of a wave
-// runs the same trip count ((a1 - a0) differs by at most one between lanes);
-// the line's position is split anew at each plane boundary.  Per-plane sums
-// are added in plane order.  Reads run one hit past a1 (the tile's spare
-// entries cover it).
+// R only at one line: lane `sub` of a group of L lanes (L a power of two)
+// takes hits sub, sub + L, sub + 2 L, ... of every plane segment of a
+// resident event.  The group's lanes read consecutive hits (other groups read
+// the same ones), the lanes' trip counts per segment differ by at most one,
+// and the line is split once per plane.  Per lane: two running sums per plane
+// (alternate hits of its share) added at the plane's end, planes in order.
+// Read-ahead indices are clamped to the segment's last hit.
 template <int D>
-__device__ __forceinline__ float range_response(const float* __restrict__ s_hits, const int* s_poff,
-                                                const float* s_pz, int P, int a0, int a1, const float* th,
-                                                float nc)
+__device__ __forceinline__ float strided_response(const float* __restrict__ s_hits, const int* s_poff,
+                                                  const float* s_pz, int P, int sub, int L, const float* th,
+                                                  float nc)
 {
-    if (a0 >= a1) return 0.0f;
-    // plane of hit a0: the first p with s_poff[p + 1] > a0
-    int lo = 0, hi = P - 1;
-    while (lo < hi) {
-        const int mid = (lo + hi) >> 1;
-        if (s_poff[mid + 1] <= a0) lo = mid + 1;
-        else hi = mid;
-    }
-    int pl = lo;
-    int next = s_poff[pl + 1];
-    float sx, lx, sy = 0.0f, ly = 0.0f;
-    auto split = [&](int q) {
-        const float z = s_pz[q];
+    float R = 0.0f;
+    for (int p = 0; p < P; ++p) {
+        const int lo = __builtin_amdgcn_readfirstlane(s_poff[p]);
+        const int hi = __builtin_amdgcn_readfirstlane(s_poff[p + 1]);
+        if (lo >= hi) continue;
+        const float z = s_pz[p];
+        float sx, lx, sy = 0.0f, ly = 0.0f;
         if constexpr (D == 2) {
             line_split(th[0], th[2], z, sx, lx);
             line_split(th[1], th[3], z, sy, ly);
         } else {
             line_split(th[0], th[1], z, sx, lx);
         }
-    };
-    split(pl);
-    float R = 0.0f, pe = 0.0f;
-    if constexpr (D == 2) {
-        const float2* h = reinterpret_cast<const float2*>(s_hits);
-        float2 v = h[a0];
-        for (int k = a0; k < a1; ++k) {
-            const float2 nv = h[k + 1];
-            if (k >= next) {
-                R += pe;
-                pe = 0.0f;
-                do { ++pl; next = s_poff[pl + 1]; } while (next <= k);
-                split(pl);
+        const int last = hi - 1;
+        float pa = 0.0f, pb = 0.0f;
+        int k = lo + sub;
+        if constexpr (D == 2) {
+            const float2* h = reinterpret_cast<const float2*>(s_hits);
+            auto term = [&](const float2 v) {
+                const float rx = (v.x - sx) - lx;
+                const float ry = (v.y - sy) - ly;
+                return __builtin_amdgcn_exp2f(__builtin_fmaf(ry, ry, rx * rx) * nc);
+            };
+            float2 a = h[min(k, last)], b = h[min(k + L, last)];
+            for (; k + L < hi; k += 2 * L) {
+                const float2 na = h[min(k + 2 * L, last)], nb = h[min(k + 3 * L, last)];
+                pa += term(a);
+                pb += term(b);
+                a = na;
+                b = nb;
             }
-            const float rx = (v.x - sx) - lx;
-            const float ry = (v.y - sy) - ly;
-            pe += __builtin_amdgcn_exp2f(__builtin_fmaf(ry, ry, rx * rx) * nc);
-            v = nv;
-        }
-    } else {
-        float v = s_hits[a0];
-        for (int k = a0; k < a1; ++k) {
-            const float nv = s_hits[k + 1];
-            if (k >= next) {
-                R += pe;
-                pe = 0.0f;
-                do { ++pl; next = s_poff[pl + 1]; } while (next <= k);
-                split(pl);
+            if (k < hi) pa += term(a);
+        } else {
+            auto term = [&](const float v) {
+                const float r = (v - sx) - lx;
+                return __builtin_amdgcn_exp2f((r * r) * nc);
+            };
+            float a = s_hits[min(k, last)], b = s_hits[min(k + L, last)];
+            for (; k + L < hi; k += 2 * L) {
+                const float na = s_hits[min(k + 2 * L, last)], nb = s_hits[min(k + 3 * L, last)];
+                pa += term(a);
+                pb += term(b);
+                a = na;
+                b = nb;
             }
-            const float r = (v - sx) - lx;
-            pe += __builtin_amdgcn_exp2f((r * r) * nc);
-            v = nv;
+            if (k < hi) pa += term(a);
         }
+        R += pa + pb;
     }
-    return R + pe;
+    return R;
 }
 
 // Backtracking line search of one wave's seeds, wave-local (no work-group
 // barrier), for the split ascent on a resident event.  The QS lanes of a seed
 // hold identical state.  Each round takes the wave's m pending seeds (by their
 // owner lanes), gives each trial point L = 64 / m lanes (rounded down to a
-// power of two), lane `sub` of a point summing R over the sub-th of L
-// contiguous, equal ranges of the event's hits; a butterfly inside the group
-// of L lanes adds the parts in a fixed order.  Every seed either accepts,
+// power of two), lane `sub` of a point summing R over every L-th hit of each
+// plane segment from the segment's sub-th; a butterfly inside the group of L
+// lanes adds the parts in a fixed order.  Every seed either accepts,
 // halves its step or stalls in a round, so at most ls_trials rounds run.
 // Returns the pair evaluations of the wave (counted once, in lane 0).
 template <int D, int QS>
@@ -811,8 +807,7 @@ __device__ __forceinline__ uint64_t wave_line_search(const Desc* __restrict__ d,
             tt[a] = __builtin_fmaf(alpha, p[a], th[a]);
             tq[a] = __shfl(tt[a], src);
         }
-        const int a0 = (int)((int64_t)ev.n * sub / L), a1 = (int)((int64_t)ev.n * (sub + 1) / L);
-        float part = qlive ? range_response<D>(s_hits, s_poff, s_pz, ev.P, a0, a1, tq, nc) : 0.0f;
+        float part = qlive ? strided_response<D>(s_hits, s_poff, s_pz, ev.P, sub, L, tq, nc) : 0.0f;
 #pragma unroll
         for (int w = kWave / 2; w >= 1; w >>= 1)
             if (w < L) part += __shfl_xor(part, w);
