@@ -118,16 +118,35 @@ def _sample_size(run_one, target_s, cap):
     return int(max(1, min(cap, target_s / dt)))
 
 
+def _timed_in_parts(cfg, n_events, run, label, parts=8):
+    """run(batch) over the first n_events events of cfg, as up to `parts`
+    consecutive sub-batches (generated before the clock starts; one progress
+    line per sub-batch); returns the summed run time and the joined tracks
+    (theta, R, track_offsets)."""
+    import numpy as np
+    from paper_1709_08610_amd import events
+    k = -(-n_events // parts)
+    subs = [events.make_batch(cfg, min(k, n_events - s), start=s) for s in range(0, n_events, k)]
+    theta, R, off, dt = [], [], [np.zeros(1, np.int64)], 0.0
+    for i, sb in enumerate(subs):
+        t0 = time.perf_counter()
+        r = run(sb)
+        dt += time.perf_counter() - t0
+        theta.append(r["theta"])
+        R.append(r["R"])
+        off.append(off[-1][-1] + r["track_offsets"][1:])
+        log("%s: %d of %d sub-batches, %.1f s" % (label, i + 1, len(subs), dt))
+    return dt, dict(theta=np.concatenate(theta), R=np.concatenate(R), track_offsets=np.concatenate(off))
+
+
 def cpu_baseline(cfg, P, target_s=12.0, cap=256):
     import oracle
     from paper_1709_08610_amd import events
     threads = os.cpu_count() or 1
     n_events = _sample_size(lambda: oracle.find_tracks(events.make_batch(cfg, 1), P, n_threads=threads),
                             target_s, cap)
-    b = events.make_batch(cfg, n_events)
-    t0 = time.perf_counter()
-    ref = oracle.find_tracks(b, P, n_threads=threads)
-    dt = time.perf_counter() - t0
+    dt, ref = _timed_in_parts(cfg, n_events, lambda b: oracle.find_tracks(b, P, n_threads=threads),
+                              "cpu lattice")
     return dict(value=n_events / dt, unit="events/s", cores=threads, kind="oracle",
                 sample="first %d of %d %s events, FP64 oracle, %dx%d lattice, %.1f s"
                        % (n_events, cfg["n_events"], cfg["name"], P["lattice_n"][0], P["lattice_n"][1], dt)), ref
@@ -160,10 +179,7 @@ def cpu_baseline_learned(cfg, LS, model, target_s=12.0, cap=256):
                                   n_threads=threads)
 
     n_events = _sample_size(lambda: run(events.make_batch(cfg, 1)), target_s, cap)
-    b = events.make_batch(cfg, n_events)
-    t0 = time.perf_counter()
-    ref = run(b)
-    dt = time.perf_counter() - t0
+    dt, ref = _timed_in_parts(cfg, n_events, run, "cpu learned")
     return dict(value=n_events / dt, unit="events/s", cores=threads, kind="oracle",
                 sample="first %d of %d %s events, FP64 oracle proposer (numpy) + FP64 method on its "
                        "seeds, %.1f s" % (n_events, cfg["n_events"], cfg["name"], dt)), ref
