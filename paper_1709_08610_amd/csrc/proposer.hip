@@ -633,13 +633,32 @@ __device__ __forceinline__ int64_t chunked_off(int64_t e, int chunk, int r, int 
     return (((e * 4 + chunk) * kImg + r) * kImg + col) * 32;
 }
 
+// band processed by work-group `wg` in round `i` (G work-groups): the
+// work-groups of XCD x (wg % 8 == x) take a contiguous run of bands
+__device__ __forceinline__ int xcd_band(int wg, int i, int G)
+{
+    if (G % 8 != 0) return i * G + wg;
+    const int per = G / 8;
+    return i * G + (wg % 8) * per + wg / 8;
+}
+
+// Layers 1 and 2, persistent over 4-row bands.  Per band: layer 1 from the
+// staged image rows into the LDS act1 tile, then layer 2's nine taps, each
+// tap's 128 x 64 weight slice double-buffered in LDS with the next slice
+// (the next band's tap 0 after tap 8) loaded during this tap's products.
+// The next band's image rows are loaded into registers while layer 2 runs and
+// stored once the last tap has no use for the staging area; the results go
+// from the accumulators straight to act2.
 __global__ __launch_bounds__(kCvThreads) void k_conv12(const uint16_t* __restrict__ img,
                                                        const uint16_t* __restrict__ w1,
                                                        const float* __restrict__ b1,
                                                        const uint16_t* __restrict__ w2,
-                                                       const float* __restrict__ b2, uint16_t* __restrict__ y)
+                                                       const float* __restrict__ b2, uint16_t* __restrict__ y,
+                                                       int n_bands)
 {
-    constexpr int COUT = 128, NB = 4;
+    constexpr int COUT = 128, NB = 4, BPE = kImg / kCvRows;
+    constexpr int IMGU = kC12ImgRows * kC12ImgCols;              // staged image words (1056)
+    constexpr int IPT = (IMGU + kCvThreads - 1) / kCvThreads;    // per thread (3)
     extern __shared__ float4 s_dyn[];
     uint16_t* s_in = reinterpret_cast<uint16_t*>(s_dyn);
     uint16_t* s_w = s_in + (kCvRows + 2) * kCvCols * kCvPitch;
@@ -647,121 +666,211 @@ __global__ __launch_bounds__(kCvThreads) void k_conv12(const uint16_t* __restric
     const int t = threadIdx.x, lane = t & 63;
     const int wave = __builtin_amdgcn_readfirstlane(t >> 6);
     const int orow = wave >> 1, ocol0 = (wave & 1) * 64;
-    const int64_t e = blockIdx.x / (kImg / kCvRows);
-    const int r0 = (int)(blockIdx.x % (kImg / kCvRows)) * kCvRows;
+    const int G = gridDim.x;
 
-    // image rows r0 - 2 .. r0 + 5, columns -2 .. 129 (both channels in one word)
-    for (int u = t; u < kC12ImgRows * kC12ImgCols; u += kCvThreads) {
-        const int r = r0 - 2 + u / kC12ImgCols, col = u % kC12ImgCols - 2;
-        uint32_t v = 0;
-        if (r >= 0 && r < kImg && col >= 0 && col < kImg)
-            v = *reinterpret_cast<const uint32_t*>(img + ((e * kImg + r) * kImg + col) * 2);
-        s_img[u] = v;
-    }
+    // image rows r0 - 2 .. r0 + 5, columns -2 .. 129 of a band (both channels in one word)
+    uint32_t ireg[IPT];
+    auto load_img = [&](int band) {
+        const int64_t e = band / BPE;
+        const int r0 = (band % BPE) * kCvRows;
+#pragma unroll
+        for (int i = 0; i < IPT; ++i) {
+            const int u = t + i * kCvThreads;
+            const int r = r0 - 2 + u / kC12ImgCols, col = u % kC12ImgCols - 2;
+            uint32_t v = 0;
+            if (u < IMGU && r >= 0 && r < kImg && col >= 0 && col < kImg)
+                v = *reinterpret_cast<const uint32_t*>(img + ((e * kImg + r) * kImg + col) * 2);
+            ireg[i] = v;
+        }
+    };
+    auto store_img = [&]() {
+#pragma unroll
+        for (int i = 0; i < IPT; ++i) {
+            const int u = t + i * kCvThreads;
+            if (u < IMGU) s_img[u] = ireg[i];
+        }
+    };
+
+    int band = xcd_band(blockIdx.x, 0, G);
+    if (band >= n_bands) return;
+    load_img(band);
+    store_img();
+    // weight slices in tap order, the same for every band: slice q of the
+    // work-group's sequence sits in LDS buffer q & 1
     u32x4 wreg[2];
     c12_load_w(w2, 0, t, wreg);
+    c12_store_w(s_w, t, wreg);
+    c12_load_w(w2, 1, t, wreg);
     __syncthreads();
 
-    // layer 1 on the act1 tile (rows r0 - 1 .. r0 + 4, columns -1 .. 128):
-    // D = W1 (64 x 32, K = 18 zero-padded) x X^T (32 x 32 positions) per block
-    // of 32 tile positions; act1 outside the image is the zero padding of layer 2
-    v8bf aw[2][2];
+    int q = 0;  // weight slices consumed so far
+    for (int round = 0; band < n_bands; ++round) {
+        // the bias and layer-1 weight reads below stay inside the loop (hoisted
+        // out of it, their values would hold over a hundred registers for the
+        // whole kernel)
+        int bz = 0;
+        asm volatile("" : "+s"(bz));
+        const float* b1r = b1 + bz;
+        const float* b2r = b2 + bz;
+        const uint16_t* w1r = w1 + bz;
+        const int64_t e = band / BPE;
+        const int r0 = (band % BPE) * kCvRows;
+        const int nband = xcd_band(blockIdx.x, round + 1, G);
+        const bool more = nband < n_bands;
+
+        // layer 1 on the act1 tile (rows r0 - 1 .. r0 + 4, columns -1 .. 128):
+        // D = W1 (64 x 32, K = 18 zero-padded) x X^T (32 x 32 positions) per block
+        // of 32 tile positions; act1 outside the image is the zero padding of layer 2
+        v8bf aw[2][2];
 #pragma unroll
-    for (int cb = 0; cb < 2; ++cb)
+        for (int cb = 0; cb < 2; ++cb)
 #pragma unroll
-        for (int ks = 0; ks < 2; ++ks)
-            aw[cb][ks] = *reinterpret_cast<const v8bf*>(w1 + (cb * 32 + (lane & 31)) * conv_kp(2) + ks * 16 +
-                                                       8 * (lane >> 5));
-    for (int pb = wave; pb < (kC12A1 + 31) / 32; pb += kCvThreads / 64) {
-        const int p = pb * 32 + (lane & 31);
-        const int jr = p / kCvCols, ic = p % kCvCols;  // act1 position = image (r0 - 1 + jr, ic - 1)
-        v8bf xv[2];
+            for (int ks = 0; ks < 2; ++ks)
+                aw[cb][ks] = *reinterpret_cast<const v8bf*>(w1r + (cb * 32 + (lane & 31)) * conv_kp(2) + ks * 16 +
+                                                           8 * (lane >> 5));
+        // the wave's position blocks (pb = wave + 8 i) two at a time: both blocks'
+        // image reads in flight together, then per block the products and
+        // bias + ReLU + BF16 into the tile
+        constexpr int NPB = (kC12A1 + 31) / 32;                       // position blocks (25)
+        constexpr int NW = kCvThreads / 64;
+        constexpr int BPW = (NPB + NW - 1) / NW;                      // per wave, at most 4
+        static_assert(BPW % 2 == 0, "blocks in pairs");
 #pragma unroll
-        for (int ks = 0; ks < 2; ++ks)
+        for (int i0 = 0; i0 < BPW; i0 += 2) {
+            v8bf xv[2][2];
 #pragma unroll
-            for (int q = 0; q < 4; ++q) {
-                const int tap = (ks * 16 + 8 * (lane >> 5)) / 2 + q;
-                uint32_t v = 0;
-                // the tap adds (tap / 3 - 1, tap % 3 - 1); s_img starts at image (r0 - 2, -2)
-                if (tap < 9 && p < kC12A1) v = s_img[(jr + tap / 3) * kC12ImgCols + ic + tap % 3];
-                xv[ks][2 * q] = bits_bf((uint16_t)(v & 0xFFFFu));
-                xv[ks][2 * q + 1] = bits_bf((uint16_t)(v >> 16));
+            for (int i = 0; i < 2; ++i) {
+                const int p = (wave + (i0 + i) * NW) * 32 + (lane & 31);
+                const int jr = p / kCvCols, ic = p % kCvCols;  // act1 position = image (r0 - 1 + jr, ic - 1)
+#pragma unroll
+                for (int ks = 0; ks < 2; ++ks)
+#pragma unroll
+                    for (int qq = 0; qq < 4; ++qq) {
+                        const int tap = (ks * 16 + 8 * (lane >> 5)) / 2 + qq;
+                        uint32_t v = 0;
+                        // the tap adds (tap / 3 - 1, tap % 3 - 1); s_img starts at image (r0 - 2, -2)
+                        if (tap < 9 && p < kC12A1) v = s_img[(jr + tap / 3) * kC12ImgCols + ic + tap % 3];
+                        xv[i][ks][2 * qq] = bits_bf((uint16_t)(v & 0xFFFFu));
+                        xv[i][ks][2 * qq + 1] = bits_bf((uint16_t)(v >> 16));
+                    }
             }
-        const int ar = r0 - 1 + jr, ac = ic - 1;
-        const bool inside = p < kC12A1 && ar >= 0 && ar < kImg && ac >= 0 && ac < kImg;
 #pragma unroll
-        for (int cb = 0; cb < 2; ++cb) {
-            v16f a1;
+            for (int i = 0; i < 2; ++i) {
+                if (wave + (i0 + i) * NW >= NPB) continue;
+                const int p = (wave + (i0 + i) * NW) * 32 + (lane & 31);
+                const int jr = p / kCvCols, ic = p % kCvCols;
+                const int ar = r0 - 1 + jr, ac = ic - 1;
+                const bool inside = p < kC12A1 && ar >= 0 && ar < kImg && ac >= 0 && ac < kImg;
 #pragma unroll
-            for (int r = 0; r < 16; ++r) a1[r] = 0.0f;
+                for (int cb = 0; cb < 2; ++cb) {
+                    v16f a1;
 #pragma unroll
-            for (int ks = 0; ks < 2; ++ks) a1 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(aw[cb][ks], xv[ks], a1, 0, 0, 0);
-            if (p < kC12A1) {
+                    for (int r = 0; r < 16; ++r) a1[r] = 0.0f;
 #pragma unroll
-                for (int g = 0; g < 4; ++g) {
-                    const int co = cb * 32 + 8 * g + 4 * (lane >> 5);
-                    const float4 bb = *reinterpret_cast<const float4*>(b1 + co);
-                    const uint2 v = inside ? pack4_bf16(fmaxf(a1[4 * g] + bb.x, 0.0f), fmaxf(a1[4 * g + 1] + bb.y, 0.0f),
-                                                        fmaxf(a1[4 * g + 2] + bb.z, 0.0f),
-                                                        fmaxf(a1[4 * g + 3] + bb.w, 0.0f))
-                                           : make_uint2(0u, 0u);
-                    *reinterpret_cast<uint2*>(s_in + p * kCvPitch + co) = v;
+                    for (int ks = 0; ks < 2; ++ks)
+                        a1 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(aw[cb][ks], xv[i][ks], a1, 0, 0, 0);
+                    if (p < kC12A1) {
+#pragma unroll
+                        for (int g = 0; g < 4; ++g) {
+                            const int co = cb * 32 + 8 * g + 4 * (lane >> 5);
+                            const float4 bb = *reinterpret_cast<const float4*>(b1r + co);
+                            const uint2 v = inside ? pack4_bf16(fmaxf(a1[4 * g] + bb.x, 0.0f),
+                                                                fmaxf(a1[4 * g + 1] + bb.y, 0.0f),
+                                                                fmaxf(a1[4 * g + 2] + bb.z, 0.0f),
+                                                                fmaxf(a1[4 * g + 3] + bb.w, 0.0f))
+                                                   : make_uint2(0u, 0u);
+                            *reinterpret_cast<uint2*>(s_in + p * kCvPitch + co) = v;
+                        }
+                    }
                 }
             }
         }
-    }
-    c12_store_w(s_w, t, wreg);
-    __syncthreads();
+        if (more) load_img(nband);  // in flight during layer 2
+        __syncthreads();            // the act1 tile is complete
 
-    // layer 2 (64 -> 128) on the act1 tile
-    v16f acc[NB][2];
+        // layer 2 (64 -> 128) on the act1 tile
+        v16f acc[NB][2];
 #pragma unroll
-    for (int i = 0; i < NB; ++i)
+        for (int i = 0; i < NB; ++i)
 #pragma unroll
-        for (int j = 0; j < 2; ++j)
+            for (int j = 0; j < 2; ++j)
 #pragma unroll
-            for (int r = 0; r < 16; ++r) acc[i][j][r] = 0.0f;
-    for (int tap = 0; tap < 9; ++tap) {
-        if (tap < 8) c12_load_w(w2, tap + 1, t, wreg);
-        const int dr = tap / 3 - 1, dc = tap % 3 - 1;
-        const uint16_t* xrow = s_in + ((orow + 1 + dr) * kCvCols + (ocol0 + 1 + dc)) * kCvPitch;
-        const uint16_t* wb = s_w + (tap & 1) * COUT * kCvPitch;
-        // fragments of k-step kk + 1 are read while the products of kk run: the
-        // scheduling barriers keep each read above the products it runs under
-        v8bf xf[2][2], wf[2][NB];
-        auto frags = [&](int kk, int set) __attribute__((always_inline)) {
-            const int ko = kk * 16 + 8 * (lane >> 5);
-#pragma unroll
-            for (int mb = 0; mb < 2; ++mb)
-                xf[set][mb] = *reinterpret_cast<const v8bf*>(xrow + (mb * 32 + (lane & 31)) * kCvPitch + ko);
-#pragma unroll
-            for (int nb = 0; nb < NB; ++nb)
-                wf[set][nb] = *reinterpret_cast<const v8bf*>(wb + (nb * 32 + (lane & 31)) * kCvPitch + ko);
-        };
-        frags(0, 0);
-#pragma unroll
-        for (int kk = 0; kk < 4; ++kk) {
-            if (kk < 3) frags(kk + 1, (kk + 1) & 1);
-            __builtin_amdgcn_sched_barrier(0);
-#pragma unroll
-            for (int nb = 0; nb < NB; ++nb)
+                for (int r = 0; r < 16; ++r) acc[i][j][r] = 0.0f;
+        for (int tap = 0; tap < 9; ++tap, ++q) {
+            const int dr = tap / 3 - 1, dc = tap % 3 - 1;
+            const uint16_t* xrow = s_in + ((orow + 1 + dr) * kCvCols + (ocol0 + 1 + dc)) * kCvPitch;
+            const uint16_t* wb = s_w + (q & 1) * COUT * kCvPitch;
+            // fragments of k-step kk + 1 are read while the products of kk run: the
+            // scheduling barriers keep each read above the products it runs under
+            v8bf xf[2][2], wf[2][NB];
+            auto frags = [&](int kk, int set) __attribute__((always_inline)) {
+                const int ko = kk * 16 + 8 * (lane >> 5);
 #pragma unroll
                 for (int mb = 0; mb < 2; ++mb)
-                    acc[nb][mb] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(wf[kk & 1][nb], xf[kk & 1][mb], acc[nb][mb],
-                                                                         0, 0, 0);
-            __builtin_amdgcn_sched_barrier(0);
+                    xf[set][mb] = *reinterpret_cast<const v8bf*>(xrow + (mb * 32 + (lane & 31)) * kCvPitch + ko);
+#pragma unroll
+                for (int nb = 0; nb < NB; ++nb)
+                    wf[set][nb] = *reinterpret_cast<const v8bf*>(wb + (nb * 32 + (lane & 31)) * kCvPitch + ko);
+            };
+            frags(0, 0);
+#pragma unroll
+            for (int kk = 0; kk < 4; ++kk) {
+                if (kk < 3) frags(kk + 1, (kk + 1) & 1);
+                __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+                for (int nb = 0; nb < NB; ++nb)
+#pragma unroll
+                    for (int mb = 0; mb < 2; ++mb)
+                        acc[nb][mb] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(wf[kk & 1][nb], xf[kk & 1][mb],
+                                                                             acc[nb][mb], 0, 0, 0);
+                __builtin_amdgcn_sched_barrier(0);
+            }
+            // slice q + 1 into the buffer read during slice q - 1 (behind the
+            // last barrier), then slice q + 2 requested
+            if (tap < 8 || more) {
+                c12_store_w(s_w + ((q + 1) & 1) * COUT * kCvPitch, t, wreg);
+                if (tap < 7 || more) c12_load_w(w2, (tap + 2) % 9, t, wreg);
+            }
+            if (tap == 8 && more) store_img();  // the image rows were last read by layer 1
+            __syncthreads();
         }
-        if (tap < 8) c12_store_w(s_w + ((tap + 1) & 1) * COUT * kCvPitch, t, wreg);
-        __syncthreads();
-    }
-    uint16_t* s_out = reinterpret_cast<uint16_t*>(s_dyn) + wave * 64 * (COUT + 8);
-    stage_act<NB, COUT>(s_out, acc, b2, lane);
-    __syncthreads();
-    // this wave's 64 pixels x 128 channels -> four chunks of 64 x 32 channels
-    for (int u = lane; u < 64 * COUT / 8; u += 64) {
-        const int px = u / (COUT / 8), q = u % (COUT / 8);
-        *reinterpret_cast<uint4*>(y + chunked_off(e, q >> 2, r0 + orow, ocol0 + px) + (q & 3) * 8) =
-            *reinterpret_cast<const uint4*>(s_out + px * (COUT + 8) + q * 8);
+
+        // epilogue: act2 = BF16(ReLU(acc + b2)).  In each 32-channel chunk a lane
+        // holds channels 8 g + 4 h .. + 3 (g = 0..3, h = lane / 32) of its pixel;
+        // the half-waves swap two of the four (lane ^ 32), so that each lane
+        // writes two runs of eight channels, 16 j + 8 h .. + 7 (j = 0, 1), as
+        // 16-byte stores
+        const int h = lane >> 5;
+#pragma unroll
+        for (int nb = 0; nb < NB; ++nb) {
+            uint2 pk[2][4];
+#pragma unroll
+            for (int g = 0; g < 4; ++g) {
+                const float4 bb = *reinterpret_cast<const float4*>(b2r + nb * 32 + 8 * g + 4 * h);
+#pragma unroll
+                for (int mb = 0; mb < 2; ++mb) {
+                    const v16f& a = acc[nb][mb];
+                    pk[mb][g] = pack4_bf16(fmaxf(a[4 * g] + bb.x, 0.0f), fmaxf(a[4 * g + 1] + bb.y, 0.0f),
+                                           fmaxf(a[4 * g + 2] + bb.z, 0.0f), fmaxf(a[4 * g + 3] + bb.w, 0.0f));
+                }
+            }
+#pragma unroll
+            for (int mb = 0; mb < 2; ++mb) {
+                // h = 0 keeps g = 0, 2 and sends g = 1, 3; h = 1 the other way round
+                const uint2 s0 = h ? pk[mb][0] : pk[mb][1];
+                const uint2 s1 = h ? pk[mb][2] : pk[mb][3];
+                const uint2 q0 = make_uint2((uint32_t)__shfl_xor((int)s0.x, 32), (uint32_t)__shfl_xor((int)s0.y, 32));
+                const uint2 q1 = make_uint2((uint32_t)__shfl_xor((int)s1.x, 32), (uint32_t)__shfl_xor((int)s1.y, 32));
+                const uint4 run0 = h ? make_uint4(q0.x, q0.y, pk[mb][1].x, pk[mb][1].y)
+                                     : make_uint4(pk[mb][0].x, pk[mb][0].y, q0.x, q0.y);
+                const uint4 run1 = h ? make_uint4(q1.x, q1.y, pk[mb][3].x, pk[mb][3].y)
+                                     : make_uint4(pk[mb][2].x, pk[mb][2].y, q1.x, q1.y);
+                uint16_t* dst = y + chunked_off(e, nb, r0 + orow, ocol0 + mb * 32 + (lane & 31)) + 8 * h;
+                *reinterpret_cast<uint4*>(dst) = run0;
+                *reinterpret_cast<uint4*>(dst + 16) = run1;
+            }
+        }
+        band = nband;
     }
 }
 
@@ -915,15 +1024,6 @@ constexpr int kL3WElems = 9 * 96 * kL3Pitch;                       // one weight
 
 constexpr size_t conv3i_lds() { return (size_t)2 * (kL3InElems + kL3WElems) * 2; }
 
-// band processed by work-group `wg` in round `i` (G work-groups): the
-// work-groups of XCD x (wg % 8 == x) take a contiguous run of bands
-__device__ __forceinline__ int l3_band(int wg, int i, int G)
-{
-    if (G % 8 != 0) return i * G + wg;
-    const int per = G / 8;
-    return i * G + (wg % 8) * per + wg / 8;
-}
-
 __global__ __launch_bounds__(kCvThreads) void k_conv3i(const uint16_t* __restrict__ x, const uint16_t* __restrict__ w,
                                                        const float* __restrict__ bias,
                                                        const uint16_t* __restrict__ w4, float* __restrict__ u_out,
@@ -986,14 +1086,14 @@ __global__ __launch_bounds__(kCvThreads) void k_conv3i(const uint16_t* __restric
         }
     };
 
-    int band = l3_band(blockIdx.x, 0, G);
+    int band = xcd_band(blockIdx.x, 0, G);
     if (band >= n_bands) return;
     load_half(band, 0, 0);
     store_half(0, 0);
     load_half(band, 0, 1);
     store_half(0, 1);
     __syncthreads();
-    for (int round = 0; band < n_bands; band = l3_band(blockIdx.x, ++round, G)) {
+    for (int round = 0; band < n_bands; band = xcd_band(blockIdx.x, ++round, G)) {
         v16f acc[NB][2];
 #pragma unroll
         for (int i = 0; i < NB; ++i)
@@ -1003,7 +1103,7 @@ __global__ __launch_bounds__(kCvThreads) void k_conv3i(const uint16_t* __restric
                 for (int r = 0; r < 16; ++r) acc[i][j][r] = 0.0f;
         for (int c = 0; c < NST; ++c) {
             // the next stage: this band's next channels, or the next band's first
-            const int nband = c + 1 < NST ? band : l3_band(blockIdx.x, round + 1, G);
+            const int nband = c + 1 < NST ? band : xcd_band(blockIdx.x, round + 1, G);
             const bool more = nband < n_bands;
             const int ncs = c + 1 < NST ? c + 1 : 0;
             if (more) load_half(nband, ncs, 0);
@@ -1148,9 +1248,11 @@ void launch_forward(const uint16_t* img, const uint16_t* wbf, const float* w32, 
         hipLaunchKernelGGL(k_conv_head, dim3((unsigned)(E * (kImg / kHeadRows))), dim3(256), 0, st, act3,
                            wbf + L.w_off[3], w32 + L.b_off[3], logits);
     } else {
-        hipLaunchKernelGGL(k_conv12, dim3(gm), dim3(kCvThreads), l12, st, img, wbf + L.w_off[0], w32 + L.b_off[0],
-                           wbf + L.w_off[1], w32 + L.b_off[1], act2);
+        // both persistent, one work-group per CU (their LDS tiles fill it)
         const int n_bands = (int)gm;
+        const unsigned g12 = (unsigned)std::min<int64_t>(n_bands, (int64_t)n_cu);
+        hipLaunchKernelGGL(k_conv12, dim3(g12), dim3(kCvThreads), l12, st, img, wbf + L.w_off[0], w32 + L.b_off[0],
+                           wbf + L.w_off[1], w32 + L.b_off[1], act2, n_bands);
         const unsigned g3 = (unsigned)std::min<int64_t>(n_bands, (int64_t)n_cu);
         hipLaunchKernelGGL(k_conv3i, dim3(g3), dim3(kCvThreads), l3i, st, act2, wbf + L.w_off[2], w32 + L.b_off[2],
                            wbf + L.w_off[3], u, n_bands);
