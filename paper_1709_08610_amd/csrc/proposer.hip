@@ -569,10 +569,12 @@ constexpr int kC12ImgCols = kImg + 4;             // image columns staged
 constexpr int kC12A1 = (kCvRows + 2) * kCvCols;   // act1 positions of the tile (780)
 constexpr int kUPitch = 12;                       // floats per pixel of U (9 used, 16-byte rows)
 
+constexpr int kC12Consts = 64 + 128 + 64 * 32 / 2;  // floats: b1, b2, then W1 (64 x 32 BF16)
+
 constexpr size_t conv12_lds()
 {
     return (size_t)(kCvRows + 2) * kCvCols * kCvPitch * 2 + (size_t)2 * 128 * kCvPitch * 2 +
-           (size_t)kC12ImgRows * kC12ImgCols * 4;
+           (size_t)kC12ImgRows * kC12ImgCols * 4 + (size_t)kC12Consts * 4;
 }
 
 __device__ __forceinline__ __bf16 bits_bf(uint16_t h) { return __builtin_bit_cast(__bf16, h); }
@@ -663,6 +665,12 @@ __global__ __launch_bounds__(kCvThreads) void k_conv12(const uint16_t* __restric
     uint16_t* s_in = reinterpret_cast<uint16_t*>(s_dyn);
     uint16_t* s_w = s_in + (kCvRows + 2) * kCvCols * kCvPitch;
     uint32_t* s_img = reinterpret_cast<uint32_t*>(s_w + 2 * COUT * kCvPitch);
+    // biases and layer 1's weights in LDS for the whole kernel: read there, they
+    // never make a wait on global memory (which would also wait for the act2
+    // stores issued before them)
+    float* s_b1 = reinterpret_cast<float*>(s_img + IMGU);
+    float* s_b2 = s_b1 + 64;
+    uint16_t* s_w1 = reinterpret_cast<uint16_t*>(s_b2 + COUT);
     const int t = threadIdx.x, lane = t & 63;
     const int wave = __builtin_amdgcn_readfirstlane(t >> 6);
     const int orow = wave >> 1, ocol0 = (wave & 1) * 64;
@@ -693,6 +701,9 @@ __global__ __launch_bounds__(kCvThreads) void k_conv12(const uint16_t* __restric
 
     int band = xcd_band(blockIdx.x, 0, G);
     if (band >= n_bands) return;
+    if (t < 64) s_b1[t] = b1[t];
+    if (t < COUT) s_b2[t] = b2[t];
+    if (t < 64 * 32 / 8) *reinterpret_cast<u32x4*>(s_w1 + 8 * t) = *reinterpret_cast<const u32x4*>(w1 + 8 * t);
     load_img(band);
     store_img();
     // weight slices in tap order, the same for every band: slice q of the
@@ -705,18 +716,17 @@ __global__ __launch_bounds__(kCvThreads) void k_conv12(const uint16_t* __restric
 
     int q = 0;  // weight slices consumed so far
     for (int round = 0; band < n_bands; ++round) {
-        // the bias and layer-1 weight reads below stay inside the loop (hoisted
-        // out of it, their values would hold over a hundred registers for the
-        // whole kernel)
-        int bz = 0;
-        asm volatile("" : "+s"(bz));
-        const float* b1r = b1 + bz;
-        const float* b2r = b2 + bz;
-        const uint16_t* w1r = w1 + bz;
         const int64_t e = band / BPE;
         const int r0 = (band % BPE) * kCvRows;
         const int nband = xcd_band(blockIdx.x, round + 1, G);
         const bool more = nband < n_bands;
+        // the weight-slice reads and layer 1's image-read addresses below stay
+        // inside the loop (the same every band, they would otherwise be hoisted
+        // out of it and held in scratch memory across layer 2)
+        int wz = 0;
+        asm volatile("" : "+s"(wz));
+        const uint16_t* w2r = w2 + wz;
+        const uint32_t* s_imgr = s_img + wz;
 
         // layer 1 on the act1 tile (rows r0 - 1 .. r0 + 4, columns -1 .. 128):
         // D = W1 (64 x 32, K = 18 zero-padded) x X^T (32 x 32 positions) per block
@@ -726,8 +736,9 @@ __global__ __launch_bounds__(kCvThreads) void k_conv12(const uint16_t* __restric
         for (int cb = 0; cb < 2; ++cb)
 #pragma unroll
             for (int ks = 0; ks < 2; ++ks)
-                aw[cb][ks] = *reinterpret_cast<const v8bf*>(w1r + (cb * 32 + (lane & 31)) * conv_kp(2) + ks * 16 +
+                aw[cb][ks] = *reinterpret_cast<const v8bf*>(s_w1 + (cb * 32 + (lane & 31)) * conv_kp(2) + ks * 16 +
                                                            8 * (lane >> 5));
+        const int lz = lane + wz;  // = lane, recomputed each band (see above)
         // the wave's position blocks (pb = wave + 8 i) two at a time: both blocks'
         // image reads in flight together, then per block the products and
         // bias + ReLU + BF16 into the tile
@@ -740,16 +751,16 @@ __global__ __launch_bounds__(kCvThreads) void k_conv12(const uint16_t* __restric
             v8bf xv[2][2];
 #pragma unroll
             for (int i = 0; i < 2; ++i) {
-                const int p = (wave + (i0 + i) * NW) * 32 + (lane & 31);
+                const int p = (wave + (i0 + i) * NW) * 32 + (lz & 31);
                 const int jr = p / kCvCols, ic = p % kCvCols;  // act1 position = image (r0 - 1 + jr, ic - 1)
 #pragma unroll
                 for (int ks = 0; ks < 2; ++ks)
 #pragma unroll
                     for (int qq = 0; qq < 4; ++qq) {
-                        const int tap = (ks * 16 + 8 * (lane >> 5)) / 2 + qq;
+                        const int tap = (ks * 16 + 8 * (lz >> 5)) / 2 + qq;
                         uint32_t v = 0;
                         // the tap adds (tap / 3 - 1, tap % 3 - 1); s_img starts at image (r0 - 2, -2)
-                        if (tap < 9 && p < kC12A1) v = s_img[(jr + tap / 3) * kC12ImgCols + ic + tap % 3];
+                        if (tap < 9 && p < kC12A1) v = s_imgr[(jr + tap / 3) * kC12ImgCols + ic + tap % 3];
                         xv[i][ks][2 * qq] = bits_bf((uint16_t)(v & 0xFFFFu));
                         xv[i][ks][2 * qq + 1] = bits_bf((uint16_t)(v >> 16));
                     }
@@ -757,7 +768,7 @@ __global__ __launch_bounds__(kCvThreads) void k_conv12(const uint16_t* __restric
 #pragma unroll
             for (int i = 0; i < 2; ++i) {
                 if (wave + (i0 + i) * NW >= NPB) continue;
-                const int p = (wave + (i0 + i) * NW) * 32 + (lane & 31);
+                const int p = (wave + (i0 + i) * NW) * 32 + (lz & 31);
                 const int jr = p / kCvCols, ic = p % kCvCols;
                 const int ar = r0 - 1 + jr, ac = ic - 1;
                 const bool inside = p < kC12A1 && ar >= 0 && ar < kImg && ac >= 0 && ac < kImg;
@@ -772,8 +783,8 @@ __global__ __launch_bounds__(kCvThreads) void k_conv12(const uint16_t* __restric
                     if (p < kC12A1) {
 #pragma unroll
                         for (int g = 0; g < 4; ++g) {
-                            const int co = cb * 32 + 8 * g + 4 * (lane >> 5);
-                            const float4 bb = *reinterpret_cast<const float4*>(b1r + co);
+                            const int co = cb * 32 + 8 * g + 4 * (lz >> 5);
+                            const float4 bb = *reinterpret_cast<const float4*>(s_b1 + co);
                             const uint2 v = inside ? pack4_bf16(fmaxf(a1[4 * g] + bb.x, 0.0f),
                                                                 fmaxf(a1[4 * g + 1] + bb.y, 0.0f),
                                                                 fmaxf(a1[4 * g + 2] + bb.z, 0.0f),
@@ -829,7 +840,7 @@ __global__ __launch_bounds__(kCvThreads) void k_conv12(const uint16_t* __restric
             // last barrier), then slice q + 2 requested
             if (tap < 8 || more) {
                 c12_store_w(s_w + ((q + 1) & 1) * COUT * kCvPitch, t, wreg);
-                if (tap < 7 || more) c12_load_w(w2, (tap + 2) % 9, t, wreg);
+                if (tap < 7 || more) c12_load_w(w2r, (tap + 2) % 9, t, wreg);
             }
             if (tap == 8 && more) store_img();  // the image rows were last read by layer 1
             __syncthreads();
@@ -846,7 +857,7 @@ __global__ __launch_bounds__(kCvThreads) void k_conv12(const uint16_t* __restric
             uint2 pk[2][4];
 #pragma unroll
             for (int g = 0; g < 4; ++g) {
-                const float4 bb = *reinterpret_cast<const float4*>(b2r + nb * 32 + 8 * g + 4 * h);
+                const float4 bb = *reinterpret_cast<const float4*>(s_b2 + nb * 32 + 8 * g + 4 * h);
 #pragma unroll
                 for (int mb = 0; mb < 2; ++mb) {
                     const v16f& a = acc[nb][mb];
@@ -1013,7 +1024,7 @@ __global__ __launch_bounds__(kCvThreads) void k_conv3(const uint16_t* __restrict
 // pixel, so with the contraction index ordered the same way in W4's fragment,
 // each 8-value half of a run pair is already a B fragment of the product.
 constexpr int kL3Stage = 16;                                       // input channels per stage
-constexpr int kL3Pitch = kL3Stage + 8;                             // LDS elements per pixel / weight row (48 B)
+constexpr int kL3Pitch = kL3Stage;  // LDS elements per pixel / weight row (32 B: a fragment read's 8 lanes hit distinct banks)
 constexpr int kL3Rows = kCvRows + 2;                               // staged input rows (halo 1)
 constexpr int kL3InUnits = kL3Rows * kCvCols * (kL3Stage / 8);     // 16-byte units of a stage's input (1560)
 constexpr int kL3WUnits = 9 * 96 * (kL3Stage / 8);                 // ... of its weights (1728)
@@ -1022,7 +1033,9 @@ constexpr int kL3WPT = (kL3WUnits + kCvThreads - 1) / kCvThreads;
 constexpr int kL3InElems = kL3Rows * kCvCols * kL3Pitch;           // one input buffer
 constexpr int kL3WElems = 9 * 96 * kL3Pitch;                       // one weight buffer
 
-constexpr size_t conv3i_lds() { return (size_t)2 * (kL3InElems + kL3WElems) * 2; }
+constexpr int kL3HeadFrags = 6 * 64;                               // head-weight fragments (nb, ks, lane), 16 B each
+
+constexpr size_t conv3i_lds() { return (size_t)2 * (kL3InElems + kL3WElems) * 2 + (size_t)kL3HeadFrags * 16 + 96 * 4; }
 
 __global__ __launch_bounds__(kCvThreads) void k_conv3i(const uint16_t* __restrict__ x, const uint16_t* __restrict__ w,
                                                        const float* __restrict__ bias,
@@ -1035,6 +1048,9 @@ __global__ __launch_bounds__(kCvThreads) void k_conv3i(const uint16_t* __restric
     extern __shared__ float4 s_dyn[];
     uint16_t* s_in = reinterpret_cast<uint16_t*>(s_dyn);
     uint16_t* s_w = s_in + 2 * kL3InElems;
+    // the head's weight fragments and layer 3's bias, in LDS for the whole kernel
+    v8bf* s_hf = reinterpret_cast<v8bf*>(s_w + 2 * kL3WElems);
+    float* s_b3 = reinterpret_cast<float*>(s_hf + kL3HeadFrags);
     const int t = threadIdx.x, lane = t & 63;
     const int wave = __builtin_amdgcn_readfirstlane(t >> 6);
     const int orow = wave >> 1, ocol0 = (wave & 1) * 64;
@@ -1088,6 +1104,19 @@ __global__ __launch_bounds__(kCvThreads) void k_conv3i(const uint16_t* __restric
 
     int band = xcd_band(blockIdx.x, 0, G);
     if (band >= n_bands) return;
+    if (t < kL3HeadFrags) {
+        // fragment (nb, ks) of lane l: k position 4 g + q is head weight (tap
+        // l % 32, channel nb 32 + 8 (2 ks + g) + 4 (l / 32) + q), zero for taps >= 9
+        const int nb = t / 128, ks = (t / 64) % 2, l = t % 64, n = l & 31, hh = l >> 5;
+        v8bf f;
+#pragma unroll
+        for (int g = 0; g < 2; ++g)
+#pragma unroll
+            for (int q = 0; q < 4; ++q)
+                f[4 * g + q] = n < 9 ? bits_bf(w4[n * COUT + nb * 32 + 8 * (2 * ks + g) + 4 * hh + q]) : bits_bf(0);
+        s_hf[t] = f;
+    }
+    if (t < COUT) s_b3[t] = bias[t];
     load_half(band, 0, 0);
     store_half(0, 0);
     load_half(band, 0, 1);
@@ -1148,8 +1177,8 @@ __global__ __launch_bounds__(kCvThreads) void k_conv3i(const uint16_t* __restric
             __syncthreads();
         }
 
-        // epilogue (registers and global memory only): act3 = BF16(ReLU(acc + b3)),
-        // U^T (9 taps padded to 32 rows x 32 pixels) = W4 x act3^T per pixel block
+        // epilogue: act3 = BF16(ReLU(acc + b3)), U^T (9 taps padded to 32 rows x
+        // 32 pixels) = W4 x act3^T per pixel block; W4's fragments and b3 from LDS
         const int64_t e = band / BPE;
         const int r0 = (band % BPE) * kCvRows;
         const int64_t pix0 = (e * kImg + r0 + orow) * kImg + ocol0;
@@ -1165,17 +1194,16 @@ __global__ __launch_bounds__(kCvThreads) void k_conv3i(const uint16_t* __restric
                 for (int ks = 0; ks < 2; ++ks) {
                     // k position j of this lane's half = result r = 8 ks + j: channel
                     // nb 32 + 8 (r / 4) + 4 h + r % 4 (the same order in W4's fragment)
-                    v8bf xa, wa;
+                    v8bf xa;
+                    const v8bf wa = s_hf[(nb * 2 + ks) * 64 + lane];
 #pragma unroll
                     for (int g = 0; g < 2; ++g) {
                         const int ch = nb * 32 + 8 * (2 * ks + g) + 4 * h;
-                        const float4 bb = *reinterpret_cast<const float4*>(bias + ch);
+                        const float4 bb = *reinterpret_cast<const float4*>(s_b3 + ch);
                         const float bv[4] = {bb.x, bb.y, bb.z, bb.w};
 #pragma unroll
-                        for (int q = 0; q < 4; ++q) {
+                        for (int q = 0; q < 4; ++q)
                             xa[4 * g + q] = bits_bf(f2bf(fmaxf(acc[nb][mb][8 * ks + 4 * g + q] + bv[q], 0.0f)));
-                            wa[4 * g + q] = n < 9 ? bits_bf(w4[n * COUT + ch + q]) : bits_bf(0);
-                        }
                     }
                     au = __builtin_amdgcn_mfma_f32_32x32x16_bf16(wa, xa, au, 0, 0, 0);
                 }
