@@ -1057,10 +1057,10 @@ __global__ __launch_bounds__(kCvThreads) void k_conv3i(const uint16_t* __restric
     const int G = gridDim.x;
 
     // a stage is moved in two halves (units i = 2 k, 2 k + 1 of each thread's
-    // input and weight units), so that at most half of it sits in registers
+    // input and weight units), each through its own set of registers
     static_assert(kL3InPT == 4 && kL3WPT == 4, "two halves of two units each");
-    u32x4 pin[2], pw[2];
-    auto load_half = [&](int band, int c, int k) {
+    u32x4 ra_in[2], ra_w[2], rb_in[2], rb_w[2];
+    auto load_half = [&](int band, int c, int k, u32x4 (&pin)[2], u32x4 (&pw)[2]) {
         const int64_t e = band / BPE;
         const int r0 = (band % BPE) * kCvRows;
 #pragma unroll
@@ -1087,7 +1087,7 @@ __global__ __launch_bounds__(kCvThreads) void k_conv3i(const uint16_t* __restric
             pw[i] = v;
         }
     };
-    auto store_half = [&](int buf, int k) {
+    auto store_half = [&](int buf, int k, const u32x4 (&pin)[2], const u32x4 (&pw)[2]) {
 #pragma unroll
         for (int i = 0; i < 2; ++i) {
             const int u = t + (2 * k + i) * kCvThreads;
@@ -1117,10 +1117,12 @@ __global__ __launch_bounds__(kCvThreads) void k_conv3i(const uint16_t* __restric
         s_hf[t] = f;
     }
     if (t < COUT) s_b3[t] = bias[t];
-    load_half(band, 0, 0);
-    store_half(0, 0);
-    load_half(band, 0, 1);
-    store_half(0, 1);
+    load_half(band, 0, 0, ra_in, ra_w);
+    store_half(0, 0, ra_in, ra_w);
+    load_half(band, 0, 1, rb_in, rb_w);
+    store_half(0, 1, rb_in, rb_w);
+    load_half(band, 1, 0, ra_in, ra_w);  // stage 1 in flight
+    load_half(band, 1, 1, rb_in, rb_w);
     __syncthreads();
     for (int round = 0; band < n_bands; band = xcd_band(blockIdx.x, ++round, G)) {
         v16f acc[NB][2];
@@ -1130,13 +1132,19 @@ __global__ __launch_bounds__(kCvThreads) void k_conv3i(const uint16_t* __restric
             for (int j = 0; j < 2; ++j)
 #pragma unroll
                 for (int r = 0; r < 16; ++r) acc[i][j][r] = 0.0f;
+        const int nxt = xcd_band(blockIdx.x, round + 1, G);
+#pragma unroll
         for (int c = 0; c < NST; ++c) {
-            // the next stage: this band's next channels, or the next band's first
-            const int nband = c + 1 < NST ? band : xcd_band(blockIdx.x, round + 1, G);
-            const bool more = nband < n_bands;
-            const int ncs = c + 1 < NST ? c + 1 : 0;
-            if (more) load_half(nband, ncs, 0);
-            __builtin_amdgcn_sched_barrier(0);  // the next stage's loads go out first
+            // stage s + 1 (in registers since stage s - 1) goes into the buffer not
+            // read in this stage, and stage s + 2 is requested: each half of a stage
+            // has a whole stage of products to arrive.  Stages run on into the
+            // next band's first ones.
+            const int b1 = c + 1 < NST ? band : nxt;
+            const int b2 = c + 2 < NST ? band : nxt, c2 = (c + 2) % NST;
+            const bool m1 = b1 < n_bands, m2 = b2 < n_bands;
+            if (m1) store_half((c + 1) & 1, 0, ra_in, ra_w);
+            if (m2) load_half(b2, c2, 0, ra_in, ra_w);
+            __builtin_amdgcn_sched_barrier(0);  // the loads go out first
             const uint16_t* ti = s_in + (c & 1) * kL3InElems;
             const uint16_t* tw = s_w + (c & 1) * kL3WElems;
             v8bf xf[2][2], wf[2][NB];
@@ -1154,11 +1162,9 @@ __global__ __launch_bounds__(kCvThreads) void k_conv3i(const uint16_t* __restric
             frags(0, 0);
 #pragma unroll
             for (int tap = 0; tap < 9; ++tap) {
-                if (tap == 4 && more) {
-                    // first half of the next stage in (its buffer is not read in
-                    // this stage), second half requested
-                    store_half((c + 1) & 1, 0);
-                    load_half(nband, ncs, 1);
+                if (tap == 4) {
+                    if (m1) store_half((c + 1) & 1, 1, rb_in, rb_w);
+                    if (m2) load_half(b2, c2, 1, rb_in, rb_w);
                 }
                 if (tap < 8) frags(tap + 1, (tap + 1) & 1);
                 // keep the next tap's reads above this tap's products (the
@@ -1172,8 +1178,7 @@ __global__ __launch_bounds__(kCvThreads) void k_conv3i(const uint16_t* __restric
                                                                              acc[nb][mb], 0, 0, 0);
                 __builtin_amdgcn_sched_barrier(0);
             }
-            // the buffer being filled was last read in the previous stage, before the barrier below it
-            if (more) store_half((c + 1) & 1, 1);
+            // the buffer filled here was last read in the previous stage, before the barrier below it
             __syncthreads();
         }
 
