@@ -29,6 +29,8 @@
 // the plane's z in a scalar register.  The FP64 polish evaluates at an FP64
 // theta split into two floats (hi + lo); the low words join l, so the
 // gradient it solves with belongs to the FP64 point.
+#include <type_traits>
+
 #include "rt_internal.h"
 
 namespace rt {
@@ -36,10 +38,12 @@ namespace rt {
 constexpr float kLog2e = 1.44269504088896340736f;
 // Lanes per seed of the split ascent (one candidate per lane, Newton steps):
 // each of a seed's lanes walks every kSplitLanes-th hit of a plane segment.
+// Work items with few seeds run with up to kMaxSplitLanes lanes per seed.
 constexpr int kSplitLanes = 4;
+constexpr int kMaxSplitLanes = 16;
 // spare hit entries after the LDS tile: the meas_dim-2 hit loops read ahead
 // of the segment they walk, up to index tile_hits + 2 * lanes per seed - 1
-constexpr int kTilePad = 2 * kSplitLanes;
+constexpr int kTilePad = 2 * kMaxSplitLanes;
 
 template <int D>
 struct Acc;  // number of accumulators
@@ -861,7 +865,6 @@ __global__ __launch_bounds__(kBlock) void k_ascent(const Desc* __restrict__ d, i
     static_assert(QS == 1 || (C == 1 && U == 0), "split: one candidate per lane, Newton steps");
     constexpr int NP = 2 * D;
     constexpr int NA = Acc<D>::N;
-    constexpr int SL = kWave / QS;  // seeds per wave and candidate slot
     // dynamic LDS follows the static arrays: declared float4 so it starts 16-byte
     // aligned (the (x, y) hit pairs are read with 8-byte LDS loads)
     extern __shared__ float4 s_dyn[];
@@ -877,8 +880,6 @@ __global__ __launch_bounds__(kBlock) void k_ascent(const Desc* __restrict__ d, i
     if ((int)threadIdx.x < kMaxPlanes) s_pz[threadIdx.x] = d->plane_z[threadIdx.x];
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);  // scalar: same in every lane
     const int lane = threadIdx.x & (kWave - 1);
-    const int slane = lane & (SL - 1);   // the lane's seed within the wave's slot
-    const bool owner = lane < SL;  // queues line-search points, writes the results
     const int64_t n_items = d->cnt->n_items;
     const int n_steps = d->n_sigma + d->n_final_steps;
     const float zr = d->z_ref;
@@ -913,414 +914,431 @@ __global__ __launch_bounds__(kBlock) void k_ascent(const Desc* __restrict__ d, i
         const EventView ev = begin_event(d, e, s_hits, s_poff, tile_cap);
         const int64_t sbase = d->seed_off[e];
         const int ns = (int)(d->seed_off[e + 1] - sbase);
+        // lanes per seed for this item: a part-filled item spreads its seeds over
+        // all four waves with more lanes each (every pass then walks the hits in
+        // fewer strides), so that it costs less than a full one
+        auto item_body = [&](auto qtag) {
+            constexpr int QS2 = decltype(qtag)::value;
+            constexpr int SL2 = kWave / QS2;  // seeds per wave and candidate slot
+            const int slane2 = lane & (SL2 - 1);  // the lane's seed within the wave's slot
+            const bool owner2 = lane < SL2;       // queues line-search points, writes the results
 
-        // seeds
-        float th[C][NP];
-        bool active[C];
-        int flags[C], nre[C];
-        // BFGS state per candidate (scaled coordinates): inverse-Hessian model
-        // of -R, the previous step's scaled gradient and its accepted step
-        constexpr int CQ = U == 2 ? C : 1;
-        float Bq[CQ][NP][NP], bq[CQ][NP], sq[CQ][NP];
-        float sig_prev = 0.0f;
-#pragma unroll
-        for (int j = 0; j < C; ++j) {
-            const int sj = it.y + (wave * C + j) * SL + slane;
-            active[j] = sj < ns;
-            flags[j] = 0;
-            nre[j] = 0;
-            const int sjc = active[j] ? sj : 0;
-            if (d->seed_mode == RETINA_SEED_EXPLICIT) {
-                const double* s = d->in_seeds + (sbase + sjc) * NP;
-                bool finite = true;
-#pragma unroll
-                for (int a = 0; a < NP; ++a) {
-                    th[j][a] = active[j] ? (float)s[a] : 0.0f;
-                    finite = finite && isfinite(th[j][a]);
-                }
-                if (!finite) {
-                    // device-memory seeds are validated here: the call fails
-                    // (no output is written) and the seed stays out of the passes
-                    atomicOr(&d->cnt->err, kErrSeedVal);
-                    active[j] = false;
-#pragma unroll
-                    for (int a = 0; a < NP; ++a) th[j][a] = 0.0f;
-                }
-            } else {
-                lattice_point<D>(d, sjc, th[j]);
-            }
-        }
-
-        // waves without a live seed skip the arithmetic of every pass
-        bool any_active = false;
-#pragma unroll
-        for (int j = 0; j < C; ++j) any_active = any_active || active[j];
-        const bool wave_work = __builtin_amdgcn_readfirstlane((int)(__any(any_active) != 0)) != 0;
-        uint64_t ls_pairs = 0;  // executed line-search pair evaluations (same in every thread)
-        uint64_t wls_pairs = 0; // ... of the wave-local searches (this wave's, in every lane)
-        for (int s = 0; s < n_steps; ++s) {
-            const float sig = s < d->n_sigma ? d->sigma[s] : d->sigma_final;
-            const float nc = -kLog2e / (sig * sig);
-            Cands<C> c;
-#pragma unroll
-            for (int j = 0; j < C; ++j) set_cand<D, C>(c, j, th[j]);
-            float acc[C][NA];
-            event_pass<D, C, true, false, PR, QS>(d, s_hits, s_poff, ev, c, zero_c, nc, acc, wave_work, active);
-            float p[C][NP], Rc[C], gp[C], alpha[C];
-            bool pend[C];
-            int trial[C];
-            const bool slope_only = D == 2 && s < d->n_slope_steps;
-#pragma unroll
+            // seeds
+            float th[C][NP];
+            bool active[C];
+            int flags[C], nre[C];
+            // BFGS state per candidate (scaled coordinates): inverse-Hessian model
+            // of -R, the previous step's scaled gradient and its accepted step
+            constexpr int CQ = U == 2 ? C : 1;
+            float Bq[CQ][NP][NP], bq[CQ][NP], sq[CQ][NP];
+            float sig_prev = 0.0f;
+    #pragma unroll
             for (int j = 0; j < C; ++j) {
-                float g[NP], H[NP][NP];
-                grad_hess<D, float>(acc[j], sig, g, H);
-                float pn;
-                bool neg;
-                if constexpr (U != 0) {
-                    // scaled gradient (offset components zero while they are held)
-                    float b[NP], q[NP], bb = 0.0f;
-#pragma unroll
-                    for (int a = 0; a < NP; ++a) b[a] = (D == 2 && slope_only && a < 2) ? 0.0f : g[a] / ds[a];
-#pragma unroll
-                    for (int a = 0; a < NP; ++a) bb = __builtin_fmaf(b[a], b[a], bb);
-                    const float bn = sqrtf(bb);
-                    if constexpr (U == 1) {
-#pragma unroll
-                        for (int a = 0; a < NP; ++a) q[a] = bn > 0.0f ? sig * (b[a] / bn) : 0.0f;
-                    } else {
-                        float (&B)[NP][NP] = Bq[U == 2 ? j : 0];
-                        if (s == 0 || sig != sig_prev) {
-                            // (re)start: the normalised gradient step of one bandwidth
-#pragma unroll
-                            for (int a = 0; a < NP; ++a)
-#pragma unroll
-                                for (int c2 = 0; c2 < NP; ++c2) B[a][c2] = a == c2 ? (bn > 0.0f ? sig / bn : 0.0f) : 0.0f;
+                const int sj = it.y + (wave * C + j) * SL2 + slane2;
+                active[j] = sj < ns;
+                flags[j] = 0;
+                nre[j] = 0;
+                const int sjc = active[j] ? sj : 0;
+                if (d->seed_mode == RETINA_SEED_EXPLICIT) {
+                    const double* s = d->in_seeds + (sbase + sjc) * NP;
+                    bool finite = true;
+    #pragma unroll
+                    for (int a = 0; a < NP; ++a) {
+                        th[j][a] = active[j] ? (float)s[a] : 0.0f;
+                        finite = finite && isfinite(th[j][a]);
+                    }
+                    if (!finite) {
+                        // device-memory seeds are validated here: the call fails
+                        // (no output is written) and the seed stays out of the passes
+                        atomicOr(&d->cnt->err, kErrSeedVal);
+                        active[j] = false;
+    #pragma unroll
+                        for (int a = 0; a < NP; ++a) th[j][a] = 0.0f;
+                    }
+                } else {
+                    lattice_point<D>(d, sjc, th[j]);
+                }
+            }
+
+            // waves without a live seed skip the arithmetic of every pass
+            bool any_active = false;
+    #pragma unroll
+            for (int j = 0; j < C; ++j) any_active = any_active || active[j];
+            const bool wave_work = __builtin_amdgcn_readfirstlane((int)(__any(any_active) != 0)) != 0;
+            uint64_t ls_pairs = 0;  // executed line-search pair evaluations (same in every thread)
+            uint64_t wls_pairs = 0; // ... of the wave-local searches (this wave's, in every lane)
+            for (int s = 0; s < n_steps; ++s) {
+                const float sig = s < d->n_sigma ? d->sigma[s] : d->sigma_final;
+                const float nc = -kLog2e / (sig * sig);
+                Cands<C> c;
+    #pragma unroll
+                for (int j = 0; j < C; ++j) set_cand<D, C>(c, j, th[j]);
+                float acc[C][NA];
+                event_pass<D, C, true, false, PR, QS2>(d, s_hits, s_poff, ev, c, zero_c, nc, acc, wave_work, active);
+                float p[C][NP], Rc[C], gp[C], alpha[C];
+                bool pend[C];
+                int trial[C];
+                const bool slope_only = D == 2 && s < d->n_slope_steps;
+    #pragma unroll
+                for (int j = 0; j < C; ++j) {
+                    float g[NP], H[NP][NP];
+                    grad_hess<D, float>(acc[j], sig, g, H);
+                    float pn;
+                    bool neg;
+                    if constexpr (U != 0) {
+                        // scaled gradient (offset components zero while they are held)
+                        float b[NP], q[NP], bb = 0.0f;
+    #pragma unroll
+                        for (int a = 0; a < NP; ++a) b[a] = (D == 2 && slope_only && a < 2) ? 0.0f : g[a] / ds[a];
+    #pragma unroll
+                        for (int a = 0; a < NP; ++a) bb = __builtin_fmaf(b[a], b[a], bb);
+                        const float bn = sqrtf(bb);
+                        if constexpr (U == 1) {
+    #pragma unroll
+                            for (int a = 0; a < NP; ++a) q[a] = bn > 0.0f ? sig * (b[a] / bn) : 0.0f;
                         } else {
-                            // BFGS with y = -(b - b_prev) (gradient change of -R) and
-                            // the accepted step, in the expanded form
-                            // B + ((s.y + y.B.y) / (s.y)^2) s s^T - (B y s^T + s y^T B) / s.y
-                            float y[NP], sy = 0.0f;
-#pragma unroll
-                            for (int a = 0; a < NP; ++a) {
-                                y[a] = bq[U == 2 ? j : 0][a] - b[a];
-                                sy = __builtin_fmaf(sq[U == 2 ? j : 0][a], y[a], sy);
-                            }
-                            if (sy > 0.0f) {
-                                float By[NP], yBy = 0.0f;
-#pragma unroll
-                                for (int a = 0; a < NP; ++a) {
-                                    float v = 0.0f;
-#pragma unroll
-                                    for (int c2 = 0; c2 < NP; ++c2) v = __builtin_fmaf(B[a][c2], y[c2], v);
-                                    By[a] = v;
-                                    yBy = __builtin_fmaf(y[a], v, yBy);
-                                }
-                                const float inv = 1.0f / sy;
-                                const float cs = (sy + yBy) * inv * inv;
-                                const float* sv = sq[U == 2 ? j : 0];
-#pragma unroll
+                            float (&B)[NP][NP] = Bq[U == 2 ? j : 0];
+                            if (s == 0 || sig != sig_prev) {
+                                // (re)start: the normalised gradient step of one bandwidth
+    #pragma unroll
                                 for (int a = 0; a < NP; ++a)
-#pragma unroll
-                                    for (int c2 = 0; c2 < NP; ++c2)
-                                        B[a][c2] += cs * sv[a] * sv[c2] - (By[a] * sv[c2] + sv[a] * By[c2]) * inv;
+    #pragma unroll
+                                    for (int c2 = 0; c2 < NP; ++c2) B[a][c2] = a == c2 ? (bn > 0.0f ? sig / bn : 0.0f) : 0.0f;
+                            } else {
+                                // BFGS with y = -(b - b_prev) (gradient change of -R) and
+                                // the accepted step, in the expanded form
+                                // B + ((s.y + y.B.y) / (s.y)^2) s s^T - (B y s^T + s y^T B) / s.y
+                                float y[NP], sy = 0.0f;
+    #pragma unroll
+                                for (int a = 0; a < NP; ++a) {
+                                    y[a] = bq[U == 2 ? j : 0][a] - b[a];
+                                    sy = __builtin_fmaf(sq[U == 2 ? j : 0][a], y[a], sy);
+                                }
+                                if (sy > 0.0f) {
+                                    float By[NP], yBy = 0.0f;
+    #pragma unroll
+                                    for (int a = 0; a < NP; ++a) {
+                                        float v = 0.0f;
+    #pragma unroll
+                                        for (int c2 = 0; c2 < NP; ++c2) v = __builtin_fmaf(B[a][c2], y[c2], v);
+                                        By[a] = v;
+                                        yBy = __builtin_fmaf(y[a], v, yBy);
+                                    }
+                                    const float inv = 1.0f / sy;
+                                    const float cs = (sy + yBy) * inv * inv;
+                                    const float* sv = sq[U == 2 ? j : 0];
+    #pragma unroll
+                                    for (int a = 0; a < NP; ++a)
+    #pragma unroll
+                                        for (int c2 = 0; c2 < NP; ++c2)
+                                            B[a][c2] += cs * sv[a] * sv[c2] - (By[a] * sv[c2] + sv[a] * By[c2]) * inv;
+                                }
+                            }
+    #pragma unroll
+                            for (int a = 0; a < NP; ++a) {
+                                float v = 0.0f;
+    #pragma unroll
+                                for (int c2 = 0; c2 < NP; ++c2) v = __builtin_fmaf(B[a][c2], b[c2], v);
+                                q[a] = v;
+                                bq[U == 2 ? j : 0][a] = b[a];
+                                sq[U == 2 ? j : 0][a] = 0.0f;
                             }
                         }
-#pragma unroll
-                        for (int a = 0; a < NP; ++a) {
-                            float v = 0.0f;
-#pragma unroll
-                            for (int c2 = 0; c2 < NP; ++c2) v = __builtin_fmaf(B[a][c2], b[c2], v);
-                            q[a] = v;
-                            bq[U == 2 ? j : 0][a] = b[a];
-                            sq[U == 2 ? j : 0][a] = 0.0f;
+                        float qq = 0.0f;
+    #pragma unroll
+                        for (int a = 0; a < NP; ++a) qq = __builtin_fmaf(q[a], q[a], qq);
+                        pn = sqrtf(qq);
+                        const float lim = d->step_cap * sig;
+                        if (pn > lim) {
+                            const float sc = lim / pn;
+    #pragma unroll
+                            for (int a = 0; a < NP; ++a) q[a] *= sc;
+                            pn = lim;
                         }
-                    }
-                    float qq = 0.0f;
-#pragma unroll
-                    for (int a = 0; a < NP; ++a) qq = __builtin_fmaf(q[a], q[a], qq);
-                    pn = sqrtf(qq);
-                    const float lim = d->step_cap * sig;
-                    if (pn > lim) {
-                        const float sc = lim / pn;
-#pragma unroll
-                        for (int a = 0; a < NP; ++a) q[a] *= sc;
-                        pn = lim;
-                    }
-#pragma unroll
-                    for (int a = 0; a < NP; ++a) p[j][a] = q[a] / ds[a];
-                    neg = false;
-                } else if constexpr (D == 2) {
-                    if (slope_only) {
-                        const float gs[2] = {g[2], g[3]};
-                        const float Hs[2][2] = {{H[2][2], H[2][3]}, {H[3][2], H[3][3]}};
-                        const float dss[2] = {ds[2], ds[3]};
-                        float ps[2];
-                        newton_cg<2>(gs, Hs, dss, sig, d->step_cap, ps, pn, neg);
-                        p[j][0] = 0.0f; p[j][1] = 0.0f; p[j][2] = ps[0]; p[j][3] = ps[1];
+    #pragma unroll
+                        for (int a = 0; a < NP; ++a) p[j][a] = q[a] / ds[a];
+                        neg = false;
+                    } else if constexpr (D == 2) {
+                        if (slope_only) {
+                            const float gs[2] = {g[2], g[3]};
+                            const float Hs[2][2] = {{H[2][2], H[2][3]}, {H[3][2], H[3][3]}};
+                            const float dss[2] = {ds[2], ds[3]};
+                            float ps[2];
+                            newton_cg<2>(gs, Hs, dss, sig, d->step_cap, ps, pn, neg);
+                            p[j][0] = 0.0f; p[j][1] = 0.0f; p[j][2] = ps[0]; p[j][3] = ps[1];
+                        } else {
+                            newton_cg<NP>(g, H, ds, sig, d->step_cap, p[j], pn, neg);
+                        }
                     } else {
                         newton_cg<NP>(g, H, ds, sig, d->step_cap, p[j], pn, neg);
                     }
-                } else {
-                    newton_cg<NP>(g, H, ds, sig, d->step_cap, p[j], pn, neg);
-                }
-                if (neg) flags[j] |= RETINA_NEGCURV;
-                Rc[j] = acc[j][0];
-                float dot = 0.0f;
-#pragma unroll
-                for (int a = 0; a < NP; ++a) dot = __builtin_fmaf(g[a], p[j][a], dot);
-                gp[j] = dot;
-                alpha[j] = 1.0f;
-                trial[j] = 0;
-                if (!active[j]) {
-                    pend[j] = false;  // an empty slot never searches
-                } else if (!neg && pn <= d->small_step * sig) {
-#pragma unroll
-                    for (int a = 0; a < NP; ++a) th[j][a] += p[j][a];
-                    if constexpr (U == 2) {
-#pragma unroll
-                        for (int a = 0; a < NP; ++a) sq[j][a] = ds[a] * p[j][a];
-                    }
-                    pend[j] = false;
-                } else {
-                    pend[j] = true;
-                }
-            }
-            sig_prev = sig;
-            if constexpr (QS > 1 && !PR) {
-                if (ev.resident) {
-                    // every hit in LDS: each wave searches for its own seeds
-                    wls_pairs += wave_line_search<D, QS>(d, s_hits, s_poff, s_pz, ev, th[0], p[0], Rc[0], gp[0],
-                                                         pend[0], nre[0], flags[0], nc);
-                    continue;
-                }
-            }
-            // Backtracking line search.  Each round gathers the work-group's
-            // pending trial points into an LDS list and evaluates R only for
-            // those.  One candidate per lane and up to 64 pending points: the
-            // 256 threads split into 256 / P parts per point (P = the count
-            // rounded up to a power of two), each summing R over every
-            // (256 / P)-th hit of each plane segment.  Otherwise: rounds of
-            // 64 * C points per wave, every wave over its quarter of each plane
-            // segment (C candidates per lane share each hit read; measured
-            // faster for C = 2 even when few points are pending).  Partial sums
-            // are added in a fixed order.  The list is in (slot j, wave, lane)
-            // order, so which points share a wave (and, with pruning, its hit
-            // window) is the same on every run.
-            for (;;) {
-                float tt[C][NP];
-                int slot[C], rank[C];
-                uint64_t bal[C];
-#pragma unroll
-                for (int j = 0; j < C; ++j) {
-                    if (pend[j]) {
-#pragma unroll
-                        for (int a = 0; a < NP; ++a) tt[j][a] = __builtin_fmaf(alpha[j], p[j][a], th[j][a]);
-                    }
-                    bal[j] = __ballot(pend[j] && owner);
-                    rank[j] = __popcll(bal[j] & ((1ull << lane) - 1ull));
-                }
-                __syncthreads();  // the previous round is done with the list
-                if (lane == 0) {
-#pragma unroll
-                    for (int j = 0; j < C; ++j) s_wcnt[j * kNW + wave] = __popcll(bal[j]);
-                }
-                __syncthreads();
-                int npend = 0, base[C];
-#pragma unroll
-                for (int j = 0; j < C; ++j) {
-                    base[j] = 0;
-                    for (int w = 0; w < kNW; ++w) {
-                        if (w == wave) base[j] = npend;
-                        npend += s_wcnt[j * kNW + w];
-                    }
-                }
-#pragma unroll
-                for (int j = 0; j < C; ++j) {
-                    slot[j] = pend[j] && owner ? base[j] + rank[j] : -1;
-                    if (slot[j] >= 0) {
-#pragma unroll
-                        for (int a = 0; a < NP; ++a) s_lth[slot[j]][a] = tt[j][a];
-                    }
-                }
-                if constexpr (QS > 1) {
-                    // the other lanes of a seed read its point
-#pragma unroll
-                    for (int j = 0; j < C; ++j) slot[j] = __shfl(slot[j], slane);
-                }
-                __syncthreads();
-                npend = __builtin_amdgcn_readfirstlane(npend);
-                if (npend == 0) break;
-                if (C == 1 && npend <= kWave) {
-                    // npend points, parts = 256 / npend threads on each (the last
-                    // 256 - parts * npend threads duplicate a part and are not read)
-                    const int per = npend;
-                    const int parts = kBlock / per;
-                    const int used = parts * per;
-                    const bool in = (int)threadIdx.x < used;
-                    const int pt = in ? (int)threadIdx.x % per : 0, part = in ? (int)threadIdx.x / per : 0;
-                    float lt[NP];
-#pragma unroll
-                    for (int a = 0; a < NP; ++a) lt[a] = s_lth[pt][a];
-                    s_red[threadIdx.x] = event_pass_split<D, PR>(d, s_hits, s_poff, ev, lt, nc, part, parts, in);
-                    __syncthreads();  // every thread holds its point and partial
-                    if ((int)threadIdx.x < per) {
-                        float Rt = 0.0f;
-                        for (int q = 0; q < parts; ++q) Rt += s_red[q * per + threadIdx.x];
-                        s_lth[threadIdx.x][0] = Rt;
-                    }
-                    ls_pairs += (uint64_t)per * (uint64_t)ev.n;
-                } else {
-                    const int per_round = kWave * C;
-                    const int rounds = (npend + per_round - 1) / per_round;
-                    for (int r = 0; r < rounds; ++r) {
-                        Cands<C> cc;
-                        bool live[C];
-                        int ent[C];
-#pragma unroll
-                        for (int j = 0; j < C; ++j) {
-                            ent[j] = r * per_round + j * kWave + lane;
-                            live[j] = ent[j] < npend;
-                            float lt[NP];
-#pragma unroll
-                            for (int a = 0; a < NP; ++a) lt[a] = live[j] ? s_lth[ent[j]][a] : 0.0f;
-                            set_cand<D, C>(cc, j, lt);
+                    if (neg) flags[j] |= RETINA_NEGCURV;
+                    Rc[j] = acc[j][0];
+                    float dot = 0.0f;
+    #pragma unroll
+                    for (int a = 0; a < NP; ++a) dot = __builtin_fmaf(g[a], p[j][a], dot);
+                    gp[j] = dot;
+                    alpha[j] = 1.0f;
+                    trial[j] = 0;
+                    if (!active[j]) {
+                        pend[j] = false;  // an empty slot never searches
+                    } else if (!neg && pn <= d->small_step * sig) {
+    #pragma unroll
+                        for (int a = 0; a < NP; ++a) th[j][a] += p[j][a];
+                        if constexpr (U == 2) {
+    #pragma unroll
+                            for (int a = 0; a < NP; ++a) sq[j][a] = ds[a] * p[j][a];
                         }
-                        __syncthreads();  // all waves hold the round's points before partials overwrite them
-                        float racc[C][NA];
-                        event_pass_part<D, C, PR>(d, s_hits, s_poff, ev, cc, nc, wave, kBlock / kWave, racc, live);
-#pragma unroll
-                        for (int j = 0; j < C; ++j)
-                            if (live[j]) s_lth[ent[j]][wave] = racc[j][0];
+                        pend[j] = false;
+                    } else {
+                        pend[j] = true;
+                    }
+                }
+                sig_prev = sig;
+                if constexpr (QS2 > 1 && !PR) {
+                    if (ev.resident) {
+                        // every hit in LDS: each wave searches for its own seeds
+                        wls_pairs += wave_line_search<D, QS2>(d, s_hits, s_poff, s_pz, ev, th[0], p[0], Rc[0], gp[0],
+                                                             pend[0], nre[0], flags[0], nc);
+                        continue;
+                    }
+                }
+                // Backtracking line search.  Each round gathers the work-group's
+                // pending trial points into an LDS list and evaluates R only for
+                // those.  One candidate per lane and up to 64 pending points: the
+                // 256 threads split into 256 / P parts per point (P = the count
+                // rounded up to a power of two), each summing R over every
+                // (256 / P)-th hit of each plane segment.  Otherwise: rounds of
+                // 64 * C points per wave, every wave over its quarter of each plane
+                // segment (C candidates per lane share each hit read; measured
+                // faster for C = 2 even when few points are pending).  Partial sums
+                // are added in a fixed order.  The list is in (slot j, wave, lane)
+                // order, so which points share a wave (and, with pruning, its hit
+                // window) is the same on every run.
+                for (;;) {
+                    float tt[C][NP];
+                    int slot[C], rank[C];
+                    uint64_t bal[C];
+    #pragma unroll
+                    for (int j = 0; j < C; ++j) {
+                        if (pend[j]) {
+    #pragma unroll
+                            for (int a = 0; a < NP; ++a) tt[j][a] = __builtin_fmaf(alpha[j], p[j][a], th[j][a]);
+                        }
+                        bal[j] = __ballot(pend[j] && owner2);
+                        rank[j] = __popcll(bal[j] & ((1ull << lane) - 1ull));
+                    }
+                    __syncthreads();  // the previous round is done with the list
+                    if (lane == 0) {
+    #pragma unroll
+                        for (int j = 0; j < C; ++j) s_wcnt[j * kNW + wave] = __popcll(bal[j]);
                     }
                     __syncthreads();
-                    // ((wave 0 + wave 1) + wave 2) + wave 3, into slot 0
-#pragma unroll
+                    int npend = 0, base[C];
+    #pragma unroll
                     for (int j = 0; j < C; ++j) {
-                        const int e2 = (int)threadIdx.x + j * kBlock;
-                        if (e2 < npend) {
-                            const float* pr = s_lth[e2];
-                            const float Rt = ((pr[0] + pr[1]) + pr[2]) + pr[3];
-                            s_lth[e2][0] = Rt;
+                        base[j] = 0;
+                        for (int w = 0; w < kNW; ++w) {
+                            if (w == wave) base[j] = npend;
+                            npend += s_wcnt[j * kNW + w];
                         }
                     }
-                    ls_pairs += (uint64_t)rounds * per_round * (uint64_t)ev.n;
-                }
-                __syncthreads();
-#pragma unroll
-                for (int j = 0; j < C; ++j) {
-                    if (!pend[j]) continue;
-                    ++nre[j];
-                    const float Rt = s_lth[slot[j]][0];
-                    if (Rt >= Rc[j] + d->armijo_c1 * alpha[j] * gp[j]) {
-#pragma unroll
-                        for (int a = 0; a < NP; ++a) th[j][a] = tt[j][a];
-                        if constexpr (U == 2) {
-#pragma unroll
-                            for (int a = 0; a < NP; ++a) sq[j][a] = ds[a] * (alpha[j] * p[j][a]);
+    #pragma unroll
+                    for (int j = 0; j < C; ++j) {
+                        slot[j] = pend[j] && owner2 ? base[j] + rank[j] : -1;
+                        if (slot[j] >= 0) {
+    #pragma unroll
+                            for (int a = 0; a < NP; ++a) s_lth[slot[j]][a] = tt[j][a];
                         }
-                        pend[j] = false;
-                    } else if (++trial[j] >= d->ls_trials) {
-                        pend[j] = false;
-                        flags[j] |= RETINA_STALLED;
+                    }
+                    if constexpr (QS2 > 1) {
+                        // the other lanes of a seed read its point
+    #pragma unroll
+                        for (int j = 0; j < C; ++j) slot[j] = __shfl(slot[j], slane2);
+                    }
+                    __syncthreads();
+                    npend = __builtin_amdgcn_readfirstlane(npend);
+                    if (npend == 0) break;
+                    if (C == 1 && npend <= kWave) {
+                        // npend points, parts = 256 / npend threads on each (the last
+                        // 256 - parts * npend threads duplicate a part and are not read)
+                        const int per = npend;
+                        const int parts = kBlock / per;
+                        const int used = parts * per;
+                        const bool in = (int)threadIdx.x < used;
+                        const int pt = in ? (int)threadIdx.x % per : 0, part = in ? (int)threadIdx.x / per : 0;
+                        float lt[NP];
+    #pragma unroll
+                        for (int a = 0; a < NP; ++a) lt[a] = s_lth[pt][a];
+                        s_red[threadIdx.x] = event_pass_split<D, PR>(d, s_hits, s_poff, ev, lt, nc, part, parts, in);
+                        __syncthreads();  // every thread holds its point and partial
+                        if ((int)threadIdx.x < per) {
+                            float Rt = 0.0f;
+                            for (int q = 0; q < parts; ++q) Rt += s_red[q * per + threadIdx.x];
+                            s_lth[threadIdx.x][0] = Rt;
+                        }
+                        ls_pairs += (uint64_t)per * (uint64_t)ev.n;
                     } else {
-                        alpha[j] *= 0.5f;
-                    }
-                }
-            }
-        }
-
-        // FP64 Newton polish at sigma_final
-        double T[C][NP];
-#pragma unroll
-        for (int j = 0; j < C; ++j)
-#pragma unroll
-            for (int a = 0; a < NP; ++a) T[j][a] = (double)th[j][a];
-        const float sf = d->sigma_final;
-        const float ncf = -kLog2e / (sf * sf);
-        float Rfin[C];
-        double step[C];
-        bool pd[C];
-        for (int it2 = 0; it2 < d->n_polish; ++it2) {
-            // n_slope_steps counts on from the steps into the polish iterations
-            const bool slope_pol = D == 2 && n_steps + it2 < d->n_slope_steps;
-            Cands<C> ch, cl;
-#pragma unroll
-            for (int j = 0; j < C; ++j) {
-                float hi[NP], lo[NP];
-#pragma unroll
-                for (int a = 0; a < NP; ++a) {
-                    hi[a] = (float)T[j][a];
-                    lo[a] = (float)(T[j][a] - (double)hi[a]);
-                }
-                set_cand<D, C>(ch, j, hi);
-                set_cand<D, C>(cl, j, lo);
-            }
-            float acc[C][NA];
-            event_pass<D, C, true, true, PR, QS>(d, s_hits, s_poff, ev, ch, cl, ncf, acc, wave_work, active);
-#pragma unroll
-            for (int j = 0; j < C; ++j) {
-                double g[NP], H[NP][NP], A[NP][NP], dl[NP];
-                grad_hess<D, double>(acc[j], sf, g, H);
-#pragma unroll
-                for (int a = 0; a < NP; ++a)
-#pragma unroll
-                    for (int b = 0; b < NP; ++b) A[a][b] = -H[a][b];
-                if (slope_pol) {
-                    // offsets held: identity on the offset block and a zero offset
-                    // gradient leave the Newton system of the slope block (its
-                    // Cholesky factor is the block's own) and zero offset steps
-#pragma unroll
-                    for (int a = 0; a < NP; ++a)
-#pragma unroll
-                        for (int b = 0; b < 2; ++b) {
-                            A[a][b] = a == b ? 1.0 : 0.0;
-                            A[b][a] = a == b ? 1.0 : 0.0;
+                        const int per_round = kWave * C;
+                        const int rounds = (npend + per_round - 1) / per_round;
+                        for (int r = 0; r < rounds; ++r) {
+                            Cands<C> cc;
+                            bool live[C];
+                            int ent[C];
+    #pragma unroll
+                            for (int j = 0; j < C; ++j) {
+                                ent[j] = r * per_round + j * kWave + lane;
+                                live[j] = ent[j] < npend;
+                                float lt[NP];
+    #pragma unroll
+                                for (int a = 0; a < NP; ++a) lt[a] = live[j] ? s_lth[ent[j]][a] : 0.0f;
+                                set_cand<D, C>(cc, j, lt);
+                            }
+                            __syncthreads();  // all waves hold the round's points before partials overwrite them
+                            float racc[C][NA];
+                            event_pass_part<D, C, PR>(d, s_hits, s_poff, ev, cc, nc, wave, kBlock / kWave, racc, live);
+    #pragma unroll
+                            for (int j = 0; j < C; ++j)
+                                if (live[j]) s_lth[ent[j]][wave] = racc[j][0];
                         }
-                    g[0] = 0.0;
-                    g[1] = 0.0;
-                }
-                pd[j] = chol_solve<NP>(A, g, dl);
-                Rfin[j] = acc[j][0];
-                if (pd[j]) {
-                    double s2 = 0.0;
-#pragma unroll
-                    for (int a = 0; a < NP; ++a) {
-                        T[j][a] += dl[a];
-                        const double sd = (double)ds[a] * dl[a];
-                        s2 += sd * sd;
+                        __syncthreads();
+                        // ((wave 0 + wave 1) + wave 2) + wave 3, into slot 0
+    #pragma unroll
+                        for (int j = 0; j < C; ++j) {
+                            const int e2 = (int)threadIdx.x + j * kBlock;
+                            if (e2 < npend) {
+                                const float* pr = s_lth[e2];
+                                const float Rt = ((pr[0] + pr[1]) + pr[2]) + pr[3];
+                                s_lth[e2][0] = Rt;
+                            }
+                        }
+                        ls_pairs += (uint64_t)rounds * per_round * (uint64_t)ev.n;
                     }
-                    step[j] = sqrt(s2);
-                } else {
-                    step[j] = INFINITY;
+                    __syncthreads();
+    #pragma unroll
+                    for (int j = 0; j < C; ++j) {
+                        if (!pend[j]) continue;
+                        ++nre[j];
+                        const float Rt = s_lth[slot[j]][0];
+                        if (Rt >= Rc[j] + d->armijo_c1 * alpha[j] * gp[j]) {
+    #pragma unroll
+                            for (int a = 0; a < NP; ++a) th[j][a] = tt[j][a];
+                            if constexpr (U == 2) {
+    #pragma unroll
+                                for (int a = 0; a < NP; ++a) sq[j][a] = ds[a] * (alpha[j] * p[j][a]);
+                            }
+                            pend[j] = false;
+                        } else if (++trial[j] >= d->ls_trials) {
+                            pend[j] = false;
+                            flags[j] |= RETINA_STALLED;
+                        } else {
+                            alpha[j] *= 0.5f;
+                        }
+                    }
                 }
             }
-        }
-#pragma unroll
-        for (int j = 0; j < C; ++j) {
-            if (!pd[j]) flags[j] |= RETINA_NOT_PD;
-            else if (step[j] <= (double)d->conv_tol * (double)sf) flags[j] |= RETINA_CONVERGED;
-            if (!active[j] || !owner) continue;
-            const int sj = it.y + (wave * C + j) * SL + slane;
-            const int64_t gs = sbase + sj;
-            double* o = d->s_theta + gs * 4;
-#pragma unroll
-            for (int a = 0; a < 4; ++a) o[a] = a < NP ? T[j][a] : 0.0;
-            d->s_R[gs] = Rfin[j];
-            d->s_flags[gs] = flags[j];
-            d->s_nreval[gs] = nre[j];
-        }
-        if (lane == 0 && wave_work) {
-            const uint64_t per_pass = (uint64_t)ev.n * SL;
-            atomicAdd((unsigned long long*)&d->cnt->exec_pairs,
-                      (unsigned long long)(per_pass * C * (uint64_t)(n_steps + d->n_polish)));
-        }
-        if (threadIdx.x == 0) {
-            atomicAdd((unsigned long long*)&d->cnt->exec_pairs, (unsigned long long)ls_pairs);
-            atomicAdd((unsigned long long*)&d->cnt->exec_rpairs, (unsigned long long)ls_pairs);
-        }
-        if (lane == 0 && wls_pairs) {
-            atomicAdd((unsigned long long*)&d->cnt->exec_pairs, (unsigned long long)wls_pairs);
-            atomicAdd((unsigned long long*)&d->cnt->exec_rpairs, (unsigned long long)wls_pairs);
+
+            // FP64 Newton polish at sigma_final
+            double T[C][NP];
+    #pragma unroll
+            for (int j = 0; j < C; ++j)
+    #pragma unroll
+                for (int a = 0; a < NP; ++a) T[j][a] = (double)th[j][a];
+            const float sf = d->sigma_final;
+            const float ncf = -kLog2e / (sf * sf);
+            float Rfin[C];
+            double step[C];
+            bool pd[C];
+            for (int it2 = 0; it2 < d->n_polish; ++it2) {
+                // n_slope_steps counts on from the steps into the polish iterations
+                const bool slope_pol = D == 2 && n_steps + it2 < d->n_slope_steps;
+                Cands<C> ch, cl;
+    #pragma unroll
+                for (int j = 0; j < C; ++j) {
+                    float hi[NP], lo[NP];
+    #pragma unroll
+                    for (int a = 0; a < NP; ++a) {
+                        hi[a] = (float)T[j][a];
+                        lo[a] = (float)(T[j][a] - (double)hi[a]);
+                    }
+                    set_cand<D, C>(ch, j, hi);
+                    set_cand<D, C>(cl, j, lo);
+                }
+                float acc[C][NA];
+                event_pass<D, C, true, true, PR, QS2>(d, s_hits, s_poff, ev, ch, cl, ncf, acc, wave_work, active);
+    #pragma unroll
+                for (int j = 0; j < C; ++j) {
+                    double g[NP], H[NP][NP], A[NP][NP], dl[NP];
+                    grad_hess<D, double>(acc[j], sf, g, H);
+    #pragma unroll
+                    for (int a = 0; a < NP; ++a)
+    #pragma unroll
+                        for (int b = 0; b < NP; ++b) A[a][b] = -H[a][b];
+                    if (slope_pol) {
+                        // offsets held: identity on the offset block and a zero offset
+                        // gradient leave the Newton system of the slope block (its
+                        // Cholesky factor is the block's own) and zero offset steps
+    #pragma unroll
+                        for (int a = 0; a < NP; ++a)
+    #pragma unroll
+                            for (int b = 0; b < 2; ++b) {
+                                A[a][b] = a == b ? 1.0 : 0.0;
+                                A[b][a] = a == b ? 1.0 : 0.0;
+                            }
+                        g[0] = 0.0;
+                        g[1] = 0.0;
+                    }
+                    pd[j] = chol_solve<NP>(A, g, dl);
+                    Rfin[j] = acc[j][0];
+                    if (pd[j]) {
+                        double s2 = 0.0;
+    #pragma unroll
+                        for (int a = 0; a < NP; ++a) {
+                            T[j][a] += dl[a];
+                            const double sd = (double)ds[a] * dl[a];
+                            s2 += sd * sd;
+                        }
+                        step[j] = sqrt(s2);
+                    } else {
+                        step[j] = INFINITY;
+                    }
+                }
+            }
+    #pragma unroll
+            for (int j = 0; j < C; ++j) {
+                if (!pd[j]) flags[j] |= RETINA_NOT_PD;
+                else if (step[j] <= (double)d->conv_tol * (double)sf) flags[j] |= RETINA_CONVERGED;
+                if (!active[j] || !owner2) continue;
+                const int sj = it.y + (wave * C + j) * SL2 + slane2;
+                const int64_t gs = sbase + sj;
+                double* o = d->s_theta + gs * 4;
+    #pragma unroll
+                for (int a = 0; a < 4; ++a) o[a] = a < NP ? T[j][a] : 0.0;
+                d->s_R[gs] = Rfin[j];
+                d->s_flags[gs] = flags[j];
+                d->s_nreval[gs] = nre[j];
+            }
+            if (lane == 0 && wave_work) {
+                const uint64_t per_pass = (uint64_t)ev.n * SL2;
+                atomicAdd((unsigned long long*)&d->cnt->exec_pairs,
+                          (unsigned long long)(per_pass * C * (uint64_t)(n_steps + d->n_polish)));
+            }
+            if (threadIdx.x == 0) {
+                atomicAdd((unsigned long long*)&d->cnt->exec_pairs, (unsigned long long)ls_pairs);
+                atomicAdd((unsigned long long*)&d->cnt->exec_rpairs, (unsigned long long)ls_pairs);
+            }
+            if (lane == 0 && wls_pairs) {
+                atomicAdd((unsigned long long*)&d->cnt->exec_pairs, (unsigned long long)wls_pairs);
+                atomicAdd((unsigned long long*)&d->cnt->exec_rpairs, (unsigned long long)wls_pairs);
+            }
+        };
+        if constexpr (QS > 1) {
+            const int r = min(ns - it.y, d->seeds_per_item);
+            if (r <= kNW * (kWave / kMaxSplitLanes)) item_body(std::integral_constant<int, kMaxSplitLanes>{});
+            else if (r <= kNW * (kWave / (kMaxSplitLanes / 2))) item_body(std::integral_constant<int, kMaxSplitLanes / 2>{});
+            else item_body(std::integral_constant<int, QS>{});
+        } else {
+            item_body(std::integral_constant<int, QS>{});
         }
         __syncthreads();
     }
