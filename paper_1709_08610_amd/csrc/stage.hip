@@ -282,23 +282,27 @@ __global__ __launch_bounds__(1024) void k_plan(const Desc* __restrict__ d, int m
     const int spi = d->seeds_per_item;
     if (mode == 0 || mode == 1) {
         // track finding: the events of rank r (longest first) go to XCD queue
-        // r % kXcds, each queue in rank order; position of an event's items =
-        // its queue's start + the items of the queue's earlier events
-        __shared__ int64_t s_qcarry[kXcds], s_qstart[kXcds + 1];
+        // r % kXcds.  Each queue holds first the full items of its events, then
+        // their part-filled last items (cheaper, so the work ends on short
+        // items), both in rank order.  Full and part-filled item counts are
+        // summed together, packed into the low and high halves of one word.
+        __shared__ int64_t s_qcarry[kXcds], s_qstart[kXcds + 1], s_qfull[kXcds];
         for (int pass = 0; pass < 2; ++pass) {
             if (t < kXcds) s_qcarry[t] = 0;
             __syncthreads();
             for (int64_t r0 = 0; r0 < E; r0 += 1024) {
                 const int64_t r = r0 + t;  // r % kXcds == t % kXcds (1024 is a multiple of kXcds)
-                int64_t nb = 0;
+                int64_t nf = 0, np = 0;
                 int e = 0;
                 if (r < E) {
                     e = d->order[r];
                     const int64_t ns = d->seed_off[e + 1] - d->seed_off[e];
-                    nb = (ns + spi - 1) / spi;
+                    nf = ns / spi;
+                    np = ns % spi ? 1 : 0;
                 }
+                const int64_t v = nf | (np << 32);
                 // inclusive prefix over this chunk's ranks of the same queue
-                s_tmp[t] = nb;
+                s_tmp[t] = v;
                 __syncthreads();
                 for (int off = kXcds; off < 1024; off <<= 1) {
                     const int64_t add = t >= off ? s_tmp[t - off] : 0;
@@ -307,11 +311,16 @@ __global__ __launch_bounds__(1024) void k_plan(const Desc* __restrict__ d, int m
                     __syncthreads();
                 }
                 const int q = t % kXcds;
-                const int64_t ex = s_tmp[t] - nb + s_qcarry[q];
+                const int64_t ex = s_tmp[t] - v + s_qcarry[q];
                 if (pass == 1 && r < E) {
-                    for (int64_t b = 0; b < nb; ++b) {
-                        const int64_t it = s_qstart[q] + ex + b;
+                    const int64_t exf = ex & 0xFFFFFFFFll, exp_ = ex >> 32;
+                    for (int64_t b = 0; b < nf; ++b) {
+                        const int64_t it = s_qstart[q] + exf + b;
                         if (it < d->items_cap) d->items[it] = make_int2(e, (int)b);
+                    }
+                    if (np) {
+                        const int64_t it = s_qstart[q] + s_qfull[q] + exp_;
+                        if (it < d->items_cap) d->items[it] = make_int2(e, (int)nf);
                     }
                 }
                 __syncthreads();
@@ -322,7 +331,8 @@ __global__ __launch_bounds__(1024) void k_plan(const Desc* __restrict__ d, int m
                 int64_t acc = 0;
                 for (int q = 0; q < kXcds; ++q) {
                     s_qstart[q] = acc;
-                    acc += s_qcarry[q];
+                    s_qfull[q] = s_qcarry[q] & 0xFFFFFFFFll;
+                    acc += s_qfull[q] + (s_qcarry[q] >> 32);
                 }
                 s_qstart[kXcds] = acc;
             }
