@@ -43,7 +43,11 @@ constexpr int kSplitLanes = 4;
 constexpr int kMaxSplitLanes = 16;
 // spare hit entries after the LDS tile: the meas_dim-2 hit loops read ahead
 // of the segment they walk, up to index tile_hits + 2 * lanes per seed - 1
-constexpr int kTilePad = 2 * kMaxSplitLanes;
+// (split kernels: up to kMaxSplitLanes lanes per seed; the others: one).  The
+// pad is part of the tile's LDS bytes, so it is kept as small as each shape
+// allows: the dense ascent's tile is sized to fit three work-groups per CU.
+constexpr int kTilePadSplit = 2 * kMaxSplitLanes;
+constexpr int kTilePad = 8;
 
 template <int D>
 struct Acc;  // number of accumulators
@@ -121,8 +125,8 @@ __device__ __forceinline__ void seg_accumulate(const float* __restrict__ s_hits,
         };
         // two hits per iteration; the next two are read from LDS while these
         // are processed.  The reads run up to 2 QS - 1 entries past the
-        // segment: the LDS tile carries kTilePad spare entries, so they stay
-        // inside it, and their values are never used.
+        // segment: the LDS tile carries kTilePad (QS = 1) or kTilePadSplit
+        // spare entries, so they stay inside it, and their values are never used.
         if constexpr (QS == 1) {
             float2 a = h[lo], b = h[lo + 1];
             int k = lo;
@@ -875,9 +879,13 @@ __global__ __launch_bounds__(kBlock) void k_ascent(const Desc* __restrict__ d, i
     __shared__ int s_wcnt[C * kNW];         // line-search list: pending points per (slot j, wave),
     __shared__ float s_lth[kBlock * C][4];  // the points, then their responses (slot 0)
     __shared__ float s_red[kBlock];         // partial responses of a line-search round
-    __shared__ float s_pz[kMaxPlanes];      // plane positions (per-lane plane lookups)
+    // plane positions for the wave-local line search's per-plane reads (split
+    // kernels only: the dense kernels' LDS must stay within a third of the CU's)
+    __shared__ float s_pz[QS > 1 ? kMaxPlanes : 1];
     if (d->cnt->err) return;
-    if ((int)threadIdx.x < kMaxPlanes) s_pz[threadIdx.x] = d->plane_z[threadIdx.x];
+    if constexpr (QS > 1) {
+        if ((int)threadIdx.x < kMaxPlanes) s_pz[threadIdx.x] = d->plane_z[threadIdx.x];
+    }
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);  // scalar: same in every lane
     const int lane = threadIdx.x & (kWave - 1);
     const int64_t n_items = d->cnt->n_items;
@@ -1485,7 +1493,10 @@ void launch_response_reduce(const Desc* d, int D, bool deriv, int64_t n_theta, h
 // ------------------------------------------------------------------ launch
 int hot_seeds_per_item(const HotConfig& c) { return (kBlock / kWave) * kWave * c.cand / (c.split ? kSplitLanes : 1); }
 
-size_t hot_lds_bytes(int meas_dim, const HotConfig& c) { return (size_t)(c.tile_hits + kTilePad) * meas_dim * sizeof(float); }
+size_t hot_lds_bytes(int meas_dim, const HotConfig& c)
+{
+    return (size_t)(c.tile_hits + (c.split ? kTilePadSplit : kTilePad)) * meas_dim * sizeof(float);
+}
 
 template <typename K>
 static int occupancy(K kern, size_t lds)
