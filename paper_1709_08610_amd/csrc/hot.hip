@@ -29,6 +29,7 @@
 // the plane's z in a scalar register.  The FP64 polish evaluates at an FP64
 // theta split into two floats (hi + lo); the low words join l, so the
 // gradient it solves with belongs to the FP64 point.
+#include <algorithm>
 #include <type_traits>
 
 #include "rt_internal.h"
@@ -1503,6 +1504,20 @@ static int occupancy(K kern, size_t lds)
 {
     int nb = 0;
     if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, kern, kBlock, lds) != hipSuccess) return 1;
+    // LDS bound with the static and the dynamic part each rounded up to the
+    // 512-byte allocation unit: the occupancy query has counted one work-group
+    // more than fitted (a kernel 160 bytes under a third of the CU's LDS by the
+    // plain sum, over it once the parts are rounded), and a persistent grid
+    // sized by that count leaves the extra work-groups waiting for a slot
+    hipFuncAttributes fa;
+    int dev = 0, cu_lds = 0;
+    if (hipFuncGetAttributes(&fa, reinterpret_cast<const void*>(kern)) == hipSuccess && hipGetDevice(&dev) == hipSuccess &&
+        hipDeviceGetAttribute(&cu_lds, hipDeviceAttributeMaxSharedMemoryPerMultiprocessor, dev) == hipSuccess &&
+        cu_lds > 0) {
+        auto up = [](size_t b) { return (b + 511) / 512 * 512; };
+        const size_t per = up(fa.sharedSizeBytes) + up(lds);
+        if (per > 0) nb = std::min<int>(nb, (int)((size_t)cu_lds / per));
+    }
     return nb > 0 ? nb : 1;
 }
 
