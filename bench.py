@@ -65,15 +65,16 @@ FLOP_NET_EVENT = 2 * 16384 * 9 * (2 * 64 + 64 * 128 + 128 * 96 + 96 * 1)
 # WRITE_SIZE runs of this script (profiles/k_ascent_c3_learned.md), each scaled
 # by the counter's reading for a 1 GiB device copy (FETCH_SIZE x 2.0, WRITE_SIZE
 # x 1.0).  Valid only for the kernel source they were taken with (hash of
-# csrc/hot.hip + csrc/rt_internal.h); reported as null otherwise.
-MEASURED_TRAFFIC = {("c3", "learned"): {"bytes": 154.6e6, "fetch": 146.8e6, "write": 7.8e6,
-                                         "source_sha256_16": "685acee4fc24cad6"}}
+# csrc/hot.hip + csrc/rt_internal.h + csrc/stage.hip, the kernel and the plan
+# that orders its work); reported as null otherwise.
+MEASURED_TRAFFIC = {("c3", "learned"): {"bytes": 75.94e6, "fetch": 67.63e6, "write": 8.31e6,
+                                         "source_sha256_16": "6bd7802d8280bb9f"}}
 
 
 def kernel_source_hash():
     import hashlib
     h = hashlib.sha256()
-    for f in ("hot.hip", "rt_internal.h"):
+    for f in ("hot.hip", "rt_internal.h", "stage.hip"):
         with open(os.path.join(ROOT, "paper_1709_08610_amd", "csrc", f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]
