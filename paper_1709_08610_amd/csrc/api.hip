@@ -505,12 +505,13 @@ int retina_create(int device_ordinal, retina_ctx** out)
     for (int D = 1; D <= 2; ++D) {
         c->ascent_cfg[D] = default_hot(c, D, true);
         c->resp_cfg[D] = default_hot(c, D, false);
-        // few seeds per event (learned seeding): one candidate per lane keeps the
-        // 256-seed work items full, and a smaller tile leaves room for more
-        // work-groups per CU
+        // few seeds per event (learned seeding): one candidate per lane with
+        // several lanes per seed; a 5632-hit tile keeps all but the largest
+        // events of an uneven batch resident (their line searches run
+        // wave-local), at three work-groups per CU
         HotConfig h = c->ascent_cfg[D];
         h.cand = 1;
-        h.tile_hits = D == 2 ? 4096 : 8192;
+        h.tile_hits = D == 2 ? 5632 : 8192;
         h.grid = c->n_cu * hot_max_blocks_per_cu(D, h, true);
         c->sparse_cfg[D] = h;
     }

@@ -43,11 +43,12 @@ constexpr float kLog2e = 1.44269504088896340736f;
 constexpr int kSplitLanes = 4;
 constexpr int kMaxSplitLanes = 16;
 // spare hit entries after the LDS tile: the meas_dim-2 hit loops read ahead
-// of the segment they walk, up to index tile_hits + 2 * lanes per seed - 1
-// (split kernels: up to kMaxSplitLanes lanes per seed; the others: one).  The
-// pad is part of the tile's LDS bytes, so it is kept as small as each shape
-// allows: the dense ascent's tile is sized to fit three work-groups per CU.
-constexpr int kTilePadSplit = 2 * kMaxSplitLanes;
+// of the segment they walk, up to index tile_hits + 2 * stride - 1 (split
+// kernels: the line search walks with up to 64 lanes per trial point; the
+// others: stride one).  The pad is part of the tile's LDS bytes, so it is
+// kept as small as each shape allows: the dense ascent's tile is sized to fit
+// three work-groups per CU.
+constexpr int kTilePadSplit = 2 * kWave;
 constexpr int kTilePad = 8;
 
 template <int D>
@@ -711,82 +712,45 @@ __device__ __forceinline__ EventView begin_event(const Desc* __restrict__ d, int
     return ev;
 }
 
-// R only at one line: lane `sub` of a group of L lanes (L a power of two)
-// takes hits sub, sub + L, sub + 2 L, ... of every plane segment of a
-// resident event.  The group's lanes read consecutive hits (other groups read
-// the same ones), the lanes' trip counts per segment differ by at most one,
-// and the line is split once per plane.  Per lane: two running sums per plane
-// (alternate hits of its share) added at the plane's end, planes in order.
-// Read-ahead indices are clamped to the segment's last hit.
-template <int D>
-__device__ __forceinline__ float strided_response(const float* __restrict__ s_hits, const int* s_poff,
-                                                  const float* s_pz, int P, int sub, int L, const float* th,
-                                                  float nc)
+// R only at one line per lane group over a resident event: the point of lane
+// l is point l % (64 / L), and its L lanes walk every L-th hit of each plane
+// segment with the passes' own hit loop (R only), then a butterfly over the
+// L lanes adds their sums in a fixed order.  Reads run up to 2 L - 1 entries
+// past a segment (the split tile's spare entries cover L = 64).
+template <int D, int L>
+__device__ __forceinline__ float group_response(const Desc* __restrict__ d, const float* s_hits, const int* s_poff,
+                                                const EventView& ev, const float* th, float nc)
 {
-    float R = 0.0f;
-    for (int p = 0; p < P; ++p) {
+    static_assert(2 * L <= kTilePadSplit, "the read-ahead stays inside the tile's spare entries");
+    Cands<1> c;
+    set_cand<D, 1>(c, 0, th);
+    const Cands<1> zero_c = {};
+    float acc[1][Acc<D>::N];
+#pragma unroll
+    for (int a = 0; a < Acc<D>::N; ++a) acc[0][a] = 0.0f;
+    for (int p = 0; p < ev.P; ++p) {
         const int lo = __builtin_amdgcn_readfirstlane(s_poff[p]);
         const int hi = __builtin_amdgcn_readfirstlane(s_poff[p + 1]);
         if (lo >= hi) continue;
-        const float z = s_pz[p];
-        float sx, lx, sy = 0.0f, ly = 0.0f;
-        if constexpr (D == 2) {
-            line_split(th[0], th[2], z, sx, lx);
-            line_split(th[1], th[3], z, sy, ly);
-        } else {
-            line_split(th[0], th[1], z, sx, lx);
-        }
-        const int last = hi - 1;
-        float pa = 0.0f, pb = 0.0f;
-        int k = lo + sub;
-        if constexpr (D == 2) {
-            const float2* h = reinterpret_cast<const float2*>(s_hits);
-            auto term = [&](const float2 v) {
-                const float rx = (v.x - sx) - lx;
-                const float ry = (v.y - sy) - ly;
-                return __builtin_amdgcn_exp2f(__builtin_fmaf(ry, ry, rx * rx) * nc);
-            };
-            float2 a = h[min(k, last)], b = h[min(k + L, last)];
-            for (; k + L < hi; k += 2 * L) {
-                const float2 na = h[min(k + 2 * L, last)], nb = h[min(k + 3 * L, last)];
-                pa += term(a);
-                pb += term(b);
-                a = na;
-                b = nb;
-            }
-            if (k < hi) pa += term(a);
-        } else {
-            auto term = [&](const float v) {
-                const float r = (v - sx) - lx;
-                return __builtin_amdgcn_exp2f((r * r) * nc);
-            };
-            float a = s_hits[min(k, last)], b = s_hits[min(k + L, last)];
-            for (; k + L < hi; k += 2 * L) {
-                const float na = s_hits[min(k + 2 * L, last)], nb = s_hits[min(k + 3 * L, last)];
-                pa += term(a);
-                pb += term(b);
-                a = na;
-                b = nb;
-            }
-            if (k < hi) pa += term(a);
-        }
-        R += pa + pb;
+        seg_accumulate<D, 1, false, false, L>(s_hits, lo, hi, d->plane_z[p], c, zero_c, nc, acc);
     }
-    return R;
+    float r = acc[0][0];
+#pragma unroll
+    for (int m = kWave / 2; m >= kWave / L; m >>= 1) r += __shfl_xor(r, m);
+    return r;
 }
 
 // Backtracking line search of one wave's seeds, wave-local (no work-group
 // barrier), for the split ascent on a resident event.  The QS lanes of a seed
 // hold identical state.  Each round takes the wave's m pending seeds (by their
 // owner lanes), gives each trial point L = 64 / m lanes (rounded down to a
-// power of two), lane `sub` of a point summing R over every L-th hit of each
-// plane segment from the segment's sub-th; a butterfly inside the group of L
-// lanes adds the parts in a fixed order.  Every seed either accepts,
+// power of two), which walk its hits as a pass does (group_response); a
+// butterfly over the L lanes adds their parts in a fixed order.  Every seed either accepts,
 // halves its step or stalls in a round, so at most ls_trials rounds run.
 // Returns the pair evaluations of the wave (counted once, in lane 0).
 template <int D, int QS>
 __device__ __forceinline__ uint64_t wave_line_search(const Desc* __restrict__ d, const float* s_hits,
-                                                     const int* s_poff, const float* s_pz, const EventView& ev,
+                                                     const int* s_poff, const EventView& ev,
                                                      float (&th)[2 * D], const float (&p)[2 * D], float Rc,
                                                      float gp, bool& pend, int& nre, int& flags, float nc)
 {
@@ -804,7 +768,7 @@ __device__ __forceinline__ uint64_t wave_line_search(const Desc* __restrict__ d,
         if (m == 0) break;
         int L = kWave;
         while (L * m > kWave) L >>= 1;
-        const int q = lane / L, sub = lane & (L - 1);
+        const int q = lane & (kWave / L - 1);  // this lane's point
         const bool qlive = q < m;
         // owner lane of point q: the q-th set bit of bal
         uint64_t b = bal;
@@ -816,13 +780,18 @@ __device__ __forceinline__ uint64_t wave_line_search(const Desc* __restrict__ d,
             tt[a] = __builtin_fmaf(alpha, p[a], th[a]);
             tq[a] = __shfl(tt[a], src);
         }
-        float part = qlive ? strided_response<D>(s_hits, s_poff, s_pz, ev.P, sub, L, tq, nc) : 0.0f;
-#pragma unroll
-        for (int w = kWave / 2; w >= 1; w >>= 1)
-            if (w < L) part += __shfl_xor(part, w);
-        // the seed's lanes read the sum of its point (group of rank r, lane r * L)
+        // lanes of points past m evaluate point 0's line again (not read)
+        float Rq;
+        switch (L) {
+        case 64: Rq = group_response<D, 64>(d, s_hits, s_poff, ev, tq, nc); break;
+        case 32: Rq = group_response<D, 32>(d, s_hits, s_poff, ev, tq, nc); break;
+        case 16: Rq = group_response<D, 16>(d, s_hits, s_poff, ev, tq, nc); break;
+        case 8: Rq = group_response<D, 8>(d, s_hits, s_poff, ev, tq, nc); break;
+        default: Rq = group_response<D, 4>(d, s_hits, s_poff, ev, tq, nc); break;
+        }
+        // the seed's lanes read the sum of its point (point r sits in lane r)
         const int rank = __popcll(bal & ((1ull << slane) - 1ull));
-        const float Rt = __shfl(part, (rank * L) & (kWave - 1));
+        const float Rt = __shfl(Rq, rank);
         pairs += (uint64_t)m * (uint64_t)ev.n;
         if (pend) {
             ++nre;
@@ -880,13 +849,7 @@ __global__ __launch_bounds__(kBlock) void k_ascent(const Desc* __restrict__ d, i
     __shared__ int s_wcnt[C * kNW];         // line-search list: pending points per (slot j, wave),
     __shared__ float s_lth[kBlock * C][4];  // the points, then their responses (slot 0)
     __shared__ float s_red[kBlock];         // partial responses of a line-search round
-    // plane positions for the wave-local line search's per-plane reads (split
-    // kernels only: the dense kernels' LDS must stay within a third of the CU's)
-    __shared__ float s_pz[QS > 1 ? kMaxPlanes : 1];
     if (d->cnt->err) return;
-    if constexpr (QS > 1) {
-        if ((int)threadIdx.x < kMaxPlanes) s_pz[threadIdx.x] = d->plane_z[threadIdx.x];
-    }
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);  // scalar: same in every lane
     const int lane = threadIdx.x & (kWave - 1);
     const int64_t n_items = d->cnt->n_items;
@@ -1107,7 +1070,7 @@ __global__ __launch_bounds__(kBlock) void k_ascent(const Desc* __restrict__ d, i
                 if constexpr (QS2 > 1 && !PR) {
                     if (ev.resident) {
                         // every hit in LDS: each wave searches for its own seeds
-                        wls_pairs += wave_line_search<D, QS2>(d, s_hits, s_poff, s_pz, ev, th[0], p[0], Rc[0], gp[0],
+                        wls_pairs += wave_line_search<D, QS2>(d, s_hits, s_poff, ev, th[0], p[0], Rc[0], gp[0],
                                                              pend[0], nre[0], flags[0], nc);
                         continue;
                     }

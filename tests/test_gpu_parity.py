@@ -236,6 +236,40 @@ def test_find_tracks_split_lanes_item_edges(ctx, cfg_name):
         _say("  %d seeds: %d tracks" % (counts[e], len(R)))
 
 
+def test_find_tracks_split_lanes_streamed_tile(ctx):
+    """The split ascent with its hits streamed through a 1024-hit LDS tile (the
+    work-group-wide line search), at seed counts that run 16, 8 and 4 lanes per
+    seed in an item, against the oracle."""
+    _say("find_tracks split lanes, streamed tile")
+    counts = [1, 16, 17, 32, 33, 64, 65]
+    cfg = events.load_config("c3")
+    P = cfg["params"]
+    b = events.make_batch(cfg, len(counts), start=40)
+    rng = np.random.default_rng(11)
+    seeds, offs = [], [0]
+    for e, n in enumerate(counts):
+        t = b.truth[e][np.arange(n) % len(b.truth[e])]
+        s = np.zeros((n, 4))
+        s[:, 2:] = t[:, 2:] + rng.normal(0, 0.002, (n, 2))
+        seeds.append(s.astype(np.float32).astype(np.float64))
+        offs.append(offs[-1] + n)
+    seeds = np.concatenate(seeds)
+    offs = np.array(offs, np.int64)
+    assert int(np.diff(b.event_offsets).min()) > 1024
+    old = ctx.retina_get_tuning(2, 2)
+    try:
+        ctx.retina_set_tuning(2, 2, 1, 1024)
+        res = _find(ctx, b, P, seeds=seeds, seed_offsets=offs)
+    finally:
+        ctx.retina_set_tuning(2, 2, old["cand"], old["tile_hits"])
+    ref = oracle.find_tracks(b, P, seeds=seeds, seed_offsets=offs)
+    for e in range(len(counts)):
+        th, R = event_tracks(res, e, 2)
+        a, c = ref["track_offsets"][e], ref["track_offsets"][e + 1]
+        assert_tracks_match(2, th, R, ref["theta"][a:c], ref["R"][a:c], P["d_merge"], 20.0, 750.0)
+        _say("  %d seeds: %d tracks" % (counts[e], len(R)))
+
+
 def test_find_tracks_tiled_ascent_matches(ctx):
     """Events streamed through a small LDS tile give the same track set."""
     _say("find_tracks tiled")
