@@ -67,8 +67,8 @@ FLOP_NET_EVENT = 2 * 16384 * 9 * (2 * 64 + 64 * 128 + 128 * 96 + 96 * 1)
 # x 1.0).  Valid only for the kernel source they were taken with (hash of
 # csrc/hot.hip + csrc/rt_internal.h + csrc/stage.hip, the kernel and the plan
 # that orders its work); reported as null otherwise.
-MEASURED_TRAFFIC = {("c3", "learned"): {"bytes": 75.94e6, "fetch": 67.63e6, "write": 8.31e6,
-                                         "source_sha256_16": "6bd7802d8280bb9f"}}
+MEASURED_TRAFFIC = {("c3", "learned"): {"bytes": 80.58e6, "fetch": 72.12e6, "write": 8.46e6,
+                                         "source_sha256_16": "06d84dd086d0ce97"}}
 
 
 def kernel_source_hash():
@@ -297,6 +297,30 @@ def profiled(ctx, step, steps):
     return {k: (v / n if k != "calls" else v) for k, v in prof.items()}
 
 
+def shape_sweep(ctx, D, learned_step, lattice_step, steps):
+    """Ascent launch time (library HIP events, mean of `steps` eager calls) of
+    the learned step over the sparse shape's hit tiles (one candidate per lane,
+    several lanes per seed) and of the lattice step over the dense shape's
+    tiles and candidates per lane; the tunings in force are restored."""
+    out = {"sparse": [], "dense": []}
+    for kernel, key, step, shapes in ((2, "sparse", learned_step, [(1, t) for t in (2048, 4096, 5632, 6144, 8192)]),
+                                      (0, "dense", lattice_step,
+                                       [(c, t) for c in (1, 2) for t in (2048, 4096, 5632, 8192)])):
+        old = ctx.retina_get_tuning(D, kernel)
+        try:
+            for cand, tile in shapes:
+                ctx.retina_set_tuning(D, kernel, cand, tile)
+                step()
+                pr = profiled(ctx, step, max(1, steps))
+                tn = ctx.retina_get_tuning(D, kernel)
+                out[key].append({"cand": cand, "tile_hits": tile, "grid": tn["grid"], "ascent_ms": pr["ms_hot"]})
+                log("shape sweep %s: cand %d tile %d (grid %d): ascent %.3f ms" % (key, cand, tile, tn["grid"],
+                                                                                  pr["ms_hot"]))
+        finally:
+            ctx.retina_set_tuning(D, kernel, old["cand"], old["tile_hits"])
+    return out
+
+
 def lattice_sweep(ctx, retina, b, dev_hits, P, sizes, quality, reps=2, prune_u=0.0):
     import torch
     D = b.meas_dim
@@ -343,6 +367,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--studies", action="store_true",
                     help="also run the pruned comparison, the alpha-budget scans and the update rules")
+    ap.add_argument("--shape-sweep", action="store_true",
+                    help="also time both ascent launch shapes over hit tiles and candidates per lane")
     ap.add_argument("--detail-out", default=None, help="write the full report (JSON) to this file")
     ap.add_argument("--calib-copy-mib", type=int, default=0,
                     help="after the run, one plain device-to-device copy of this many MiB (a known-size "
@@ -475,6 +501,8 @@ def main():
     studies = {}
     if args.studies:
         studies = run_studies(ctx, retina, events, cfg, b, dev_hits, P, PL, LS, model, sizes, quality, args)
+    if args.shape_sweep:
+        studies["shape_sweep"] = shape_sweep(ctx, D, learned_step, lattice_step, args.steps)
 
     cpu = cpu_l = prec = None
     if not args.no_cpu_baseline:

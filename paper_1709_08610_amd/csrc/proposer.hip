@@ -1380,16 +1380,40 @@ void launch_reduce_dw(const float* part, int nc, int64_t n, float* g, hipStream_
 
 // bias gradient: per chunk of pixels a partial sum of dz over the chunk (one
 // thread per channel, pixels in order), then an ordered sum over chunks
-__global__ void k_bias_part(const uint16_t* __restrict__ dz, int64_t npix, int cout, int nchunk,
-                            float* __restrict__ part)
+// Bias gradient, per chunk of pixels: the chunk's dz values are one contiguous
+// run of per x cout BF16 values; the block's threads walk it with a stride of
+// (256 / cout) cout, so each thread stays on one channel (t % cout), with four
+// running sums over alternate elements; then the threads of a channel are
+// added in a fixed order in LDS.
+__global__ __launch_bounds__(256) void k_bias_part(const uint16_t* __restrict__ dz, int64_t npix, int cout,
+                                                   int nchunk, float* __restrict__ part)
 {
-    const int co = threadIdx.x;
+    __shared__ float s_sum[256];
+    const int t = threadIdx.x;
     const int c = blockIdx.x;
-    if (co >= cout) return;
+    const int groups = 256 / cout;  // threads per channel
+    const int stride = groups * cout;
     const int64_t per = npix / nchunk;
-    float s = 0.0f;
-    for (int64_t p = c * per; p < (c + 1) * per; ++p) s += bf2f(dz[p * cout + co]);
-    part[(int64_t)c * cout + co] = s;
+    const int64_t n = per * cout;
+    const uint16_t* src = dz + (int64_t)c * n;
+    float s[4] = {0.0f, 0.0f, 0.0f, 0.0f};
+    if (t < stride) {
+        int64_t i = t;
+        for (; i + 3 * stride < n; i += 4 * stride) {
+#pragma unroll
+            for (int k = 0; k < 4; ++k) s[k] += bf2f(src[i + k * stride]);
+        }
+        if (i < n) s[0] += bf2f(src[i]);
+        if (i + stride < n) s[1] += bf2f(src[i + stride]);
+        if (i + 2 * stride < n) s[2] += bf2f(src[i + 2 * stride]);
+    }
+    s_sum[t] = (s[0] + s[1]) + (s[2] + s[3]);
+    __syncthreads();
+    if (t < cout) {
+        float v = 0.0f;
+        for (int g = 0; g < groups; ++g) v += s_sum[g * cout + t];
+        part[(int64_t)c * cout + t] = v;
+    }
 }
 
 __global__ void k_bias_reduce(const float* __restrict__ part, int cout, int nchunk, float* __restrict__ g)
@@ -1403,7 +1427,7 @@ __global__ void k_bias_reduce(const float* __restrict__ part, int cout, int nchu
 
 void launch_bias_grad(const uint16_t* dz, int64_t npix, int cout, int nchunk, float* part, float* gb, hipStream_t st)
 {
-    hipLaunchKernelGGL(k_bias_part, dim3(nchunk), dim3(128), 0, st, dz, npix, cout, nchunk, part);
+    hipLaunchKernelGGL(k_bias_part, dim3(nchunk), dim3(256), 0, st, dz, npix, cout, nchunk, part);
     hipLaunchKernelGGL(k_bias_reduce, dim3(1), dim3(128), 0, st, part, cout, nchunk, gb);
 }
 
