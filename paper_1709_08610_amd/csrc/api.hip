@@ -1270,7 +1270,7 @@ int proposer_stage(retina_ctx* c, const retina_geometry* g, const retina_hits* h
 
 struct Acts {
     uint16_t* act[kLayers];  // act[0] = image, act[l] = output of layer l-1 (post-ReLU)
-    float* u;                // inference: the head's per-tap partial sums
+    float* u;                // inference: the head's band-edge terms
     float* logits;
 };
 
@@ -1285,7 +1285,7 @@ int ensure_acts(retina_ctx* c, int64_t E, Acts& A, bool train)
     if (train) {
         if ((rc = ensure_t(c, B_ACT1, px * kChan[1], &A.act[1])) || (rc = ensure_t(c, B_ACT3, px * kChan[3], &A.act[3])))
             return rc;
-    } else if ((rc = ensure_t(c, B_HEADU, px * 12, &A.u))) {
+    } else if ((rc = ensure_t(c, B_HEADU, head_edge_floats(E), &A.u))) {
         return rc;
     }
     return RETINA_OK;

@@ -49,8 +49,9 @@ void launch_gemm(const GemmArgs& a, hipStream_t st);
 
 // forward pass of the four layers (direct convolutions; see proposer.hip).
 // train: store act1..act3 for the backward pass; otherwise only act2 and the
-// head's per-tap partial sums u (E * kPix * 12 floats, 9 used) pass through HBM.
+// head's band-edge terms u (head_edge_floats(E) floats) pass through HBM.
 int prepare_forward();
+size_t head_edge_floats(int64_t n_events);
 void launch_forward(const uint16_t* img, const uint16_t* wbf, const float* w32, const NetLayout& L, int64_t E,
                     uint16_t* act1, uint16_t* act2, uint16_t* act3, float* u, float* logits, bool train,
                     hipStream_t st);

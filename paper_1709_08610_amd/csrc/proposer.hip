@@ -560,14 +560,15 @@ __global__ __launch_bounds__(256) void k_conv_head(const uint16_t* __restrict__ 
 //             reaches HBM); layer 1 runs on MFMA with K = 18 padded to 32;
 //   k_conv3i  layer 3 (persistent, pipelined; below), whose epilogue
 //             multiplies the BF16 act3 tile by the head's weights on MFMA
-//             (U[q][tap], 9 floats per pixel) instead of storing act3;
-//             k_head_sum adds the nine shifted U values.
+//             (U[q][tap], 9 floats per pixel) instead of storing act3, and
+//             adds the nine shifted U values of every logit whose taps lie in
+//             the band; k_head_edges finishes the band-edge rows.
 // Training keeps every activation (k_conv_in, k_conv_mid<64, 128>, k_conv3,
 // k_conv_head).
 constexpr int kC12ImgRows = kCvRows + 4;          // image rows staged (halo 2)
 constexpr int kC12ImgCols = kImg + 4;             // image columns staged
 constexpr int kC12A1 = (kCvRows + 2) * kCvCols;   // act1 positions of the tile (780)
-constexpr int kUPitch = 12;                       // floats per pixel of U (9 used, 16-byte rows)
+constexpr int kEdgeFloats = 13 * kImg;            // band-edge terms of the head per band (see k_conv3i)
 
 constexpr int kC12Consts = 64 + 128 + 64 * 32 / 2;  // floats: b1, b2, then W1 (64 x 32 BF16)
 
@@ -1035,12 +1036,17 @@ constexpr int kL3WElems = 9 * 96 * kL3Pitch;                       // one weight
 
 constexpr int kL3HeadFrags = 6 * 64;                               // head-weight fragments (nb, ks, lane), 16 B each
 
-constexpr size_t conv3i_lds() { return (size_t)2 * (kL3InElems + kL3WElems) * 2 + (size_t)kL3HeadFrags * 16 + 96 * 4; }
+constexpr int kL3UFloats = 9 * kCvRows * kImg;  // the band's U, tap-major
+constexpr size_t conv3i_lds()
+{
+    return (size_t)2 * (kL3InElems + kL3WElems) * 2 + (size_t)kL3HeadFrags * 16 + 96 * 4 + (size_t)kL3UFloats * 4;
+}
 
 __global__ __launch_bounds__(kCvThreads) void k_conv3i(const uint16_t* __restrict__ x, const uint16_t* __restrict__ w,
                                                        const float* __restrict__ bias,
-                                                       const uint16_t* __restrict__ w4, float* __restrict__ u_out,
-                                                       int n_bands)
+                                                       const uint16_t* __restrict__ w4,
+                                                       const float* __restrict__ hbias, float* __restrict__ edge,
+                                                       float* __restrict__ logits, int n_bands)
 {
     constexpr int CIN = 128, COUT = 96, NB = 3, NST = CIN / kL3Stage, KP = 9 * CIN;
     constexpr int BPE = kImg / kCvRows;  // bands per event
@@ -1051,6 +1057,7 @@ __global__ __launch_bounds__(kCvThreads) void k_conv3i(const uint16_t* __restric
     // the head's weight fragments and layer 3's bias, in LDS for the whole kernel
     v8bf* s_hf = reinterpret_cast<v8bf*>(s_w + 2 * kL3WElems);
     float* s_b3 = reinterpret_cast<float*>(s_hf + kL3HeadFrags);
+    float* s_u = s_b3 + 96;  // U of the band's 4 x 128 pixels, [tap][row][column]
     const int t = threadIdx.x, lane = t & 63;
     const int wave = __builtin_amdgcn_readfirstlane(t >> 6);
     const int orow = wave >> 1, ocol0 = (wave & 1) * 64;
@@ -1117,6 +1124,7 @@ __global__ __launch_bounds__(kCvThreads) void k_conv3i(const uint16_t* __restric
         s_hf[t] = f;
     }
     if (t < COUT) s_b3[t] = bias[t];
+    const float b4 = hbias[0];
     load_half(band, 0, 0, ra_in, ra_w);
     store_half(0, 0, ra_in, ra_w);
     load_half(band, 0, 1, rb_in, rb_w);
@@ -1185,9 +1193,15 @@ __global__ __launch_bounds__(kCvThreads) void k_conv3i(const uint16_t* __restric
         // epilogue: act3 = BF16(ReLU(acc + b3)), U^T (9 taps padded to 32 rows x
         // 32 pixels) = W4 x act3^T per pixel block; W4's fragments and b3 from LDS
         const int64_t e = band / BPE;
-        const int r0 = (band % BPE) * kCvRows;
-        const int64_t pix0 = (e * kImg + r0 + orow) * kImg + ocol0;
-        const int h = lane >> 5, n = lane & 31;
+        const int kb = band % BPE, r0 = kb * kCvRows;
+        const bool above = kb > 0, below = kb < BPE - 1;  // neighbour bands in the event
+        float* eb = edge + (int64_t)band * kEdgeFloats;
+        // lane-dependent addresses formed anew per band (an opaque zero: hoisted
+        // out of the band loop they would be held in scratch memory)
+        int wz = 0;
+        asm volatile("" : "+s"(wz));
+        const int lz = lane + wz, tz = t + wz;
+        const int h = lz >> 5, n = lz & 31;
 #pragma unroll
         for (int mb = 0; mb < 2; ++mb) {
             v16f au;
@@ -1214,28 +1228,88 @@ __global__ __launch_bounds__(kCvThreads) void k_conv3i(const uint16_t* __restric
                 }
             }
             // lane < 32 holds taps 0-3 and 8 of pixel n, lane >= 32 taps 4-7
-            float* dst = u_out + (pix0 + mb * 32 + n) * kUPitch;
-            *reinterpret_cast<float4*>(dst + 4 * h) = make_float4(au[0], au[1], au[2], au[3]);
-            if (h == 0) dst[8] = au[4];
+            const int col = ocol0 + mb * 32 + n;
+            // band-edge terms (per band, 13 rows of 128 floats): 0-5 taps 3-8 of
+            // row 0, 6-8 taps 6-8 of row 1 (when a band lies above: its last
+            // logit row needs row 0's taps 6-8, and this band's first logit row
+            // is finished after that band's taps 0-2), 9-11 taps 0-2 of row 3
+            // (when a band lies below), 12 the partial sum of row 3
+            auto put = [&](int tap, float v) {
+                s_u[(tap * kCvRows + orow) * kImg + col] = v;
+                if (orow == 0 && above && tap >= 3) eb[(tap - 3) * kImg + col] = v;
+                if (orow == 1 && above && tap >= 6) eb[tap * kImg + col] = v;
+                if (orow == 3 && below && tap < 3) eb[(9 + tap) * kImg + col] = v;
+            };
+#pragma unroll
+            for (int q = 0; q < 4; ++q) put(4 * h + q, au[q]);
+            if (h == 0) put(8, au[4]);
+        }
+        // logits whose nine taps lie in the band, added in tap order (zero
+        // outside the image), and the first six terms of the last row when a
+        // band lies below.  The barrier orders LDS only: the next band's
+        // stage loads stay in flight.
+        __builtin_amdgcn_s_waitcnt(0xc07f);  // lgkmcnt(0)
+        asm volatile("" ::: "memory");
+        __builtin_amdgcn_s_barrier();
+        asm volatile("" ::: "memory");
+        {
+            static_assert(kCvThreads == kCvRows * kImg, "one thread per pixel of the band");
+            const int row = tz / kImg, col = tz % kImg;
+            const bool edge_row = (row == 0 && above) || (row == kCvRows - 1 && below);
+            float z = b4;
+            const int ntap = edge_row ? (row == 0 ? 0 : 6) : 9;
+#pragma unroll
+            for (int tap = 0; tap < 9; ++tap) {
+                const int rr = row + tap / 3 - 1, cc = col + tap % 3 - 1;
+                if (tap < ntap && rr >= 0 && rr < kCvRows && cc >= 0 && cc < kImg)
+                    z += s_u[(tap * kCvRows + rr) * kImg + cc];
+            }
+            if (!edge_row) logits[(e * kImg + r0 + row) * kImg + col] = z;
+            else if (row == kCvRows - 1) eb[12 * kImg + col] = z;
         }
     }
 }
 
-// logit[p] = b + sum_tap U[p + offset(tap)][tap] (zero outside the image)
-__global__ __launch_bounds__(256) void k_head_sum(const float* __restrict__ u, const float* __restrict__ bias,
-                                                  int64_t npix, float* __restrict__ logits)
+// The head's band-edge logit rows, from the terms k_conv3i wrote per band:
+// the first row of a band with a band above adds, after the bias, that band's
+// row-3 taps 0-2 and then its own row-0 taps 3-5 and row-1 taps 6-8; the last
+// row of a band with a band below continues its partial sum with that band's
+// row-0 taps 6-8 (tap order, zero outside the image).
+__global__ __launch_bounds__(256) void k_head_edges(const float* __restrict__ edge, const float* __restrict__ bias,
+                                                    int64_t n_bands, float* __restrict__ logits)
 {
+    constexpr int BPE = kImg / kCvRows;
     const float b = bias[0];
-    for (int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; p < npix; p += (int64_t)gridDim.x * blockDim.x) {
-        const int64_t ev = p / kPix;
-        const int r = (int)((p / kImg) % kImg), c = (int)(p % kImg);
-        float z = b;
+    const int64_t n = n_bands * 2 * kImg;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t band = i / (2 * kImg);
+        const int last = (int)((i / kImg) & 1), col = (int)(i % kImg);
+        const int kb = (int)(band % BPE);
+        const int64_t e = band / BPE;
+        const float* eb = edge + band * kEdgeFloats;
+        float z;
+        if (!last) {
+            if (kb == 0) continue;
+            const float* ea = eb - kEdgeFloats;  // the band above
+            z = b;
 #pragma unroll
-        for (int tap = 0; tap < 9; ++tap) {
-            const int rr = r + tap / 3 - 1, cc = c + tap % 3 - 1;
-            if (rr >= 0 && rr < kImg && cc >= 0 && cc < kImg) z += u[(ev * kPix + rr * kImg + cc) * kUPitch + tap];
+            for (int tap = 0; tap < 9; ++tap) {
+                const int cc = col + tap % 3 - 1;
+                if (cc < 0 || cc >= kImg) continue;
+                z += tap < 3 ? ea[(9 + tap) * kImg + cc] : eb[(tap < 6 ? tap - 3 : tap) * kImg + cc];
+            }
+            logits[(e * kImg + kb * kCvRows) * kImg + col] = z;
+        } else {
+            if (kb == BPE - 1) continue;
+            const float* en = eb + kEdgeFloats;  // the band below
+            z = eb[12 * kImg + col];
+#pragma unroll
+            for (int tap = 6; tap < 9; ++tap) {
+                const int cc = col + tap % 3 - 1;
+                if (cc >= 0 && cc < kImg) z += en[(tap - 3) * kImg + cc];
+            }
+            logits[(e * kImg + kb * kCvRows + kCvRows - 1) * kImg + col] = z;
         }
-        logits[p] = z;
     }
 }
 
@@ -1288,9 +1362,9 @@ void launch_forward(const uint16_t* img, const uint16_t* wbf, const float* w32, 
                            wbf + L.w_off[1], w32 + L.b_off[1], act2, n_bands);
         const unsigned g3 = (unsigned)std::min<int64_t>(n_bands, (int64_t)n_cu);
         hipLaunchKernelGGL(k_conv3i, dim3(g3), dim3(kCvThreads), l3i, st, act2, wbf + L.w_off[2], w32 + L.b_off[2],
-                           wbf + L.w_off[3], u, n_bands);
-        const int gh = (int)std::min<int64_t>((npix + 255) / 256, 65536);
-        hipLaunchKernelGGL(k_head_sum, dim3(gh), dim3(256), 0, st, u, w32 + L.b_off[3], npix, logits);
+                           wbf + L.w_off[3], w32 + L.b_off[3], u, logits, n_bands);
+        const int gh = (int)std::min<int64_t>(((int64_t)n_bands * 2 * kImg + 255) / 256, 65536);
+        hipLaunchKernelGGL(k_head_edges, dim3(gh), dim3(256), 0, st, u, w32 + L.b_off[3], (int64_t)n_bands, logits);
     }
 }
 
@@ -1728,6 +1802,8 @@ __global__ __launch_bounds__(256) void k_flag_fallback_desc(const Desc* __restri
          e += (int64_t)gridDim.x * blockDim.x)
         if (fallback[e]) ev_flags[e] |= 16;
 }
+
+size_t head_edge_floats(int64_t n_events) { return (size_t)n_events * (kImg / kCvRows) * kEdgeFloats; }
 
 void launch_flag_fallback_desc(const Desc* d, const int32_t* fallback, int64_t n_events, hipStream_t st)
 {
