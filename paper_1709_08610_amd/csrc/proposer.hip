@@ -567,7 +567,6 @@ __global__ __launch_bounds__(256) void k_conv_head(const uint16_t* __restrict__ 
 // k_conv_head).
 constexpr int kC12ImgRows = kCvRows + 4;          // image rows staged (halo 2)
 constexpr int kC12ImgCols = kImg + 4;             // image columns staged
-constexpr int kC12A1 = (kCvRows + 2) * kCvCols;   // act1 positions of the tile (780)
 constexpr int kEdgeFloats = 13 * kImg;            // band-edge terms of the head per band (see k_conv3i)
 
 constexpr int kC12Consts = 64 + 128 + 64 * 32 / 2;  // floats: b1, b2, then W1 (64 x 32 BF16)
@@ -700,8 +699,17 @@ __global__ __launch_bounds__(kCvThreads) void k_conv12(const uint16_t* __restric
         }
     };
 
-    int band = xcd_band(blockIdx.x, 0, G);
-    if (band >= n_bands) return;
+    // consecutive bands per work-group: a band takes the two act1 rows it
+    // shares with the previous band of its event from the tile
+    const int b_hi = (int)((int64_t)(blockIdx.x + 1) * n_bands / G);
+    int band = (int)((int64_t)blockIdx.x * n_bands / G);
+    if (band >= b_hi) return;
+    // the tile's halo columns (-1 and 128: layer 2's zero padding) are never written again
+    if (t < (kCvRows + 2) * 2 * 8) {
+        const int pos = t >> 3, chunk = t & 7;
+        const int col = (pos & 1) ? kCvCols - 1 : 0;
+        *reinterpret_cast<uint4*>(s_in + ((pos >> 1) * kCvCols + col) * kCvPitch + chunk * 8) = make_uint4(0u, 0u, 0u, 0u);
+    }
     if (t < 64) s_b1[t] = b1[t];
     if (t < COUT) s_b2[t] = b2[t];
     if (t < 64 * 32 / 8) *reinterpret_cast<u32x4*>(s_w1 + 8 * t) = *reinterpret_cast<const u32x4*>(w1 + 8 * t);
@@ -715,12 +723,17 @@ __global__ __launch_bounds__(kCvThreads) void k_conv12(const uint16_t* __restric
     c12_load_w(w2, 1, t, wreg);
     __syncthreads();
 
-    int q = 0;  // weight slices consumed so far
-    for (int round = 0; band < n_bands; ++round) {
+    int q = 0;     // weight slices consumed so far
+    int base = 0;  // act1 row j of the band (image row r0 - 1 + j) sits in tile row (j + base) % 6
+    for (int round = 0; band < b_hi; ++round) {
         const int64_t e = band / BPE;
         const int r0 = (band % BPE) * kCvRows;
-        const int nband = xcd_band(blockIdx.x, round + 1, G);
-        const bool more = nband < n_bands;
+        const int nband = band + 1;
+        const bool more = nband < b_hi;
+        // rows 4 and 5 of the previous band of the event are rows 0 and 1 of this one
+        const bool fresh = round == 0 || band % BPE == 0;
+        base = fresh ? 0 : (base + 4) % (kCvRows + 2);
+        const int j0 = fresh ? 0 : 2;  // first act1 row computed here
         // the weight-slice reads and layer 1's image-read addresses below stay
         // inside the loop (the same every band, they would otherwise be hoisted
         // out of it and held in scratch memory across layer 2)
@@ -729,9 +742,10 @@ __global__ __launch_bounds__(kCvThreads) void k_conv12(const uint16_t* __restric
         const uint16_t* w2r = w2 + wz;
         const uint32_t* s_imgr = s_img + wz;
 
-        // layer 1 on the act1 tile (rows r0 - 1 .. r0 + 4, columns -1 .. 128):
-        // D = W1 (64 x 32, K = 18 zero-padded) x X^T (32 x 32 positions) per block
-        // of 32 tile positions; act1 outside the image is the zero padding of layer 2
+        // layer 1 on the act1 tile (rows j0 .. 5 of image rows r0 - 1 .. r0 + 4,
+        // columns 0 .. 127): D = W1 (64 x 32, K = 18 zero-padded) x X^T (32 x 32
+        // positions) per block of 32 positions of one row; act1 outside the image
+        // is the zero padding of layer 2
         v8bf aw[2][2];
 #pragma unroll
         for (int cb = 0; cb < 2; ++cb)
@@ -740,62 +754,64 @@ __global__ __launch_bounds__(kCvThreads) void k_conv12(const uint16_t* __restric
                 aw[cb][ks] = *reinterpret_cast<const v8bf*>(s_w1 + (cb * 32 + (lane & 31)) * conv_kp(2) + ks * 16 +
                                                            8 * (lane >> 5));
         const int lz = lane + wz;  // = lane, recomputed each band (see above)
-        // the wave's position blocks (pb = wave + 8 i) two at a time: both blocks'
-        // image reads in flight together, then per block the products and
-        // bias + ReLU + BF16 into the tile
-        constexpr int NPB = (kC12A1 + 31) / 32;                       // position blocks (25)
         constexpr int NW = kCvThreads / 64;
-        constexpr int BPW = (NPB + NW - 1) / NW;                      // per wave, at most 4
-        static_assert(BPW % 2 == 0, "blocks in pairs");
+        constexpr int BPR = kImg / 32;  // position blocks per act1 row
+        const int nblk = (kCvRows + 2 - j0) * BPR;  // 24 or 16: three or two per wave
+        // block pb: its image reads, then its products and bias + ReLU + BF16
+        // into the tile; a wave's first two blocks' reads are in flight together
+        auto gather = [&](int pb, v8bf (&xv)[2]) {
+            const int p = pb * 32 + (lz & 31);
+            const int j = j0 + p / kImg, ic = p % kImg;  // act1 (r0 - 1 + j, ic)
 #pragma unroll
-        for (int i0 = 0; i0 < BPW; i0 += 2) {
-            v8bf xv[2][2];
+            for (int ks = 0; ks < 2; ++ks)
 #pragma unroll
-            for (int i = 0; i < 2; ++i) {
-                const int p = (wave + (i0 + i) * NW) * 32 + (lz & 31);
-                const int jr = p / kCvCols, ic = p % kCvCols;  // act1 position = image (r0 - 1 + jr, ic - 1)
+                for (int qq = 0; qq < 4; ++qq) {
+                    const int tap = (ks * 16 + 8 * (lz >> 5)) / 2 + qq;
+                    uint32_t v = 0;
+                    // the tap adds (tap / 3 - 1, tap % 3 - 1); s_img starts at image (r0 - 2, -2)
+                    if (tap < 9) v = s_imgr[(j + tap / 3) * kC12ImgCols + ic + 1 + tap % 3];
+                    xv[ks][2 * qq] = bits_bf((uint16_t)(v & 0xFFFFu));
+                    xv[ks][2 * qq + 1] = bits_bf((uint16_t)(v >> 16));
+                }
+        };
+        auto finish = [&](int pb, const v8bf (&xv)[2]) {
+            const int p = pb * 32 + (lz & 31);
+            const int j = j0 + p / kImg, ic = p % kImg;
+            const int ar = r0 - 1 + j;
+            const bool inside = ar >= 0 && ar < kImg;
+            int pr = j + base;
+            if (pr >= kCvRows + 2) pr -= kCvRows + 2;
+            uint16_t* dst = s_in + (pr * kCvCols + ic + 1) * kCvPitch;
 #pragma unroll
-                for (int ks = 0; ks < 2; ++ks)
+            for (int cb = 0; cb < 2; ++cb) {
+                v16f a1;
 #pragma unroll
-                    for (int qq = 0; qq < 4; ++qq) {
-                        const int tap = (ks * 16 + 8 * (lz >> 5)) / 2 + qq;
-                        uint32_t v = 0;
-                        // the tap adds (tap / 3 - 1, tap % 3 - 1); s_img starts at image (r0 - 2, -2)
-                        if (tap < 9 && p < kC12A1) v = s_imgr[(jr + tap / 3) * kC12ImgCols + ic + tap % 3];
-                        xv[i][ks][2 * qq] = bits_bf((uint16_t)(v & 0xFFFFu));
-                        xv[i][ks][2 * qq + 1] = bits_bf((uint16_t)(v >> 16));
-                    }
-            }
+                for (int r = 0; r < 16; ++r) a1[r] = 0.0f;
 #pragma unroll
-            for (int i = 0; i < 2; ++i) {
-                if (wave + (i0 + i) * NW >= NPB) continue;
-                const int p = (wave + (i0 + i) * NW) * 32 + (lz & 31);
-                const int jr = p / kCvCols, ic = p % kCvCols;
-                const int ar = r0 - 1 + jr, ac = ic - 1;
-                const bool inside = p < kC12A1 && ar >= 0 && ar < kImg && ac >= 0 && ac < kImg;
+                for (int ks = 0; ks < 2; ++ks) a1 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(aw[cb][ks], xv[ks], a1, 0, 0, 0);
 #pragma unroll
-                for (int cb = 0; cb < 2; ++cb) {
-                    v16f a1;
-#pragma unroll
-                    for (int r = 0; r < 16; ++r) a1[r] = 0.0f;
-#pragma unroll
-                    for (int ks = 0; ks < 2; ++ks)
-                        a1 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(aw[cb][ks], xv[i][ks], a1, 0, 0, 0);
-                    if (p < kC12A1) {
-#pragma unroll
-                        for (int g = 0; g < 4; ++g) {
-                            const int co = cb * 32 + 8 * g + 4 * (lz >> 5);
-                            const float4 bb = *reinterpret_cast<const float4*>(s_b1 + co);
-                            const uint2 v = inside ? pack4_bf16(fmaxf(a1[4 * g] + bb.x, 0.0f),
-                                                                fmaxf(a1[4 * g + 1] + bb.y, 0.0f),
-                                                                fmaxf(a1[4 * g + 2] + bb.z, 0.0f),
-                                                                fmaxf(a1[4 * g + 3] + bb.w, 0.0f))
-                                                   : make_uint2(0u, 0u);
-                            *reinterpret_cast<uint2*>(s_in + p * kCvPitch + co) = v;
-                        }
-                    }
+                for (int g = 0; g < 4; ++g) {
+                    const int co = cb * 32 + 8 * g + 4 * (lz >> 5);
+                    const float4 bb = *reinterpret_cast<const float4*>(s_b1 + co);
+                    const uint2 v = inside ? pack4_bf16(fmaxf(a1[4 * g] + bb.x, 0.0f), fmaxf(a1[4 * g + 1] + bb.y, 0.0f),
+                                                        fmaxf(a1[4 * g + 2] + bb.z, 0.0f),
+                                                        fmaxf(a1[4 * g + 3] + bb.w, 0.0f))
+                                           : make_uint2(0u, 0u);
+                    *reinterpret_cast<uint2*>(dst + co) = v;
                 }
             }
+        };
+        {
+            v8bf xa[2], xb[2];
+            gather(wave, xa);
+            gather(wave + NW, xb);
+            finish(wave, xa);
+            finish(wave + NW, xb);
+        }
+        if (nblk > 2 * NW) {
+            v8bf xc[2];
+            gather(wave + 2 * NW, xc);
+            finish(wave + 2 * NW, xc);
         }
         if (more) load_img(nband);  // in flight during layer 2
         __syncthreads();            // the act1 tile is complete
@@ -810,7 +826,9 @@ __global__ __launch_bounds__(kCvThreads) void k_conv12(const uint16_t* __restric
                 for (int r = 0; r < 16; ++r) acc[i][j][r] = 0.0f;
         for (int tap = 0; tap < 9; ++tap, ++q) {
             const int dr = tap / 3 - 1, dc = tap % 3 - 1;
-            const uint16_t* xrow = s_in + ((orow + 1 + dr) * kCvCols + (ocol0 + 1 + dc)) * kCvPitch;
+            int lr = orow + 1 + dr + base;  // tile row of act1 row orow + 1 + dr
+            if (lr >= kCvRows + 2) lr -= kCvRows + 2;
+            const uint16_t* xrow = s_in + (lr * kCvCols + (ocol0 + 1 + dc)) * kCvPitch;
             const uint16_t* wb = s_w + (q & 1) * COUT * kCvPitch;
             // fragments of k-step kk + 1 are read while the products of kk run: the
             // scheduling barriers keep each read above the products it runs under
