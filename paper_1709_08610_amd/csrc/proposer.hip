@@ -1150,6 +1150,33 @@ __global__ __launch_bounds__(kCvThreads) void k_conv3i(const uint16_t* __restric
     load_half(band, 1, 0, ra_in, ra_w);  // stage 1 in flight
     load_half(band, 1, 1, rb_in, rb_w);
     __syncthreads();
+    // logits of band pb whose nine taps lie in the band, added in tap order
+    // (zero outside the image) from its U in LDS, and the first six terms of
+    // its last row when a band lies below.  Run behind a barrier that follows
+    // the band's epilogue: the first stage barrier of the next band, or the one
+    // after the last band.
+    auto head_logits = [&](int pb) {
+        static_assert(kCvThreads == kCvRows * kImg, "one thread per pixel of the band");
+        const int64_t pe = pb / BPE;
+        const int kb = pb % BPE;
+        const bool above = kb > 0, below = kb < BPE - 1;
+        int wz = 0;
+        asm volatile("" : "+s"(wz));
+        const int tz = t + wz;  // see the epilogue
+        const int row = tz / kImg, col = tz % kImg;
+        const bool edge_row = (row == 0 && above) || (row == kCvRows - 1 && below);
+        float z = b4;
+        const int ntap = edge_row ? (row == 0 ? 0 : 6) : 9;
+#pragma unroll
+        for (int tap = 0; tap < 9; ++tap) {
+            const int rr = row + tap / 3 - 1, cc = col + tap % 3 - 1;
+            if (tap < ntap && rr >= 0 && rr < kCvRows && cc >= 0 && cc < kImg)
+                z += s_u[(tap * kCvRows + rr) * kImg + cc];
+        }
+        if (!edge_row) logits[(pe * kImg + kb * kCvRows + row) * kImg + col] = z;
+        else if (row == kCvRows - 1) edge[(int64_t)pb * kEdgeFloats + 12 * kImg + col] = z;
+    };
+    int prev = -1;  // the band whose logits are still to be summed from U
     for (int round = 0; band < n_bands; band = xcd_band(blockIdx.x, ++round, G)) {
         v16f acc[NB][2];
 #pragma unroll
@@ -1206,19 +1233,19 @@ __global__ __launch_bounds__(kCvThreads) void k_conv3i(const uint16_t* __restric
             }
             // the buffer filled here was last read in the previous stage, before the barrier below it
             __syncthreads();
+            if (c == 0 && prev >= 0) head_logits(prev);  // U of the previous band is complete
         }
 
         // epilogue: act3 = BF16(ReLU(acc + b3)), U^T (9 taps padded to 32 rows x
         // 32 pixels) = W4 x act3^T per pixel block; W4's fragments and b3 from LDS
-        const int64_t e = band / BPE;
-        const int kb = band % BPE, r0 = kb * kCvRows;
+        const int kb = band % BPE;
         const bool above = kb > 0, below = kb < BPE - 1;  // neighbour bands in the event
         float* eb = edge + (int64_t)band * kEdgeFloats;
         // lane-dependent addresses formed anew per band (an opaque zero: hoisted
         // out of the band loop they would be held in scratch memory)
         int wz = 0;
         asm volatile("" : "+s"(wz));
-        const int lz = lane + wz, tz = t + wz;
+        const int lz = lane + wz;
         const int h = lz >> 5, n = lz & 31;
 #pragma unroll
         for (int mb = 0; mb < 2; ++mb) {
@@ -1262,29 +1289,15 @@ __global__ __launch_bounds__(kCvThreads) void k_conv3i(const uint16_t* __restric
             for (int q = 0; q < 4; ++q) put(4 * h + q, au[q]);
             if (h == 0) put(8, au[4]);
         }
-        // logits whose nine taps lie in the band, added in tap order (zero
-        // outside the image), and the first six terms of the last row when a
-        // band lies below.  The barrier orders LDS only: the next band's
-        // stage loads stay in flight.
+        prev = band;
+    }
+    if (prev >= 0) {
+        // the last band's U: an LDS-only barrier (the epilogue's stores need no wait)
         __builtin_amdgcn_s_waitcnt(0xc07f);  // lgkmcnt(0)
         asm volatile("" ::: "memory");
         __builtin_amdgcn_s_barrier();
         asm volatile("" ::: "memory");
-        {
-            static_assert(kCvThreads == kCvRows * kImg, "one thread per pixel of the band");
-            const int row = tz / kImg, col = tz % kImg;
-            const bool edge_row = (row == 0 && above) || (row == kCvRows - 1 && below);
-            float z = b4;
-            const int ntap = edge_row ? (row == 0 ? 0 : 6) : 9;
-#pragma unroll
-            for (int tap = 0; tap < 9; ++tap) {
-                const int rr = row + tap / 3 - 1, cc = col + tap % 3 - 1;
-                if (tap < ntap && rr >= 0 && rr < kCvRows && cc >= 0 && cc < kImg)
-                    z += s_u[(tap * kCvRows + rr) * kImg + cc];
-            }
-            if (!edge_row) logits[(e * kImg + r0 + row) * kImg + col] = z;
-            else if (row == kCvRows - 1) eb[12 * kImg + col] = z;
-        }
+        head_logits(prev);
     }
 }
 

@@ -115,6 +115,41 @@ def test_forward_logits_parity(ctx, batch):
         assert rel < 1e-3, "event %d: relative L2 error %g" % (e, rel)
 
 
+def test_forward_logits_many_bands_per_work_group(ctx):
+    """40 events: 1280 bands of four rows over at most 256 persistent
+    work-groups, so a work-group runs several consecutive bands (taking the
+    act1 rows a band shares with the previous one of its event) and some
+    cross an event boundary.  Every event's logits equal, bit for bit, those
+    of the event run alone (one band per work-group), and three events stay
+    within the oracle's bound."""
+    _say("proposer: forward logits, consecutive bands per work-group")
+    cfg = events.load_config("c4")
+    evs = [events.make_event(cfg, 100 + i) for i in range(40)]
+    evs[17] = events.Event(np.zeros(0, np.float32), np.zeros(0, np.float32), np.zeros(0, np.int32),
+                           np.zeros(0, np.int32), np.zeros((0, 4)), np.zeros(0, np.int32))
+    z = events.plane_z(cfg)
+    big = events.batch_from_events(2, z, evs)
+    m = ctx.retina_model_create(INIT_KEY)
+    p = m.retina_model_get_params()
+    rng = np.random.default_rng(11)
+    layers = op.unpack_params(p)
+    q = np.concatenate([np.concatenate([W.ravel(), rng.normal(0, 0.05, bb.shape)]) for W, bb in layers])
+    m.retina_model_set_params(q.astype(np.float32))
+    params = op.unpack_params(m.retina_model_get_params())
+    _, logits = ctx.retina_model_forward(m, big.plane_z, big.event_offsets, big.x, big.y, big.plane)
+    for e in range(len(evs)):
+        one = events.batch_from_events(2, z, [evs[e]])
+        _, l1 = ctx.retina_model_forward(m, one.plane_z, one.event_offsets, one.x, one.y, one.plane)
+        assert np.array_equal(logits[e].view(np.uint32), l1[0].view(np.uint32)), \
+            "event %d: logits differ from the event run alone (%d entries)" % (e, int((logits[e] != l1[0]).sum()))
+    imgs = _oracle_images(big)
+    for e in (0, 17, 39):
+        _, zr = op.forward(imgs[e], params, store_bf16=True)
+        bound = _logit_bound(imgs[e], params)
+        d = np.abs(logits[e].astype(np.float64) - zr)
+        assert not (d > 1.5 * bound + 1e-6).any(), "event %d: logits outside the bound" % e
+
+
 # ------------------------------------------------------------------ gradients
 def _oracle_loss_grad(b, params, pos_weight, want_bound=False):
     """Loss and gradient of the FP64 oracle; with want_bound also the
