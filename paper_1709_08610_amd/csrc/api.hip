@@ -947,7 +947,8 @@ static int find_tracks_impl(retina_ctx* c, const retina_geometry* g, const retin
     }
     hc.small_merge = n_seeds <= (int64_t)kMergeSmallKeys * E;
     d.seeds_per_item = hot_seeds_per_item(hc);
-    d.items_cap = n_seeds / d.seeds_per_item + E + 1;
+    d.half_parts = hc.split;
+    d.items_cap = n_seeds / d.seeds_per_item + 2 * E + 1;
     if ((rc = ensure_t(c, B_ITEMS, (size_t)d.items_cap, &d.items))) return rc;
     d.seed_mode = P->seed_mode;
     if (P->seed_mode == RETINA_SEED_LATTICE && (rc = set_lattice(c, d, P->lattice_n, P->lattice_lo, P->lattice_hi)))
@@ -1714,7 +1715,8 @@ int learned_impl(retina_ctx* c, const retina_geometry* g, const retina_hits* h, 
     }
     hc.small_merge = k_max <= kMergeSmallKeys;
     d.seeds_per_item = hot_seeds_per_item(hc);
-    d.items_cap = cap / d.seeds_per_item + E + 1;
+    d.half_parts = hc.split;
+    d.items_cap = cap / d.seeds_per_item + 2 * E + 1;
     if ((rc = ensure_t(c, B_ITEMS, (size_t)d.items_cap, &d.items))) return rc;
     d.seed_mode = RETINA_SEED_EXPLICIT;
     d.in_seeds = pa.seeds;

@@ -881,7 +881,9 @@ __global__ __launch_bounds__(kBlock) void k_ascent(const Desc* __restrict__ d, i
         const int item = __builtin_amdgcn_readfirstlane(s_item);
         if (item < 0) break;
         const int2 it0 = d->items[item];
-        const int2 it = make_int2(it0.x, it0.y * d->seeds_per_item);  // (event, first seed)
+        // seeds [it.y, it.y + isz) of event it.x; a negative block is a half block
+        const int isz = it0.y < 0 ? d->seeds_per_item / 2 : d->seeds_per_item;
+        const int2 it = make_int2(it0.x, (it0.y < 0 ? ~it0.y : it0.y) * isz);
         const int e = __builtin_amdgcn_readfirstlane(it.x);
         const EventView ev = begin_event(d, e, s_hits, s_poff, tile_cap);
         const int64_t sbase = d->seed_off[e];
@@ -907,7 +909,7 @@ __global__ __launch_bounds__(kBlock) void k_ascent(const Desc* __restrict__ d, i
     #pragma unroll
             for (int j = 0; j < C; ++j) {
                 const int sj = it.y + (wave * C + j) * SL2 + slane2;
-                active[j] = sj < ns;
+                active[j] = sj < ns && sj < it.y + isz;
                 flags[j] = 0;
                 nre[j] = 0;
                 const int sjc = active[j] ? sj : 0;
@@ -1305,7 +1307,7 @@ __global__ __launch_bounds__(kBlock) void k_ascent(const Desc* __restrict__ d, i
             }
         };
         if constexpr (QS > 1) {
-            const int r = min(ns - it.y, d->seeds_per_item);
+            const int r = min(ns - it.y, isz);
             if (r <= kNW * (kWave / kMaxSplitLanes)) item_body(std::integral_constant<int, kMaxSplitLanes>{});
             else if (r <= kNW * (kWave / (kMaxSplitLanes / 2))) item_body(std::integral_constant<int, kMaxSplitLanes / 2>{});
             else item_body(std::integral_constant<int, QS>{});

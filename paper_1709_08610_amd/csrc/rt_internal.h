@@ -109,8 +109,11 @@ struct Desc {
     int32_t* ev_sorted;          // n_events: 1 when every plane segment is sorted by x (pruning allowed)
     // work items
     int32_t seeds_per_item;
+    int32_t half_parts;          // 1: an event's part-filled seeds go in items of seeds_per_item / 2
     int32_t* order;              // events, longest first
-    int2* items;                 // (event, block * parts + part): seeds [block * seeds_per_item, ...)
+    // (event, block * parts + part): seeds [block * seeds_per_item, ...); with
+    // half_parts a negative block ~b is half-block b: [b * seeds_per_item / 2, ...)
+    int2* items;
     int64_t items_cap;
     // per-seed results (pool)
     double* s_theta;             // n_seeds * 4

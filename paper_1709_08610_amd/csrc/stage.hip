@@ -284,8 +284,11 @@ __global__ __launch_bounds__(1024) void k_plan(const Desc* __restrict__ d, int m
         // track finding: the events of rank r (longest first) go to XCD queue
         // r % kXcds.  Each queue holds first the full items of its events, then
         // their part-filled last items (cheaper, so the work ends on short
-        // items), both in rank order.  Full and part-filled item counts are
-        // summed together, packed into the low and high halves of one word.
+        // items), both in rank order; with half_parts an event's part-filled
+        // seeds form one or two half items (the split shape runs a half item
+        // with 8 or 16 lanes per seed on all four waves).  Full and part-filled
+        // item counts are summed together, packed into the low and high halves
+        // of one word.
         __shared__ int64_t s_qcarry[kXcds], s_qstart[kXcds + 1], s_qfull[kXcds];
         for (int pass = 0; pass < 2; ++pass) {
             if (t < kXcds) s_qcarry[t] = 0;
@@ -298,7 +301,8 @@ __global__ __launch_bounds__(1024) void k_plan(const Desc* __restrict__ d, int m
                     e = d->order[r];
                     const int64_t ns = d->seed_off[e + 1] - d->seed_off[e];
                     nf = ns / spi;
-                    np = ns % spi ? 1 : 0;
+                    const int64_t rem = ns % spi;
+                    np = rem == 0 ? 0 : (d->half_parts && 2 * rem > spi ? 2 : 1);
                 }
                 const int64_t v = nf | (np << 32);
                 // inclusive prefix over this chunk's ranks of the same queue
@@ -318,9 +322,10 @@ __global__ __launch_bounds__(1024) void k_plan(const Desc* __restrict__ d, int m
                         const int64_t it = s_qstart[q] + exf + b;
                         if (it < d->items_cap) d->items[it] = make_int2(e, (int)b);
                     }
-                    if (np) {
-                        const int64_t it = s_qstart[q] + s_qfull[q] + exp_;
-                        if (it < d->items_cap) d->items[it] = make_int2(e, (int)nf);
+                    for (int64_t k = 0; k < np; ++k) {
+                        const int64_t it = s_qstart[q] + s_qfull[q] + exp_ + k;
+                        const int blk = d->half_parts ? ~(int)(2 * nf + k) : (int)nf;
+                        if (it < d->items_cap) d->items[it] = make_int2(e, blk);
                     }
                 }
                 __syncthreads();
