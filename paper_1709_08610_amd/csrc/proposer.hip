@@ -644,8 +644,10 @@ __device__ __forceinline__ int xcd_band(int wg, int i, int G)
     return i * G + (wg % 8) * per + wg / 8;
 }
 
-// Layers 1 and 2, persistent over 4-row bands.  Per band: layer 1 from the
-// staged image rows into the LDS act1 tile, then layer 2's nine taps, each
+// Layers 1 and 2, persistent over 4-row bands, a run of consecutive bands per
+// work-group.  Per band: layer 1 from the staged image rows into the LDS act1
+// tile (the rows a band shares with the previous band of its event stay in
+// the tile), then layer 2's nine taps, each
 // tap's 128 x 64 weight slice double-buffered in LDS with the next slice
 // (the next band's tap 0 after tap 8) loaded during this tap's products.
 // The next band's image rows are loaded into registers while layer 2 runs and
