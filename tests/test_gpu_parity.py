@@ -206,9 +206,11 @@ def test_find_tracks_split_lanes_item_edges(ctx, cfg_name):
     """Few seeds per event run one candidate per lane with four lanes per seed
     (16 seeds per wave, 64 per work item): seed counts on both sides of the
     wave and item boundaries, meas_dim 1 (c1) and 2 (c3 events), seeds near the
-    true tracks, against the oracle."""
+    true tracks, against the oracle.  An event's part-filled seeds go in one or
+    two half items of at most 32 seeds (48, 63 and 127 seeds: two, the second
+    with 16, 31 and 31)."""
     _say("find_tracks split lanes: %s" % cfg_name)
-    counts = [1, 15, 16, 17, 63, 64, 65] + ([128, 129] if cfg_name == "c2" else [])
+    counts = [1, 15, 16, 17, 33, 48, 63, 64, 65, 127] + ([128, 129] if cfg_name == "c2" else [])
     cfg = events.load_config("c1" if cfg_name == "c1" else "c3")
     P = cfg["params"]
     D = 1 if cfg_name == "c1" else 2
