@@ -554,6 +554,9 @@ def main():
                     "efficiency": round(q_lat["efficiency"], 5), "fake_rate": round(q_lat["fake_rate"], 5)},
         "speedup_vs_lattice": r5(wall_lat / wall_lrn),
         "roofline": roofline,
+        "roofline_proposer": {"bound": "mfma", "achieved": r5(net_tflops), "peak": PEAK_BF16_TFLOPS,
+                              "unit": "TFLOP/s", "frac": r5(net_tflops / PEAK_BF16_TFLOPS),
+                              "ms": r5(prof_lrn["ms_propose"])},
         "response": {"RGH_pair_evals_per_s": r5(resp["RGH"]["pair_evals_per_s"]),
                      "RGH_frac_fp32_peak": r5(resp["RGH"]["frac_fp32_peak"]),
                      "R_pair_evals_per_s": r5(resp["R"]["pair_evals_per_s"]),
