@@ -43,6 +43,7 @@ __global__ __launch_bounds__(kBlock, WPS) void k_merge(const Desc* __restrict__ 
     constexpr int NP = 2 * D;
     __shared__ uint64_t s_keys[KC];
     __shared__ double s_lth[LC][NP];
+    __shared__ double s_cth[kBlock][NP];  // the chunk's candidate lines
     __shared__ int s_join[kBlock];
     __shared__ int s_wcnt[kBlock / kWave];
     __shared__ int s_n;
@@ -115,7 +116,10 @@ __global__ __launch_bounds__(kBlock, WPS) void k_merge(const Desc* __restrict__ 
                 sj = (int)(0xFFFFFFFFu - (uint32_t)(keys[c] & 0xFFFFFFFFull));
                 const double* src = d->s_theta + (s0 + sj) * 4;
 #pragma unroll
-                for (int a = 0; a < NP; ++a) th[a] = src[a];
+                for (int a = 0; a < NP; ++a) {
+                    th[a] = src[a];
+                    s_cth[t][a] = th[a];
+                }
                 int join = -1;
                 for (int l = 0; l < nl_old; ++l) {
                     double lt[NP];
@@ -143,9 +147,8 @@ __global__ __launch_bounds__(kBlock, WPS) void k_merge(const Desc* __restrict__ 
                     if (s_join[u] != -1) continue;  // uniform: LDS value written before the barrier
                     const int su = (int)(0xFFFFFFFFu - (uint32_t)(keys[c0 + u] & 0xFFFFFFFFull));
                     double tu[NP];
-                    const double* src = d->s_theta + (s0 + su) * 4;
 #pragma unroll
-                    for (int a = 0; a < NP; ++a) tu[a] = src[a];
+                    for (int a = 0; a < NP; ++a) tu[a] = s_cth[u][a];
                     int found = -1;
                     for (int l0 = nl_old; l0 < nl && found < 0; l0 += kWave) {
                         const int l = l0 + lane;
@@ -179,8 +182,14 @@ __global__ __launch_bounds__(kBlock, WPS) void k_merge(const Desc* __restrict__ 
                         }
                         ++nl;
                     }
-                    // make lane 0's LDS / global writes visible to the wave's next reads
-                    __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "workgroup");
+                    // make lane 0's LDS writes visible to the wave's next reads, and
+                    // its global ones once leaders lie past the LDS cache (their
+                    // lines are then read through lead[]); below that the fence
+                    // leaves the stores to lead[] and memb[] in flight
+                    if (nl > LC)
+                        __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "workgroup");
+                    else
+                        __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "workgroup", "local");
                     __builtin_amdgcn_wave_barrier();
                 }
                 if (lane == 0) s_nl = nl;
