@@ -8,9 +8,15 @@
 //   3. greedy leader clustering in key order, 256 candidates at a time:
 //      every candidate first tests the leaders founded before its chunk (in
 //      parallel; the first within d_merge wins, which is exactly what the
-//      sequential rule gives since earlier leaders come first), then wave 0
-//      resolves the chunk's remaining candidates in order against the
-//      leaders founded inside the chunk, founding new ones.
+//      sequential rule gives since earlier leaders come first).  The chunk's
+//      remaining candidates are resolved among themselves without walking
+//      them in order: each gets the bit mask of its earlier remaining
+//      neighbours within d_merge; in rounds, a candidate with a leader among
+//      them becomes a member, one whose neighbours are all members (or none)
+//      founds a leader.  The sequential rule gives the same split (a
+//      candidate founds a leader exactly when no earlier leader lies within
+//      d_merge), and a member joins its earliest leader neighbour, which is
+//      the first leader founded among them.
 // The cluster distance is the largest in-plane separation of the two lines
 // over the detector's two end planes, in FP64.
 #include "rt_internal.h"
@@ -45,6 +51,7 @@ __global__ __launch_bounds__(kBlock, WPS) void k_merge(const Desc* __restrict__ 
     __shared__ double s_lth[LC][NP];
     __shared__ double s_cth[kBlock][NP];  // the chunk's candidate lines
     __shared__ int s_join[kBlock];
+    __shared__ uint64_t s_lm[kBlock / kWave], s_um[kBlock / kWave];  // leader / unresolved masks of a chunk
     __shared__ int s_wcnt[kBlock / kWave];
     __shared__ int s_n;
     __shared__ int s_nl;
@@ -138,61 +145,94 @@ __global__ __launch_bounds__(kBlock, WPS) void k_merge(const Desc* __restrict__ 
                 s_join[t] = -2;
             }
             __syncthreads();
-            // wave 0 resolves the chunk's unmatched candidates in order; the
-            // leader count nl is kept identical in every lane (uniform updates)
-            if (wave == 0) {
-                const int nchunk = min(kBlock, nc - c0);
-                int nl = nl_old;
-                for (int u = 0; u < nchunk; ++u) {
-                    if (s_join[u] != -1) continue;  // uniform: LDS value written before the barrier
-                    const int su = (int)(0xFFFFFFFFu - (uint32_t)(keys[c0 + u] & 0xFFFFFFFFull));
-                    double tu[NP];
+            // the chunk's unmatched candidates among themselves (see the top)
+            constexpr int NW = kBlock / kWave;
+            const bool un = c < nc && s_join[t] == -1;
+            uint64_t nb[NW];  // earlier unmatched neighbours within d_merge, by chunk position
 #pragma unroll
-                    for (int a = 0; a < NP; ++a) tu[a] = s_cth[u][a];
-                    int found = -1;
-                    for (int l0 = nl_old; l0 < nl && found < 0; l0 += kWave) {
-                        const int l = l0 + lane;
-                        bool hit = false;
-                        if (l < nl) {
-                            double lt[NP];
-                            if (l < LC) {
+            for (int w = 0; w < NW; ++w) {
+                uint64_t m = 0;
+                if (un) {
+                    for (int k = 0; k < kWave; ++k) {
+                        const int v = w * kWave + k;
+                        if (v >= t) break;
+                        if (s_join[v] != -1) continue;
+                        double lt[NP];
 #pragma unroll
-                                for (int a = 0; a < NP; ++a) lt[a] = s_lth[l][a];
-                            } else {
-                                const double* ls = d->s_theta + (s0 + lead[l]) * 4;
-#pragma unroll
-                                for (int a = 0; a < NP; ++a) lt[a] = ls[a];
-                            }
-                            hit = line_dist<D>(tu, lt, z0, z1) <= dm;
-                        }
-                        const uint64_t m = __ballot(hit);
-                        if (m) found = l0 + __ffsll((unsigned long long)m) - 1;
+                        for (int a = 0; a < NP; ++a) lt[a] = s_cth[v][a];
+                        if (line_dist<D>(th, lt, z0, z1) <= dm) m |= 1ull << k;
                     }
-                    if (found >= 0) {
-                        if (lane == 0) s_join[u] = found;
-                    } else {
-                        if (lane == 0) {
-                            if (nl < LC) {
-#pragma unroll
-                                for (int a = 0; a < NP; ++a) s_lth[nl][a] = tu[a];
-                            }
-                            lead[nl] = su;
-                            memb[nl] = 0;
-                            s_join[u] = nl;
-                        }
-                        ++nl;
-                    }
-                    // make lane 0's LDS writes visible to the wave's next reads, and
-                    // its global ones once leaders lie past the LDS cache (their
-                    // lines are then read through lead[]); below that the fence
-                    // leaves the stores to lead[] and memb[] in flight
-                    if (nl > LC)
-                        __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "workgroup");
-                    else
-                        __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "workgroup", "local");
-                    __builtin_amdgcn_wave_barrier();
                 }
-                if (lane == 0) s_nl = nl;
+                nb[w] = m;
+            }
+            bool lead_u = false, done = !un;
+            uint64_t m_un = __ballot(un);
+            if (lane == 0) { s_lm[wave] = 0ull; s_um[wave] = m_un; }
+            for (;;) {
+                __syncthreads();
+                bool any = false;
+                uint64_t lm[NW], um[NW];
+#pragma unroll
+                for (int w = 0; w < NW; ++w) {
+                    lm[w] = s_lm[w];
+                    um[w] = s_um[w];
+                    any = any || um[w] != 0ull;
+                }
+                if (!any) break;  // uniform: every thread read the same masks
+                if (!done) {
+                    bool hit_leader = false, open = false;
+#pragma unroll
+                    for (int w = 0; w < NW; ++w) {
+                        hit_leader = hit_leader || (nb[w] & lm[w]) != 0ull;
+                        open = open || (nb[w] & um[w]) != 0ull;
+                    }
+                    if (hit_leader) done = true;
+                    else if (!open) { done = true; lead_u = true; }
+                }
+                const uint64_t ml = __ballot(lead_u), mu = __ballot(!done);
+                __syncthreads();  // every thread has read the round's masks
+                if (lane == 0) { s_lm[wave] = ml; s_um[wave] = mu; }
+            }
+            // indices: leaders in chunk order after the nl_old earlier ones; a
+            // member joins its earliest leader neighbour
+            {
+                uint64_t lm[NW];
+                int nl_new = 0;
+#pragma unroll
+                for (int w = 0; w < NW; ++w) {
+                    lm[w] = s_lm[w];
+                    nl_new += __popcll(lm[w]);
+                }
+                auto rank = [&](int v) {
+                    int r = 0;
+#pragma unroll
+                    for (int w = 0; w < NW; ++w) {
+                        if (w < (v >> 6)) r += __popcll(lm[w]);
+                        else if (w == (v >> 6)) r += __popcll(lm[w] & ((1ull << (v & 63)) - 1ull));
+                    }
+                    return nl_old + r;
+                };
+                if (un) {
+                    if (lead_u) {
+                        const int l = rank(t);
+                        if (l < LC) {
+#pragma unroll
+                            for (int a = 0; a < NP; ++a) s_lth[l][a] = th[a];
+                        }
+                        lead[l] = sj;
+                        memb[l] = 0;
+                        s_join[t] = l;
+                    } else {
+                        int v = -1;
+#pragma unroll
+                        for (int w = NW - 1; w >= 0; --w) {
+                            const uint64_t m = nb[w] & lm[w];
+                            if (m) v = w * kWave + __builtin_ctzll(m);
+                        }
+                        s_join[t] = rank(v);
+                    }
+                }
+                if (t == 0) s_nl = nl_old + nl_new;
             }
             __syncthreads();
             if (c < nc) atomicAdd(&memb[s_join[t]], 1);
