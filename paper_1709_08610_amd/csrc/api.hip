@@ -721,7 +721,7 @@ int response_impl(retina_ctx* c, const retina_geometry* g, const retina_hits* h,
     if ((rc = upload_desc(c))) return rc;
     prof_mark(c, 0);
     launch_reset(c->d_desc, c->stream);
-    launch_stage(c->d_desc, (int)std::min<int64_t>((E + 3) / 4, (int64_t)c->n_cu * 8), c->stream);
+    launch_stage(c->d_desc, (int)std::min<int64_t>(E, (int64_t)c->n_cu * 8), c->stream);
     prof_mark(c, 1);
     launch_plan_response(c->d_desc, c->stream);
     prof_mark(c, 2);
@@ -852,7 +852,7 @@ int retina_grid_search(retina_ctx* c, const retina_geometry* g, const retina_hit
     if ((rc = upload_desc(c))) return rc;
     prof_mark(c, 0);
     launch_reset(c->d_desc, c->stream);
-    launch_stage(c->d_desc, (int)std::min<int64_t>((E + 3) / 4, (int64_t)c->n_cu * 8), c->stream);
+    launch_stage(c->d_desc, (int)std::min<int64_t>(E, (int64_t)c->n_cu * 8), c->stream);
     prof_mark(c, 1);
     launch_plan_grid(c->d_desc, c->stream);
     prof_mark(c, 2);

@@ -69,24 +69,38 @@ __global__ __launch_bounds__(256) void k_bin_image(const float* __restrict__ hit
                                                    uint16_t* __restrict__ img, const uint32_t* __restrict__ err)
 {
     __shared__ uint32_t s_h[kPix];
+    __shared__ int s_po[kMaxPlanes + 1];
+    __shared__ float s_z[kMaxPlanes];
     if (err && *err) return;
     const float w = (kSlopeHi - kSlopeLo) / kImg;
     for (int64_t e = blockIdx.x; e < E; e += gridDim.x) {
         const int32_t* po = plane_off + e * (P + 1);
-        const bool packed = po[P] - po[0] <= 0xFFFF;
+        if ((int)threadIdx.x <= P) s_po[threadIdx.x] = po[threadIdx.x];
+        if ((int)threadIdx.x < P) s_z[threadIdx.x] = plane_z[threadIdx.x];
+        for (int i = threadIdx.x; i < kPix; i += blockDim.x) s_h[i] = 0;
+        __syncthreads();
+        const int h0 = s_po[0], h1 = s_po[P];
+        const bool packed = h1 - h0 <= 0xFFFF;
         for (int pass = 0; pass < (packed ? 1 : 2); ++pass) {
-            for (int i = threadIdx.x; i < kPix; i += blockDim.x) s_h[i] = 0;
-            __syncthreads();
-            for (int p = 0; p < P; ++p) {
-                const int ch = p < P / 2 ? 0 : 1;
-                if (!packed && ch != pass) continue;
-                const float z = plane_z[p];
-                for (int k = po[p] + threadIdx.x; k < po[p + 1]; k += blockDim.x) {
-                    const float x = hits[(int64_t)k * D];
-                    const float y = D == 2 ? hits[(int64_t)k * D + 1] : 0.0f;
-                    const int bin = slope_bin(x, y, z, w);
-                    if (bin >= 0) atomicAdd(&s_h[bin], packed ? 1u << (16 * ch) : 1u);
+            if (pass) {
+                for (int i = threadIdx.x; i < kPix; i += blockDim.x) s_h[i] = 0;
+                __syncthreads();
+            }
+            // one walk over the event's hits (sorted by plane): a hit's plane is
+            // the last p with s_po[p] <= k, found by bisection
+            for (int k = h0 + threadIdx.x; k < h1; k += blockDim.x) {
+                int lo = 0, hi = P;  // s_po[lo] <= k < s_po[hi]
+                while (hi - lo > 1) {
+                    const int mid = (lo + hi) >> 1;
+                    if (s_po[mid] <= k) lo = mid;
+                    else hi = mid;
                 }
+                const int ch = lo < P / 2 ? 0 : 1;
+                if (!packed && ch != pass) continue;
+                const float x = hits[(int64_t)k * D];
+                const float y = D == 2 ? hits[(int64_t)k * D + 1] : 0.0f;
+                const int bin = slope_bin(x, y, s_z[lo], w);
+                if (bin >= 0) atomicAdd(&s_h[bin], packed ? 1u << (16 * ch) : 1u);
             }
             __syncthreads();
             if (packed) {

@@ -46,7 +46,9 @@ static_assert(kMaxPlanes <= (1 << kPlaneBits) && kMaxPlanes <= kWave, "one lane 
 
 __global__ __launch_bounds__(kBlock) void k_stage(const Desc* __restrict__ d)
 {
-    __shared__ int s_cnt[kBlock / kWave][kMaxPlanes];
+    constexpr int NW = kBlock / kWave;
+    __shared__ int s_cnt[NW][kMaxPlanes];  // per wave: plane counts, then a chunk's counts
+    __shared__ int s_bad;
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);  // scalar: same in every lane
     const int lane = threadIdx.x & (kWave - 1);
     const int P = d->n_planes;
@@ -54,21 +56,26 @@ __global__ __launch_bounds__(kBlock) void k_stage(const Desc* __restrict__ d)
     const int64_t E = d->n_events;
     int* cnt = s_cnt[wave];
     uint32_t err = 0;
-    for (int64_t e = (int64_t)blockIdx.x * (kBlock / kWave) + wave; e < E;
-         e += (int64_t)gridDim.x * (kBlock / kWave)) {
+    // one event per work-group; wave w validates, counts and scatters the w-th
+    // quarter of its hits (contiguous, whole 64-hit chunks), so the placement
+    // is the one-wave stable counting sort's
+    for (int64_t e = blockIdx.x; e < E; e += gridDim.x) {
         const int64_t a = d->in_off[e];
         const int64_t b = d->in_off[e + 1];
         if ((e == 0 && a != 0) || b < a || b > d->n_hits) {
             err |= kErrOffsets;
-            continue;
+            continue;  // uniform over the work-group
         }
+        __syncthreads();  // the previous event is done with s_cnt and s_bad
+        if (threadIdx.x == 0) s_bad = 0;
         if (lane < P) cnt[lane] = 0;
-        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-        __builtin_amdgcn_wave_barrier();
+        const int64_t q = ((b - a + NW - 1) / NW + kWave - 1) / kWave * kWave;
+        const int64_t wa = min(b, a + wave * q), wb = min(b, wa + q);
+        __syncthreads();
         bool bad = false;
-        for (int64_t k0 = a; k0 < b; k0 += kWave) {
+        for (int64_t k0 = wa; k0 < wb; k0 += kWave) {
             const int64_t k = k0 + lane;
-            if (k < b) {
+            if (k < wb) {
                 const int p = d->in_plane[k];
                 const float x = d->in_x[k];
                 const float y = D == 2 ? d->in_y[k] : 0.0f;
@@ -77,33 +84,49 @@ __global__ __launch_bounds__(kBlock) void k_stage(const Desc* __restrict__ d)
                 if (!isfinite(x) || !isfinite(y)) { err |= kErrCoord; bad = true; }
             }
         }
-        __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
-        __builtin_amdgcn_wave_barrier();
-        if (__any(bad)) continue;
-        // exclusive scan of the plane counts (lanes 0..P-1)
-        int c = lane < P ? cnt[lane] : 0;
-        int incl = c;
+        if (__any(bad) && lane == 0) s_bad = 1;
+        __syncthreads();
+        if (s_bad) continue;  // uniform: read after the barrier
+        // lane p: the event's hits of planes < p (an exclusive scan of the
+        // totals) plus those of plane p in the waves before this one
+        int tot = 0, before = 0;
+        if (lane < P) {
+            for (int w = 0; w < NW; ++w) {
+                const int c = s_cnt[w][lane];
+                tot += c;
+                if (w < wave) before += c;
+            }
+        }
+        int incl = tot;
         for (int off = 1; off < kWave; off <<= 1) {
             const int v = __shfl_up(incl, off, kWave);
             if (lane >= off) incl += v;
         }
-        int cursor = (int)a + incl - c;  // lane p: next free slot of plane p
-        int32_t* po = d->plane_off + e * (P + 1);
-        if (lane < P) po[lane] = cursor;
-        if (lane == 0) {
-            po[P] = (int)b;
-            d->ev_nhits[e] = (int)(b - a);
+        int cursor = (int)a + incl - tot + before;  // lane p: this wave's next free slot of plane p
+        if (wave == 0) {
+            int32_t* po = d->plane_off + e * (P + 1);
+            if (lane < P) po[lane] = (int)a + incl - tot;
+            if (lane == 0) {
+                po[P] = (int)b;
+                d->ev_nhits[e] = (int)(b - a);
+            }
         }
+        __syncthreads();  // every wave has read the counts before its row is reused
         // per 64-hit chunk: the lanes holding the same plane are those whose
         // plane numbers agree bit by bit (one ballot per bit), a hit's slot is
         // its plane's cursor plus the number of earlier lanes of that plane
         // (stable), and the last lane of each plane hands the chunk's count
         // to the lane that keeps the plane's cursor
         const uint64_t gt = lane == kWave - 1 ? 0ull : (~0ull << (lane + 1));
-        for (int64_t k0 = a; k0 < b; k0 += kWave) {
+        for (int64_t k0 = wa; k0 < wb; k0 += kWave) {
             const int64_t k = k0 + lane;
-            const bool live = k < b;
+            const bool live = k < wb;
             const int p = live ? d->in_plane[k] : 0;
+            float2 v = make_float2(0.0f, 0.0f);
+            if (live) {
+                v.x = d->in_x[k];
+                if (D == 2) v.y = d->in_y[k];
+            }
             uint64_t same = __ballot(live);
 #pragma unroll
             for (int bit = 0; bit < kPlaneBits; ++bit) {
@@ -123,14 +146,8 @@ __global__ __launch_bounds__(kBlock) void k_stage(const Desc* __restrict__ d)
             __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
             __builtin_amdgcn_wave_barrier();
             if (live) {
-                if (D == 2) {
-                    float2 v;
-                    v.x = d->in_x[k];
-                    v.y = d->in_y[k];
-                    reinterpret_cast<float2*>(d->hits)[pos] = v;
-                } else {
-                    d->hits[pos] = d->in_x[k];
-                }
+                if (D == 2) reinterpret_cast<float2*>(d->hits)[pos] = v;
+                else d->hits[pos] = v.x;
             }
         }
     }
