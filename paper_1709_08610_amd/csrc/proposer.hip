@@ -71,8 +71,11 @@ __global__ __launch_bounds__(256) void k_bin_image(const float* __restrict__ hit
     __shared__ uint32_t s_h[kPix];
     __shared__ int s_po[kMaxPlanes + 1];
     __shared__ float s_z[kMaxPlanes];
+    __shared__ uint16_t s_lut[256];  // BF16(log1p(n)) for the common small counts
     if (err && *err) return;
     const float w = (kSlopeHi - kSlopeLo) / kImg;
+    for (int n = threadIdx.x; n < 256; n += blockDim.x) s_lut[n] = f2bf(log1pf((float)n));
+    auto enc = [&](uint32_t n) -> uint32_t { return n < 256 ? s_lut[n] : f2bf(log1pf((float)n)); };
     for (int64_t e = blockIdx.x; e < E; e += gridDim.x) {
         const int32_t* po = plane_off + e * (P + 1);
         if ((int)threadIdx.x <= P) s_po[threadIdx.x] = po[threadIdx.x];
@@ -107,12 +110,11 @@ __global__ __launch_bounds__(256) void k_bin_image(const float* __restrict__ hit
                 uint32_t* out = reinterpret_cast<uint32_t*>(img + e * kPix * 2);
                 for (int i = threadIdx.x; i < kPix; i += blockDim.x) {
                     const uint32_t c = s_h[i];
-                    const float a = log1pf((float)(c & 0xFFFFu)), b = log1pf((float)(c >> 16));
-                    out[i] = (uint32_t)f2bf(a) | ((uint32_t)f2bf(b) << 16);
+                    out[i] = enc(c & 0xFFFFu) | (enc(c >> 16) << 16);
                 }
             } else {
                 uint16_t* out = img + e * kPix * 2;
-                for (int i = threadIdx.x; i < kPix; i += blockDim.x) out[2 * i + pass] = f2bf(log1pf((float)s_h[i]));
+                for (int i = threadIdx.x; i < kPix; i += blockDim.x) out[2 * i + pass] = (uint16_t)enc(s_h[i]);
             }
             __syncthreads();
         }
