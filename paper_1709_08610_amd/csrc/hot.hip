@@ -888,9 +888,10 @@ __global__ __launch_bounds__(kBlock) void k_ascent(const Desc* __restrict__ d, i
         const EventView ev = begin_event(d, e, s_hits, s_poff, tile_cap);
         const int64_t sbase = d->seed_off[e];
         const int ns = (int)(d->seed_off[e + 1] - sbase);
-        // lanes per seed for this item: a part-filled item spreads its seeds over
-        // all four waves with more lanes each (every pass then walks the hits in
-        // fewer strides), so that it costs less than a full one
+        // lanes per seed for this item: a half item (an event's part-filled
+        // seeds, at most 32) spreads its seeds over all four waves with 8 or
+        // 16 lanes each (every pass then walks the hits in fewer strides), so
+        // that it costs less than a full one
         auto item_body = [&](auto qtag) {
             constexpr int QS2 = decltype(qtag)::value;
             constexpr int SL2 = kWave / QS2;  // seeds per wave and candidate slot
