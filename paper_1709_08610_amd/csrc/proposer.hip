@@ -1642,12 +1642,22 @@ __global__ __launch_bounds__(256) void k_propose_select(ProposeArgs a)
         }
         float best = -INFINITY;
         __syncthreads();
-        for (int i = threadIdx.x; i < kPix; i += blockDim.x) {
-            const float v = z[i];
-            best = fmaxf(best, v);
-            if (!is_cand(z, i, v, ltau, a.nms)) continue;
-            const int slot = atomicAdd(&s_n, 1);
-            if (slot < kCandCap) s_key[slot] = cand_key(v, i);
+        // the logit reads of four positions go out together (the loop is
+        // otherwise one dependent global read per position)
+        constexpr int T = 256;  // the launch's work-group size
+        static_assert(kPix % (4 * T) == 0, "whole groups of four positions per thread");
+        for (int i0 = threadIdx.x; i0 < kPix; i0 += 4 * T) {
+            float v4[4];
+#pragma unroll
+            for (int q = 0; q < 4; ++q) v4[q] = z[i0 + q * T];
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                const int i = i0 + q * T;
+                best = fmaxf(best, v4[q]);
+                if (!is_cand(z, i, v4[q], ltau, a.nms)) continue;
+                const int slot = atomicAdd(&s_n, 1);
+                if (slot < kCandCap) s_key[slot] = cand_key(v4[q], i);
+            }
         }
         s_best[threadIdx.x] = best;
         __syncthreads();
