@@ -1336,26 +1336,36 @@ __global__ __launch_bounds__(256) void k_head_edges(const float* __restrict__ ed
         const int kb = (int)(band % BPE);
         const int64_t e = band / BPE;
         const float* eb = edge + band * kEdgeFloats;
+        // every term is read first (at a clamped column), then added in tap
+        // order where its column lies in the image: the reads go out together
         float z;
         if (!last) {
             if (kb == 0) continue;
             const float* ea = eb - kEdgeFloats;  // the band above
+            float v[9];
+#pragma unroll
+            for (int tap = 0; tap < 9; ++tap) {
+                const int cc = min(max(col + tap % 3 - 1, 0), kImg - 1);
+                v[tap] = tap < 3 ? ea[(9 + tap) * kImg + cc] : eb[(tap < 6 ? tap - 3 : tap) * kImg + cc];
+            }
             z = b;
 #pragma unroll
             for (int tap = 0; tap < 9; ++tap) {
                 const int cc = col + tap % 3 - 1;
-                if (cc < 0 || cc >= kImg) continue;
-                z += tap < 3 ? ea[(9 + tap) * kImg + cc] : eb[(tap < 6 ? tap - 3 : tap) * kImg + cc];
+                z = (cc >= 0 && cc < kImg) ? z + v[tap] : z;
             }
             logits[(e * kImg + kb * kCvRows) * kImg + col] = z;
         } else {
             if (kb == BPE - 1) continue;
             const float* en = eb + kEdgeFloats;  // the band below
+            float v[3];
+#pragma unroll
+            for (int k = 0; k < 3; ++k) v[k] = en[(3 + k) * kImg + min(max(col + k - 1, 0), kImg - 1)];
             z = eb[12 * kImg + col];
 #pragma unroll
-            for (int tap = 6; tap < 9; ++tap) {
-                const int cc = col + tap % 3 - 1;
-                if (cc >= 0 && cc < kImg) z += en[(tap - 3) * kImg + cc];
+            for (int k = 0; k < 3; ++k) {
+                const int cc = col + k - 1;
+                z = (cc >= 0 && cc < kImg) ? z + v[k] : z;
             }
             logits[(e * kImg + kb * kCvRows + kCvRows - 1) * kImg + col] = z;
         }
