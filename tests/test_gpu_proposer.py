@@ -76,6 +76,42 @@ def test_bin_image_exact(ctx, batch):
     assert not _bf16_bits_to_f64(img[3]).any()
 
 
+def test_bin_image_large_counts_and_events(ctx):
+    """Bin counts above the 256-entry table of BF16(log1p(count)) (300 hits on
+    every plane of one line through the origin: 3,900 per plane group in one
+    bin) and an event of more than 65,535 hits (two passes, one per plane
+    group, 16-bit counts no longer packed in pairs), against the oracle's
+    binning bit for bit."""
+    _say("proposer: bin image, large counts and events")
+    cfg = events.load_config("c4")
+    z = events.plane_z(cfg)
+    P = len(z)
+    rng = np.random.default_rng(23)
+    w = (0.35 - (-0.35)) / 128
+    tx, ty = -0.35 + 40.5 * w, -0.35 + 90.5 * w  # bin centres: every plane's hit lands in bin (40, 90)
+    pl = np.repeat(np.arange(P, dtype=np.int32), 300)
+    zz = z[pl].astype(np.float64)
+    line = events.Event((tx * zz).astype(np.float32), (ty * zz).astype(np.float32), pl,
+                        np.zeros(len(pl), np.int32), np.array([[0.0, 0.0, tx, ty]]), np.array([len(pl)], np.int32))
+    n = 70_000
+    pl2 = np.sort(rng.integers(0, P, n)).astype(np.int32)
+    z2 = z[pl2].astype(np.float64)
+    wide = events.Event((rng.uniform(-0.34, 0.34, n) * z2).astype(np.float32),
+                        (rng.uniform(-0.34, 0.34, n) * z2).astype(np.float32), pl2,
+                        np.full(n, -1, np.int32), np.zeros((0, 4)), np.zeros(0, np.int32))
+    b = events.batch_from_events(2, z, [line, wide])
+    m = ctx.retina_model_create(INIT_KEY)
+    img, _ = ctx.retina_model_forward(m, b.plane_z, b.event_offsets, b.x, b.y, b.plane)
+    ref = _oracle_images(b)
+    cnt = op.bin_counts(*(lambda ev: (ev.x, ev.y, ev.plane))(b.event(0)), b.plane_z)
+    assert cnt.max() > 255, "the line's bin should exceed the table"
+    assert b.event_offsets[2] - b.event_offsets[1] > 0xFFFF
+    for e in range(b.n_events):
+        want = op.bf16_round(ref[e])
+        got = _bf16_bits_to_f64(img[e])
+        assert np.array_equal(got, want), "event %d: %d bins differ" % (e, int((got != want).sum()))
+
+
 def test_model_params_round_trip(ctx):
     m = ctx.retina_model_create(INIT_KEY)
     p = m.retina_model_get_params()
