@@ -68,7 +68,7 @@ __global__ __launch_bounds__(256) void k_bin_image(const float* __restrict__ hit
                                                    const float* __restrict__ plane_z, int64_t E,
                                                    uint16_t* __restrict__ img, const uint32_t* __restrict__ err)
 {
-    __shared__ uint32_t s_h[kPix];
+    __shared__ __attribute__((aligned(16))) uint32_t s_h[kPix];  // read and cleared as uint4
     __shared__ int s_po[kMaxPlanes + 1];
     __shared__ float s_z[kMaxPlanes];
     __shared__ uint16_t s_lut[256];  // BF16(log1p(n)) for the common small counts
@@ -80,13 +80,14 @@ __global__ __launch_bounds__(256) void k_bin_image(const float* __restrict__ hit
         const int32_t* po = plane_off + e * (P + 1);
         if ((int)threadIdx.x <= P) s_po[threadIdx.x] = po[threadIdx.x];
         if ((int)threadIdx.x < P) s_z[threadIdx.x] = plane_z[threadIdx.x];
-        for (int i = threadIdx.x; i < kPix; i += blockDim.x) s_h[i] = 0;
+        for (int i = threadIdx.x; i < kPix / 4; i += blockDim.x) reinterpret_cast<uint4*>(s_h)[i] = make_uint4(0u, 0u, 0u, 0u);
         __syncthreads();
         const int h0 = s_po[0], h1 = s_po[P];
         const bool packed = h1 - h0 <= 0xFFFF;
         for (int pass = 0; pass < (packed ? 1 : 2); ++pass) {
             if (pass) {
-                for (int i = threadIdx.x; i < kPix; i += blockDim.x) s_h[i] = 0;
+                for (int i = threadIdx.x; i < kPix / 4; i += blockDim.x)
+                    reinterpret_cast<uint4*>(s_h)[i] = make_uint4(0u, 0u, 0u, 0u);
                 __syncthreads();
             }
             // one walk over the event's hits (sorted by plane): a hit's plane is
@@ -107,10 +108,14 @@ __global__ __launch_bounds__(256) void k_bin_image(const float* __restrict__ hit
             }
             __syncthreads();
             if (packed) {
-                uint32_t* out = reinterpret_cast<uint32_t*>(img + e * kPix * 2);
-                for (int i = threadIdx.x; i < kPix; i += blockDim.x) {
-                    const uint32_t c = s_h[i];
-                    out[i] = enc(c & 0xFFFFu) | (enc(c >> 16) << 16);
+                // four pixels (both channels each) per 16-byte store
+                uint4* out = reinterpret_cast<uint4*>(img + e * kPix * 2);
+                for (int i = threadIdx.x; i < kPix / 4; i += blockDim.x) {
+                    const uint4 c = reinterpret_cast<const uint4*>(s_h)[i];
+                    out[i] = make_uint4(enc(c.x & 0xFFFFu) | (enc(c.x >> 16) << 16),
+                                        enc(c.y & 0xFFFFu) | (enc(c.y >> 16) << 16),
+                                        enc(c.z & 0xFFFFu) | (enc(c.z >> 16) << 16),
+                                        enc(c.w & 0xFFFFu) | (enc(c.w >> 16) << 16));
                 }
             } else {
                 uint16_t* out = img + e * kPix * 2;
